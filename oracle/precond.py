@@ -1,0 +1,75 @@
+"""Preconditioners of Section 6 (oracle).
+
+Test infrastructure only.
+
+* 'vl_as'  -- vertical lumping + additive smoother, eq. ourpreconditioner:
+              z = E~ Vcyc_S(E~^T r) + Z Vcyc_Abar(Z^T r), Z = [0; I].
+              The two terms are independent; with exact solves in both and
+              the exact extrapolation E this is A^{-1} (eq. E multigrid).
+* 'vl_sor' -- vertical lumping as the first coarsening of an ordinary
+              multigrid cycle with one forward SOR sweep on A before and one
+              backward sweep after (Section 6, second preconditioner):
+              x = GS_fwd(A, r); x += E~ Vcyc_S(E~^T (r - A x)); x = GS_bwd(A, r, x).
+* 'sa'     -- one smoothed aggregation V-cycle on the whole A (the first
+              preconditioner of Section 6, the paper's baseline, which shows
+              eps-dependent plateaus).
+* 'jacobi' -- z = r / diag(A).
+* 'none'   -- z = r.
+In mode D the surface branch is empty (all top values are fixed) and
+'vl_as' reduces to the additive smoother alone.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import amg
+
+
+def _vl_as(s):
+    def apply(r):
+        z = np.zeros_like(r)
+        if s.n_top > 0:
+            z += s.E @ amg.vcycle(s.S_levels, s.E.T @ r)
+        z[s.n_top:] += amg.vcycle(s.Abar_levels, r[s.n_top:])
+        return z
+    return apply
+
+
+def _vl_sor(s):
+    def apply(r):
+        x = amg.gs_sweep(s.A, s.diag, s.colour, r, np.zeros_like(r), forward=True)
+        if s.n_top > 0:
+            res = r - s.A @ x
+            x = x + s.E @ amg.vcycle(s.S_levels, s.E.T @ res)
+        x = amg.gs_sweep(s.A, s.diag, s.colour, r, x, forward=False)
+        return x
+    return apply
+
+
+def _sa(s):
+    if getattr(s, "_sa_levels", None) is None:
+        # colour-sorted order over the whole A_UU: stable sort by colour
+        perm = np.argsort(s.colour, kind="stable")
+        A = amg.permute(s.A, perm)
+        s._sa_levels = (perm, amg.build_hierarchy(A, s.colour[perm]))
+    perm, levels = s._sa_levels
+
+    def apply(r):
+        z = np.zeros_like(r)
+        z[perm] = amg.vcycle(levels, r[perm])
+        return z
+    return apply
+
+
+def make(s, pc):
+    if pc == "sa":
+        return _sa(s)
+    if pc == "vl_as":
+        return _vl_as(s)
+    if pc == "vl_sor":
+        return _vl_sor(s)
+    if pc == "jacobi":
+        return lambda r: r / s.diag
+    if pc == "none":
+        return lambda r: r.copy()
+    raise ValueError(pc)

@@ -1,0 +1,142 @@
+"""End-to-end oracle: setup in the device node order, and solve.
+
+Test infrastructure only.
+
+Order of the free unknowns ("storage order"): top block first (paper
+eq. phi_decomposition), each block in locality order, then stably sorted by
+the greedy colour of A_UU computed in locality order (see ordering.py).  The
+non-top block is the matrix A_bar of eq. equation_decomposition; its colouring
+is the restriction of the colouring of A_UU.  The surface operator
+S = E~^T A E~ is coloured in the top block's storage order and stored colour
+by colour as well; E~'s columns follow that order.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import amg, extrap, fem, ordering, pcg, precond
+
+
+@dataclass
+class OracleSetup:
+    mode: str
+    n_nodes: int
+    pin: int
+    perm: np.ndarray          # storage position -> natural node index
+    n_top: int                # free top unknowns (= m')
+    Aoff: sp.csr_matrix       # off-diagonals of A_UU, storage order
+    d: np.ndarray             # deficit, storage order
+    A: sp.csr_matrix          # standard form A_UU, storage order
+    diag: np.ndarray
+    colour: np.ndarray        # colour of every storage row (sorted within each block)
+    E: sp.csr_matrix | None   # n x m', columns in S storage order
+    S_perm: np.ndarray | None  # S storage position -> top-block position
+    S_levels: list | None
+    Abar_levels: list
+    mass: sp.csr_matrix       # full consistent mass matrix, natural order
+    xyz: np.ndarray
+    top: np.ndarray
+
+    @property
+    def n(self):
+        return self.perm.size
+
+
+def setup(mesh, mode="N", coarse_max=256, max_levels=10):
+    """Assembly (Section 3), E~ (Section 5.4) and both SA hierarchies (Section 6)."""
+    xyz, tets, top = mesh.xyz, mesh.tets, mesh.top
+    n_nodes = xyz.shape[0]
+    _, Aoff_full = fem.assemble_stiffness(xyz, tets)
+    pin = fem.pin_node(xyz, top) if mode == "N" else -1
+    D = fem.dirichlet_set(xyz, top, mode, pin)
+    free = ~D
+    # locality order and colouring of A_UU (indices in natural numbering)
+    loc = ordering.locality_order(xyz, top, free)
+    U, Auu_nat, d_nat = fem.reduce_to_unknowns(Aoff_full, D)
+    pos_in_U = np.full(n_nodes, -1, dtype=np.int64)
+    pos_in_U[U] = np.arange(U.size)
+    loc_u = pos_in_U[loc]
+    colour_u = ordering.greedy_colouring(Auu_nat, loc_u)
+    block = np.where(top[U], 0, 1)
+    order_u = ordering.colour_sorted(loc_u, colour_u, block)
+    perm = U[order_u]
+    Aoff = ordering_permute(Auu_nat, order_u)
+    d = d_nat[order_u] + 0.0
+    A = fem.full_matrix(Aoff, d)
+    diag = fem.diagonal_of(Aoff, d)
+    colour = colour_u[order_u]
+    n_top = int(np.count_nonzero(top[perm]))
+    n = perm.size
+
+    # surface branch: E~, S = E~^T A E~ and its hierarchy (mode N only)
+    E = None
+    S_perm = None
+    S_levels = None
+    if n_top > 0:
+        E0, _ = extrap.vertical_extrapolation(xyz, tets, top, perm, D)
+        S0 = amg.structural_product(E0.T.tocsr(), A, E0)
+        S_perm, S_col = amg.colour_level(S0)
+        E = E0[:, S_perm].tocsr()
+        E.sort_indices()
+        # near-kernel of the vertically lumped operator: the constant and the
+        # two horizontal coordinates (P1 extrapolation of a linear function
+        # of x, y has no vertical gradient, so it lies in ker A_0, Section 4)
+        top_nodes = perm[:n_top][S_perm]
+        B0 = np.column_stack([np.ones(n_top), xyz[top_nodes, 0], xyz[top_nodes, 1]])
+        S_levels = amg.build_hierarchy(amg.permute(S0, S_perm), S_col, B0, coarse_max, max_levels)
+
+    # interior branch: A_bar = non-top block
+    Abar = A[n_top:, n_top:].tocsr()
+    Abar.sort_indices()
+    Abar_levels = amg.build_hierarchy(Abar, colour[n_top:], None, coarse_max, max_levels)
+
+    return OracleSetup(mode=mode, n_nodes=n_nodes, pin=pin, perm=perm, n_top=n_top,
+                       Aoff=Aoff, d=d, A=A, diag=diag, colour=colour, E=E, S_perm=S_perm,
+                       S_levels=S_levels, Abar_levels=Abar_levels,
+                       mass=fem.assemble_mass(xyz, tets), xyz=xyz, top=top)
+
+
+def ordering_permute(A, order):
+    B = A.tocsr()[order][:, order].tocsr()
+    B.sort_indices()
+    return B
+
+
+def apply_A(s: OracleSetup, x):
+    """A_UU x in difference form (the operator CG solves)."""
+    return fem.apply_difference_form(s.Aoff, s.d, x)
+
+
+def rhs_from_field(s: OracleSetup, f_nodal):
+    """b = M f (eq. Ax=b) restricted to the free nodes, storage order.  In
+    mode N the Neumann problem needs int f = 0; b is first made orthogonal to
+    constants by subtracting (sum b / sum w) w, w = M 1 (reading)."""
+    b = s.mass @ f_nodal
+    if s.mode == "N":
+        w = s.mass @ np.ones(s.n_nodes)
+        b = b - (b.sum() / w.sum()) * w
+    return b[s.perm]
+
+
+def rhs_from_solution(s: OracleSetup, x_nodal):
+    """b = A_UU x* for a chosen solution x* (the paper's error protocol,
+    Section 6: choose a solution and multiply by the matrix).  Values of x*
+    at Dirichlet nodes are ignored (taken as zero)."""
+    return apply_A(s, x_nodal[s.perm])
+
+
+def to_natural(s: OracleSetup, x):
+    out = np.zeros(s.n_nodes)
+    out[s.perm] = x
+    return out
+
+
+def solve(s: OracleSetup, b, tol=1e-8, pc="vl_as", max_iter=1000):
+    """PCG on A_UU x = b (storage order), stopping test confirmed on the true
+    residual.  Returns (x, iterations, true relative residual, converged)."""
+    M = precond.make(s, pc)
+    x, it, rel, ok, _ = pcg.pcg_restarted(lambda v: apply_A(s, v), M, b, tol, max_iter)
+    return x, it, rel, ok

@@ -1,0 +1,103 @@
+"""Pins of the preconditioners (Sections 5.2-5.5, 6) and of PCG."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from inputs import box_mesh, fourier_field, manufactured_u
+from oracle import pcg, precond, solver
+
+
+@pytest.fixture(scope="module", params=["N", "D"])
+def small(request):
+    m = box_mesh(8, 7, 5, 0.01, jitter=0.25, seed=21, bathymetry=True)
+    return m, solver.setup(m, request.param, coarse_max=20)
+
+
+def test_schur_and_exact_inverse_decomposition():
+    # eq. E equation: E^T A E = B - C A_bar^{-1} C^T, and eq. E multigrid:
+    # A^{-1} = E (E^T A E)^{-1} E^T + Z A_bar^{-1} Z^T, with E = [I; -A_bar^{-1} C^T]
+    m = box_mesh(6, 5, 4, 0.05, jitter=0.2, seed=2)
+    s = solver.setup(m, "N", coarse_max=10)
+    A = s.A.toarray()
+    nt = s.n_top
+    B, C, Abar = A[:nt, :nt], A[:nt, nt:], A[nt:, nt:]
+    Ai = np.linalg.inv(Abar)
+    E = np.vstack([np.eye(nt), -Ai @ C.T])
+    schur = B - C @ Ai @ C.T
+    assert np.abs(E.T @ A @ E - schur).max() < 1e-10 * np.abs(schur).max()
+    Z = np.vstack([np.zeros((nt, A.shape[0] - nt)), np.eye(A.shape[0] - nt)])
+    Minv = E @ np.linalg.inv(E.T @ A @ E) @ E.T + Z @ Ai @ Z.T
+    Ainv = np.linalg.inv(A)
+    assert np.abs(Minv - Ainv).max() < 1e-8 * np.abs(Ainv).max()
+
+
+@pytest.mark.parametrize("pc", ["vl_as", "vl_sor", "jacobi"])
+def test_preconditioners_symmetric_positive_definite(small, pc):
+    m, s = small
+    M = precond.make(s, pc)
+    Bm = np.column_stack([M(e) for e in np.eye(s.n)])
+    assert np.abs(Bm - Bm.T).max() < 1e-10 * np.abs(Bm).max()
+    assert np.linalg.eigvalsh(0.5 * (Bm + Bm.T)).min() > 0
+
+
+@pytest.mark.parametrize("pc", ["vl_as", "vl_sor", "jacobi", "none"])
+def test_pcg_matches_direct_solve(small, pc):
+    m, s = small
+    b = solver.rhs_from_field(s, fourier_field(m.xyz, 0.01, 3))
+    x, it, rel, ok = solver.solve(s, b, 1e-11, pc, max_iter=5000)
+    assert ok
+    xd = spla.spsolve(s.A.tocsc(), b)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-9
+
+
+def test_manufactured_discrete_solution_recovered():
+    # the paper's protocol: choose x*, set b = A x*, so the error is known exactly
+    m = box_mesh(9, 9, 5, 0.01, jitter=0.2, seed=1)
+    s = solver.setup(m, "N", coarse_max=20)
+    xs = manufactured_u(m.xyz, 0.01)
+    b = solver.rhs_from_solution(s, xs)
+    x, it, rel, ok = solver.solve(s, b, 1e-11, "vl_as")
+    assert ok
+    ref = xs[s.perm]
+    assert np.max(np.abs(x - ref)) / np.max(np.abs(ref)) < 1e-9
+
+
+def test_cg_error_decreases_in_energy_norm(small):
+    m, s = small
+    b = solver.rhs_from_field(s, fourier_field(m.xyz, 0.01, 4))
+    xd = spla.spsolve(s.A.tocsc(), b)
+    M = precond.make(s, "vl_as")
+    errs = []
+    for k in range(1, 15):
+        x, it, _, _ = pcg.pcg(lambda v: solver.apply_A(s, v), M, b, 0.0, max_iter=k)
+        e = x - xd
+        errs.append(e @ (s.A @ e))
+    assert all(b2 <= b1 * (1 + 1e-9) for b1, b2 in zip(errs, errs[1:]))
+
+
+def test_zero_rhs_and_breakdown():
+    x, it, hist, ok = pcg.pcg(lambda v: v, lambda r: r, np.zeros(5), 1e-8)
+    assert it == 0 and ok and not x.any()
+    with pytest.raises(pcg.Breakdown):
+        pcg.pcg(lambda v: -v, lambda r: r, np.ones(5), 1e-8)
+
+
+@pytest.mark.parametrize("jitter", [0.0, 0.3])
+def test_vertical_lumping_iterations_flat_in_aspect_ratio(jitter):
+    # Section 6: with vertical lumping the iteration count stops depending on
+    # eps for small eps.  Plain smoothed aggregation on A also copes with
+    # aligned columns, but on broken columns (the paper's vertically
+    # unstructured case) it develops eps-dependent plateaus.
+    its = {pc: [] for pc in ("vl_as", "vl_sor", "sa")}
+    for H in (1e-2, 1e-3, 1e-4):
+        m = box_mesh(17, 17, 9, H, jitter=jitter, seed=1, bathymetry=True)
+        s = solver.setup(m, "N")
+        b = solver.rhs_from_field(s, fourier_field(m.xyz, H, 9))
+        for pc in its:
+            _, it, _, ok = solver.solve(s, b, 1e-8, pc, max_iter=20000)
+            its[pc].append(it)
+    for pc in ("vl_as", "vl_sor"):
+        assert its[pc][2] <= 1.3 * its[pc][0], its
+    if jitter > 0:
+        assert its["sa"][2] >= 1.5 * its["sa"][0], its
+        assert its["sa"][2] >= 2 * its["vl_sor"][2], its
