@@ -1,0 +1,187 @@
+/*
+ * vemg.h -- C ABI of the vertical-extrapolation multigrid PCG solver for the
+ * P1 finite-element Poisson equation on thin (small aspect ratio)
+ * tetrahedral domains, after Kramer, Cotter & Pain, "Solving the Poisson
+ * equation on small aspect ratio domains using unstructured meshes".
+ *
+ * Problem (Section 3): -Lap(phi) = f on Omega with homogeneous Neumann
+ * conditions on the floor and the vertical coasts, and on the top surface
+ * either
+ *   VEMG_TOP_PINNED     Neumann plus the point condition phi(x_0) = 0 with
+ *                       x_0 a top node (eq. point condition), or
+ *   VEMG_TOP_DIRICHLET  phi = 0 on the whole top surface (eq. dirichlet).
+ * The library assembles the P1 stiffness matrix A (eq. Ax=b) restricted to
+ * the free nodes and solves A phi = b by preconditioned conjugate gradients.
+ *
+ * Preconditioners (Section 6):
+ *   VEMG_PC_VL_ADDITIVE  E~ Vcyc_S(E~^T r) + Z Vcyc_Abar(Z^T r), eq.
+ *                        ourpreconditioner: vertical extrapolation E~
+ *                        (Section 5.4) to the surface, the Galerkin surface
+ *                        operator S = E~^T A E~ approximated by a smoothed
+ *                        aggregation V-cycle, plus the additive smoother, an
+ *                        SA V-cycle on the Dirichlet-top block A_bar.
+ *   VEMG_PC_VL_SOR       E~ as the first coarsening of a multigrid cycle
+ *                        with one forward / one backward SOR sweep on A.
+ *   VEMG_PC_JACOBI, VEMG_PC_NONE  baselines.
+ *
+ * Conventions
+ *   - Every call returns a vemg_status: 0 success, < 0 error, > 0 warning.
+ *   - Vectors passed to solve/matvec are device pointers in the caller's
+ *     natural node order, length n_nodes, FP64.  Entries of b at fixed nodes
+ *     are ignored; x is returned as 0 there.
+ *   - The library copies the mesh during setup; the caller may free it.
+ *     It owns every device buffer it allocates; the caller owns b and x.
+ *   - All device work is ordered on the stream given to vemg_create (the
+ *     null stream if NULL); calls return after that work has finished.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef VEMG_H
+#define VEMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vemg_solver_s *vemg_solver;
+
+typedef enum {
+  VEMG_OK = 0,
+  VEMG_WARN_MAXITER = 1,      /* max_iter reached; x holds the last iterate */
+  VEMG_WARN_FLOOR = 2,        /* true residual stalled above rtol (rounding floor) */
+  VEMG_ERR_INVALID_ARG = -1,  /* null pointer, bad size or option */
+  VEMG_ERR_MESH = -2,         /* inverted tetrahedron, node out of range, no top surface */
+  VEMG_ERR_PROJECTION = -3,   /* a node does not project onto the top surface */
+  VEMG_ERR_OOM = -4,          /* device or host allocation failed */
+  VEMG_ERR_DEVICE = -5,       /* HIP runtime error */
+  VEMG_ERR_BREAKDOWN = -6,    /* p.Ap <= 0 or not finite (e.g. NaN in b) */
+  VEMG_ERR_STATE = -7         /* call out of order (e.g. solve before setup) */
+} vemg_status;
+
+typedef enum { VEMG_TOP_PINNED = 0, VEMG_TOP_DIRICHLET = 1 } vemg_top_bc;
+
+typedef enum {
+  VEMG_PC_VL_ADDITIVE = 0,
+  VEMG_PC_VL_SOR = 1,
+  VEMG_PC_JACOBI = 2,
+  VEMG_PC_NONE = 3
+} vemg_pc;
+
+typedef struct {
+  int top_bc;          /* vemg_top_bc */
+  int64_t pin_node;    /* pinned top node (natural index); -1: top node closest to the origin */
+  int pc;              /* vemg_pc */
+  double theta;        /* strength threshold, 0.01 (Section 6) */
+  double prolong_omega;/* prolongator smoothing, 2/3 (Section 6) */
+  int max_levels;      /* per hierarchy, 10 */
+  int64_t coarse_max;  /* unknowns on the coarsest level, 256 */
+  int poll_every;      /* PCG iterations per host poll of the convergence flag, 8 */
+  int max_restarts;    /* restarts from the true residual, 5 */
+  int use_graphs;      /* capture one PCG iteration in a hipGraph, 1 */
+} vemg_options;
+
+typedef struct {
+  int64_t n_nodes;     /* mesh nodes */
+  int64_t n;           /* free unknowns */
+  int64_t n_top;       /* free top unknowns m' (0 with a Dirichlet top) */
+  int64_t pin_node;    /* pinned node, -1 with a Dirichlet top */
+  int64_t nnz_offdiag; /* stored off-diagonals of A */
+  int s_levels, abar_levels;
+  int64_t s_rows[16], abar_rows[16];     /* unknowns per level */
+  int64_t s_nnz[16], abar_nnz[16];       /* stored entries per level (off-diagonal) */
+  int64_t p_nnz_s[16], p_nnz_abar[16];   /* prolongator entries per level */
+  int64_t e_nnz;       /* entries of E~ */
+  int fine_colours_top, fine_colours_bar;
+  size_t device_bytes; /* device memory held by the handle */
+} vemg_info;
+
+/* Fills o with the paper's parameters and the defaults above. */
+void vemg_default_options(vemg_options *o);
+
+/* Creates a handle on `device` (HIP ordinal; -1 = host-only setup, for
+ * inspecting the setup without a GPU) using `hip_stream` (a hipStream_t, may
+ * be NULL).  *out is NULL on error. */
+vemg_status vemg_create(const vemg_options *o, int device, void *hip_stream, vemg_solver *out);
+
+/* Setup (Sections 3, 5.4, 6): assembly of A on the free nodes, node order
+ * (top block first, eq. phi_decomposition), colouring, E~, both SA
+ * hierarchies, upload to HBM.  xyz: host [n_nodes][3]; tets: host
+ * [n_tets][4], 0-based, positively oriented; top_mask: host [n_nodes],
+ * nonzero for nodes on the top surface.  Errors: VEMG_ERR_MESH (first bad
+ * tetrahedron in vemg_last_error), VEMG_ERR_PROJECTION, VEMG_ERR_INVALID_ARG. */
+vemg_status vemg_setup(vemg_solver s, int64_t n_nodes, const double *xyz, int64_t n_tets,
+                       const int64_t *tets, const uint8_t *top_mask);
+
+/* Right-hand side of eq. Ax=b from nodal source values: b = M f with the
+ * consistent P1 mass matrix; with the pinned top, b is first made
+ * orthogonal to constants (the Neumann problem needs int f = 0).  Host
+ * arrays, natural order, length n_nodes; fixed nodes get 0. */
+vemg_status vemg_rhs(vemg_solver s, const double *f_host, double *b_host);
+
+/* y = A x on the free nodes (difference form), device pointers, natural
+ * order; y is 0 at fixed nodes. */
+vemg_status vemg_matvec(vemg_solver s, const double *x_dev, double *y_dev);
+
+/* Solves A x = b for nrhs right-hand sides stored one after another
+ * ([nrhs][n_nodes], device).  Stops when ||b - A x||_2 <= rtol ||b||_2 on
+ * the true residual or after max_iter iterations (products with A).
+ * iters and relres (host, length nrhs, may be NULL) receive the iteration
+ * count and the final true relative residual of each right-hand side.
+ * Returns VEMG_WARN_MAXITER / VEMG_WARN_FLOOR with the last iterate when
+ * rtol was not reached, VEMG_ERR_BREAKDOWN on p.Ap <= 0 or NaN. */
+vemg_status vemg_solve(vemg_solver s, int nrhs, const double *b_dev, double *x_dev, double rtol,
+                       int max_iter, int *iters, double *relres);
+
+/* Operators of the hot path, for testing one step at a time.  Vectors are
+ * device FP64 in the library's storage order (see vemg_export "perm"):
+ *   VEMG_OP_A          out[n]  = A in[n]           (difference form)
+ *   VEMG_OP_PRECOND    out[n]  = M^{-1} in[n]      (the handle's preconditioner)
+ *   VEMG_OP_ET         out[m'] = E~^T in[n]
+ *   VEMG_OP_E          out[n]  = E~ in[m']
+ *   VEMG_OP_VCYCLE_S   out[m'] = Vcyc_S(in[m'])    (zero initial guess)
+ *   VEMG_OP_VCYCLE_ABAR out[n-m'] = Vcyc_Abar(in[n-m'])
+ *   VEMG_OP_GS_FWD     out[n]  = one forward multicolour SOR sweep on A x = in, x0 = 0 */
+typedef enum {
+  VEMG_OP_A = 0,
+  VEMG_OP_PRECOND = 1,
+  VEMG_OP_ET = 2,
+  VEMG_OP_E = 3,
+  VEMG_OP_VCYCLE_S = 4,
+  VEMG_OP_VCYCLE_ABAR = 5,
+  VEMG_OP_GS_FWD = 6
+} vemg_op;
+vemg_status vemg_apply(vemg_solver s, int op, const double *in_dev, double *out_dev);
+
+/* Benchmark support: average device time in milliseconds of one
+ * application of VEMG_OP_A (one SpMV launch) or VEMG_OP_GS_FWD (one forward
+ * multicolour sweep over all rows, one launch per colour), measured with HIP
+ * events on the handle's own stream around `reps` back-to-back applications
+ * on internal buffers, after one untimed application.  *launches receives
+ * the number of kernel launches per application (may be NULL). */
+vemg_status vemg_time_op(vemg_solver s, int op, int reps, double *avg_ms, int *launches);
+
+vemg_status vemg_get_info(vemg_solver s, vemg_info *info);
+
+/* Copies a setup array to host memory for inspection (bit-exact tests).
+ * name: "perm" (int64 [n], storage -> natural), "colour" (int32 [n]),
+ * "Aoff.ptr" (int64), "Aoff.idx" (int32), "Aoff.val", "d", "diag" (double),
+ * "E.ptr", "E.idx", "E.val", "S_perm" (int64),
+ * "<h>.<level>.<what>" with h in {S, Abar} and what in {A.ptr, A.idx, A.val,
+ * P.ptr, P.idx, P.val, colour, node, agg, Cinv}.  With buf == NULL only
+ * *bytes is set; otherwise *bytes must hold the buffer size. */
+vemg_status vemg_export(vemg_solver s, const char *name, void *buf, size_t *bytes);
+
+vemg_status vemg_destroy(vemg_solver s);
+
+const char *vemg_status_string(vemg_status st);
+
+/* Message of the last error on this handle ("" if none). */
+const char *vemg_last_error(vemg_solver s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VEMG_H */

@@ -228,7 +228,15 @@ def diagonal_of(Aoff, d):
 
 
 def full_matrix(Aoff, d):
-    """Standard CSR form of A_UU (for direct solves and dense checks)."""
-    A = (Aoff + sp.diags(diagonal_of(Aoff, d))).tocsr()
-    A.sort_indices()
+    """Standard CSR form of A_UU: the off-diagonal pattern (numerical zeros
+    kept) plus the diagonal a_ii = d_i - sum_j a_ij."""
+    Aoff = Aoff.tocsr()
+    n = Aoff.shape[0]
+    rows = np.concatenate([np.repeat(np.arange(n), np.diff(Aoff.indptr)), np.arange(n)])
+    cols = np.concatenate([Aoff.indices, np.arange(n)])
+    vals = np.concatenate([Aoff.data, diagonal_of(Aoff, d)])
+    order = np.lexsort((cols, rows))
+    indptr = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=n))])
+    A = sp.csr_matrix((vals[order], cols[order], indptr), shape=(n, n))
+    A.has_sorted_indices = True
     return A

@@ -1,0 +1,201 @@
+"""ctypes binding of libvemg.so (argument marshalling only).
+
+Device vectors are torch.float64 CUDA tensors (HIP on ROCm) passed by
+data_ptr(); the handle runs on the caller's current torch stream.  Nothing
+here computes: a missing library raises at once.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+STATUS = {0: "ok", 1: "max_iter", 2: "floor", -1: "invalid_arg", -2: "mesh", -3: "projection",
+          -4: "oom", -5: "device", -6: "breakdown", -7: "state"}
+OP_A, OP_PRECOND, OP_ET, OP_E, OP_VCYCLE_S, OP_VCYCLE_ABAR, OP_GS_FWD = range(7)
+_PC = {"vl_as": 0, "vl_sor": 1, "jacobi": 2, "none": 3}
+_TOP = {"pinned": 0, "N": 0, "dirichlet": 1, "D": 1}
+
+
+class VemgError(RuntimeError):
+    def __init__(self, status, msg=""):
+        super().__init__(f"vemg status {status} ({STATUS.get(status, '?')}): {msg}")
+        self.status = status
+
+
+class Options(C.Structure):
+    _fields_ = [("top_bc", C.c_int), ("pin_node", C.c_int64), ("pc", C.c_int),
+                ("theta", C.c_double), ("prolong_omega", C.c_double), ("max_levels", C.c_int),
+                ("coarse_max", C.c_int64), ("poll_every", C.c_int), ("max_restarts", C.c_int),
+                ("use_graphs", C.c_int)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n", C.c_int64), ("n_top", C.c_int64), ("pin_node", C.c_int64),
+                ("nnz_offdiag", C.c_int64), ("s_levels", C.c_int), ("abar_levels", C.c_int),
+                ("s_rows", C.c_int64 * 16), ("abar_rows", C.c_int64 * 16),
+                ("s_nnz", C.c_int64 * 16), ("abar_nnz", C.c_int64 * 16),
+                ("p_nnz_s", C.c_int64 * 16), ("p_nnz_abar", C.c_int64 * 16),
+                ("e_nnz", C.c_int64), ("fine_colours_top", C.c_int), ("fine_colours_bar", C.c_int),
+                ("device_bytes", C.c_size_t)]
+
+
+def library_path():
+    return os.path.join(_HERE, "libvemg.so")
+
+
+def load_library():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_0912_1976_amd/build.py")
+    lib = C.CDLL(path)
+    P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int, C.c_double
+    lib.vemg_default_options.argtypes = [C.POINTER(Options)]
+    lib.vemg_default_options.restype = None
+    lib.vemg_create.argtypes = [C.POINTER(Options), I32, P, C.POINTER(P)]
+    lib.vemg_setup.argtypes = [P, I64, P, I64, P, P]
+    lib.vemg_rhs.argtypes = [P, P, P]
+    lib.vemg_matvec.argtypes = [P, P, P]
+    lib.vemg_solve.argtypes = [P, I32, P, P, D, I32, P, P]
+    lib.vemg_apply.argtypes = [P, I32, P, P]
+    lib.vemg_get_info.argtypes = [P, C.POINTER(Info)]
+    lib.vemg_time_op.argtypes = [P, I32, I32, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    lib.vemg_export.argtypes = [P, C.c_char_p, P, C.POINTER(C.c_size_t)]
+    lib.vemg_destroy.argtypes = [P]
+    lib.vemg_status_string.argtypes = [I32]
+    lib.vemg_status_string.restype = C.c_char_p
+    lib.vemg_last_error.argtypes = [P]
+    lib.vemg_last_error.restype = C.c_char_p
+    for f in ("vemg_create", "vemg_setup", "vemg_rhs", "vemg_matvec", "vemg_solve", "vemg_apply",
+              "vemg_get_info", "vemg_export", "vemg_destroy", "vemg_time_op"):
+        getattr(lib, f).restype = I32
+    _LIB = lib
+    return lib
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One mesh, set up once, solved many times.
+
+    device: HIP ordinal, or -1 for a host-only setup (inspection, no solves).
+    """
+
+    def __init__(self, xyz, tets, top, *, top_bc="pinned", pc="vl_as", device=0, pin_node=-1,
+                 use_graphs=True, poll_every=8, coarse_max=256, max_levels=10, max_restarts=5):
+        self._lib = load_library()
+        opt = Options()
+        self._lib.vemg_default_options(C.byref(opt))
+        opt.top_bc = _TOP[top_bc]
+        opt.pc = _PC[pc]
+        opt.pin_node = pin_node
+        opt.use_graphs = int(bool(use_graphs))
+        opt.poll_every = poll_every
+        opt.coarse_max = coarse_max
+        opt.max_levels = max_levels
+        opt.max_restarts = max_restarts
+        self.device = device
+        stream = None
+        if device >= 0:
+            import torch
+            self._torch = torch
+            self.dev = torch.device("cuda", device)
+            stream = C.c_void_p(torch.cuda.current_stream(self.dev).cuda_stream)
+        h = C.c_void_p()
+        self._check(self._lib.vemg_create(C.byref(opt), device, stream, C.byref(h)), None)
+        self._h = h
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tets = np.ascontiguousarray(tets, dtype=np.int64)
+        top = np.ascontiguousarray(top, dtype=np.uint8)
+        self.n_nodes = xyz.shape[0]
+        self._check(self._lib.vemg_setup(h, self.n_nodes, xyz.ctypes.data, tets.shape[0], tets.ctypes.data,
+                                         top.ctypes.data), h)
+
+    def _check(self, st, h):
+        if st < 0:
+            msg = self._lib.vemg_last_error(h).decode() if h else ""
+            raise VemgError(st, msg)
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.vemg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- info
+    def info(self):
+        inf = Info()
+        self._check(self._lib.vemg_get_info(self._h, C.byref(inf)), self._h)
+        out = {k: getattr(inf, k) for k, _ in Info._fields_}
+        for k in ("s_rows", "abar_rows", "s_nnz", "abar_nnz", "p_nnz_s", "p_nnz_abar"):
+            out[k] = list(out[k])
+        out["s_rows"] = out["s_rows"][: inf.s_levels]
+        out["abar_rows"] = out["abar_rows"][: inf.abar_levels]
+        for k, nl in (("s_nnz", inf.s_levels), ("p_nnz_s", inf.s_levels), ("abar_nnz", inf.abar_levels),
+                      ("p_nnz_abar", inf.abar_levels)):
+            out[k] = out[k][:nl]
+        return out
+
+    def export(self, name, dtype):
+        nb = C.c_size_t(0)
+        self._check(self._lib.vemg_export(self._h, name.encode(), None, C.byref(nb)), self._h)
+        arr = np.empty(nb.value // np.dtype(dtype).itemsize, dtype=dtype)
+        self._check(self._lib.vemg_export(self._h, name.encode(), arr.ctypes.data, C.byref(nb)), self._h)
+        return arr
+
+    # ---------------------------------------------------------------- compute
+    def rhs(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        b = np.empty_like(f)
+        self._check(self._lib.vemg_rhs(self._h, f.ctypes.data, b.ctypes.data), self._h)
+        return b
+
+    def _dev(self, a):
+        t = self._torch
+        if not isinstance(a, t.Tensor):
+            a = t.as_tensor(np.asarray(a, dtype=np.float64))
+        return a.to(device=self.dev, dtype=t.float64).contiguous()
+
+    def matvec(self, x):
+        x = self._dev(x)
+        y = self._torch.empty_like(x)
+        self._check(self._lib.vemg_matvec(self._h, _ptr(x), _ptr(y)), self._h)
+        return y
+
+    def solve(self, b, rtol=1e-8, max_iter=1000):
+        """b: [n_nodes] or [nrhs, n_nodes].  Returns (x, iters, relres, status)."""
+        b = self._dev(b)
+        nrhs = 1 if b.dim() == 1 else b.shape[0]
+        x = self._torch.empty_like(b)
+        its = (C.c_int * nrhs)()
+        rel = (C.c_double * nrhs)()
+        st = self._check(self._lib.vemg_solve(self._h, nrhs, _ptr(b), _ptr(x), rtol, max_iter, its, rel), self._h)
+        return x, list(its), list(rel), st
+
+    def time_op(self, op, reps=20):
+        """(average ms per application, kernel launches per application)."""
+        ms = C.c_double(0.0)
+        nl = C.c_int(0)
+        self._check(self._lib.vemg_time_op(self._h, op, reps, C.byref(ms), C.byref(nl)), self._h)
+        return ms.value, nl.value
+
+    def apply(self, op, v, out_len):
+        v = self._dev(v)
+        out = self._torch.empty(out_len, dtype=self._torch.float64, device=self.dev)
+        self._check(self._lib.vemg_apply(self._h, op, _ptr(v), _ptr(out)), self._h)
+        return out

@@ -1,0 +1,767 @@
+// Host setup (see setup.hpp).  Built with -ffp-contract=off: edge values,
+// row sums, the locality key and the barycentric weights are computed in a
+// fixed operation order, so the integer structure derived from them (node
+// order, colours, extrapolation pattern, aggregates) is reproducible.
+#include "setup.hpp"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <sstream>
+#include <tuple>
+
+namespace vemg {
+
+namespace {
+
+constexpr int kPairs[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+constexpr double kTolInside = 1e-12;
+constexpr double kTieRtol = 1e-10;
+constexpr double kGsDrop = 1e-10;
+
+struct V3 {
+  double x, y, z;
+};
+inline V3 sub(const V3 &a, const V3 &b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 cross(const V3 &a, const V3 &b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+inline double dot(const V3 &a, const V3 &b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw SetupError(code, msg); }
+
+// Scaled gradients of the P1 basis on one tetrahedron: grad N_a = c_a / det.
+void tet_gradients(const double *xyz, const int64_t *t, V3 c[4], double &det) {
+  V3 X[4];
+  for (int a = 0; a < 4; ++a) X[a] = {xyz[3 * t[a]], xyz[3 * t[a] + 1], xyz[3 * t[a] + 2]};
+  V3 e1 = sub(X[1], X[0]), e2 = sub(X[2], X[0]), e3 = sub(X[3], X[0]);
+  c[1] = cross(e2, e3);
+  c[2] = cross(e3, e1);
+  c[3] = cross(e1, e2);
+  c[0] = {-((c[1].x + c[2].x) + c[3].x), -((c[1].y + c[2].y) + c[3].y), -((c[1].z + c[2].z) + c[3].z)};
+  det = dot(e1, c[1]);
+}
+
+// ---------------------------------------------------------------- assembly
+// Off-diagonal stiffness on the edge graph, natural numbering.  Each edge
+// value is a left-to-right sum over its elements in ascending element order.
+Csr assemble_offdiag(int64_t n, const double *xyz, int64_t T, const int64_t *tets) {
+  std::vector<std::vector<int32_t>> nb(n);
+  for (int64_t e = 0; e < T; ++e)
+    for (auto &p : kPairs) {
+      int64_t i = tets[4 * e + p[0]], j = tets[4 * e + p[1]];
+      nb[i].push_back((int32_t)j);
+      nb[j].push_back((int32_t)i);
+    }
+  Csr A;
+  A.nrows = A.ncols = n;
+  A.ptr.assign(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    auto &v = nb[i];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    A.ptr[i + 1] = A.ptr[i] + (int64_t)v.size();
+  }
+  A.idx.resize(A.ptr[n]);
+  for (int64_t i = 0; i < n; ++i) std::copy(nb[i].begin(), nb[i].end(), A.idx.begin() + A.ptr[i]);
+  nb.clear();
+  nb.shrink_to_fit();
+  A.val.assign(A.idx.size(), 0.0);
+  auto find = [&](int64_t i, int32_t j) {
+    auto b = A.idx.begin() + A.ptr[i], e = A.idx.begin() + A.ptr[i + 1];
+    return (int64_t)(std::lower_bound(b, e, j) - A.idx.begin());
+  };
+  for (int64_t e = 0; e < T; ++e) {
+    V3 c[4];
+    double det;
+    tet_gradients(xyz, tets + 4 * e, c, det);
+    if (!(det > 0.0)) {
+      std::ostringstream os;
+      os << "tetrahedron " << e << " is not positively oriented (6 vol = " << det << ")";
+      fail(-2, os.str());
+    }
+    for (auto &p : kPairs) {
+      const V3 &ca = c[p[0]], &cb = c[p[1]];
+      double k = ((ca.x * cb.x + ca.y * cb.y) + ca.z * cb.z) / (6.0 * det);
+      int64_t i = tets[4 * e + p[0]], j = tets[4 * e + p[1]];
+      int64_t lo = std::min(i, j), hi = std::max(i, j);
+      A.val[find(lo, (int32_t)hi)] += k;
+    }
+  }
+  // mirror the upper triangle (lo < hi) to the lower one
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      int64_t j = A.idx[k];
+      if (j < i) A.val[k] = A.val[find(j, (int32_t)i)];
+    }
+  return A;
+}
+
+// ---------------------------------------------------------------- colouring
+std::vector<int32_t> greedy_colouring(const Csr &A, const std::vector<int64_t> &order) {
+  std::vector<int32_t> col(A.nrows, -1);
+  std::vector<int64_t> seen;  // seen[c] == i marks colour c as used around node i
+  for (int64_t i : order) {
+    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      int64_t j = A.idx[k];
+      if (j != i && col[j] >= 0) {
+        if ((int64_t)seen.size() <= col[j]) seen.resize(col[j] + 1, -1);
+        seen[col[j]] = i;
+      }
+    }
+    int32_t c = 0;
+    while (c < (int32_t)seen.size() && seen[c] == i) ++c;
+    col[i] = c;
+  }
+  return col;
+}
+
+std::vector<int64_t> colour_ranges(const std::vector<int32_t> &col, int64_t a, int64_t b) {
+  int32_t nc = 0;
+  for (int64_t i = a; i < b; ++i) nc = std::max(nc, col[i] + 1);
+  std::vector<int64_t> st(nc + 1, b);
+  st[0] = a;
+  for (int32_t c = 0; c < nc; ++c) {
+    int64_t i = st[c];
+    while (i < b && col[i] == c) ++i;
+    st[c + 1] = i;
+  }
+  return st;
+}
+
+// ---------------------------------------------------------------- SA pieces
+// Strong node graph: ||A_IJ||_F > theta sqrt(||A_II||_F ||A_JJ||_F), I != J.
+Csr node_strength(const Csr &A, const std::vector<int32_t> &node, int64_t nnodes, double theta) {
+  std::vector<std::vector<std::pair<int32_t, double>>> acc(nnodes);
+  for (int64_t r = 0; r < A.nrows; ++r)
+    for (int64_t k = A.ptr[r]; k < A.ptr[r + 1]; ++k)
+      acc[node[r]].emplace_back(node[A.idx[k]], A.val[k] * A.val[k]);
+  Csr F;
+  F.nrows = F.ncols = nnodes;
+  F.ptr.assign(nnodes + 1, 0);
+  std::vector<double> fd(nnodes, 0.0);
+  std::vector<std::vector<std::pair<int32_t, double>>> rows(nnodes);
+  for (int64_t I = 0; I < nnodes; ++I) {
+    auto &v = acc[I];
+    std::stable_sort(v.begin(), v.end(), [](auto &x, auto &y) { return x.first < y.first; });
+    for (size_t k = 0; k < v.size();) {
+      size_t l = k;
+      double s = 0.0;
+      while (l < v.size() && v[l].first == v[k].first) s += v[l++].second;
+      double f = std::sqrt(s);
+      if (v[k].first == I) fd[I] = f;
+      else rows[I].emplace_back(v[k].first, f);
+      k = l;
+    }
+    v.clear();
+    v.shrink_to_fit();
+  }
+  for (int64_t I = 0; I < nnodes; ++I) {
+    for (auto &e : rows[I])
+      if (e.second > theta * std::sqrt(fd[I] * fd[e.first])) {
+        F.idx.push_back(e.first);
+        F.val.push_back(e.second);
+      }
+    F.ptr[I + 1] = (int64_t)F.idx.size();
+  }
+  return F;
+}
+
+// Three aggregation passes over the node order (see the oracle's reading).
+std::vector<int32_t> aggregate_graph(const Csr &G) {
+  int64_t n = G.nrows;
+  std::vector<int32_t> agg(n, -1);
+  int32_t na = 0;
+  for (int64_t i = 0; i < n; ++i) {  // P1
+    if (agg[i] >= 0) continue;
+    bool free = true;
+    for (int64_t k = G.ptr[i]; k < G.ptr[i + 1]; ++k)
+      if (agg[G.idx[k]] >= 0) {
+        free = false;
+        break;
+      }
+    if (!free) continue;
+    agg[i] = na;
+    for (int64_t k = G.ptr[i]; k < G.ptr[i + 1]; ++k) agg[G.idx[k]] = na;
+    ++na;
+  }
+  std::vector<int32_t> p1 = agg;
+  for (int64_t i = 0; i < n; ++i) {  // P2
+    if (agg[i] >= 0) continue;
+    double wmax = -1.0;
+    for (int64_t k = G.ptr[i]; k < G.ptr[i + 1]; ++k)
+      if (p1[G.idx[k]] >= 0) wmax = std::max(wmax, G.val[k]);
+    if (wmax < 0.0) continue;
+    int32_t best = -1;
+    for (int64_t k = G.ptr[i]; k < G.ptr[i + 1]; ++k) {
+      int32_t j = G.idx[k];
+      if (p1[j] >= 0 && G.val[k] >= wmax * (1.0 - kTieRtol) && (best < 0 || j < best)) best = j;
+    }
+    agg[i] = p1[best];
+  }
+  for (int64_t i = 0; i < n; ++i) {  // P3
+    if (agg[i] >= 0) continue;
+    agg[i] = na;
+    for (int64_t k = G.ptr[i]; k < G.ptr[i + 1]; ++k)
+      if (agg[G.idx[k]] < 0) agg[G.idx[k]] = na;
+    ++na;
+  }
+  return agg;
+}
+
+// Tentative prolongator from the near-kernel vectors: modified Gram-Schmidt
+// on each aggregate.  Fills P0 (CSR n x nc), Bc (nc x k), cnode.
+void tentative(const Level &L, const std::vector<int32_t> &agg, Csr &P0, std::vector<double> &Bc,
+               std::vector<int32_t> &cnode) {
+  int64_t n = L.n(), k = L.k;
+  int32_t na = 0;
+  for (auto a : agg) na = std::max(na, a + 1);
+  std::vector<std::vector<int64_t>> dofs(na);
+  for (int64_t r = 0; r < n; ++r) dofs[agg[L.node[r]]].push_back(r);
+  std::vector<std::vector<std::pair<int32_t, double>>> rows(n);
+  int32_t nc = 0;
+  Bc.clear();
+  cnode.clear();
+  std::vector<std::vector<double>> Q;
+  for (int32_t a = 0; a < na; ++a) {
+    auto &idx = dofs[a];
+    size_t m = idx.size();
+    Q.clear();
+    for (int64_t c = 0; c < k; ++c) {
+      std::vector<double> v(m);
+      for (size_t t = 0; t < m; ++t) v[t] = L.B[idx[t] * k + c];
+      double n0 = 0.0;
+      for (double x : v) n0 += x * x;
+      n0 = std::sqrt(n0);
+      for (auto &q : Q) {
+        double s = 0.0;
+        for (size_t t = 0; t < m; ++t) s += q[t] * v[t];
+        for (size_t t = 0; t < m; ++t) v[t] = v[t] - s * q[t];
+      }
+      double nv = 0.0;
+      for (double x : v) nv += x * x;
+      nv = std::sqrt(nv);
+      if (n0 > 0.0 && nv > kGsDrop * n0) {
+        for (auto &x : v) x /= nv;
+        Q.push_back(std::move(v));
+      }
+    }
+    for (auto &q : Q) {
+      for (size_t t = 0; t < m; ++t) rows[idx[t]].emplace_back(nc, q[t]);
+      for (int64_t c = 0; c < k; ++c) {
+        double s = 0.0;
+        for (size_t t = 0; t < m; ++t) s += q[t] * L.B[idx[t] * k + c];
+        Bc.push_back(s);
+      }
+      cnode.push_back(a);
+      ++nc;
+    }
+  }
+  P0.nrows = n;
+  P0.ncols = nc;
+  P0.ptr.assign(n + 1, 0);
+  P0.idx.clear();
+  P0.val.clear();
+  for (int64_t r = 0; r < n; ++r) {
+    for (auto &e : rows[r]) {
+      P0.idx.push_back(e.first);
+      P0.val.push_back(e.second);
+    }
+    P0.ptr[r + 1] = (int64_t)P0.idx.size();
+  }
+}
+
+// S = I - omega D^{-1} A on the pattern of A plus the diagonal.
+Csr jacobi_smoother(const Csr &A, double omega) {
+  auto dg = diagonal(A);
+  Csr S;
+  S.nrows = S.ncols = A.nrows;
+  S.ptr.assign(A.nrows + 1, 0);
+  for (int64_t i = 0; i < A.nrows; ++i) {
+    bool has_diag = false;
+    double inv = 1.0 / dg[i];
+    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      int32_t j = A.idx[k];
+      if (!has_diag && j > i) {
+        S.idx.push_back((int32_t)i);
+        S.val.push_back(1.0);
+        has_diag = true;
+      }
+      double v = omega * (inv * A.val[k]);
+      if (j == i) {
+        S.idx.push_back(j);
+        S.val.push_back(1.0 - v);
+        has_diag = true;
+      } else {
+        S.idx.push_back(j);
+        S.val.push_back(-v);
+      }
+    }
+    if (!has_diag) {
+      S.idx.push_back((int32_t)i);
+      S.val.push_back(1.0);
+    }
+    S.ptr[i + 1] = (int64_t)S.idx.size();
+  }
+  return S;
+}
+
+std::vector<int64_t> stable_colour_sort(const std::vector<int32_t> &col) {
+  std::vector<int64_t> p(col.size());
+  std::iota(p.begin(), p.end(), 0);
+  std::stable_sort(p.begin(), p.end(), [&](int64_t a, int64_t b) { return col[a] < col[b]; });
+  return p;
+}
+
+// Dense Cholesky inverse of a small SPD matrix (row-major, in place).
+void spd_inverse(std::vector<double> &M, int64_t n) {
+  std::vector<double> L(n * n, 0.0);
+  for (int64_t j = 0; j < n; ++j) {
+    double s = M[j * n + j];
+    for (int64_t k = 0; k < j; ++k) s -= L[j * n + k] * L[j * n + k];
+    if (!(s > 0.0)) fail(-2, "coarsest multigrid level is not positive definite");
+    double ljj = std::sqrt(s);
+    L[j * n + j] = ljj;
+    for (int64_t i = j + 1; i < n; ++i) {
+      double t = M[i * n + j];
+      for (int64_t k = 0; k < j; ++k) t -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = t / ljj;
+    }
+  }
+  std::vector<double> inv(n * n, 0.0), y(n);
+  for (int64_t c = 0; c < n; ++c) {
+    for (int64_t i = 0; i < n; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      for (int64_t k = 0; k < i; ++k) t -= L[i * n + k] * y[k];
+      y[i] = t / L[i * n + i];
+    }
+    for (int64_t i = n - 1; i >= 0; --i) {
+      double t = y[i];
+      for (int64_t k = i + 1; k < n; ++k) t -= L[k * n + i] * inv[k * n + c];
+      inv[i * n + c] = t / L[i * n + i];
+    }
+  }
+  M.swap(inv);
+}
+
+void build_hierarchy(std::vector<Level> &levels, const SetupOptions &opt) {
+  int64_t nnodes = levels[0].n();
+  while (true) {
+    Level &L = levels.back();
+    L.colour_start = colour_ranges(L.colour, 0, L.n());
+    if (L.n() <= opt.coarse_max || (int)levels.size() >= opt.max_levels) break;
+    Csr G = node_strength(L.A, L.node, nnodes, opt.theta);
+    std::vector<int32_t> agg = aggregate_graph(G);
+    Csr P0;
+    std::vector<double> Bc;
+    std::vector<int32_t> cnode;
+    tentative(L, agg, P0, Bc, cnode);
+    int64_t nc = P0.ncols;
+    if ((double)nc > 0.8 * (double)L.n()) break;
+    Csr P = spgemm(jacobi_smoother(L.A, opt.prolong_omega), P0);
+    Csr Pt = transpose(P);
+    Csr Ac = spgemm(Pt, spgemm(L.A, P));
+    std::vector<int64_t> ident(nc);
+    std::iota(ident.begin(), ident.end(), 0);
+    std::vector<int32_t> ccol = greedy_colouring(Ac, ident);
+    std::vector<int64_t> cperm = stable_colour_sort(ccol);
+    std::vector<int64_t> cinv(nc);
+    for (int64_t i = 0; i < nc; ++i) cinv[cperm[i]] = i;
+    L.P = permute_cols(P, cinv);
+    L.agg = agg;
+    nnodes = 0;
+    for (auto a : agg) nnodes = std::max<int64_t>(nnodes, a + 1);
+    Level C;
+    C.A = permute_sym(Ac, cperm);
+    C.colour.resize(nc);
+    C.node.resize(nc);
+    C.k = L.k;
+    C.B.resize(nc * L.k);
+    for (int64_t i = 0; i < nc; ++i) {
+      C.colour[i] = ccol[cperm[i]];
+      C.node[i] = cnode[cperm[i]];
+      for (int c = 0; c < L.k; ++c) C.B[i * L.k + c] = Bc[cperm[i] * L.k + c];
+    }
+    levels.push_back(std::move(C));
+  }
+  Level &last = levels.back();
+  int64_t m = last.n();
+  last.Cinv.assign(m * m, 0.0);
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t k = last.A.ptr[i]; k < last.A.ptr[i + 1]; ++k) last.Cinv[i * m + last.A.idx[k]] = last.A.val[k];
+  spd_inverse(last.Cinv, m);
+}
+
+// ---------------------------------------------------------------- E~
+struct Locator {
+  const double *xyz;
+  const std::vector<std::array<int64_t, 3>> &tri;
+  int64_t ng;
+  double gx0, gy0, sx, sy;
+  std::vector<int64_t> cstart;
+  std::vector<int32_t> ctri;
+
+  Locator(const double *xyz_, const std::vector<std::array<int64_t, 3>> &tri_, double px0, double py0,
+          double px1, double py1)
+      : xyz(xyz_), tri(tri_) {
+    int64_t nt = (int64_t)tri.size();
+    ng = std::max<int64_t>(1, (int64_t)std::sqrt((double)nt / 2.0));
+    double x0 = px0, y0 = py0, x1 = px1, y1 = py1;
+    for (auto &t : tri)
+      for (int a = 0; a < 3; ++a) {
+        x0 = std::min(x0, xyz[3 * t[a]]);
+        x1 = std::max(x1, xyz[3 * t[a]]);
+        y0 = std::min(y0, xyz[3 * t[a] + 1]);
+        y1 = std::max(y1, xyz[3 * t[a] + 1]);
+      }
+    gx0 = x0;
+    gy0 = y0;
+    sx = std::max(x1 - x0, 1e-300);
+    sy = std::max(y1 - y0, 1e-300);
+    std::vector<std::vector<int32_t>> cells(ng * ng);
+    for (int64_t ti = 0; ti < nt; ++ti) {
+      double lx = 1e300, hx = -1e300, ly = 1e300, hy = -1e300;
+      for (int a = 0; a < 3; ++a) {
+        lx = std::min(lx, xyz[3 * tri[ti][a]]);
+        hx = std::max(hx, xyz[3 * tri[ti][a]]);
+        ly = std::min(ly, xyz[3 * tri[ti][a] + 1]);
+        hy = std::max(hy, xyz[3 * tri[ti][a] + 1]);
+      }
+      int64_t cx0 = cell(lx - 1e-9 * sx, gx0, sx), cx1 = cell(hx + 1e-9 * sx, gx0, sx);
+      int64_t cy0 = cell(ly - 1e-9 * sy, gy0, sy), cy1 = cell(hy + 1e-9 * sy, gy0, sy);
+      for (int64_t cy = cy0; cy <= cy1; ++cy)
+        for (int64_t cx = cx0; cx <= cx1; ++cx) cells[cy * ng + cx].push_back((int32_t)ti);
+    }
+    cstart.assign(ng * ng + 1, 0);
+    for (int64_t c = 0; c < ng * ng; ++c) cstart[c + 1] = cstart[c] + (int64_t)cells[c].size();
+    ctri.reserve(cstart.back());
+    for (auto &c : cells) ctri.insert(ctri.end(), c.begin(), c.end());
+  }
+  int64_t cell(double v, double g0, double s) const {
+    int64_t c = (int64_t)std::floor((v - g0) / s * (double)ng);
+    return std::min<int64_t>(ng - 1, std::max<int64_t>(0, c));
+  }
+  // smallest triangle containing (x, y); lam gets the barycentric coordinates
+  int64_t locate(double x, double y, double lam[3]) const {
+    int64_t c = cell(y, gy0, sy) * ng + cell(x, gx0, sx);
+    int64_t best = -1;
+    for (int64_t k = cstart[c]; k < cstart[c + 1]; ++k) {
+      int64_t t = ctri[k];
+      if (best >= 0 && t >= best) continue;
+      double x1 = xyz[3 * tri[t][0]], y1 = xyz[3 * tri[t][0] + 1];
+      double x2 = xyz[3 * tri[t][1]], y2 = xyz[3 * tri[t][1] + 1];
+      double x3 = xyz[3 * tri[t][2]], y3 = xyz[3 * tri[t][2] + 1];
+      double det = (y2 - y3) * (x1 - x3) + (x3 - x2) * (y1 - y3);
+      double l1 = ((y2 - y3) * (x - x3) + (x3 - x2) * (y - y3)) / det;
+      double l2 = ((y3 - y1) * (x - x3) + (x1 - x3) * (y - y3)) / det;
+      double l3 = (1.0 - l1) - l2;
+      if (l1 >= -kTolInside && l2 >= -kTolInside && l3 >= -kTolInside) {
+        best = t;
+        lam[0] = l1;
+        lam[1] = l2;
+        lam[2] = l3;
+      }
+    }
+    return best;
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------- driver
+void build_problem(Problem &P, const SetupOptions &opt, int64_t n_nodes, const double *xyz,
+                   int64_t n_tets, const int64_t *tets, const uint8_t *top) {
+  if (n_nodes < 4 || n_tets < 1 || !xyz || !tets || !top) fail(-1, "empty mesh or null pointer");
+  for (int64_t k = 0; k < 4 * n_tets; ++k)
+    if (tets[k] < 0 || tets[k] >= n_nodes) {
+      std::ostringstream os;
+      os << "tetrahedron " << k / 4 << " refers to node " << tets[k] << " outside [0, " << n_nodes << ")";
+      fail(-2, os.str());
+    }
+  P.opt = opt;
+  P.n_nodes = n_nodes;
+  P.xyz.assign(xyz, xyz + 3 * n_nodes);
+  P.tets.assign(tets, tets + 4 * n_tets);
+  P.top.resize(n_nodes);
+  int64_t m_top = 0;
+  for (int64_t i = 0; i < n_nodes; ++i) {
+    P.top[i] = top[i] ? 1 : 0;
+    m_top += P.top[i];
+  }
+  if (m_top < 3) fail(-2, "the top surface needs at least 3 nodes");
+
+  // Dirichlet set
+  std::vector<uint8_t> fixed(n_nodes, 0);
+  if (opt.top_dirichlet) {
+    for (int64_t i = 0; i < n_nodes; ++i) fixed[i] = P.top[i];
+  } else {
+    int64_t pin = opt.pin_node;
+    if (pin < 0) {
+      double best = 0.0;
+      for (int64_t i = 0; i < n_nodes; ++i)
+        if (P.top[i]) {
+          double d2 = (xyz[3 * i] * xyz[3 * i] + xyz[3 * i + 1] * xyz[3 * i + 1]) + xyz[3 * i + 2] * xyz[3 * i + 2];
+          if (pin < 0 || d2 < best) {
+            best = d2;
+            pin = i;
+          }
+        }
+    } else if (pin >= n_nodes || !P.top[pin]) {
+      fail(-1, "pin_node must be a top-surface node");
+    }
+    P.pin = pin;
+    fixed[pin] = 1;
+  }
+
+  // assembly (natural numbering)
+  Csr Afull = assemble_offdiag(n_nodes, xyz, n_tets, tets);
+
+  // free nodes U (ascending natural index), A_UU and the deficit
+  std::vector<int64_t> U;
+  std::vector<int64_t> posU(n_nodes, -1);
+  for (int64_t i = 0; i < n_nodes; ++i)
+    if (!fixed[i]) {
+      posU[i] = (int64_t)U.size();
+      U.push_back(i);
+    }
+  int64_t n = (int64_t)U.size();
+  Csr Auu;
+  Auu.nrows = Auu.ncols = n;
+  Auu.ptr.assign(n + 1, 0);
+  std::vector<double> dnat(n, 0.0);
+  for (int64_t u = 0; u < n; ++u) {
+    int64_t i = U[u];
+    double s = 0.0;
+    for (int64_t k = Afull.ptr[i]; k < Afull.ptr[i + 1]; ++k) {
+      int64_t j = Afull.idx[k];
+      if (fixed[j]) {
+        s += Afull.val[k];
+      } else {
+        Auu.idx.push_back((int32_t)posU[j]);
+        Auu.val.push_back(Afull.val[k]);
+      }
+    }
+    dnat[u] = -s + 0.0;
+    Auu.ptr[u + 1] = (int64_t)Auu.idx.size();
+  }
+  Afull = Csr();
+
+  // locality order (top block first)
+  double xmin = xyz[0], xmax = xyz[0], ymin = xyz[1], ymax = xyz[1];
+  for (int64_t i = 0; i < n_nodes; ++i) {
+    xmin = std::min(xmin, xyz[3 * i]);
+    xmax = std::max(xmax, xyz[3 * i]);
+    ymin = std::min(ymin, xyz[3 * i + 1]);
+    ymax = std::max(ymax, xyz[3 * i + 1]);
+  }
+  int64_t T = std::max<int64_t>(1, (int64_t)std::nearbyint(std::sqrt((double)m_top / 64.0)));
+  int64_t F = 8 * T;
+  struct Key {
+    int64_t block, tile, fine;
+    double negz;
+    int64_t node;
+  };
+  std::vector<Key> keys(n);
+  for (int64_t u = 0; u < n; ++u) {
+    int64_t i = U[u];
+    int64_t fx = std::min<int64_t>(F - 1, (int64_t)std::floor((xyz[3 * i] - xmin) / (xmax - xmin) * (double)F));
+    int64_t fy = std::min<int64_t>(F - 1, (int64_t)std::floor((xyz[3 * i + 1] - ymin) / (ymax - ymin) * (double)F));
+    keys[u] = {P.top[i] ? 0 : 1, (fy / 8) * T + fx / 8, (fy % 8) * 8 + fx % 8, -xyz[3 * i + 2], i};
+  }
+  std::vector<int64_t> loc(n);
+  std::iota(loc.begin(), loc.end(), 0);
+  std::sort(loc.begin(), loc.end(), [&](int64_t a, int64_t b) {
+    const Key &p = keys[a], &q = keys[b];
+    return std::tie(p.block, p.tile, p.fine, p.negz, p.node) < std::tie(q.block, q.tile, q.fine, q.negz, q.node);
+  });
+  std::vector<int32_t> colu = greedy_colouring(Auu, loc);
+  std::vector<int64_t> order = loc;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    return std::make_pair(keys[a].block, colu[a]) < std::make_pair(keys[b].block, colu[b]);
+  });
+  P.n = n;
+  P.perm.resize(n);
+  P.pos.assign(n_nodes, -1);
+  for (int64_t s = 0; s < n; ++s) {
+    P.perm[s] = U[order[s]];
+    P.pos[P.perm[s]] = s;
+  }
+  P.n_top = 0;
+  for (int64_t s = 0; s < n; ++s) P.n_top += P.top[P.perm[s]];
+  P.Aoff = permute_sym(Auu, order);
+  Auu = Csr();
+  P.d.resize(n);
+  P.colour.resize(n);
+  for (int64_t s = 0; s < n; ++s) {
+    P.d[s] = dnat[order[s]] + 0.0;
+    P.colour[s] = colu[order[s]];
+  }
+  P.diag.resize(n);
+  for (int64_t s = 0; s < n; ++s) {
+    double rs = 0.0;
+    for (int64_t k = P.Aoff.ptr[s]; k < P.Aoff.ptr[s + 1]; ++k) rs += P.Aoff.val[k];
+    P.diag[s] = P.d[s] - rs;
+  }
+  P.top_colour_start = colour_ranges(P.colour, 0, P.n_top);
+  P.bar_colour_start = colour_ranges(P.colour, P.n_top, n);
+
+  // standard form A_UU (diagonal inserted in sorted position)
+  Csr A;
+  A.nrows = A.ncols = n;
+  A.ptr.assign(n + 1, 0);
+  A.idx.reserve(P.Aoff.nnz() + n);
+  A.val.reserve(P.Aoff.nnz() + n);
+  for (int64_t s = 0; s < n; ++s) {
+    bool put = false;
+    for (int64_t k = P.Aoff.ptr[s]; k < P.Aoff.ptr[s + 1]; ++k) {
+      if (!put && P.Aoff.idx[k] > s) {
+        A.idx.push_back((int32_t)s);
+        A.val.push_back(P.diag[s]);
+        put = true;
+      }
+      A.idx.push_back(P.Aoff.idx[k]);
+      A.val.push_back(P.Aoff.val[k]);
+    }
+    if (!put) {
+      A.idx.push_back((int32_t)s);
+      A.val.push_back(P.diag[s]);
+    }
+    A.ptr[s + 1] = (int64_t)A.idx.size();
+  }
+
+  // vertical extrapolation E~ and the surface hierarchy
+  int64_t m = P.n_top;
+  if (m > 0) {
+    std::vector<std::array<int64_t, 3>> tri;
+    for (int64_t e = 0; e < n_tets; ++e) {
+      static const int faces[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
+      for (auto &f : faces) {
+        std::array<int64_t, 3> t = {tets[4 * e + f[0]], tets[4 * e + f[1]], tets[4 * e + f[2]]};
+        if (P.top[t[0]] && P.top[t[1]] && P.top[t[2]]) {
+          std::sort(t.begin(), t.end());
+          tri.push_back(t);
+        }
+      }
+    }
+    std::sort(tri.begin(), tri.end());
+    tri.erase(std::unique(tri.begin(), tri.end()), tri.end());
+    if (tri.empty()) fail(-2, "no top-surface triangles (faces with three top nodes)");
+    Locator loc2(xyz, tri, xmin, ymin, xmax, ymax);
+    Csr E0;
+    E0.nrows = n;
+    E0.ncols = m;
+    E0.ptr.assign(n + 1, 0);
+    for (int64_t s = 0; s < n; ++s) {
+      int64_t i = P.perm[s];
+      if (P.top[i]) {
+        E0.idx.push_back((int32_t)s);
+        E0.val.push_back(1.0);
+      } else {
+        double lam[3];
+        int64_t t = loc2.locate(xyz[3 * i], xyz[3 * i + 1], lam);
+        if (t < 0) {
+          std::ostringstream os;
+          os << "node " << i << " does not project onto the top surface";
+          fail(-3, os.str());
+        }
+        for (double &l : lam)
+          if (std::fabs(l) <= kTolInside) l = 0.0;
+        double sum = (lam[0] + lam[1]) + lam[2];
+        std::vector<std::pair<int32_t, double>> ent;
+        for (int a = 0; a < 3; ++a) {
+          double w = lam[a] / sum;
+          int64_t v = tri[t][a];
+          if (w != 0.0 && !fixed[v]) ent.emplace_back((int32_t)P.pos[v], w);
+        }
+        std::sort(ent.begin(), ent.end());
+        for (auto &e : ent) {
+          E0.idx.push_back(e.first);
+          E0.val.push_back(e.second);
+        }
+      }
+      E0.ptr[s + 1] = (int64_t)E0.idx.size();
+    }
+    Csr E0t = transpose(E0);
+    Csr S0 = spgemm(E0t, spgemm(A, E0));
+    std::vector<int64_t> ident(m);
+    std::iota(ident.begin(), ident.end(), 0);
+    std::vector<int32_t> scol = greedy_colouring(S0, ident);
+    P.S_perm = stable_colour_sort(scol);
+    std::vector<int64_t> sinv(m);
+    for (int64_t i = 0; i < m; ++i) sinv[P.S_perm[i]] = i;
+    P.E = permute_cols(E0, sinv);
+    P.Et = transpose(P.E);
+    Level L0;
+    L0.A = permute_sym(S0, P.S_perm);
+    L0.colour.resize(m);
+    L0.node.resize(m);
+    L0.k = 3;
+    L0.B.resize(3 * m);
+    for (int64_t i = 0; i < m; ++i) {
+      L0.colour[i] = scol[P.S_perm[i]];
+      L0.node[i] = (int32_t)i;
+      int64_t nd = P.perm[P.S_perm[i]];
+      L0.B[3 * i] = 1.0;
+      L0.B[3 * i + 1] = xyz[3 * nd];
+      L0.B[3 * i + 2] = xyz[3 * nd + 1];
+    }
+    P.S.clear();
+    P.S.push_back(std::move(L0));
+    build_hierarchy(P.S, opt);
+  }
+
+  // interior hierarchy on A_bar (non-top block)
+  Level B0;
+  int64_t nb = n - m;
+  if (nb <= 0) fail(-2, "no interior nodes below the top surface");
+  B0.A.nrows = B0.A.ncols = nb;
+  B0.A.ptr.assign(nb + 1, 0);
+  for (int64_t s = m; s < n; ++s) {
+    for (int64_t k = A.ptr[s]; k < A.ptr[s + 1]; ++k)
+      if (A.idx[k] >= m) {
+        B0.A.idx.push_back(A.idx[k] - (int32_t)m);
+        B0.A.val.push_back(A.val[k]);
+      }
+    B0.A.ptr[s - m + 1] = (int64_t)B0.A.idx.size();
+  }
+  B0.colour.assign(P.colour.begin() + m, P.colour.end());
+  B0.node.resize(nb);
+  std::iota(B0.node.begin(), B0.node.end(), 0);
+  B0.k = 1;
+  B0.B.assign(nb, 1.0);
+  P.Abar.clear();
+  P.Abar.push_back(std::move(B0));
+  build_hierarchy(P.Abar, opt);
+}
+
+void mass_rhs(const Problem &P, const double *f, double *b) {
+  int64_t N = P.n_nodes, T = (int64_t)P.tets.size() / 4;
+  std::vector<double> bf(N, 0.0), w(N, 0.0);
+  for (int64_t e = 0; e < T; ++e) {
+    V3 c[4];
+    double det;
+    tet_gradients(P.xyz.data(), P.tets.data() + 4 * e, c, det);
+    double vol = det / 6.0;
+    const int64_t *t = P.tets.data() + 4 * e;
+    for (int a = 0; a < 4; ++a) {
+      double s = 0.0;
+      for (int bb = 0; bb < 4; ++bb) s += (a == bb ? 2.0 : 1.0) * f[t[bb]];
+      bf[t[a]] += vol / 20.0 * s;
+      w[t[a]] += vol / 20.0 * 5.0;
+    }
+  }
+  if (!P.opt.top_dirichlet) {
+    double sb = 0.0, sw = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+      sb += bf[i];
+      sw += w[i];
+    }
+    double c = sb / sw;
+    for (int64_t i = 0; i < N; ++i) bf[i] -= c * w[i];
+  }
+  for (int64_t i = 0; i < N; ++i) b[i] = P.pos[i] >= 0 ? bf[i] : 0.0;
+}
+
+}  // namespace vemg

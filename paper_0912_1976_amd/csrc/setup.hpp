@@ -1,0 +1,70 @@
+// Host setup of the vertical-extrapolation multigrid: P1 assembly, node
+// ordering and colouring, the vertical extrapolation operator E~ and the two
+// smoothed aggregation hierarchies.  Everything here runs once per mesh on
+// the host; the GPU only ever sees the packed results.
+#pragma once
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "sparse.hpp"
+
+namespace vemg {
+
+struct SetupError : std::runtime_error {
+  int code;
+  SetupError(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+struct Level {
+  Csr A;                              // standard form, storage (colour-sorted) order
+  std::vector<int32_t> colour;        // per row, non-decreasing
+  std::vector<int64_t> colour_start;  // ncolours + 1
+  std::vector<int32_t> node;          // aggregation node of each row
+  std::vector<double> B;              // near-kernel vectors, row-major [n][k]
+  int k = 1;
+  Csr P;                              // prolongator from the next level (empty on the coarsest)
+  std::vector<int32_t> agg;           // aggregate of each node
+  std::vector<double> Cinv;           // coarsest level: explicit inverse, row-major
+  int64_t n() const { return A.nrows; }
+};
+
+struct SetupOptions {
+  int top_dirichlet = 0;     // 0: point condition at pin_node, 1: Dirichlet on the whole top
+  int64_t pin_node = -1;     // -1: top node closest to the origin corner
+  double theta = 0.01;
+  double prolong_omega = 2.0 / 3.0;
+  int max_levels = 10;
+  int64_t coarse_max = 256;
+};
+
+struct Problem {
+  SetupOptions opt;
+  int64_t n_nodes = 0, n = 0, n_top = 0, pin = -1;
+  std::vector<double> xyz;            // mesh copy (natural order)
+  std::vector<int64_t> tets;
+  std::vector<uint8_t> top;
+  std::vector<int64_t> perm;          // storage position -> natural node
+  std::vector<int64_t> pos;           // natural node -> storage position (-1: fixed)
+  Csr Aoff;                           // off-diagonals of A_UU, storage order
+  std::vector<double> d;              // deficit d_i = -sum_{j fixed} a_ij
+  std::vector<double> diag;           // a_ii = d_i - sum_j a_ij
+  std::vector<int32_t> colour;        // fine colouring (sorted within each block)
+  std::vector<int64_t> top_colour_start, bar_colour_start;  // ranges in storage order
+  Csr E, Et;                          // E~ (n x m') and its transpose
+  std::vector<int64_t> S_perm;        // S storage position -> top-block position
+  std::vector<Level> S, Abar;         // hierarchies (S empty when m' = 0)
+};
+
+// Builds the whole problem.  Throws SetupError with a status code on
+// invalid meshes (-2), projection failure (-3) or invalid arguments (-1).
+void build_problem(Problem &P, const SetupOptions &opt, int64_t n_nodes, const double *xyz,
+                   int64_t n_tets, const int64_t *tets, const uint8_t *top);
+
+// b = M f (consistent P1 mass matrix) in natural order; in the pinned
+// (Neumann) case b is made orthogonal to constants first.  Fixed nodes get 0.
+void mass_rhs(const Problem &P, const double *f, double *b);
+
+}  // namespace vemg

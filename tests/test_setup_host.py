@@ -1,0 +1,143 @@
+"""The library's host setup against the oracle, without a GPU.
+
+Integer structure (node order, colours, CSR patterns of A, E~ and every
+multigrid level, aggregates) must match bit for bit; the fine-level matrix
+values too (both sides sum in the same fixed order); values derived through
+products must match to 1e-13 relative."""
+import numpy as np
+import pytest
+
+from inputs import box_mesh
+
+lib = pytest.importorskip("paper_0912_1976_amd")
+
+from oracle import solver as osolver  # noqa: E402
+
+
+CASES = [
+    ("N", dict(nx=9, ny=8, nz=5, H=0.01, jitter=0.3, seed=11, bathymetry=True)),
+    ("D", dict(nx=9, ny=8, nz=5, H=0.01, jitter=0.3, seed=11, bathymetry=True)),
+    ("N", dict(nx=17, ny=17, nz=9, H=0.01, jitter=0.2, seed=1, bathymetry=False)),
+    ("N", dict(nx=21, ny=19, nz=7, H=1e-4, jitter=0.3, seed=5, bathymetry=True)),
+]
+
+
+def _mk(mode, kw):
+    kw = dict(kw)
+    m = box_mesh(kw.pop("nx"), kw.pop("ny"), kw.pop("nz"), kw.pop("H"), **kw)
+    s = lib.Solver(m.xyz, m.tets, m.top, top_bc=mode, device=-1, coarse_max=40)
+    o = osolver.setup(m, mode, coarse_max=40)
+    return m, s, o
+
+
+@pytest.fixture(scope="module", params=range(len(CASES)))
+def pair(request):
+    mode, kw = CASES[request.param]
+    return _mk(mode, kw)
+
+
+def _csr(s, name):
+    return (s.export(name + ".ptr", np.int64), s.export(name + ".idx", np.int32), s.export(name + ".val", np.float64))
+
+
+def _same_pattern(got, ref):
+    ptr, idx, _ = got
+    ref = ref.tocsr()
+    ref.sort_indices()
+    assert np.array_equal(ptr, ref.indptr)
+    assert np.array_equal(idx, ref.indices)
+
+
+def _close(a, b, rtol=1e-13):
+    scale = max(np.abs(b).max(), 1e-300)
+    assert np.max(np.abs(a - b)) <= rtol * scale
+
+
+def test_order_and_colours_bit_exact(pair):
+    m, s, o = pair
+    assert np.array_equal(s.export("perm", np.int64), o.perm)
+    assert np.array_equal(s.export("colour", np.int32), o.colour)
+    info = s.info()
+    assert info["n_top"] == o.n_top
+    assert info["pin_node"] == o.pin
+
+
+def test_fine_matrix_bit_exact(pair):
+    m, s, o = pair
+    got = _csr(s, "Aoff")
+    _same_pattern(got, o.Aoff)
+    assert np.array_equal(got[2], o.Aoff.data)          # same summation order
+    assert np.array_equal(s.export("d", np.float64), o.d)
+    assert np.array_equal(s.export("diag", np.float64), o.diag)
+
+
+def test_extrapolation_pattern_and_weights(pair):
+    m, s, o = pair
+    if o.n_top == 0:
+        return
+    assert np.array_equal(s.export("S_perm", np.int64), o.S_perm)
+    got = _csr(s, "E")
+    _same_pattern(got, o.E)
+    assert np.array_equal(got[2], o.E.data)
+
+
+@pytest.mark.parametrize("which", ["S", "Abar"])
+def test_hierarchies(pair, which):
+    m, s, o = pair
+    levels = o.S_levels if which == "S" else o.Abar_levels
+    if levels is None:
+        assert s.info()["s_levels"] == 0
+        return
+    info = s.info()
+    nlev = info["s_levels"] if which == "S" else info["abar_levels"]
+    assert nlev == len(levels)
+    for l, L in enumerate(levels):
+        pre = f"{which}.{l}."
+        assert np.array_equal(s.export(pre + "colour", np.int32), L.colour)
+        assert np.array_equal(s.export(pre + "node", np.int32), L.node)
+        A = _csr(s, pre + "A")
+        _same_pattern(A, L.A)
+        _close(A[2], L.A.data)
+        if l + 1 < len(levels):
+            assert np.array_equal(s.export(pre + "agg", np.int32), L.agg)
+            P = _csr(s, pre + "P")
+            _same_pattern(P, L.P)
+            _close(P[2], L.P.data, 1e-12)
+        else:
+            # explicit inverse of the coarsest operator (ill-conditioned at small
+            # eps, so compare its action rather than its entries)
+            Cinv = s.export(pre + "Cinv", np.float64).reshape(L.n, L.n)
+            assert np.abs(Cinv @ L.A.toarray() - np.eye(L.n)).max() < 1e-7
+
+
+def test_mass_rhs_matches_oracle(pair):
+    m, s, o = pair
+    f = np.cos(3 * m.xyz[:, 0]) + m.xyz[:, 1] ** 2
+    b = s.rhs(f)
+    ref = osolver.rhs_from_field(o, f)
+    _close(b[o.perm], ref, 1e-13)
+    fixed = np.ones(m.n, bool)
+    fixed[o.perm] = False
+    assert np.all(b[fixed] == 0.0)
+
+
+def test_setup_errors():
+    m = box_mesh(5, 5, 3, 0.01)
+    bad = m.tets.copy()
+    bad[7, [1, 2]] = bad[7, [2, 1]]
+    with pytest.raises(lib.VemgError) as e:
+        lib.Solver(m.xyz, bad, m.top, device=-1)
+    assert e.value.status == -2 and "tetrahedron 7" in str(e.value)
+    xyz = m.xyz.copy()
+    xyz[0, 0] = -0.5
+    with pytest.raises(lib.VemgError) as e:
+        lib.Solver(xyz, m.tets, m.top, device=-1)
+    assert e.value.status in (-2, -3)
+    with pytest.raises(lib.VemgError) as e:
+        lib.Solver(m.xyz, m.tets, np.zeros(m.n, bool), device=-1)
+    assert e.value.status == -2
+    t2 = m.tets.copy()
+    t2[0, 0] = m.n + 5
+    with pytest.raises(lib.VemgError) as e:
+        lib.Solver(m.xyz, t2, m.top, device=-1)
+    assert e.value.status == -2
