@@ -45,7 +45,7 @@ class OracleSetup:
         return self.perm.size
 
 
-def setup(mesh, mode="N", coarse_max=256, max_levels=10):
+def setup(mesh, mode="N", coarse_max=2048, max_levels=10):
     """Assembly (Section 3), E~ (Section 5.4) and both SA hierarchies (Section 6)."""
     xyz, tets, top = mesh.xyz, mesh.tets, mesh.top
     n_nodes = xyz.shape[0]

@@ -91,7 +91,7 @@ class Solver:
     """
 
     def __init__(self, xyz, tets, top, *, top_bc="pinned", pc="vl_as", device=0, pin_node=-1,
-                 use_graphs=True, poll_every=8, coarse_max=256, max_levels=10, max_restarts=5):
+                 use_graphs=True, poll_every=8, coarse_max=2048, max_levels=10, max_restarts=5):
         self._lib = load_library()
         opt = Options()
         self._lib.vemg_default_options(C.byref(opt))

@@ -122,13 +122,46 @@ Sell pack_sell(Arena &ar, hipStream_t st, const Csr &A, bool square, const std::
   return M;
 }
 
+// CSR (host) -> CsrG (device).  Square matrices keep only off-diagonals and
+// move the diagonal into `d`.  G = smallest power of two >= half the mean
+// row length, clamped to [4, 64].
+CsrG pack_csrg(Arena &ar, hipStream_t st, const Csr &A, bool square, int64_t *stored = nullptr) {
+  std::vector<int32_t> ptr(A.nrows + 1, 0), col;
+  std::vector<double> val, d(square ? A.nrows : 0, 0.0);
+  col.reserve(A.nnz());
+  val.reserve(A.nnz());
+  for (int64_t r = 0; r < A.nrows; ++r) {
+    for (int64_t k = A.ptr[r]; k < A.ptr[r + 1]; ++k) {
+      if (square && A.idx[k] == r) {
+        d[r] = A.val[k];
+        continue;
+      }
+      col.push_back(A.idx[k]);
+      val.push_back(A.val[k]);
+    }
+    ptr[r + 1] = (int32_t)col.size();
+  }
+  double mean = A.nrows ? (double)col.size() / (double)A.nrows : 0.0;
+  int G = 4;
+  while (G < 64 && G < mean / 2.0) G *= 2;
+  if (stored) *stored = (int64_t)col.size();
+  CsrG M;
+  M.nrows = A.nrows;
+  M.G = G;
+  M.ptr = ar.upload(ptr, st);
+  M.col = ar.upload(col, st);
+  M.val = ar.upload(val, st);
+  if (square) M.d = ar.upload(d, st);
+  return M;
+}
+
 struct DLevel {
-  Sell A;                       // square operator (standard form), unused on the fine A_bar level
-  bool fine = false;            // A_bar level 0: rows [row0, row0 + n) of the fine matrix
-  bool diff = false;
+  Sell As;                      // fine A_bar level: rows [row0, row0 + n) of the fine SELL matrix
+  CsrG Ac;                      // coarse levels: standard form, G lanes per row
+  bool fine = false;
   int64_t n = 0, row0 = 0;
   std::vector<int64_t> cstart;  // colour ranges, global row indices
-  Sell P, Pt;                   // prolongation (n x n_next) and restriction
+  CsrG P, Pt;                   // prolongation (n x n_next) and restriction
   double *Cinv = nullptr;       // coarsest level only
   double *x = nullptr, *g = nullptr, *r = nullptr;  // indexed by global row
   bool coarsest = false;
@@ -147,8 +180,11 @@ struct vemg_solver_s {
   vemg::Problem P;
   vemg::Arena ar;
   vemg::Sell A;                           // fine A_UU, difference form
-  vemg::Sell E, Et;
+  vemg::Sell E;
+  vemg::CsrG Et;
   std::vector<vemg::DLevel> S, Ab;
+  hipStream_t work2 = nullptr;            // surface branch of the additive preconditioner
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *b = nullptr, *w = nullptr,
          *res = nullptr, *resA = nullptr, *diag = nullptr, *tmp = nullptr, *nat = nullptr;
   double *part_pq = nullptr, *part_rr = nullptr, *part_rz = nullptr, *part_b = nullptr, *part_t = nullptr,
@@ -181,8 +217,7 @@ void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, bool
     dl.coarsest = (l + 1 == H.size());
     if (is_abar && l == 0) {
       dl.fine = true;
-      dl.diff = true;
-      dl.A = h->A;
+      dl.As = h->A;
       dl.row0 = h->P.n_top;
       dl.cstart = h->P.bar_colour_start;  // already global
       dl.x = h->w;
@@ -191,7 +226,7 @@ void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, bool
       nnz.push_back(h->nnz_A);
     } else {
       int64_t st_nnz = 0;
-      dl.A = pack_sell(h->ar, st, L.A, true, nullptr, &st_nnz);
+      dl.Ac = pack_csrg(h->ar, st, L.A, true, &st_nnz);
       nnz.push_back(st_nnz);
       dl.cstart = L.colour_start;
       dl.x = h->ar.alloc<double>(dl.n);
@@ -200,8 +235,8 @@ void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, bool
     }
     if (!dl.coarsest) {
       int64_t pn = 0;
-      dl.P = pack_sell(h->ar, st, L.P, false, nullptr, &pn);
-      dl.Pt = pack_sell(h->ar, st, transpose(L.P), false, nullptr);
+      dl.P = pack_csrg(h->ar, st, L.P, false, &pn);
+      dl.Pt = pack_csrg(h->ar, st, transpose(L.P), false);
       pnnz.push_back(pn);
     } else {
       dl.Cinv = h->ar.upload(L.Cinv, st);
@@ -210,8 +245,7 @@ void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, bool
   }
 }
 
-void vcycle(Handle *h, std::vector<DLevel> &H, size_t l, const int *done) {
-  hipStream_t st = h->work;
+void vcycle(hipStream_t st, std::vector<DLevel> &H, size_t l, const int *done) {
   DLevel &L = H[l];
   if (L.coarsest) {
     launch_dense(st, L.Cinv, L.n, L.g + L.row0, L.x + L.row0, done);
@@ -219,13 +253,22 @@ void vcycle(Handle *h, std::vector<DLevel> &H, size_t l, const int *done) {
   }
   launch_fill(st, L.x + L.row0, L.n, 0.0, done);
   int nc = (int)L.cstart.size() - 1;
-  for (int c = 0; c < nc; ++c) launch_gs(st, L.A, L.diff, L.cstart[c], L.cstart[c + 1], 0, 0, L.g, L.x, done);
-  launch_spmv(st, L.A, L.diff, 1, L.row0, L.row0 + L.n, L.x, L.g, L.r, nullptr, done);
+  auto gs = [&](int c) {
+    if (L.fine)
+      launch_gs(st, L.As, true, L.cstart[c], L.cstart[c + 1], 0, 0, L.g, L.x, done);
+    else
+      launch_csr_gs(st, L.Ac, L.cstart[c], L.cstart[c + 1], L.g, L.x, done);
+  };
+  for (int c = 0; c < nc; ++c) gs(c);
+  if (L.fine)
+    launch_spmv(st, L.As, true, 1, L.row0, L.row0 + L.n, L.x, L.g, L.r, nullptr, done);
+  else
+    launch_csr_spmv(st, L.Ac, 1, 0, L.n, L.x, L.g, L.r, done);
   DLevel &C = H[l + 1];
-  launch_rect(st, L.Pt, false, L.r + L.row0, C.g, done);
-  vcycle(h, H, l + 1, done);
-  launch_rect(st, L.P, true, C.x, L.x + L.row0, done);
-  for (int c = nc - 1; c >= 0; --c) launch_gs(st, L.A, L.diff, L.cstart[c], L.cstart[c + 1], 0, 0, L.g, L.x, done);
+  launch_csr_rect(st, L.Pt, false, L.r + L.row0, C.g, done);
+  vcycle(st, H, l + 1, done);
+  launch_csr_rect(st, L.P, true, C.x, L.x + L.row0, done);
+  for (int c = nc - 1; c >= 0; --c) gs(c);
 }
 
 // z = M^{-1} rr; partial sums of rr . z go to part_rz (count in np_rz)
@@ -235,13 +278,19 @@ void precond(Handle *h, const double *rr, double *zz, const int *done) {
   int64_t n = P.n, m = P.n_top;
   switch (h->opt.pc) {
     case VEMG_PC_VL_ADDITIVE: {
+      // the two terms of the additive preconditioner are independent: the
+      // surface branch runs on a second stream (a parallel graph branch)
       if (m > 0) {
-        launch_rect(st, h->Et, false, rr, h->S[0].g, done);
-        vcycle(h, h->S, 0, done);
+        HIPCHK(hipEventRecord(h->ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(h->work2, h->ev_fork, 0));
+        launch_csr_rect(h->work2, h->Et, false, rr, h->S[0].g, done);
+        vcycle(h->work2, h->S, 0, done);
+        HIPCHK(hipEventRecord(h->ev_join, h->work2));
       }
       h->Ab[0].g = const_cast<double *>(rr);
-      vcycle(h, h->Ab, 0, done);
+      vcycle(st, h->Ab, 0, done);
       h->Ab[0].g = h->r;
+      if (m > 0) HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
       if (m > 0) {
         launch_prolong_sum(st, h->E, m, h->S[0].x, h->w, rr, zz, h->part_rz, done);
       } else {
@@ -269,8 +318,8 @@ void precond(Handle *h, const double *rr, double *zz, const int *done) {
       for (int c = 0; c < nc; ++c) sweep(c);
       if (m > 0) {
         launch_spmv(st, h->A, true, 1, 0, n, zz, rr, h->res, nullptr, done);
-        launch_rect(st, h->Et, false, h->res, h->S[0].g, done);
-        vcycle(h, h->S, 0, done);
+        launch_csr_rect(st, h->Et, false, h->res, h->S[0].g, done);
+        vcycle(st, h->S, 0, done);
         launch_rect(st, h->E, true, h->S[0].x, zz, done);
       }
       for (int c = nc - 1; c >= 0; --c) sweep(c);
@@ -314,7 +363,7 @@ void upload(Handle *h) {
   h->A = pack_sell(h->ar, st, P.Aoff, true, &P.d, &h->nnz_A);
   if (m > 0) {
     h->E = pack_sell(h->ar, st, P.E, false, nullptr, &h->nnz_E);
-    h->Et = pack_sell(h->ar, st, P.Et, false, nullptr);
+    h->Et = pack_csrg(h->ar, st, P.Et, false);
   }
   h->x = h->ar.alloc<double>(n);
   h->r = h->ar.alloc<double>(n);
@@ -493,7 +542,7 @@ int do_apply(Handle *h, int op, const double *in, double *out) {
       break;
     case VEMG_OP_ET:
       if (m == 0) return VEMG_ERR_STATE;
-      launch_rect(st, h->Et, false, in, out, nullptr);
+      launch_csr_rect(st, h->Et, false, in, out, nullptr);
       break;
     case VEMG_OP_E:
       if (m == 0) return VEMG_ERR_STATE;
@@ -502,13 +551,13 @@ int do_apply(Handle *h, int op, const double *in, double *out) {
     case VEMG_OP_VCYCLE_S:
       if (m == 0) return VEMG_ERR_STATE;
       launch_copy(st, in, h->S[0].g, m, nullptr);
-      vcycle(h, h->S, 0, nullptr);
+      vcycle(st, h->S, 0, nullptr);
       launch_copy(st, h->S[0].x, out, m, nullptr);
       break;
     case VEMG_OP_VCYCLE_ABAR:
       launch_copy(st, in, h->tmp + m, n - m, nullptr);
       h->Ab[0].g = h->tmp;
-      vcycle(h, h->Ab, 0, nullptr);
+      vcycle(st, h->Ab, 0, nullptr);
       h->Ab[0].g = h->r;
       launch_copy(st, h->w + m, out, n - m, nullptr);
       break;
@@ -671,7 +720,7 @@ void vemg_default_options(vemg_options *o) {
   o->theta = 0.01;
   o->prolong_omega = 2.0 / 3.0;
   o->max_levels = 10;
-  o->coarse_max = 256;
+  o->coarse_max = 2048;
   o->poll_every = 8;
   o->max_restarts = 5;
   o->use_graphs = 1;
@@ -696,7 +745,10 @@ vemg_status vemg_create(const vemg_options *o, int device, void *hip_stream, vem
   int st = guarded(h, [&]() -> int {
     if (device >= 0) {
       HIPCHK(hipStreamCreate(&h->work));
+      HIPCHK(hipStreamCreate(&h->work2));
       HIPCHK(hipEventCreateWithFlags(&h->ev, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
     }
     return VEMG_OK;
   });
@@ -819,8 +871,12 @@ vemg_status vemg_destroy(vemg_solver s) {
     if (s->work) (void)hipStreamSynchronize(s->work);
     vemg::destroy_graph(s);
     s->ar.release();
+    if (s->work2) (void)hipStreamSynchronize(s->work2);
     if (s->ev) (void)hipEventDestroy(s->ev);
+    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+    if (s->ev_join) (void)hipEventDestroy(s->ev_join);
     if (s->work) (void)hipStreamDestroy(s->work);
+    if (s->work2) (void)hipStreamDestroy(s->work2);
   }
   delete s;
   return VEMG_OK;

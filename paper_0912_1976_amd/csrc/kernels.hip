@@ -47,30 +47,89 @@ __device__ __forceinline__ void row_terms(const Sell &A, int64_t s, int lane, in
   const int len = (int)((A.sptr[s + 1] - base) >> 6);
   const int32_t *__restrict__ cp = A.col + base + lane;
   const double *__restrict__ vp = A.val + base + lane;
-  double a0 = 0.0, a1 = 0.0, o0 = 0.0, o1 = 0.0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0;
   int k = 0;
-  for (; k + 1 < len; k += 2) {
+  // four independent entries in flight per lane
+  for (; k + 3 < len; k += 4) {
     const int32_t c0 = cp[(int64_t)k * 64], c1 = cp[(int64_t)(k + 1) * 64];
+    const int32_t c2 = cp[(int64_t)(k + 2) * 64], c3 = cp[(int64_t)(k + 3) * 64];
     const double v0 = vp[(int64_t)k * 64], v1 = vp[(int64_t)(k + 1) * 64];
-    const double x0 = x[c0], x1 = x[c1];
+    const double v2 = vp[(int64_t)(k + 2) * 64], v3 = vp[(int64_t)(k + 3) * 64];
+    const double x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
     if (DIFF) {
       a0 += v0 * (x0 - xr);
       a1 += v1 * (x1 - xr);
+      a2 += v2 * (x2 - xr);
+      a3 += v3 * (x3 - xr);
     } else {
       a0 += v0 * x0;
       a1 += v1 * x1;
+      a2 += v2 * x2;
+      a3 += v3 * x3;
     }
     o0 += v0;
     o1 += v1;
+    o2 += v2;
+    o3 += v3;
   }
-  if (k < len) {
+  for (; k < len; ++k) {
     const int32_t c0 = cp[(int64_t)k * 64];
     const double v0 = vp[(int64_t)k * 64];
     a0 += DIFF ? v0 * (x[c0] - xr) : v0 * x[c0];
     o0 += v0;
   }
-  acc = a0 + a1;
-  offsum = o0 + o1;
+  acc = (a0 + a1) + (a2 + a3);
+  offsum = (o0 + o1) + (o2 + o3);
+}
+
+// Sum of a row of a CsrG matrix by its group of G lanes (result in every lane
+// of the group).
+template <int G>
+__device__ __forceinline__ double group_row(const CsrG &A, int64_t r, int gl, const double *__restrict__ x) {
+  const int32_t b = A.ptr[r], e = A.ptr[r + 1];
+  double a0 = 0.0, a1 = 0.0;
+  int k = b + gl;
+  for (; k + G < e; k += 2 * G) {
+    a0 += A.val[k] * x[A.col[k]];
+    a1 += A.val[k + G] * x[A.col[k + G]];
+  }
+  if (k < e) a0 += A.val[k] * x[A.col[k]];
+  double t = a0 + a1;
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, G);
+  return t;
+}
+
+template <int G, int MODE>
+__global__ __launch_bounds__(kBlock) void k_csr_spmv(CsrG A, int64_t r0, int64_t r1, const double *__restrict__ x,
+                                                     const double *__restrict__ g, double *__restrict__ y,
+                                                     const int *__restrict__ done) {
+  if (done && *done) return;
+  const int gl = threadIdx.x & (G - 1);
+  const int64_t r = r0 + ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+  if (r >= r1) return;
+  const double t = group_row<G>(A, r, gl, x);
+  if (gl == 0) {
+    // MODE 0/1: square standard form; 2/3: rectangular, 3 accumulates
+    if (MODE == 0) y[r] = t + A.d[r] * x[r];
+    else if (MODE == 1) y[r] = g[r] - (t + A.d[r] * x[r]);
+    else if (MODE == 2) y[r] = t;
+    else y[r] += t;
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_csr_gs(CsrG A, int64_t r0, int64_t r1, const double *__restrict__ g,
+                                                   double *__restrict__ x, const int *__restrict__ done) {
+  if (done && *done) return;
+  const int gl = threadIdx.x & (G - 1);
+  const int64_t r = r0 + ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+  if (r >= r1) return;
+  const double t = group_row<G>(A, r, gl, x);  // off-diagonal part only
+  if (gl == 0) {
+    const double dr = A.d[r];
+    x[r] = (g[r] - t) / dr;
+  }
 }
 
 template <bool DIFF, int MODE, bool DOT>
@@ -414,6 +473,46 @@ void launch_gather(hipStream_t st, const double *nat, const int64_t *perm, doubl
 void launch_scatter(hipStream_t st, const double *sto, const int64_t *perm, double *nat, int64_t n) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_scatter, grid(vec_blocks(n)), dim3(kBlock), 0, st, sto, perm, nat, n);
+}
+
+template <int MODE>
+static void csr_dispatch(hipStream_t st, const CsrG &A, int64_t r0, int64_t r1, const double *x, const double *g,
+                         double *y, const int *done) {
+  int64_t rows = r1 - r0;
+  if (rows <= 0) return;
+  int64_t nb = (rows * A.G + kBlock - 1) / kBlock;
+  switch (A.G) {
+    case 4: hipLaunchKernelGGL((k_csr_spmv<4, MODE>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, x, g, y, done); break;
+    case 8: hipLaunchKernelGGL((k_csr_spmv<8, MODE>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, x, g, y, done); break;
+    case 16: hipLaunchKernelGGL((k_csr_spmv<16, MODE>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, x, g, y, done); break;
+    case 32: hipLaunchKernelGGL((k_csr_spmv<32, MODE>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, x, g, y, done); break;
+    default: hipLaunchKernelGGL((k_csr_spmv<64, MODE>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, x, g, y, done); break;
+  }
+}
+
+void launch_csr_spmv(hipStream_t st, const CsrG &A, int mode, int64_t r0, int64_t r1, const double *x,
+                     const double *g, double *y, const int *done) {
+  if (mode == 0) csr_dispatch<0>(st, A, r0, r1, x, g, y, done);
+  else csr_dispatch<1>(st, A, r0, r1, x, g, y, done);
+}
+
+void launch_csr_rect(hipStream_t st, const CsrG &P, bool accumulate, const double *x, double *y, const int *done) {
+  if (accumulate) csr_dispatch<3>(st, P, 0, P.nrows, x, nullptr, y, done);
+  else csr_dispatch<2>(st, P, 0, P.nrows, x, nullptr, y, done);
+}
+
+void launch_csr_gs(hipStream_t st, const CsrG &A, int64_t r0, int64_t r1, const double *g, double *x,
+                   const int *done) {
+  int64_t rows = r1 - r0;
+  if (rows <= 0) return;
+  int64_t nb = (rows * A.G + kBlock - 1) / kBlock;
+  switch (A.G) {
+    case 4: hipLaunchKernelGGL((k_csr_gs<4>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, g, x, done); break;
+    case 8: hipLaunchKernelGGL((k_csr_gs<8>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, g, x, done); break;
+    case 16: hipLaunchKernelGGL((k_csr_gs<16>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, g, x, done); break;
+    case 32: hipLaunchKernelGGL((k_csr_gs<32>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, g, x, done); break;
+    default: hipLaunchKernelGGL((k_csr_gs<64>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, g, x, done); break;
+  }
 }
 
 void launch_pcg_init(hipStream_t st, Scal *s, const double *pb, int64_t npb, double tol, int maxit) {

@@ -26,6 +26,20 @@ struct Sell {
   int64_t nrows = 0;
 };
 
+// CSR matrix processed by groups of G lanes per row (G = 4..64, a power of
+// two chosen from the mean row length): the group reads consecutive entries
+// of its row (coalesced) and reduces with cross-lane shuffles, so long rows
+// (coarse multigrid operators, restrictions) cost a few memory round trips
+// instead of one per entry.  `d` as for Sell (square standard form only).
+struct CsrG {
+  const int32_t *ptr = nullptr;  // nrows + 1
+  const int32_t *col = nullptr;
+  const double *val = nullptr;
+  const double *d = nullptr;
+  int64_t nrows = 0;
+  int G = 4;
+};
+
 // Device scalars of one PCG solve.
 struct Scal {
   double rho, alpha, beta, bnorm2, tol2, rr, pq, dot;
@@ -66,6 +80,14 @@ void launch_jacobi(hipStream_t st, const double *r, const double *diag, double *
 // storage <-> natural order
 void launch_gather(hipStream_t st, const double *nat, const int64_t *perm, double *sto, int64_t n);
 void launch_scatter(hipStream_t st, const double *sto, const int64_t *perm, double *nat, int64_t n);
+
+// CsrG versions.  mode 0: y = A x, 1: y = g - A x (square, standard form);
+// rect: y = P x or y += P x over rows [0, nrows).
+void launch_csr_spmv(hipStream_t st, const CsrG &A, int mode, int64_t r0, int64_t r1, const double *x,
+                     const double *g, double *y, const int *done);
+void launch_csr_gs(hipStream_t st, const CsrG &A, int64_t r0, int64_t r1, const double *g, double *x,
+                   const int *done);
+void launch_csr_rect(hipStream_t st, const CsrG &P, bool accumulate, const double *x, double *y, const int *done);
 
 // PCG pieces (single-block scalar kernels sum the partials in index order).
 void launch_pcg_init(hipStream_t st, Scal *s, const double *pb, int64_t npb, double tol, int maxit);

@@ -315,7 +315,9 @@ std::vector<int64_t> stable_colour_sort(const std::vector<int32_t> &col) {
   return p;
 }
 
-// Dense Cholesky inverse of a small SPD matrix (row-major, in place).
+// Dense inverse of a small SPD matrix (row-major, in place): Cholesky
+// A = L L^T, then L^{-1} row by row, then A^{-1} = L^{-T} L^{-1}; every inner
+// loop runs over contiguous memory.
 void spd_inverse(std::vector<double> &M, int64_t n) {
   std::vector<double> L(n * n, 0.0);
   for (int64_t j = 0; j < n; ++j) {
@@ -326,24 +328,34 @@ void spd_inverse(std::vector<double> &M, int64_t n) {
     L[j * n + j] = ljj;
     for (int64_t i = j + 1; i < n; ++i) {
       double t = M[i * n + j];
-      for (int64_t k = 0; k < j; ++k) t -= L[i * n + k] * L[j * n + k];
+      const double *li = &L[i * n], *lj = &L[j * n];
+      for (int64_t k = 0; k < j; ++k) t -= li[k] * lj[k];
       L[i * n + j] = t / ljj;
     }
   }
-  std::vector<double> inv(n * n, 0.0), y(n);
-  for (int64_t c = 0; c < n; ++c) {
-    for (int64_t i = 0; i < n; ++i) {
-      double t = (i == c) ? 1.0 : 0.0;
-      for (int64_t k = 0; k < i; ++k) t -= L[i * n + k] * y[k];
-      y[i] = t / L[i * n + i];
+  // W = L^{-1} (lower triangular): row i = (e_i - sum_{k<i} L_ik W_k) / L_ii
+  std::vector<double> W(n * n, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    double *wi = &W[i * n];
+    wi[i] = 1.0;
+    for (int64_t k = 0; k < i; ++k) {
+      double l = L[i * n + k];
+      const double *wk = &W[k * n];
+      for (int64_t j = 0; j <= k; ++j) wi[j] -= l * wk[j];
     }
-    for (int64_t i = n - 1; i >= 0; --i) {
-      double t = y[i];
-      for (int64_t k = i + 1; k < n; ++k) t -= L[k * n + i] * inv[k * n + c];
-      inv[i * n + c] = t / L[i * n + i];
+    double inv = 1.0 / L[i * n + i];
+    for (int64_t j = 0; j <= i; ++j) wi[j] *= inv;
+  }
+  // A^{-1} = W^T W: accumulate the outer product of every row of W
+  std::fill(M.begin(), M.end(), 0.0);
+  for (int64_t k = 0; k < n; ++k) {
+    const double *wk = &W[k * n];
+    for (int64_t i = 0; i <= k; ++i) {
+      double a = wk[i];
+      double *mi = &M[i * n];
+      for (int64_t j = 0; j <= k; ++j) mi[j] += a * wk[j];
     }
   }
-  M.swap(inv);
 }
 
 void build_hierarchy(std::vector<Level> &levels, const SetupOptions &opt) {

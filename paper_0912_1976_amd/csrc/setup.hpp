@@ -37,7 +37,7 @@ struct SetupOptions {
   double theta = 0.01;
   double prolong_omega = 2.0 / 3.0;
   int max_levels = 10;
-  int64_t coarse_max = 256;
+  int64_t coarse_max = 2048;
 };
 
 struct Problem {

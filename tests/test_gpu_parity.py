@@ -32,12 +32,14 @@ RAGGED = dict(nx=23, ny=13, nz=6, H=1e-3, jitter=0.3, seed=7, bathymetry=True)
 
 
 def _build(cfg, mode, pc="vl_as", **kw):
+    # small coarsest level so that these meshes exercise several levels
+    kw.setdefault("coarse_max", 64)
     _dev()
     c = dict(cfg)
     m = box_mesh(c.pop("nx"), c.pop("ny"), c.pop("nz"), c.pop("H"), **c)
     _print("case", cfg, mode, pc)
     s = lib.Solver(m.xyz, m.tets, m.top, top_bc=mode, pc=pc, device=0, **kw)
-    o = osolver.setup(m, mode, coarse_max=kw.get("coarse_max", 256))
+    o = osolver.setup(m, mode, coarse_max=kw["coarse_max"])
     return m, s, o
 
 
@@ -157,7 +159,7 @@ def test_edge_cases():
 
 def test_graph_replay_equals_eager():
     m, s1, o = _build(RAGGED, "N", use_graphs=True)
-    s2 = lib.Solver(m.xyz, m.tets, m.top, device=0, use_graphs=False)
+    s2 = lib.Solver(m.xyz, m.tets, m.top, device=0, use_graphs=False, coarse_max=64)
     b = s1.rhs(fourier_field(m.xyz, RAGGED["H"], 8))
     for _ in range(3):
         xa, ia, _, _ = s1.solve(b, rtol=1e-9)
