@@ -69,6 +69,16 @@ typedef enum {
   VEMG_PC_NONE = 3
 } vemg_pc;
 
+/* Precision of the solve.
+ *   VEMG_FP64        everything in FP64.
+ *   VEMG_MIXED_IR    FP64 iterative refinement: outer residual r = b - A x in
+ *                    FP64; inner PCG (SpMV, transfers, smoothers, vectors) in
+ *                    FP32 with per-row scaled operators, its inner products
+ *                    accumulated in FP64, coarsest solves in FP64; x += d in FP64.
+ *   VEMG_MIXED_PC    FP64 CG (SpMV, vectors, inner products) whose
+ *                    preconditioner (transfers, smoothers, V-cycles) runs in FP32. */
+typedef enum { VEMG_FP64 = 0, VEMG_MIXED_IR = 1, VEMG_MIXED_PC = 2 } vemg_precision;
+
 typedef struct {
   int top_bc;          /* vemg_top_bc */
   int64_t pin_node;    /* pinned top node (natural index); -1: top node closest to the origin */
@@ -80,6 +90,9 @@ typedef struct {
   int poll_every;      /* PCG iterations per host poll of the convergence flag, 8 */
   int max_restarts;    /* restarts from the true residual, 5 */
   int use_graphs;      /* capture one PCG iteration in a hipGraph, 1 */
+  int precision;       /* vemg_precision, VEMG_FP64 */
+  double inner_rtol;   /* VEMG_MIXED_IR: relative tolerance of each inner FP32 solve, 1e-4 */
+  int max_outer;       /* VEMG_MIXED_IR: refinement steps, 30 */
 } vemg_options;
 
 typedef struct {
@@ -125,17 +138,23 @@ vemg_status vemg_rhs(vemg_solver s, const double *f_host, double *b_host);
 vemg_status vemg_matvec(vemg_solver s, const double *x_dev, double *y_dev);
 
 /* Solves A x = b for nrhs right-hand sides stored one after another
- * ([nrhs][n_nodes], device).  Stops when ||b - A x||_2 <= rtol ||b||_2 on
- * the true residual or after max_iter iterations (products with A).
+ * ([nrhs][n_nodes], device).  Right-hand sides are solved in batches of up
+ * to 8 that share every matrix read (SpMM-style launches); each column
+ * converges on its own.  Stops when ||b - A x||_2 <= rtol ||b||_2 on the
+ * FP64 true residual or after max_iter iterations (products with A; for
+ * VEMG_MIXED_IR the inner FP32 iterations summed over refinement steps).
  * iters and relres (host, length nrhs, may be NULL) receive the iteration
  * count and the final true relative residual of each right-hand side.
- * Returns VEMG_WARN_MAXITER / VEMG_WARN_FLOOR with the last iterate when
- * rtol was not reached, VEMG_ERR_BREAKDOWN on p.Ap <= 0 or NaN. */
+ * Returns the worst status: VEMG_WARN_MAXITER / VEMG_WARN_FLOOR with the
+ * last iterate when rtol was not reached, VEMG_ERR_BREAKDOWN on p.Ap <= 0 or
+ * NaN (that column only; the others are still solved). */
 vemg_status vemg_solve(vemg_solver s, int nrhs, const double *b_dev, double *x_dev, double rtol,
                        int max_iter, int *iters, double *relres);
 
 /* Operators of the hot path, for testing one step at a time.  Vectors are
- * device FP64 in the library's storage order (see vemg_export "perm"):
+ * device FP64 in the library's storage order (see vemg_export "perm"); with
+ * a mixed-precision handle the operator runs in FP32 (input rounded to FP32,
+ * output widened to FP64):
  *   VEMG_OP_A          out[n]  = A in[n]           (difference form)
  *   VEMG_OP_PRECOND    out[n]  = M^{-1} in[n]      (the handle's preconditioner)
  *   VEMG_OP_ET         out[m'] = E~^T in[n]
@@ -156,11 +175,12 @@ vemg_status vemg_apply(vemg_solver s, int op, const double *in_dev, double *out_
 
 /* Benchmark support: average device time in milliseconds of one
  * application of VEMG_OP_A (one SpMV launch) or VEMG_OP_GS_FWD (one forward
- * multicolour sweep over all rows, one launch per colour), measured with HIP
- * events on the handle's own stream around `reps` back-to-back applications
- * on internal buffers, after one untimed application.  *launches receives
- * the number of kernel launches per application (may be NULL). */
-vemg_status vemg_time_op(vemg_solver s, int op, int reps, double *avg_ms, int *launches);
+ * multicolour sweep over all rows, one launch per colour) to nrhs (1..8)
+ * columns, in the handle's inner precision (FP32 for VEMG_MIXED_IR, FP64
+ * otherwise), measured with HIP events on the handle's own stream around
+ * `reps` back-to-back applications on internal buffers, after one untimed
+ * application.  *launches receives the kernel launches per application. */
+vemg_status vemg_time_op(vemg_solver s, int op, int nrhs, int reps, double *avg_ms, int *launches);
 
 vemg_status vemg_get_info(vemg_solver s, vemg_info *info);
 

@@ -19,6 +19,7 @@ STATUS = {0: "ok", 1: "max_iter", 2: "floor", -1: "invalid_arg", -2: "mesh", -3:
 OP_A, OP_PRECOND, OP_ET, OP_E, OP_VCYCLE_S, OP_VCYCLE_ABAR, OP_GS_FWD = range(7)
 _PC = {"vl_as": 0, "vl_sor": 1, "jacobi": 2, "none": 3}
 _TOP = {"pinned": 0, "N": 0, "dirichlet": 1, "D": 1}
+_PREC = {"fp64": 0, "mixed": 1, "mixed_ir": 1, "mixed_pc": 2}
 
 
 class VemgError(RuntimeError):
@@ -31,7 +32,8 @@ class Options(C.Structure):
     _fields_ = [("top_bc", C.c_int), ("pin_node", C.c_int64), ("pc", C.c_int),
                 ("theta", C.c_double), ("prolong_omega", C.c_double), ("max_levels", C.c_int),
                 ("coarse_max", C.c_int64), ("poll_every", C.c_int), ("max_restarts", C.c_int),
-                ("use_graphs", C.c_int)]
+                ("use_graphs", C.c_int), ("precision", C.c_int), ("inner_rtol", C.c_double),
+                ("max_outer", C.c_int)]
 
 
 class Info(C.Structure):
@@ -66,7 +68,7 @@ def load_library():
     lib.vemg_solve.argtypes = [P, I32, P, P, D, I32, P, P]
     lib.vemg_apply.argtypes = [P, I32, P, P]
     lib.vemg_get_info.argtypes = [P, C.POINTER(Info)]
-    lib.vemg_time_op.argtypes = [P, I32, I32, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    lib.vemg_time_op.argtypes = [P, I32, I32, I32, C.POINTER(C.c_double), C.POINTER(C.c_int)]
     lib.vemg_export.argtypes = [P, C.c_char_p, P, C.POINTER(C.c_size_t)]
     lib.vemg_destroy.argtypes = [P]
     lib.vemg_status_string.argtypes = [I32]
@@ -91,7 +93,8 @@ class Solver:
     """
 
     def __init__(self, xyz, tets, top, *, top_bc="pinned", pc="vl_as", device=0, pin_node=-1,
-                 use_graphs=True, poll_every=8, coarse_max=2048, max_levels=10, max_restarts=5):
+                 use_graphs=True, poll_every=8, coarse_max=2048, max_levels=10, max_restarts=5,
+                 precision="fp64", inner_rtol=1e-4, max_outer=30):
         self._lib = load_library()
         opt = Options()
         self._lib.vemg_default_options(C.byref(opt))
@@ -103,6 +106,10 @@ class Solver:
         opt.coarse_max = coarse_max
         opt.max_levels = max_levels
         opt.max_restarts = max_restarts
+        opt.precision = _PREC[precision]
+        opt.inner_rtol = inner_rtol
+        opt.max_outer = max_outer
+        self.precision = precision
         self.device = device
         stream = None
         if device >= 0:
@@ -187,11 +194,11 @@ class Solver:
         st = self._check(self._lib.vemg_solve(self._h, nrhs, _ptr(b), _ptr(x), rtol, max_iter, its, rel), self._h)
         return x, list(its), list(rel), st
 
-    def time_op(self, op, reps=20):
+    def time_op(self, op, reps=20, nrhs=1):
         """(average ms per application, kernel launches per application)."""
         ms = C.c_double(0.0)
         nl = C.c_int(0)
-        self._check(self._lib.vemg_time_op(self._h, op, reps, C.byref(ms), C.byref(nl)), self._h)
+        self._check(self._lib.vemg_time_op(self._h, op, nrhs, reps, C.byref(ms), C.byref(nl)), self._h)
         return ms.value, nl.value
 
     def apply(self, op, v, out_len):

@@ -1,11 +1,13 @@
-// Solver handle: packs the host setup into SELL-64 arrays in HBM, runs the
-// preconditioned CG loop on the device, and exposes the C ABI of vemg.h.
+// Solver handle: packs the host setup into HBM (SELL-64 fine operator,
+// G-lanes-per-row CSR for coarse operators and transfers, FP64 and FP32
+// copies), runs the preconditioned CG loop on the device for batches of up to
+// eight right-hand sides, and exposes the C ABI of vemg.h.
 //
-// The PCG iteration is a fixed sequence of kernels whose scalars (alpha,
-// beta, the convergence flag) live in device memory, so one iteration can be
-// captured in a hipGraph and replayed; every kernel returns at once when the
-// convergence flag is set, so the host only polls the flag every few
-// iterations.
+// One PCG iteration is a fixed sequence of kernels whose scalars (alpha,
+// beta, per-column convergence flags) live in device memory, so it is
+// captured once per (precision, batch width) in a hipGraph and replayed;
+// every kernel returns at once when all columns have converged, so the host
+// only polls the flags every few iterations.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,6 +16,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/vemg.h"
@@ -32,8 +35,8 @@ struct DeviceError : std::runtime_error {
   do {                                                                                            \
     hipError_t e_ = (expr);                                                                       \
     if (e_ != hipSuccess)                                                                         \
-      throw ::vemg::DeviceError(e_ == hipErrorOutOfMemory ? VEMG_ERR_OOM : VEMG_ERR_DEVICE,               \
-                        std::string(#expr) + ": " + hipGetErrorString(e_));                       \
+      throw ::vemg::DeviceError(e_ == hipErrorOutOfMemory ? VEMG_ERR_OOM : VEMG_ERR_DEVICE,       \
+                                std::string(#expr) + ": " + hipGetErrorString(e_));               \
   } while (0)
 
 // device allocations owned by a handle
@@ -66,21 +69,21 @@ struct Arena {
   }
 };
 
-// CSR (host) -> SELL-64 (device).  For a square matrix the diagonal entries
-// are taken out of the stored entries: they become the per-row term `d`
-// (standard form), unless `d` is given (difference form: d = deficit).
+// CSR (host) -> SELL-64 (device).  Square: the diagonal entries are taken
+// out of the stored entries; the FP64 per-row term is `d` if given
+// (difference form: the deficit) else a_ii.  FP32 copy: a_ij / a_ii with
+// s32 = a_ii and dh32 = d / a_ii (square), or float(a_ij) (rectangular).
 Sell pack_sell(Arena &ar, hipStream_t st, const Csr &A, bool square, const std::vector<double> *d,
-               int64_t *stored = nullptr) {
+               const std::vector<double> *diag, int64_t *stored = nullptr) {
   int64_t n = A.nrows, ns = (n + kWave - 1) / kWave;
   std::vector<int64_t> sptr(ns + 1, 0);
-  auto offdiag_len = [&](int64_t r) {
+  std::vector<int64_t> len(n);
+  for (int64_t r = 0; r < n; ++r) {
     int64_t c = 0;
     for (int64_t k = A.ptr[r]; k < A.ptr[r + 1]; ++k)
       if (!(square && A.idx[k] == r)) ++c;
-    return c;
-  };
-  std::vector<int64_t> len(n);
-  for (int64_t r = 0; r < n; ++r) len[r] = offdiag_len(r);
+    len[r] = c;
+  }
   for (int64_t s = 0; s < ns; ++s) {
     int64_t L = 0;
     for (int64_t r = s * kWave; r < std::min(n, (s + 1) * kWave); ++r) L = std::max(L, len[r]);
@@ -88,7 +91,14 @@ Sell pack_sell(Arena &ar, hipStream_t st, const Csr &A, bool square, const std::
   }
   std::vector<int32_t> col(sptr[ns]);
   std::vector<double> val(sptr[ns], 0.0);
-  std::vector<double> dv(square ? n : 0, 0.0);
+  std::vector<float> val32(sptr[ns], 0.0f);
+  std::vector<double> dv(square ? n : 0, 0.0), ad(square ? n : 0, 0.0);
+  for (int64_t r = 0; square && r < n; ++r) {
+    if (diag) ad[r] = (*diag)[r];
+    for (int64_t e = A.ptr[r]; e < A.ptr[r + 1]; ++e)
+      if (A.idx[e] == r) ad[r] = A.val[e];
+    dv[r] = d ? (*d)[r] : ad[r];
+  }
   for (int64_t s = 0; s < ns; ++s) {
     int64_t L = (sptr[s + 1] - sptr[s]) / kWave;
     for (int t = 0; t < kWave; ++t) {
@@ -96,48 +106,60 @@ Sell pack_sell(Arena &ar, hipStream_t st, const Csr &A, bool square, const std::
       int64_t k = 0;
       if (r < n) {
         for (int64_t e = A.ptr[r]; e < A.ptr[r + 1]; ++e) {
-          if (square && A.idx[e] == r) {
-            if (!d) dv[r] = A.val[e];
-            continue;
-          }
-          col[sptr[s] + k * kWave + t] = A.idx[e];
-          val[sptr[s] + k * kWave + t] = A.val[e];
+          if (square && A.idx[e] == r) continue;
+          int64_t pos = sptr[s] + k * kWave + t;
+          col[pos] = A.idx[e];
+          val[pos] = A.val[e];
+          val32[pos] = square ? (float)(A.val[e] / ad[r]) : (float)A.val[e];
           ++k;
         }
       }
       for (; k < L; ++k) {
-        col[sptr[s] + k * kWave + t] = (square && r < n) ? (int32_t)r : 0;
-        val[sptr[s] + k * kWave + t] = 0.0;
+        int64_t pos = sptr[s] + k * kWave + t;
+        col[pos] = (square && r < n) ? (int32_t)r : 0;
+        val[pos] = 0.0;
+        val32[pos] = 0.0f;
       }
     }
   }
-  if (square && d) dv = *d;
   if (stored) *stored = sptr[ns];
   Sell M;
   M.nrows = n;
   M.sptr = ar.upload(sptr, st);
   M.col = ar.upload(col, st);
-  M.val = ar.upload(val, st);
-  if (square) M.d = ar.upload(dv, st);
+  M.val64 = ar.upload(val, st);
+  M.val32 = ar.upload(val32, st);
+  if (square) {
+    std::vector<float> s32(n), dh32(n);
+    for (int64_t r = 0; r < n; ++r) {
+      s32[r] = (float)ad[r];
+      dh32[r] = (float)(dv[r] / ad[r]);
+    }
+    M.d64 = ar.upload(dv, st);
+    M.s32 = ar.upload(s32, st);
+    M.dh32 = ar.upload(dh32, st);
+  }
   return M;
 }
 
-// CSR (host) -> CsrG (device).  Square matrices keep only off-diagonals and
-// move the diagonal into `d`.  G = smallest power of two >= half the mean
-// row length, clamped to [4, 64].
+// CSR (host) -> CsrG (device).  Square matrices keep only off-diagonals
+// (FP64 values with d64 = a_ii; FP32 values a_ij / a_ii with s32 = a_ii).
+// G = smallest power of two >= half the mean row length, clamped to [4, 64].
 CsrG pack_csrg(Arena &ar, hipStream_t st, const Csr &A, bool square, int64_t *stored = nullptr) {
   std::vector<int32_t> ptr(A.nrows + 1, 0), col;
   std::vector<double> val, d(square ? A.nrows : 0, 0.0);
+  std::vector<float> val32;
   col.reserve(A.nnz());
   val.reserve(A.nnz());
+  for (int64_t r = 0; r < A.nrows && square; ++r)
+    for (int64_t k = A.ptr[r]; k < A.ptr[r + 1]; ++k)
+      if (A.idx[k] == r) d[r] = A.val[k];
   for (int64_t r = 0; r < A.nrows; ++r) {
     for (int64_t k = A.ptr[r]; k < A.ptr[r + 1]; ++k) {
-      if (square && A.idx[k] == r) {
-        d[r] = A.val[k];
-        continue;
-      }
+      if (square && A.idx[k] == r) continue;
       col.push_back(A.idx[k]);
       val.push_back(A.val[k]);
+      val32.push_back(square ? (float)(A.val[k] / d[r]) : (float)A.val[k]);
     }
     ptr[r + 1] = (int32_t)col.size();
   }
@@ -150,10 +172,23 @@ CsrG pack_csrg(Arena &ar, hipStream_t st, const Csr &A, bool square, int64_t *st
   M.G = G;
   M.ptr = ar.upload(ptr, st);
   M.col = ar.upload(col, st);
-  M.val = ar.upload(val, st);
-  if (square) M.d = ar.upload(d, st);
+  M.val64 = ar.upload(val, st);
+  M.val32 = ar.upload(val32, st);
+  if (square) {
+    std::vector<float> s32(A.nrows);
+    for (int64_t r = 0; r < A.nrows; ++r) s32[r] = (float)d[r];
+    M.d64 = ar.upload(d, st);
+    M.s32 = ar.upload(s32, st);
+  }
   return M;
 }
+
+// per-precision work vectors, each [n][kMaxBatch]
+template <class T>
+struct Work {
+  T *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *res = nullptr,
+    *resA = nullptr, *tmp = nullptr;
+};
 
 struct DLevel {
   Sell As;                      // fine A_bar level: rows [row0, row0 + n) of the fine SELL matrix
@@ -163,9 +198,25 @@ struct DLevel {
   std::vector<int64_t> cstart;  // colour ranges, global row indices
   CsrG P, Pt;                   // prolongation (n x n_next) and restriction
   double *Cinv = nullptr;       // coarsest level only
-  double *x = nullptr, *g = nullptr, *r = nullptr;  // indexed by global row
   bool coarsest = false;
+  // vectors indexed by global row, [n][kMaxBatch], per precision
+  double *x64 = nullptr, *g64 = nullptr, *r64 = nullptr;
+  float *x32 = nullptr, *g32 = nullptr, *r32 = nullptr;
+  template <class T>
+  T *&x() {
+    if constexpr (std::is_same<T, double>::value) return x64; else return x32;
+  }
+  template <class T>
+  T *&g() {
+    if constexpr (std::is_same<T, double>::value) return g64; else return g32;
+  }
+  template <class T>
+  T *&r() {
+    if constexpr (std::is_same<T, double>::value) return r64; else return r32;
+  }
 };
+
+enum GraphKind { kGraphFP64 = 0, kGraphFP32 = 1, kGraphMixedPC = 2 };
 
 }  // namespace
 }  // namespace vemg
@@ -173,8 +224,8 @@ struct DLevel {
 struct vemg_solver_s {
   vemg_options opt;
   int device = -1;
-  hipStream_t user = nullptr, work = nullptr;
-  hipEvent_t ev = nullptr;
+  hipStream_t user = nullptr, work = nullptr, work2 = nullptr;  // work2: surface branch
+  hipEvent_t ev = nullptr, ev_fork = nullptr, ev_join = nullptr;
   std::string err;
   bool ready = false;
   vemg::Problem P;
@@ -183,20 +234,14 @@ struct vemg_solver_s {
   vemg::Sell E;
   vemg::CsrG Et;
   std::vector<vemg::DLevel> S, Ab;
-  hipStream_t work2 = nullptr;            // surface branch of the additive preconditioner
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *b = nullptr, *w = nullptr,
-         *res = nullptr, *resA = nullptr, *diag = nullptr, *tmp = nullptr, *nat = nullptr;
-  double *part_pq = nullptr, *part_rr = nullptr, *part_rz = nullptr, *part_b = nullptr, *part_t = nullptr,
-         *hist = nullptr, *dscal = nullptr;
+  vemg::Work<double> v64;
+  vemg::Work<float> v32;
+  double *b = nullptr, *diag = nullptr, *scale_in = nullptr, *scale_out = nullptr, *dscal = nullptr;
+  double *part_pq = nullptr, *part_rr = nullptr, *part_rz = nullptr, *part_b = nullptr, *part_t = nullptr;
   int64_t *perm = nullptr;
   vemg::Scal *scal = nullptr;
-  int64_t np_pq = 0, np_rr = 0, np_rz = 0, np_vec = 0;
   int64_t nnz_A = 0, nnz_E = 0;
-  std::vector<int64_t> s_nnz, ab_nnz, s_pnnz, ab_pnnz;
-  hipGraphExec_t graph = nullptr;
-  hipGraph_t graph_def = nullptr;
-  int max_hist = 0;
+  std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;  // key: kind * 16 + K
 };
 
 namespace vemg {
@@ -204,12 +249,14 @@ namespace {
 
 using Handle = vemg_solver_s;
 
-void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, bool is_abar,
-                  std::vector<int64_t> &nnz, std::vector<int64_t> &pnnz) {
+template <class T>
+Work<T> &work_of(Handle *h) {
+  if constexpr (std::is_same<T, double>::value) return h->v64; else return h->v32;
+}
+
+void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, bool is_abar) {
   hipStream_t st = h->work;
   D.clear();
-  nnz.clear();
-  pnnz.clear();
   for (size_t l = 0; l < H.size(); ++l) {
     Level &L = H[l];
     DLevel dl;
@@ -220,24 +267,26 @@ void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, bool
       dl.As = h->A;
       dl.row0 = h->P.n_top;
       dl.cstart = h->P.bar_colour_start;  // already global
-      dl.x = h->w;
-      dl.g = h->r;
-      dl.r = h->resA;
-      nnz.push_back(h->nnz_A);
+      dl.x64 = h->v64.w;
+      dl.g64 = h->v64.r;
+      dl.r64 = h->v64.resA;
+      dl.x32 = h->v32.w;
+      dl.g32 = h->v32.r;
+      dl.r32 = h->v32.resA;
     } else {
-      int64_t st_nnz = 0;
-      dl.Ac = pack_csrg(h->ar, st, L.A, true, &st_nnz);
-      nnz.push_back(st_nnz);
+      dl.Ac = pack_csrg(h->ar, st, L.A, true);
       dl.cstart = L.colour_start;
-      dl.x = h->ar.alloc<double>(dl.n);
-      dl.g = h->ar.alloc<double>(dl.n);
-      dl.r = h->ar.alloc<double>(dl.n);
+      size_t cnt = (size_t)dl.n * kMaxBatch;
+      dl.x64 = h->ar.alloc<double>(cnt);
+      dl.g64 = h->ar.alloc<double>(cnt);
+      dl.r64 = h->ar.alloc<double>(cnt);
+      dl.x32 = h->ar.alloc<float>(cnt);
+      dl.g32 = h->ar.alloc<float>(cnt);
+      dl.r32 = h->ar.alloc<float>(cnt);
     }
     if (!dl.coarsest) {
-      int64_t pn = 0;
-      dl.P = pack_csrg(h->ar, st, L.P, false, &pn);
+      dl.P = pack_csrg(h->ar, st, L.P, false);
       dl.Pt = pack_csrg(h->ar, st, transpose(L.P), false);
-      pnnz.push_back(pn);
     } else {
       dl.Cinv = h->ar.upload(L.Cinv, st);
     }
@@ -245,37 +294,42 @@ void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, bool
   }
 }
 
-void vcycle(hipStream_t st, std::vector<DLevel> &H, size_t l, const int *done) {
+template <class T>
+void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *done) {
   DLevel &L = H[l];
+  T *x = L.x<T>(), *g = L.g<T>(), *r = L.r<T>();
+  const int64_t o = L.row0 * K;
   if (L.coarsest) {
-    launch_dense(st, L.Cinv, L.n, L.g + L.row0, L.x + L.row0, done);
+    launch_dense<T>(st, K, L.Cinv, L.n, g + o, x + o, done);
     return;
   }
-  launch_fill(st, L.x + L.row0, L.n, 0.0, done);
+  launch_fill<T>(st, x + o, L.n * K, T(0), done);
   int nc = (int)L.cstart.size() - 1;
   auto gs = [&](int c) {
     if (L.fine)
-      launch_gs(st, L.As, true, L.cstart[c], L.cstart[c + 1], 0, 0, L.g, L.x, done);
+      launch_gs<T>(st, K, L.As, L.cstart[c], L.cstart[c + 1], 0, 0, g, x, done);
     else
-      launch_csr_gs(st, L.Ac, L.cstart[c], L.cstart[c + 1], L.g, L.x, done);
+      launch_csr_gs<T>(st, K, L.Ac, L.cstart[c], L.cstart[c + 1], g, x, done);
   };
   for (int c = 0; c < nc; ++c) gs(c);
   if (L.fine)
-    launch_spmv(st, L.As, true, 1, L.row0, L.row0 + L.n, L.x, L.g, L.r, nullptr, done);
+    launch_spmv<T>(st, K, L.As, 1, L.row0, L.row0 + L.n, x, g, r, nullptr, done);
   else
-    launch_csr_spmv(st, L.Ac, 1, 0, L.n, L.x, L.g, L.r, done);
+    launch_csr_spmv<T>(st, K, L.Ac, 1, 0, L.n, x, g, r, done);
   DLevel &C = H[l + 1];
-  launch_csr_rect(st, L.Pt, false, L.r + L.row0, C.g, done);
-  vcycle(st, H, l + 1, done);
-  launch_csr_rect(st, L.P, true, C.x, L.x + L.row0, done);
+  launch_csr_rect<T>(st, K, L.Pt, false, r + o, C.g<T>(), done);
+  vcycle<T>(st, K, H, l + 1, done);
+  launch_csr_rect<T>(st, K, L.P, true, C.x<T>(), x + o, done);
   for (int c = nc - 1; c >= 0; --c) gs(c);
 }
 
-// z = M^{-1} rr; partial sums of rr . z go to part_rz (count in np_rz)
-void precond(Handle *h, const double *rr, double *zz, const int *done) {
+// z = M^{-1} rr in precision T; partial sums of rr . z go to part (blocks in *np)
+template <class T>
+void precond(Handle *h, int K, const T *rr, T *zz, double *part, int64_t *np, const int *done) {
   hipStream_t st = h->work;
   const Problem &P = h->P;
   int64_t n = P.n, m = P.n_top;
+  Work<T> &v = work_of<T>(h);
   switch (h->opt.pc) {
     case VEMG_PC_VL_ADDITIVE: {
       // the two terms of the additive preconditioner are independent: the
@@ -283,24 +337,27 @@ void precond(Handle *h, const double *rr, double *zz, const int *done) {
       if (m > 0) {
         HIPCHK(hipEventRecord(h->ev_fork, st));
         HIPCHK(hipStreamWaitEvent(h->work2, h->ev_fork, 0));
-        launch_csr_rect(h->work2, h->Et, false, rr, h->S[0].g, done);
-        vcycle(h->work2, h->S, 0, done);
+        launch_csr_rect<T>(h->work2, K, h->Et, false, rr, h->S[0].g<T>(), done);
+        vcycle<T>(h->work2, K, h->S, 0, done);
         HIPCHK(hipEventRecord(h->ev_join, h->work2));
       }
-      h->Ab[0].g = const_cast<double *>(rr);
-      vcycle(st, h->Ab, 0, done);
-      h->Ab[0].g = h->r;
-      if (m > 0) HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
+      T *saved = h->Ab[0].g<T>();
+      h->Ab[0].g<T>() = const_cast<T *>(rr);
+      vcycle<T>(st, K, h->Ab, 0, done);
+      h->Ab[0].g<T>() = saved;
       if (m > 0) {
-        launch_prolong_sum(st, h->E, m, h->S[0].x, h->w, rr, zz, h->part_rz, done);
+        HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
+        launch_prolong_sum<T>(st, K, h->E, m, h->S[0].x<T>(), v.w, rr, zz, part, done);
+        *np = sell_blocks(0, n);
       } else {
-        launch_copy(st, h->w, zz, n, done);
-        launch_dot(st, rr, zz, n, h->part_rz, done);
+        launch_copy<T>(st, v.w, zz, n * K, done);
+        launch_dot<T>(st, K, rr, zz, n, part, done);
+        *np = vec_blocks(n);
       }
       break;
     }
     case VEMG_PC_VL_SOR: {
-      launch_fill(st, zz, n, 0.0, done);
+      launch_fill<T>(st, zz, n * K, T(0), done);
       int nct = (int)P.top_colour_start.size() - 1, ncb = (int)P.bar_colour_start.size() - 1;
       int nc = std::max(nct, ncb);
       auto sweep = [&](int c) {
@@ -313,46 +370,295 @@ void precond(Handle *h, const double *rr, double *zz, const int *done) {
           b0 = P.bar_colour_start[c];
           b1 = P.bar_colour_start[c + 1];
         }
-        launch_gs(st, h->A, true, a0, a1, b0, b1, rr, zz, done);
+        launch_gs<T>(st, K, h->A, a0, a1, b0, b1, rr, zz, done);
       };
       for (int c = 0; c < nc; ++c) sweep(c);
       if (m > 0) {
-        launch_spmv(st, h->A, true, 1, 0, n, zz, rr, h->res, nullptr, done);
-        launch_csr_rect(st, h->Et, false, h->res, h->S[0].g, done);
-        vcycle(st, h->S, 0, done);
-        launch_rect(st, h->E, true, h->S[0].x, zz, done);
+        launch_spmv<T>(st, K, h->A, 1, 0, n, zz, rr, v.res, nullptr, done);
+        launch_csr_rect<T>(st, K, h->Et, false, v.res, h->S[0].g<T>(), done);
+        vcycle<T>(st, K, h->S, 0, done);
+        launch_rect<T>(st, K, h->E, true, h->S[0].x<T>(), zz, done);
       }
       for (int c = nc - 1; c >= 0; --c) sweep(c);
-      launch_dot(st, rr, zz, n, h->part_rz, done);
+      launch_dot<T>(st, K, rr, zz, n, part, done);
+      *np = vec_blocks(n);
       break;
     }
     case VEMG_PC_JACOBI:
-      launch_jacobi(st, rr, h->diag, zz, n, done);
-      launch_dot(st, rr, zz, n, h->part_rz, done);
+      launch_jacobi<T>(st, K, rr, h->diag, zz, n, done);
+      launch_dot<T>(st, K, rr, zz, n, part, done);
+      *np = vec_blocks(n);
       break;
     default:
-      launch_copy(st, rr, zz, n, done);
-      launch_dot(st, rr, zz, n, h->part_rz, done);
+      launch_copy<T>(st, rr, zz, n * K, done);
+      launch_dot<T>(st, K, rr, zz, n, part, done);
+      *np = vec_blocks(n);
       break;
   }
 }
 
-int64_t rz_partials(Handle *h) {
-  if (h->opt.pc == VEMG_PC_VL_ADDITIVE && h->P.n_top > 0) return sell_blocks(0, h->P.n);
-  return vec_blocks(h->P.n);
+// FP64 CG with the preconditioner applied in FP32 (columns scaled by scale_in)
+int64_t precond_mixed(Handle *h, int K, const double *rr, double *zz, const int *done) {
+  hipStream_t st = h->work;
+  int64_t n = h->P.n, np = 0;
+  launch_demote(st, K, rr, h->scale_in, h->v32.tmp, n, done);
+  precond<float>(h, K, h->v32.tmp, h->v32.z, h->part_t, &np, done);
+  launch_promote(st, K, h->v32.z, h->scale_out, zz, n, false, done);
+  launch_dot<double>(st, K, rr, zz, n, h->part_rz, done);
+  return vec_blocks(n);
 }
 
-void pcg_iteration(Handle *h) {
+// one PCG iteration in precision T (kind FP64/FP32) or FP64 with an FP32
+// preconditioner (kind MixedPC)
+template <class T>
+void pcg_iteration(Handle *h, int K, int kind) {
   hipStream_t st = h->work;
   int64_t n = h->P.n;
-  const int *done = &h->scal->done;
-  launch_spmv(st, h->A, true, 0, 0, n, h->p, nullptr, h->q, h->part_pq, done);
-  launch_pcg_alpha(st, h->scal, h->part_pq, h->np_pq);
-  launch_pcg_xr(st, h->scal, h->x, h->r, h->p, h->q, n, h->part_rr);
-  launch_pcg_conv(st, h->scal, h->part_rr, h->np_vec, h->hist);
-  precond(h, h->r, h->z, done);
-  launch_pcg_beta(st, h->scal, h->part_rz, h->np_rz);
-  launch_pcg_p(st, h->scal, h->p, h->z, n);
+  Work<T> &v = work_of<T>(h);
+  const int *done = &h->scal->all_done;
+  launch_spmv<T>(st, K, h->A, 0, 0, n, v.p, (const T *)nullptr, v.q, h->part_pq, done);
+  launch_pcg_alpha(st, K, h->scal, h->part_pq, sell_blocks(0, n));
+  launch_pcg_xr<T>(st, K, h->scal, v.x, v.r, v.p, v.q, n, h->part_rr);
+  launch_pcg_conv(st, K, h->scal, h->part_rr, vec_blocks(n));
+  int64_t np = 0;
+  if (kind == kGraphMixedPC) {
+    if constexpr (std::is_same<T, double>::value) np = precond_mixed(h, K, v.r, v.z, done);
+  } else {
+    precond<T>(h, K, v.r, v.z, h->part_rz, &np, done);
+  }
+  launch_pcg_beta(st, K, h->scal, h->part_rz, np);
+  launch_pcg_p<T>(st, K, h->scal, v.p, v.z, n);
+}
+
+void destroy_graphs(Handle *h) {
+  for (auto &kv : h->graphs) {
+    if (kv.second.second) (void)hipGraphExecDestroy(kv.second.second);
+    if (kv.second.first) (void)hipGraphDestroy(kv.second.first);
+  }
+  h->graphs.clear();
+}
+
+template <class T>
+void run_iteration(Handle *h, int K, int kind) {
+  if (!h->opt.use_graphs) {
+    pcg_iteration<T>(h, K, kind);
+    return;
+  }
+  int key = kind * 16 + K;
+  auto it = h->graphs.find(key);
+  if (it == h->graphs.end()) {
+    HIPCHK(hipStreamBeginCapture(h->work, hipStreamCaptureModeThreadLocal));
+    pcg_iteration<T>(h, K, kind);
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamEndCapture(h->work, &g));
+    hipGraphExec_t ge = nullptr;
+    HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    it = h->graphs.emplace(key, std::make_pair(g, ge)).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second.second, h->work));
+}
+
+Scal read_scal(Handle *h) {
+  Scal hs;
+  HIPCHK(hipMemcpyAsync(&hs, h->scal, sizeof(Scal), hipMemcpyDeviceToHost, h->work));
+  HIPCHK(hipStreamSynchronize(h->work));
+  return hs;
+}
+
+// iterate until every column is done
+template <class T>
+Scal iterate(Handle *h, int K, int kind) {
+  int poll = std::max(1, h->opt.poll_every);
+  while (true) {
+    for (int k = 0; k < poll; ++k) run_iteration<T>(h, K, kind);
+    Scal hs = read_scal(h);
+    if (hs.all_done) return hs;
+  }
+}
+
+// FP64 true residual res = b - A x and its squared column norms (host)
+void true_residual(Handle *h, int K, double *rr_host) {
+  hipStream_t st = h->work;
+  int64_t n = h->P.n;
+  launch_spmv<double>(st, K, h->A, 1, 0, n, h->v64.x, h->b, h->v64.res, nullptr, nullptr);
+  launch_dot<double>(st, K, h->v64.res, h->v64.res, n, h->part_t, nullptr);
+  launch_reduce(st, K, h->part_t, vec_blocks(n), h->dscal);
+  HIPCHK(hipMemcpyAsync(rr_host, h->dscal, K * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+void upload_scales(Handle *h, int K, const double *in, const double *out) {
+  HIPCHK(hipMemcpyAsync(h->scale_in, in, K * sizeof(double), hipMemcpyHostToDevice, h->work));
+  HIPCHK(hipMemcpyAsync(h->scale_out, out, K * sizeof(double), hipMemcpyHostToDevice, h->work));
+  HIPCHK(hipStreamSynchronize(h->work));
+}
+
+struct ColResult {
+  int iters = 0;
+  double rel = 0.0;
+  int status = VEMG_OK;
+};
+
+// squared column norms of b (host)
+void rhs_norms(Handle *h, int K, double *bb) {
+  hipStream_t st = h->work;
+  int64_t n = h->P.n;
+  launch_dot<double>(st, K, h->b, h->b, n, h->part_b, nullptr);
+  launch_reduce(st, K, h->part_b, vec_blocks(n), h->dscal);
+  HIPCHK(hipMemcpyAsync(bb, h->dscal, K * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+// PCG (FP64, or FP64 with FP32 preconditioner) with restarts from the true
+// residual; h->b holds K columns (storage order), result in v64.x.
+void solve_cg(Handle *h, int K, double rtol, int max_iter, ColResult *res) {
+  hipStream_t st = h->work;
+  int64_t n = h->P.n;
+  Work<double> &v = h->v64;
+  bool mixed = h->opt.precision == VEMG_MIXED_PC;
+  int kind = mixed ? kGraphMixedPC : kGraphFP64;
+  double bb[kMaxBatch];
+  rhs_norms(h, K, bb);
+  if (mixed) {
+    double sin[kMaxBatch], sout[kMaxBatch];
+    for (int k = 0; k < K; ++k) {
+      double nb = std::sqrt(bb[k]);
+      sin[k] = (nb > 0.0 && std::isfinite(nb)) ? 1.0 / nb : 0.0;
+      sout[k] = (nb > 0.0 && std::isfinite(nb)) ? nb : 0.0;
+    }
+    upload_scales(h, K, sin, sout);
+  }
+  launch_fill<double>(st, v.x, n * K, 0.0, nullptr);
+  launch_copy<double>(st, h->b, v.r, n * K, nullptr);
+  launch_dot<double>(st, K, h->b, h->b, n, h->part_b, nullptr);
+  launch_pcg_init(st, K, h->scal, h->part_b, vec_blocks(n), rtol, max_iter);
+  double prev[kMaxBatch];
+  bool final_[kMaxBatch];
+  int restarts = 0;
+  for (int k = 0; k < K; ++k) {
+    prev[k] = INFINITY;
+    final_[k] = false;
+  }
+  while (true) {
+    int64_t np = 0;
+    if (mixed)
+      np = precond_mixed(h, K, v.r, v.z, nullptr);
+    else
+      precond<double>(h, K, v.r, v.z, h->part_rz, &np, nullptr);
+    launch_pcg_set_rho(st, K, h->scal, h->part_rz, np);
+    launch_copy<double>(st, v.z, v.p, n * K, nullptr);
+    Scal hs = iterate<double>(h, K, kind);
+    double rr[kMaxBatch];
+    true_residual(h, K, rr);
+    unsigned keep = 0;
+    bool any = false;
+    for (int k = 0; k < K; ++k) {
+      ColResult &c = res[k];
+      c.iters = hs.iters[k];
+      if (final_[k]) {
+        keep |= 1u << k;
+        continue;
+      }
+      if (bb[k] == 0.0) {
+        c.rel = 0.0;
+        c.status = VEMG_OK;
+      } else if (hs.status[k] == -6 || !std::isfinite(bb[k])) {
+        c.rel = NAN;
+        c.status = VEMG_ERR_BREAKDOWN;
+      } else {
+        c.rel = std::sqrt(rr[k] / bb[k]);
+        if (c.rel <= rtol) c.status = VEMG_OK;
+        else if (hs.iters[k] >= max_iter) c.status = VEMG_WARN_MAXITER;
+        else if (restarts >= h->opt.max_restarts || c.rel > 0.5 * prev[k]) c.status = VEMG_WARN_FLOOR;
+        else {
+          prev[k] = c.rel;
+          any = true;
+          continue;  // restart this column
+        }
+      }
+      final_[k] = true;
+      keep |= 1u << k;
+    }
+    if (!any) break;
+    ++restarts;
+    launch_copy<double>(st, v.res, v.r, n * K, nullptr);
+    launch_pcg_resume(st, K, h->scal, keep);
+  }
+}
+
+// FP64 iterative refinement with FP32 inner PCG; h->b holds K columns.
+void solve_ir(Handle *h, int K, double rtol, int max_iter, ColResult *res) {
+  hipStream_t st = h->work;
+  int64_t n = h->P.n;
+  double bb[kMaxBatch];
+  rhs_norms(h, K, bb);
+  launch_fill<double>(st, h->v64.x, n * K, 0.0, nullptr);
+  double prev[kMaxBatch];
+  bool fin[kMaxBatch];
+  for (int k = 0; k < K; ++k) {
+    prev[k] = INFINITY;
+    fin[k] = false;
+    res[k] = ColResult();
+  }
+  for (int outer = 0;; ++outer) {
+    double rr[kMaxBatch];
+    true_residual(h, K, rr);  // v64.res = b - A x
+    double sin[kMaxBatch], sout[kMaxBatch];
+    bool any = false;
+    for (int k = 0; k < K; ++k) {
+      sin[k] = sout[k] = 0.0;
+      ColResult &c = res[k];
+      if (fin[k]) continue;
+      if (bb[k] == 0.0) {
+        c.rel = 0.0;
+        c.status = VEMG_OK;
+        fin[k] = true;
+        continue;
+      }
+      if (!std::isfinite(bb[k]) || !std::isfinite(rr[k])) {
+        c.rel = NAN;
+        c.status = VEMG_ERR_BREAKDOWN;
+        fin[k] = true;
+        continue;
+      }
+      c.rel = std::sqrt(rr[k] / bb[k]);
+      if (c.rel <= rtol) {
+        c.status = VEMG_OK;
+        fin[k] = true;
+      } else if (c.iters >= max_iter) {
+        c.status = VEMG_WARN_MAXITER;
+        fin[k] = true;
+      } else if (outer >= h->opt.max_outer || (outer >= 2 && c.rel > 0.5 * prev[k])) {
+        c.status = VEMG_WARN_FLOOR;
+        fin[k] = true;
+      } else {
+        double nr = std::sqrt(rr[k]);
+        sin[k] = 1.0 / nr;
+        sout[k] = nr;
+        prev[k] = c.rel;
+        any = true;
+      }
+    }
+    if (!any) break;
+    upload_scales(h, K, sin, sout);
+    // inner FP32 solve of A d = r / ||r|| (finished columns get a zero rhs)
+    Work<float> &v = h->v32;
+    launch_demote(st, K, h->v64.res, h->scale_in, v.r, n, nullptr);
+    launch_fill<float>(st, v.x, n * K, 0.0f, nullptr);
+    launch_dot<float>(st, K, v.r, v.r, n, h->part_b, nullptr);
+    int inner_max = max_iter;
+    for (int k = 0; k < K; ++k)
+      if (!fin[k]) inner_max = std::min(inner_max, std::max(1, max_iter - res[k].iters));
+    launch_pcg_init(st, K, h->scal, h->part_b, vec_blocks(n), h->opt.inner_rtol, inner_max);
+    int64_t np = 0;
+    precond<float>(h, K, v.r, v.z, h->part_rz, &np, nullptr);
+    launch_pcg_set_rho(st, K, h->scal, h->part_rz, np);
+    launch_copy<float>(st, v.z, v.p, n * K, nullptr);
+    Scal hs = iterate<float>(h, K, kGraphFP32);
+    for (int k = 0; k < K; ++k)
+      if (!fin[k]) res[k].iters += hs.iters[k];
+    launch_promote(st, K, v.x, h->scale_out, h->v64.x, n, true, nullptr);
+  }
 }
 
 void upload(Handle *h) {
@@ -360,58 +666,55 @@ void upload(Handle *h) {
   Problem &P = h->P;
   int64_t n = P.n, m = P.n_top;
   h->ar.release();
-  h->A = pack_sell(h->ar, st, P.Aoff, true, &P.d, &h->nnz_A);
+  h->A = pack_sell(h->ar, st, P.Aoff, true, &P.d, &P.diag, &h->nnz_A);
   if (m > 0) {
-    h->E = pack_sell(h->ar, st, P.E, false, nullptr, &h->nnz_E);
+    h->E = pack_sell(h->ar, st, P.E, false, nullptr, nullptr, &h->nnz_E);
     h->Et = pack_csrg(h->ar, st, P.Et, false);
   }
-  h->x = h->ar.alloc<double>(n);
-  h->r = h->ar.alloc<double>(n);
-  h->z = h->ar.alloc<double>(n);
-  h->p = h->ar.alloc<double>(n);
-  h->q = h->ar.alloc<double>(n);
-  h->b = h->ar.alloc<double>(n);
-  h->w = h->ar.alloc<double>(n);
-  h->res = h->ar.alloc<double>(n);
-  h->resA = h->ar.alloc<double>(n);
-  h->tmp = h->ar.alloc<double>(n);
-  h->nat = h->ar.alloc<double>(P.n_nodes);
+  size_t cnt = (size_t)n * kMaxBatch;
+  auto mk64 = [&](Work<double> &v) {
+    v.x = h->ar.alloc<double>(cnt);
+    v.r = h->ar.alloc<double>(cnt);
+    v.z = h->ar.alloc<double>(cnt);
+    v.p = h->ar.alloc<double>(cnt);
+    v.q = h->ar.alloc<double>(cnt);
+    v.w = h->ar.alloc<double>(cnt);
+    v.res = h->ar.alloc<double>(cnt);
+    v.resA = h->ar.alloc<double>(cnt);
+    v.tmp = h->ar.alloc<double>(cnt);
+  };
+  auto mk32 = [&](Work<float> &v) {
+    v.x = h->ar.alloc<float>(cnt);
+    v.r = h->ar.alloc<float>(cnt);
+    v.z = h->ar.alloc<float>(cnt);
+    v.p = h->ar.alloc<float>(cnt);
+    v.q = h->ar.alloc<float>(cnt);
+    v.w = h->ar.alloc<float>(cnt);
+    v.res = h->ar.alloc<float>(cnt);
+    v.resA = h->ar.alloc<float>(cnt);
+    v.tmp = h->ar.alloc<float>(cnt);
+  };
+  mk64(h->v64);
+  mk32(h->v32);
+  h->b = h->ar.alloc<double>(cnt);
   h->diag = h->ar.upload(P.diag, st);
   h->perm = h->ar.upload(P.perm, st);
-  int64_t npmax = std::max(sell_blocks(0, n), vec_blocks(n)) + 8;
+  int64_t npmax = (std::max(sell_blocks(0, n), vec_blocks(n)) + 8) * kMaxBatch;
   h->part_pq = h->ar.alloc<double>(npmax);
   h->part_rr = h->ar.alloc<double>(npmax);
   h->part_rz = h->ar.alloc<double>(npmax);
   h->part_b = h->ar.alloc<double>(npmax);
   h->part_t = h->ar.alloc<double>(npmax);
-  h->dscal = h->ar.alloc<double>(8);
-  h->max_hist = 1 << 16;
-  h->hist = h->ar.alloc<double>(h->max_hist + 1);
+  h->dscal = h->ar.alloc<double>(kMaxBatch);
+  h->scale_in = h->ar.alloc<double>(kMaxBatch);
+  h->scale_out = h->ar.alloc<double>(kMaxBatch);
   h->scal = h->ar.alloc<Scal>(1);
-  launch_fill(st, h->w, n, 0.0, nullptr);  // the top block of w stays zero
-  if (m > 0) build_levels(h, P.S, h->S, false, h->s_nnz, h->s_pnnz);
-  build_levels(h, P.Abar, h->Ab, true, h->ab_nnz, h->ab_pnnz);
-  h->np_pq = sell_blocks(0, n);
-  h->np_vec = vec_blocks(n);
-  h->np_rz = rz_partials(h);
+  // the top block of the smoother vectors stays zero
+  launch_fill<double>(st, h->v64.w, (int64_t)cnt, 0.0, nullptr);
+  launch_fill<float>(st, h->v32.w, (int64_t)cnt, 0.0f, nullptr);
+  if (m > 0) build_levels(h, P.S, h->S, false);
+  build_levels(h, P.Abar, h->Ab, true);
   HIPCHK(hipStreamSynchronize(st));
-}
-
-void destroy_graph(Handle *h) {
-  if (h->graph) (void)hipGraphExecDestroy(h->graph);
-  if (h->graph_def) (void)hipGraphDestroy(h->graph_def);
-  h->graph = nullptr;
-  h->graph_def = nullptr;
-}
-
-void ensure_graph(Handle *h) {
-  if (h->graph || !h->opt.use_graphs) return;
-  HIPCHK(hipStreamBeginCapture(h->work, hipStreamCaptureModeThreadLocal));
-  pcg_iteration(h);
-  hipGraph_t g = nullptr;
-  HIPCHK(hipStreamEndCapture(h->work, &g));
-  h->graph_def = g;
-  HIPCHK(hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0));
 }
 
 void sync_in(Handle *h) {
@@ -419,90 +722,11 @@ void sync_in(Handle *h) {
   HIPCHK(hipStreamWaitEvent(h->work, h->ev, 0));
 }
 
-double true_residual(Handle *h) {
-  hipStream_t st = h->work;
-  int64_t n = h->P.n;
-  launch_spmv(st, h->A, true, 1, 0, n, h->x, h->b, h->res, nullptr, nullptr);
-  launch_dot(st, h->res, h->res, n, h->part_t, nullptr);
-  launch_reduce(st, h->part_t, vec_blocks(n), h->dscal);
-  double rr = 0.0;
-  HIPCHK(hipMemcpyAsync(&rr, h->dscal, sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  return rr;
-}
-
-// one right-hand side, storage-order vectors already in h->b
-int solve_one(Handle *h, double rtol, int max_iter, int *iters_out, double *relres_out) {
-  hipStream_t st = h->work;
-  int64_t n = h->P.n;
-  // ||b||
-  launch_dot(st, h->b, h->b, n, h->part_b, nullptr);
-  launch_pcg_init(st, h->scal, h->part_b, vec_blocks(n), rtol, max_iter);
-  Scal hs;
-  HIPCHK(hipMemcpyAsync(&hs, h->scal, sizeof(Scal), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  launch_fill(st, h->x, n, 0.0, nullptr);
-  if (hs.bnorm2 == 0.0) {
-    if (iters_out) *iters_out = 0;
-    if (relres_out) *relres_out = 0.0;
-    return VEMG_OK;
-  }
-  if (!std::isfinite(hs.bnorm2)) {
-    if (iters_out) *iters_out = 0;
-    if (relres_out) *relres_out = NAN;
-    return VEMG_ERR_BREAKDOWN;
-  }
-  double bnorm = std::sqrt(hs.bnorm2);
-  launch_copy(st, h->b, h->r, n, nullptr);
-  double prev = INFINITY;
-  int restarts = 0;
-  int status = VEMG_OK;
-  double rel = 1.0;
-  while (true) {
-    // (re)start: z = M r, rho = r.z, p = z
-    launch_pcg_resume(st, h->scal);
-    precond(h, h->r, h->z, nullptr);
-    launch_pcg_set_rho(st, h->scal, h->part_rz, h->np_rz);
-    launch_copy(st, h->z, h->p, n, nullptr);
-    ensure_graph(h);
-    int poll = std::max(1, h->opt.poll_every);
-    while (true) {
-      for (int k = 0; k < poll; ++k) {
-        if (h->graph)
-          HIPCHK(hipGraphLaunch(h->graph, st));
-        else
-          pcg_iteration(h);
-      }
-      HIPCHK(hipMemcpyAsync(&hs, h->scal, sizeof(Scal), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      if (hs.done) break;
-    }
-    if (hs.status == -6) {
-      status = VEMG_ERR_BREAKDOWN;
-      rel = NAN;
-      break;
-    }
-    double rr = true_residual(h);
-    rel = std::sqrt(rr) / bnorm;
-    if (rel <= rtol) {
-      status = VEMG_OK;
-      break;
-    }
-    if (hs.iters >= max_iter) {
-      status = VEMG_WARN_MAXITER;
-      break;
-    }
-    if (restarts >= h->opt.max_restarts || rel > 0.5 * prev) {
-      status = VEMG_WARN_FLOOR;
-      break;
-    }
-    prev = rel;
-    ++restarts;
-    launch_copy(st, h->res, h->r, n, nullptr);
-  }
-  if (iters_out) *iters_out = hs.iters;
-  if (relres_out) *relres_out = rel;
-  return status;
+int batch_width(int m) {
+  if (m >= 8) return 8;
+  if (m >= 4) return 4;
+  if (m >= 2) return 2;
+  return 1;
 }
 
 int do_solve(Handle *h, int nrhs, const double *b_nat, double *x_nat, double rtol, int max_iter, int *iters,
@@ -511,58 +735,72 @@ int do_solve(Handle *h, int nrhs, const double *b_nat, double *x_nat, double rto
   int64_t n = h->P.n, N = h->P.n_nodes;
   sync_in(h);
   int worst = VEMG_OK;
-  for (int k = 0; k < nrhs; ++k) {
-    launch_gather(st, b_nat + (int64_t)k * N, h->perm, h->b, n);
-    int it = 0;
-    double rl = 0.0;
-    int s = solve_one(h, rtol, max_iter, &it, &rl);
-    launch_fill(st, x_nat + (int64_t)k * N, N, 0.0, nullptr);
-    launch_scatter(st, h->x, h->perm, x_nat + (int64_t)k * N, n);
-    if (iters) iters[k] = it;
-    if (relres) relres[k] = rl;
-    if (s < 0 || (worst >= 0 && s > worst)) worst = s;
+  for (int first = 0; first < nrhs;) {
+    int m = nrhs - first;
+    int K = batch_width(m);
+    if (m > 4 && m < 8) K = 8;  // pad small remainders up rather than splitting
+    else if (m == 3) K = 4;
+    int cols = std::min(K, m);
+    if (cols < K) launch_fill<double>(st, h->b, n * K, 0.0, nullptr);
+    for (int k = 0; k < cols; ++k) launch_gather(st, K, k, b_nat + (int64_t)(first + k) * N, h->perm, h->b, n);
+    ColResult res[kMaxBatch];
+    if (h->opt.precision == VEMG_MIXED_IR)
+      solve_ir(h, K, rtol, max_iter, res);
+    else
+      solve_cg(h, K, rtol, max_iter, res);
+    for (int k = 0; k < cols; ++k) {
+      double *xk = x_nat + (int64_t)(first + k) * N;
+      launch_fill<double>(st, xk, N, 0.0, nullptr);
+      launch_scatter(st, K, k, h->v64.x, h->perm, xk, n);
+      if (iters) iters[first + k] = res[k].iters;
+      if (relres) relres[first + k] = res[k].rel;
+      int s = res[k].status;
+      if (s < 0 || (worst >= 0 && s > worst)) worst = s;
+    }
+    first += cols;
   }
   HIPCHK(hipStreamSynchronize(st));
   return worst;
 }
 
-int do_apply(Handle *h, int op, const double *in, double *out) {
+template <class T>
+void apply_op(Handle *h, int op, const T *in, T *out) {
   hipStream_t st = h->work;
   const Problem &P = h->P;
   int64_t n = P.n, m = P.n_top;
-  sync_in(h);
+  Work<T> &v = work_of<T>(h);
   switch (op) {
     case VEMG_OP_A:
-      launch_spmv(st, h->A, true, 0, 0, n, in, nullptr, out, nullptr, nullptr);
+      launch_spmv<T>(st, 1, h->A, 0, 0, n, in, (const T *)nullptr, out, nullptr, nullptr);
       break;
-    case VEMG_OP_PRECOND:
-      HIPCHK(hipMemsetAsync(h->scal, 0, sizeof(Scal), st));
-      launch_copy(st, in, h->tmp, n, nullptr);
-      precond(h, h->tmp, out, nullptr);
+    case VEMG_OP_PRECOND: {
+      launch_copy<T>(st, in, v.tmp, n, nullptr);
+      int64_t np = 0;
+      precond<T>(h, 1, v.tmp, out, h->part_t, &np, nullptr);
       break;
+    }
     case VEMG_OP_ET:
-      if (m == 0) return VEMG_ERR_STATE;
-      launch_csr_rect(st, h->Et, false, in, out, nullptr);
+      launch_csr_rect<T>(st, 1, h->Et, false, in, out, nullptr);
       break;
     case VEMG_OP_E:
-      if (m == 0) return VEMG_ERR_STATE;
-      launch_rect(st, h->E, false, in, out, nullptr);
+      launch_rect<T>(st, 1, h->E, false, in, out, nullptr);
       break;
     case VEMG_OP_VCYCLE_S:
-      if (m == 0) return VEMG_ERR_STATE;
-      launch_copy(st, in, h->S[0].g, m, nullptr);
-      vcycle(st, h->S, 0, nullptr);
-      launch_copy(st, h->S[0].x, out, m, nullptr);
+      launch_copy<T>(st, in, h->S[0].g<T>(), m, nullptr);
+      vcycle<T>(st, 1, h->S, 0, nullptr);
+      launch_copy<T>(st, h->S[0].x<T>(), out, m, nullptr);
       break;
-    case VEMG_OP_VCYCLE_ABAR:
-      launch_copy(st, in, h->tmp + m, n - m, nullptr);
-      h->Ab[0].g = h->tmp;
-      vcycle(st, h->Ab, 0, nullptr);
-      h->Ab[0].g = h->r;
-      launch_copy(st, h->w + m, out, n - m, nullptr);
+    case VEMG_OP_VCYCLE_ABAR: {
+      launch_copy<T>(st, in, v.tmp + m, n - m, nullptr);
+      T *saved = h->Ab[0].g<T>();
+      h->Ab[0].g<T>() = v.tmp;
+      vcycle<T>(st, 1, h->Ab, 0, nullptr);
+      h->Ab[0].g<T>() = saved;
+      launch_copy<T>(st, v.w + m, out, n - m, nullptr);
       break;
+    }
     case VEMG_OP_GS_FWD: {
-      launch_fill(st, out, n, 0.0, nullptr);
+      launch_fill<T>(st, out, n, T(0), nullptr);
       int nct = (int)P.top_colour_start.size() - 1, ncb = (int)P.bar_colour_start.size() - 1;
       for (int c = 0; c < std::max(nct, ncb); ++c) {
         int64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
@@ -574,46 +812,84 @@ int do_apply(Handle *h, int op, const double *in, double *out) {
           b0 = P.bar_colour_start[c];
           b1 = P.bar_colour_start[c + 1];
         }
-        launch_gs(st, h->A, true, a0, a1, b0, b1, in, out, nullptr);
+        launch_gs<T>(st, 1, h->A, a0, a1, b0, b1, in, out, nullptr);
       }
       break;
     }
-    default:
-      return VEMG_ERR_INVALID_ARG;
+  }
+}
+
+int do_apply(Handle *h, int op, const double *in, double *out) {
+  hipStream_t st = h->work;
+  const Problem &P = h->P;
+  int64_t n = P.n, m = P.n_top;
+  if (op < VEMG_OP_A || op > VEMG_OP_GS_FWD) return VEMG_ERR_INVALID_ARG;
+  if ((op == VEMG_OP_ET || op == VEMG_OP_E || op == VEMG_OP_VCYCLE_S) && m == 0) return VEMG_ERR_STATE;
+  int64_t nin = (op == VEMG_OP_E || op == VEMG_OP_VCYCLE_S) ? m : (op == VEMG_OP_VCYCLE_ABAR ? n - m : n);
+  int64_t nout = (op == VEMG_OP_ET || op == VEMG_OP_VCYCLE_S) ? m : (op == VEMG_OP_VCYCLE_ABAR ? n - m : n);
+  sync_in(h);
+  HIPCHK(hipMemsetAsync(h->scal, 0, sizeof(Scal), st));
+  if (h->opt.precision == VEMG_FP64) {
+    apply_op<double>(h, op, in, out);
+  } else {
+    double one = 1.0, ones[kMaxBatch];
+    for (double &o : ones) o = one;
+    upload_scales(h, 1, ones, ones);
+    float *in32 = h->v32.res, *out32 = h->v32.q;
+    launch_demote(st, 1, in, h->scale_in, in32, nin, nullptr);
+    apply_op<float>(h, op, in32, out32);
+    launch_promote(st, 1, out32, h->scale_out, out, nout, false, nullptr);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   return VEMG_OK;
 }
 
-int do_time(Handle *h, int op, int reps, double *avg_ms, int *launches) {
+template <class T>
+void time_once(Handle *h, int op, int K) {
   hipStream_t st = h->work;
   const Problem &P = h->P;
   int64_t n = P.n;
+  Work<T> &v = work_of<T>(h);
+  if (op == VEMG_OP_A) {
+    launch_spmv<T>(st, K, h->A, 0, 0, n, v.p, (const T *)nullptr, v.q, h->part_pq, nullptr);
+    return;
+  }
   int nct = (int)P.top_colour_start.size() - 1, ncb = (int)P.bar_colour_start.size() - 1;
-  int nc = std::max(nct, ncb);
-  launch_fill(st, h->p, n, 1.0, nullptr);
-  launch_fill(st, h->r, n, 1.0, nullptr);
-  auto once = [&]() {
-    if (op == VEMG_OP_A) {
-      launch_spmv(st, h->A, true, 0, 0, n, h->p, nullptr, h->q, h->part_pq, nullptr);
-    } else {
-      for (int c = 0; c < nc; ++c) {
-        int64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-        if (c < nct) {
-          a0 = P.top_colour_start[c];
-          a1 = P.top_colour_start[c + 1];
-        }
-        if (c < ncb) {
-          b0 = P.bar_colour_start[c];
-          b1 = P.bar_colour_start[c + 1];
-        }
-        launch_gs(st, h->A, true, a0, a1, b0, b1, h->r, h->z, nullptr);
-      }
+  for (int c = 0; c < std::max(nct, ncb); ++c) {
+    int64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    if (c < nct) {
+      a0 = P.top_colour_start[c];
+      a1 = P.top_colour_start[c + 1];
     }
-  };
+    if (c < ncb) {
+      b0 = P.bar_colour_start[c];
+      b1 = P.bar_colour_start[c + 1];
+    }
+    launch_gs<T>(st, K, h->A, a0, a1, b0, b1, v.r, v.z, nullptr);
+  }
+}
+
+int do_time(Handle *h, int op, int K, int reps, double *avg_ms, int *launches) {
+  hipStream_t st = h->work;
+  const Problem &P = h->P;
+  int64_t n = P.n;
   if (op != VEMG_OP_A && op != VEMG_OP_GS_FWD) return VEMG_ERR_INVALID_ARG;
-  launch_fill(st, h->z, n, 0.0, nullptr);
+  if (K != 1 && K != 2 && K != 4 && K != 8) return VEMG_ERR_INVALID_ARG;
+  int nc = std::max((int)P.top_colour_start.size() - 1, (int)P.bar_colour_start.size() - 1);
+  bool f32 = h->opt.precision == VEMG_MIXED_IR;
+  if (f32) {
+    launch_fill<float>(st, h->v32.p, n * K, 1.0f, nullptr);
+    launch_fill<float>(st, h->v32.r, n * K, 1.0f, nullptr);
+    launch_fill<float>(st, h->v32.z, n * K, 0.0f, nullptr);
+  } else {
+    launch_fill<double>(st, h->v64.p, n * K, 1.0, nullptr);
+    launch_fill<double>(st, h->v64.r, n * K, 1.0, nullptr);
+    launch_fill<double>(st, h->v64.z, n * K, 0.0, nullptr);
+  }
+  auto once = [&]() {
+    if (f32) time_once<float>(h, op, K); else time_once<double>(h, op, K);
+  };
   once();
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -724,6 +1000,9 @@ void vemg_default_options(vemg_options *o) {
   o->poll_every = 8;
   o->max_restarts = 5;
   o->use_graphs = 1;
+  o->precision = VEMG_FP64;
+  o->inner_rtol = 1e-4;
+  o->max_outer = 30;
 }
 
 vemg_status vemg_create(const vemg_options *o, int device, void *hip_stream, vemg_solver *out) {
@@ -735,7 +1014,8 @@ vemg_status vemg_create(const vemg_options *o, int device, void *hip_stream, vem
   else
     vemg_default_options(&opt);
   if (opt.top_bc < 0 || opt.top_bc > 1 || opt.pc < 0 || opt.pc > 3 || opt.max_levels < 1 || opt.max_levels > 16 ||
-      opt.coarse_max < 1 || opt.coarse_max > 8192 || !(opt.theta >= 0.0) || opt.poll_every < 1)
+      opt.coarse_max < 1 || opt.coarse_max > 8192 || !(opt.theta >= 0.0) || opt.poll_every < 1 ||
+      opt.precision < 0 || opt.precision > 2 || !(opt.inner_rtol > 0.0 && opt.inner_rtol < 1.0) || opt.max_outer < 1)
     return VEMG_ERR_INVALID_ARG;
   auto *h = new (std::nothrow) vemg_solver_s();
   if (!h) return VEMG_ERR_OOM;
@@ -765,7 +1045,7 @@ vemg_status vemg_setup(vemg_solver s, int64_t n_nodes, const double *xyz, int64_
   if (!s) return VEMG_ERR_INVALID_ARG;
   return (vemg_status)guarded(s, [&]() -> int {
     s->ready = false;
-    vemg::destroy_graph(s);
+    vemg::destroy_graphs(s);
     s->ar.release();
     vemg::SetupOptions so;
     so.top_dirichlet = s->opt.top_bc;
@@ -799,10 +1079,10 @@ vemg_status vemg_matvec(vemg_solver s, const double *x_dev, double *y_dev) {
     hipStream_t st = s->work;
     int64_t n = s->P.n;
     vemg::sync_in(s);
-    vemg::launch_gather(st, x_dev, s->perm, s->tmp, n);
-    vemg::launch_spmv(st, s->A, true, 0, 0, n, s->tmp, nullptr, s->res, nullptr, nullptr);
-    vemg::launch_fill(st, y_dev, s->P.n_nodes, 0.0, nullptr);
-    vemg::launch_scatter(st, s->res, s->perm, y_dev, n);
+    vemg::launch_gather(st, 1, 0, x_dev, s->perm, s->v64.tmp, n);
+    vemg::launch_spmv<double>(st, 1, s->A, 0, 0, n, s->v64.tmp, nullptr, s->v64.res, nullptr, nullptr);
+    vemg::launch_fill<double>(st, y_dev, s->P.n_nodes, 0.0, nullptr);
+    vemg::launch_scatter(st, 1, 0, s->v64.res, s->perm, y_dev, n);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     return VEMG_OK;
@@ -813,7 +1093,6 @@ vemg_status vemg_solve(vemg_solver s, int nrhs, const double *b_dev, double *x_d
                        int *iters, double *relres) {
   if (!s || !b_dev || !x_dev || nrhs < 1 || !(rtol >= 0.0) || max_iter < 1) return VEMG_ERR_INVALID_ARG;
   if (!s->ready || s->device < 0) return VEMG_ERR_STATE;
-  if (max_iter > s->max_hist) max_iter = s->max_hist;
   return (vemg_status)guarded(s, [&]() -> int { return vemg::do_solve(s, nrhs, b_dev, x_dev, rtol, max_iter, iters, relres); });
 }
 
@@ -823,10 +1102,10 @@ vemg_status vemg_apply(vemg_solver s, int op, const double *in_dev, double *out_
   return (vemg_status)guarded(s, [&]() -> int { return vemg::do_apply(s, op, in_dev, out_dev); });
 }
 
-vemg_status vemg_time_op(vemg_solver s, int op, int reps, double *avg_ms, int *launches) {
+vemg_status vemg_time_op(vemg_solver s, int op, int nrhs, int reps, double *avg_ms, int *launches) {
   if (!s || !avg_ms || reps < 1) return VEMG_ERR_INVALID_ARG;
   if (!s->ready || s->device < 0) return VEMG_ERR_STATE;
-  return (vemg_status)guarded(s, [&]() -> int { return vemg::do_time(s, op, reps, avg_ms, launches); });
+  return (vemg_status)guarded(s, [&]() -> int { return vemg::do_time(s, op, nrhs, reps, avg_ms, launches); });
 }
 
 vemg_status vemg_get_info(vemg_solver s, vemg_info *info) {
@@ -869,9 +1148,9 @@ vemg_status vemg_destroy(vemg_solver s) {
   if (s->device >= 0) {
     (void)hipSetDevice(s->device);
     if (s->work) (void)hipStreamSynchronize(s->work);
-    vemg::destroy_graph(s);
-    s->ar.release();
     if (s->work2) (void)hipStreamSynchronize(s->work2);
+    vemg::destroy_graphs(s);
+    s->ar.release();
     if (s->ev) (void)hipEventDestroy(s->ev);
     if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
     if (s->ev_join) (void)hipEventDestroy(s->ev_join);

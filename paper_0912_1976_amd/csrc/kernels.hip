@@ -1,12 +1,16 @@
 // HIP kernels of the PCG hot path for gfx950 (CDNA4, wave64).
 //
 // The path is sparse and bandwidth-bound, so there is no MFMA here: every
-// kernel streams its matrix once with coalesced SELL-64 loads, gathers the
-// vector entries it needs through L2 / the Infinity Cache, and keeps
+// kernel streams its matrix once with coalesced loads (SELL-64 for the fine
+// operator, G-lanes-per-row CSR for coarse operators and transfers), reads
+// each matrix entry once for all K right-hand sides of a batch, gathers the
+// vector rows it needs through L2 / the Infinity Cache, and keeps
 // reductions deterministic (per-block partials summed in index order by a
 // single-block consumer).  Blocks are renumbered so that each of the eight
 // XCDs works on a contiguous range of rows, which keeps the gathered vector
 // lines in that XCD's L2.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace vemg {
@@ -19,149 +23,139 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
   return (x < rem) ? x * (q + 1) + i : rem * (q + 1) + (x - rem) * q + i;
 }
 
+template <class T, int K>
+struct alignas(sizeof(T) * K) Row {
+  T v[K];
+};
+
+template <class T, int K>
+__device__ __forceinline__ Row<T, K> ld(const T *__restrict__ p, int64_t r) {
+  return *reinterpret_cast<const Row<T, K> *>(p + r * K);
+}
+template <class T, int K>
+__device__ __forceinline__ void st(T *__restrict__ p, int64_t r, const Row<T, K> &v) {
+  *reinterpret_cast<Row<T, K> *>(p + r * K) = v;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-// Sum over a 256-thread block in a fixed order; result valid in thread 0.
-__device__ __forceinline__ double block_sum(double v) {
-  __shared__ double red[kSlicesPerBlock];
-  v = wave_sum(v);
-  int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) red[w] = v;
+// Sums v[0..K) over a 256-thread block in a fixed order and writes the K
+// results to out[0..K) (thread 0).  Every thread of the block must call it.
+template <int K>
+__device__ __forceinline__ void block_sum_store(const double (&v)[K], double *out) {
+  __shared__ double red[kSlicesPerBlock][kMaxBatch];
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double t = wave_sum(v[k]);
+    if ((threadIdx.x & 63) == 0) red[w][k] = t;
+  }
   __syncthreads();
-  double t = 0.0;
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < kSlicesPerBlock; ++k) t += red[k];
+    for (int k = 0; k < K; ++k) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < kSlicesPerBlock; ++q) t += red[q][k];
+      out[k] = t;
+    }
   }
-  return t;
 }
 
-template <bool DIFF>
-__device__ __forceinline__ void row_terms(const Sell &A, int64_t s, int lane, int64_t r, const double *__restrict__ x,
-                                          double xr, double &acc, double &offsum) {
+template <class T>
+__device__ __forceinline__ const T *sell_vals(const Sell &A);
+template <>
+__device__ __forceinline__ const double *sell_vals<double>(const Sell &A) {
+  return A.val64;
+}
+template <>
+__device__ __forceinline__ const float *sell_vals<float>(const Sell &A) {
+  return A.val32;
+}
+template <class T>
+__device__ __forceinline__ const T *csr_vals(const CsrG &A);
+template <>
+__device__ __forceinline__ const double *csr_vals<double>(const CsrG &A) {
+  return A.val64;
+}
+template <>
+__device__ __forceinline__ const float *csr_vals<float>(const CsrG &A) {
+  return A.val32;
+}
+
+// Off-diagonal terms of one SELL row for K columns: acc = sum_j v_j (x_j - x_r)
+// (DIFF) or sum_j v_j x_j, and off = sum_j v_j.
+template <class T, int K, bool DIFF>
+__device__ __forceinline__ void sell_row(const Sell &A, int64_t s, int lane, const T *__restrict__ x,
+                                         const Row<T, K> &xr, T (&acc)[K], T &off) {
   const int64_t base = A.sptr[s];
   const int len = (int)((A.sptr[s + 1] - base) >> 6);
   const int32_t *__restrict__ cp = A.col + base + lane;
-  const double *__restrict__ vp = A.val + base + lane;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0;
-  int k = 0;
-  // four independent entries in flight per lane
-  for (; k + 3 < len; k += 4) {
-    const int32_t c0 = cp[(int64_t)k * 64], c1 = cp[(int64_t)(k + 1) * 64];
-    const int32_t c2 = cp[(int64_t)(k + 2) * 64], c3 = cp[(int64_t)(k + 3) * 64];
-    const double v0 = vp[(int64_t)k * 64], v1 = vp[(int64_t)(k + 1) * 64];
-    const double v2 = vp[(int64_t)(k + 2) * 64], v3 = vp[(int64_t)(k + 3) * 64];
-    const double x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
-    if (DIFF) {
-      a0 += v0 * (x0 - xr);
-      a1 += v1 * (x1 - xr);
-      a2 += v2 * (x2 - xr);
-      a3 += v3 * (x3 - xr);
-    } else {
-      a0 += v0 * x0;
-      a1 += v1 * x1;
-      a2 += v2 * x2;
-      a3 += v3 * x3;
-    }
-    o0 += v0;
-    o1 += v1;
-    o2 += v2;
-    o3 += v3;
-  }
-  for (; k < len; ++k) {
-    const int32_t c0 = cp[(int64_t)k * 64];
-    const double v0 = vp[(int64_t)k * 64];
-    a0 += DIFF ? v0 * (x[c0] - xr) : v0 * x[c0];
-    o0 += v0;
-  }
-  acc = (a0 + a1) + (a2 + a3);
-  offsum = (o0 + o1) + (o2 + o3);
-}
-
-// Sum of a row of a CsrG matrix by its group of G lanes (result in every lane
-// of the group).
-template <int G>
-__device__ __forceinline__ double group_row(const CsrG &A, int64_t r, int gl, const double *__restrict__ x) {
-  const int32_t b = A.ptr[r], e = A.ptr[r + 1];
-  double a0 = 0.0, a1 = 0.0;
-  int k = b + gl;
-  for (; k + G < e; k += 2 * G) {
-    a0 += A.val[k] * x[A.col[k]];
-    a1 += A.val[k + G] * x[A.col[k + G]];
-  }
-  if (k < e) a0 += A.val[k] * x[A.col[k]];
-  double t = a0 + a1;
+  const T *__restrict__ vp = sell_vals<T>(A) + base + lane;
 #pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, G);
-  return t;
-}
-
-template <int G, int MODE>
-__global__ __launch_bounds__(kBlock) void k_csr_spmv(CsrG A, int64_t r0, int64_t r1, const double *__restrict__ x,
-                                                     const double *__restrict__ g, double *__restrict__ y,
-                                                     const int *__restrict__ done) {
-  if (done && *done) return;
-  const int gl = threadIdx.x & (G - 1);
-  const int64_t r = r0 + ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
-  if (r >= r1) return;
-  const double t = group_row<G>(A, r, gl, x);
-  if (gl == 0) {
-    // MODE 0/1: square standard form; 2/3: rectangular, 3 accumulates
-    if (MODE == 0) y[r] = t + A.d[r] * x[r];
-    else if (MODE == 1) y[r] = g[r] - (t + A.d[r] * x[r]);
-    else if (MODE == 2) y[r] = t;
-    else y[r] += t;
+  for (int k = 0; k < K; ++k) acc[k] = T(0);
+  off = T(0);
+#pragma unroll 4
+  for (int e = 0; e < len; ++e) {
+    const int32_t c = cp[(int64_t)e * 64];
+    const T v = vp[(int64_t)e * 64];
+    const Row<T, K> xc = ld<T, K>(x, c);
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += DIFF ? v * (xc.v[k] - xr.v[k]) : v * xc.v[k];
+    off += v;
   }
 }
 
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_csr_gs(CsrG A, int64_t r0, int64_t r1, const double *__restrict__ g,
-                                                   double *__restrict__ x, const int *__restrict__ done) {
-  if (done && *done) return;
-  const int gl = threadIdx.x & (G - 1);
-  const int64_t r = r0 + ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
-  if (r >= r1) return;
-  const double t = group_row<G>(A, r, gl, x);  // off-diagonal part only
-  if (gl == 0) {
-    const double dr = A.d[r];
-    x[r] = (g[r] - t) / dr;
-  }
-}
-
-template <bool DIFF, int MODE, bool DOT>
+// ------------------------------------------------------------- fine matrix
+template <class T, int K, int MODE, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmv(Sell A, int64_t r0, int64_t r1, int64_t s_first, int64_t nb,
-                                                 const double *__restrict__ x, const double *__restrict__ g,
-                                                 double *__restrict__ y, double *__restrict__ partial,
+                                                 const T *__restrict__ x, const T *__restrict__ g,
+                                                 T *__restrict__ y, double *__restrict__ partial,
                                                  const int *__restrict__ done) {
   if (done && *done) return;
   const int64_t blk = xcd_block(blockIdx.x, nb);
   const int lane = threadIdx.x & 63;
   const int64_t s = s_first + blk * kSlicesPerBlock + (threadIdx.x >> 6);
   const int64_t r = s * 64 + lane;
-  double prod = 0.0;
+  double prod[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) prod[k] = 0.0;
   if (r >= r0 && r < r1) {
-    const double xr = x[r];
-    double acc, off;
-    row_terms<DIFF>(A, s, lane, r, x, xr, acc, off);
-    acc += A.d[r] * xr;
-    const double out = (MODE == 0) ? acc : g[r] - acc;
-    y[r] = out;
-    if (DOT) prod = xr * out;
+    const Row<T, K> xr = ld<T, K>(x, r);
+    T acc[K], off;
+    sell_row<T, K, true>(A, s, lane, x, xr, acc, off);
+    Row<T, K> out;
+    if constexpr (std::is_same<T, double>::value) {
+      const double dr = A.d64[r];
+#pragma unroll
+      for (int k = 0; k < K; ++k) out.v[k] = acc[k] + dr * xr.v[k];
+    } else {
+      const float sr = A.s32[r], dh = A.dh32[r];
+#pragma unroll
+      for (int k = 0; k < K; ++k) out.v[k] = sr * (acc[k] + dh * xr.v[k]);
+    }
+    if (MODE == 1) {
+      const Row<T, K> gr = ld<T, K>(g, r);
+#pragma unroll
+      for (int k = 0; k < K; ++k) out.v[k] = gr.v[k] - out.v[k];
+    }
+    st<T, K>(y, r, out);
+    if (DOT) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) prod[k] = (double)xr.v[k] * (double)out.v[k];
+    }
   }
-  if (DOT) {
-    double t = block_sum(prod);
-    if (threadIdx.x == 0) partial[blk] = t;
-  }
+  if (DOT) block_sum_store<K>(prod, partial + blk * K);
 }
 
-template <bool DIFF>
+template <class T, int K>
 __global__ __launch_bounds__(kBlock) void k_gs(Sell A, int64_t a0, int64_t a1, int64_t sa, int64_t nba, int64_t b0,
-                                               int64_t b1, int64_t sb, int64_t nbt, const double *__restrict__ g,
-                                               double *__restrict__ x, const int *__restrict__ done) {
+                                               int64_t b1, int64_t sb, int64_t nbt, const T *__restrict__ g,
+                                               T *__restrict__ x, const int *__restrict__ done) {
   if (done && *done) return;
   int64_t blk = xcd_block(blockIdx.x, nbt);
   int64_t r0 = a0, r1 = a1, sf = sa;
@@ -175,108 +169,271 @@ __global__ __launch_bounds__(kBlock) void k_gs(Sell A, int64_t a0, int64_t a1, i
   const int64_t s = sf + blk * kSlicesPerBlock + (threadIdx.x >> 6);
   const int64_t r = s * 64 + lane;
   if (r < r0 || r >= r1) return;
-  const double xr = x[r];
-  double acc, off;
-  row_terms<DIFF>(A, s, lane, r, x, xr, acc, off);
-  const double dr = A.d[r];
-  const double diag = DIFF ? dr - off : dr;
-  x[r] = xr + (g[r] - (acc + dr * xr)) / diag;
+  const Row<T, K> xr = ld<T, K>(x, r);
+  const Row<T, K> gr = ld<T, K>(g, r);
+  T acc[K], off;
+  sell_row<T, K, true>(A, s, lane, x, xr, acc, off);
+  Row<T, K> out;
+  if constexpr (std::is_same<T, double>::value) {
+    const double dr = A.d64[r], diag = dr - off;
+#pragma unroll
+    for (int k = 0; k < K; ++k) out.v[k] = xr.v[k] + (gr.v[k] - (acc[k] + dr * xr.v[k])) / diag;
+  } else {
+    const float inv_s = 1.0f / A.s32[r], dh = A.dh32[r], diag = dh - off;
+#pragma unroll
+    for (int k = 0; k < K; ++k) out.v[k] = xr.v[k] + (gr.v[k] * inv_s - (acc[k] + dh * xr.v[k])) / diag;
+  }
+  st<T, K>(x, r, out);
 }
 
-template <bool ACC>
-__global__ __launch_bounds__(kBlock) void k_rect(Sell P, int64_t nb, const double *__restrict__ x,
-                                                 double *__restrict__ y, const int *__restrict__ done) {
+template <class T, int K, bool ACC>
+__global__ __launch_bounds__(kBlock) void k_rect(Sell E, int64_t nb, const T *__restrict__ x, T *__restrict__ y,
+                                                 const int *__restrict__ done) {
   if (done && *done) return;
   const int64_t blk = xcd_block(blockIdx.x, nb);
   const int lane = threadIdx.x & 63;
   const int64_t s = blk * kSlicesPerBlock + (threadIdx.x >> 6);
   const int64_t r = s * 64 + lane;
-  if (r >= P.nrows) return;
-  double acc, off;
-  row_terms<false>(P, s, lane, r, x, 0.0, acc, off);
-  y[r] = ACC ? y[r] + acc : acc;
+  if (r >= E.nrows) return;
+  Row<T, K> zero;
+#pragma unroll
+  for (int k = 0; k < K; ++k) zero.v[k] = T(0);
+  T acc[K], off;
+  sell_row<T, K, false>(E, s, lane, x, zero, acc, off);
+  Row<T, K> out;
+  if (ACC) out = ld<T, K>(y, r);
+#pragma unroll
+  for (int k = 0; k < K; ++k) out.v[k] = ACC ? out.v[k] + acc[k] : acc[k];
+  st<T, K>(y, r, out);
 }
 
-__global__ __launch_bounds__(kBlock) void k_prolong_sum(Sell E, int64_t n_top, int64_t nb, const double *__restrict__ ys,
-                                                        const double *__restrict__ w, const double *__restrict__ rv,
-                                                        double *__restrict__ z, double *__restrict__ partial,
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void k_prolong_sum(Sell E, int64_t n_top, int64_t nb, const T *__restrict__ ys,
+                                                        const T *__restrict__ w, const T *__restrict__ rv,
+                                                        T *__restrict__ z, double *__restrict__ partial,
                                                         const int *__restrict__ done) {
   if (done && *done) return;
   const int64_t blk = xcd_block(blockIdx.x, nb);
   const int lane = threadIdx.x & 63;
   const int64_t s = blk * kSlicesPerBlock + (threadIdx.x >> 6);
   const int64_t r = s * 64 + lane;
-  double prod = 0.0;
+  double prod[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) prod[k] = 0.0;
   if (r < E.nrows) {
-    double acc = 0.0, off;
-    if (ys) row_terms<false>(E, s, lane, r, ys, 0.0, acc, off);
-    if (r >= n_top) acc += w[r];
-    z[r] = acc;
-    prod = rv[r] * acc;
+    Row<T, K> zero;
+#pragma unroll
+    for (int k = 0; k < K; ++k) zero.v[k] = T(0);
+    T acc[K], off;
+    sell_row<T, K, false>(E, s, lane, ys, zero, acc, off);
+    Row<T, K> out;
+    if (r >= n_top) {
+      const Row<T, K> wr = ld<T, K>(w, r);
+#pragma unroll
+      for (int k = 0; k < K; ++k) out.v[k] = acc[k] + wr.v[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) out.v[k] = acc[k];
+    }
+    st<T, K>(z, r, out);
+    const Row<T, K> rr = ld<T, K>(rv, r);
+#pragma unroll
+    for (int k = 0; k < K; ++k) prod[k] = (double)rr.v[k] * (double)out.v[k];
   }
-  double t = block_sum(prod);
-  if (threadIdx.x == 0) partial[blk] = t;
+  block_sum_store<K>(prod, partial + blk * K);
 }
 
-// one wavefront per row of the dense coarsest inverse
-__global__ __launch_bounds__(kBlock) void k_dense(const double *__restrict__ C, int64_t m,
-                                                  const double *__restrict__ g, double *__restrict__ x,
-                                                  const int *__restrict__ done) {
+// ------------------------------------------------------------- CsrG
+// Off-diagonal sum of one row for K columns by its group of G lanes (the
+// result is valid in every lane of the group).
+template <class T, int K, int G>
+__device__ __forceinline__ void group_row(const CsrG &A, int64_t r, int gl, const T *__restrict__ x, T (&acc)[K]) {
+  const int32_t b = A.ptr[r], e = A.ptr[r + 1];
+  const T *__restrict__ vals = csr_vals<T>(A);
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = T(0);
+#pragma unroll 2
+  for (int j = b + gl; j < e; j += G) {
+    const T v = vals[j];
+    const Row<T, K> xc = ld<T, K>(x, A.col[j]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += v * xc.v[k];
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += __shfl_xor(acc[k], o, G);
+  }
+}
+
+// MODE 0: y = A x, 1: y = g - A x (square); 2: y = P x, 3: y += P x
+template <class T, int K, int G, int MODE>
+__global__ __launch_bounds__(kBlock) void k_csr_spmv(CsrG A, int64_t r0, int64_t r1, const T *__restrict__ x,
+                                                     const T *__restrict__ g, T *__restrict__ y,
+                                                     const int *__restrict__ done) {
+  if (done && *done) return;
+  const int gl = threadIdx.x & (G - 1);
+  const int64_t r = r0 + ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+  if (r >= r1) return;
+  T acc[K];
+  group_row<T, K, G>(A, r, gl, x, acc);
+  if (gl != 0) return;
+  Row<T, K> out;
+  if (MODE <= 1) {
+    const Row<T, K> xr = ld<T, K>(x, r);
+    if constexpr (std::is_same<T, double>::value) {
+      const double dr = A.d64[r];
+#pragma unroll
+      for (int k = 0; k < K; ++k) out.v[k] = acc[k] + dr * xr.v[k];
+    } else {
+      const float sr = A.s32[r];
+#pragma unroll
+      for (int k = 0; k < K; ++k) out.v[k] = sr * (acc[k] + xr.v[k]);
+    }
+    if (MODE == 1) {
+      const Row<T, K> gr = ld<T, K>(g, r);
+#pragma unroll
+      for (int k = 0; k < K; ++k) out.v[k] = gr.v[k] - out.v[k];
+    }
+  } else if (MODE == 2) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) out.v[k] = acc[k];
+  } else {
+    out = ld<T, K>(y, r);
+#pragma unroll
+    for (int k = 0; k < K; ++k) out.v[k] += acc[k];
+  }
+  st<T, K>(y, r, out);
+}
+
+template <class T, int K, int G>
+__global__ __launch_bounds__(kBlock) void k_csr_gs(CsrG A, int64_t r0, int64_t r1, const T *__restrict__ g,
+                                                   T *__restrict__ x, const int *__restrict__ done) {
+  if (done && *done) return;
+  const int gl = threadIdx.x & (G - 1);
+  const int64_t r = r0 + ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+  if (r >= r1) return;
+  T acc[K];
+  group_row<T, K, G>(A, r, gl, x, acc);  // off-diagonal part only
+  if (gl != 0) return;
+  const Row<T, K> gr = ld<T, K>(g, r);
+  Row<T, K> out;
+  if constexpr (std::is_same<T, double>::value) {
+    const double dr = A.d64[r];
+#pragma unroll
+    for (int k = 0; k < K; ++k) out.v[k] = (gr.v[k] - acc[k]) / dr;
+  } else {
+    const float inv_s = 1.0f / A.s32[r];
+#pragma unroll
+    for (int k = 0; k < K; ++k) out.v[k] = gr.v[k] * inv_s - acc[k];
+  }
+  st<T, K>(x, r, out);
+}
+
+// one wavefront per row of the dense FP64 coarsest inverse
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void k_dense(const double *__restrict__ C, int64_t m, const T *__restrict__ g,
+                                                  T *__restrict__ x, const int *__restrict__ done) {
   if (done && *done) return;
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
   if (i >= m) return;
-  double t = 0.0;
-  for (int64_t j = lane; j < m; j += 64) t += C[i * m + j] * g[j];
-  t = wave_sum(t);
-  if (lane == 0) x[i] = t;
+  double t[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) t[k] = 0.0;
+  for (int64_t j = lane; j < m; j += 64) {
+    const double c = C[i * m + j];
+    const Row<T, K> gj = ld<T, K>(g, j);
+#pragma unroll
+    for (int k = 0; k < K; ++k) t[k] += c * (double)gj.v[k];
+  }
+  Row<T, K> out;
+#pragma unroll
+  for (int k = 0; k < K; ++k) out.v[k] = (T)wave_sum(t[k]);
+  if (lane == 0) st<T, K>(x, i, out);
 }
 
-__global__ void k_fill(double *__restrict__ x, int64_t n, double v, const int *__restrict__ done) {
+// ------------------------------------------------------------- vectors
+template <class T>
+__global__ void k_fill(T *__restrict__ x, int64_t n, T v, const int *__restrict__ done) {
   if (done && *done) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;
 }
 
-__global__ void k_copy(const double *__restrict__ a, double *__restrict__ b, int64_t n, const int *__restrict__ done) {
+template <class T>
+__global__ void k_copy(const T *__restrict__ a, T *__restrict__ b, int64_t n, const int *__restrict__ done) {
   if (done && *done) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = a[i];
 }
 
-__global__ __launch_bounds__(kBlock) void k_dot(const double *__restrict__ a, const double *__restrict__ b, int64_t n,
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void k_dot(const T *__restrict__ a, const T *__restrict__ b, int64_t n,
                                                 double *__restrict__ partial, const int *__restrict__ done) {
   if (done && *done) return;
   int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  double t = (i < n) ? a[i] * b[i] : 0.0;
-  t = block_sum(t);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  double t[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) t[k] = 0.0;
+  if (i < n) {
+    const Row<T, K> ai = ld<T, K>(a, i), bi = ld<T, K>(b, i);
+#pragma unroll
+    for (int k = 0; k < K; ++k) t[k] = (double)ai.v[k] * (double)bi.v[k];
+  }
+  block_sum_store<K>(t, partial + (int64_t)blockIdx.x * K);
 }
 
-__global__ void k_jacobi(const double *__restrict__ r, const double *__restrict__ dg, double *__restrict__ z, int64_t n,
+template <class T, int K>
+__global__ void k_jacobi(const T *__restrict__ r, const double *__restrict__ dg, T *__restrict__ z, int64_t n,
                          const int *__restrict__ done) {
   if (done && *done) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) z[i] = r[i] / dg[i];
+  if (i >= n) return;
+  const Row<T, K> ri = ld<T, K>(r, i);
+  Row<T, K> out;
+  const double d = dg[i];
+#pragma unroll
+  for (int k = 0; k < K; ++k) out.v[k] = (T)((double)ri.v[k] / d);
+  st<T, K>(z, i, out);
 }
 
 __global__ void k_gather(const double *__restrict__ nat, const int64_t *__restrict__ perm, double *__restrict__ sto,
-                         int64_t n) {
+                         int64_t n, int K, int k) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) sto[i] = nat[perm[i]];
+  if (i < n) sto[i * K + k] = nat[perm[i]];
 }
 
 __global__ void k_scatter(const double *__restrict__ sto, const int64_t *__restrict__ perm, double *__restrict__ nat,
-                          int64_t n) {
+                          int64_t n, int K, int k) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) nat[perm[i]] = sto[i];
+  if (i < n) nat[perm[i]] = sto[i * K + k];
 }
 
-// fixed-order sum of np partials by one block
-__device__ __forceinline__ double sum_partials(const double *__restrict__ p, int64_t np) {
+__global__ void k_demote(const double *__restrict__ r64, const double *__restrict__ scale, float *__restrict__ r32,
+                         int64_t n, int K, const int *__restrict__ done) {
+  if (done && *done) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n * K) r32[i] = (float)(r64[i] * scale[i % K]);
+}
+
+template <bool ACC>
+__global__ void k_promote(const float *__restrict__ d32, const double *__restrict__ scale, double *__restrict__ x64,
+                          int64_t n, int K, const int *__restrict__ done) {
+  if (done && *done) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * K) return;
+  const double v = scale[i % K] * (double)d32[i];
+  x64[i] = ACC ? x64[i] + v : v;
+}
+
+// ------------------------------------------------------------- PCG scalars
+// fixed-order sum over np partials of column k by one block
+__device__ __forceinline__ double sum_partials(const double *__restrict__ p, int64_t np, int K, int k) {
   double t = 0.0;
-  for (int64_t k = threadIdx.x; k < np; k += kBlock) t += p[k];
+  for (int64_t j = threadIdx.x; j < np; j += kBlock) t += p[j * K + k];
   __shared__ double buf[kBlock];
+  __syncthreads();
   buf[threadIdx.x] = t;
   __syncthreads();
   for (int o = kBlock / 2; o > 0; o >>= 1) {
@@ -286,102 +443,156 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ p, int
   return buf[0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce(const double *p, int64_t np, double *out) {
-  double t = sum_partials(p, np);
-  if (threadIdx.x == 0) *out = t;
+__device__ __forceinline__ void update_all_done(Scal *s) {
+  int all = 1;
+  for (int k = 0; k < s->K; ++k) all &= s->done[k];
+  s->all_done = all;
 }
 
-__global__ __launch_bounds__(kBlock) void k_pcg_init(Scal *s, const double *pb, int64_t npb, double tol, int maxit) {
-  double t = sum_partials(pb, npb);
+__global__ __launch_bounds__(kBlock) void k_reduce(const double *p, int64_t np, int K, double *out) {
+  for (int k = 0; k < K; ++k) {
+    double t = sum_partials(p, np, K, k);
+    if (threadIdx.x == 0) out[k] = t;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pcg_init(Scal *s, const double *pb, int64_t npb, int K, double tol,
+                                                     int maxit) {
+  for (int k = 0; k < kMaxBatch; ++k) {
+    double t = (k < K) ? sum_partials(pb, npb, K, k) : 0.0;
+    if (threadIdx.x == 0) {
+      s->bnorm2[k] = t;
+      s->iters[k] = 0;
+      s->rho[k] = 0.0;
+      s->alpha[k] = 0.0;
+      s->beta[k] = 0.0;
+      if (k >= K || t == 0.0) {
+        s->done[k] = 1;
+        s->status[k] = 1;
+      } else if (!isfinite(t)) {
+        s->done[k] = 1;
+        s->status[k] = -6;
+      } else {
+        s->done[k] = 0;
+        s->status[k] = 0;
+      }
+    }
+  }
   if (threadIdx.x == 0) {
-    s->bnorm2 = t;
+    s->K = K;
     s->tol2 = tol * tol;
     s->maxit = maxit;
-    s->iters = 0;
-    s->done = 0;
-    s->status = 0;
-    s->rho = 0.0;
+    update_all_done(s);
   }
 }
 
 __global__ __launch_bounds__(kBlock) void k_pcg_set_rho(Scal *s, const double *p, int64_t np) {
-  double t = sum_partials(p, np);
-  if (threadIdx.x == 0) s->rho = t;
+  for (int k = 0; k < s->K; ++k) {
+    double t = sum_partials(p, np, s->K, k);
+    if (threadIdx.x == 0) s->rho[k] = t;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_pcg_alpha(Scal *s, const double *p, int64_t np) {
-  if (s->done) return;
-  double pq = sum_partials(p, np);
-  if (threadIdx.x == 0) {
-    s->pq = pq;
-    if (!(pq > 0.0) || !isfinite(pq) || !isfinite(s->rho)) {
-      s->done = 1;
-      s->status = -6;
-      s->alpha = 0.0;
-    } else {
-      s->alpha = s->rho / pq;
+  if (s->all_done) return;
+  for (int k = 0; k < s->K; ++k) {
+    double pq = sum_partials(p, np, s->K, k);
+    if (threadIdx.x == 0 && !s->done[k]) {
+      s->pq[k] = pq;
+      if (!(pq > 0.0) || !isfinite(pq) || !isfinite(s->rho[k])) {
+        s->done[k] = 1;
+        s->status[k] = -6;
+        s->alpha[k] = 0.0;
+      } else {
+        s->alpha[k] = s->rho[k] / pq;
+      }
     }
   }
+  if (threadIdx.x == 0) update_all_done(s);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pcg_xr(const Scal *s, double *__restrict__ x, double *__restrict__ r,
-                                                   const double *__restrict__ p, const double *__restrict__ q,
-                                                   int64_t n, double *__restrict__ partial) {
-  if (s->done) return;
-  const double a = s->alpha;
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void k_pcg_xr(const Scal *s, T *__restrict__ x, T *__restrict__ r,
+                                                   const T *__restrict__ p, const T *__restrict__ q, int64_t n,
+                                                   double *__restrict__ partial) {
+  if (s->all_done) return;
   int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  double t = 0.0;
+  double t[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) t[k] = 0.0;
   if (i < n) {
-    x[i] += a * p[i];
-    double ri = r[i] - a * q[i];
-    r[i] = ri;
-    t = ri * ri;
+    Row<T, K> xi = ld<T, K>(x, i), ri = ld<T, K>(r, i);
+    const Row<T, K> pi = ld<T, K>(p, i), qi = ld<T, K>(q, i);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (!s->done[k]) {
+        const T a = (T)s->alpha[k];
+        xi.v[k] += a * pi.v[k];
+        ri.v[k] -= a * qi.v[k];
+      }
+      t[k] = (double)ri.v[k] * (double)ri.v[k];
+    }
+    st<T, K>(x, i, xi);
+    st<T, K>(r, i, ri);
   }
-  t = block_sum(t);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  block_sum_store<K>(t, partial + (int64_t)blockIdx.x * K);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pcg_conv(Scal *s, const double *p, int64_t np, double *hist) {
-  if (s->done) return;
-  double rr = sum_partials(p, np);
-  if (threadIdx.x == 0) {
-    int it = s->iters + 1;
-    s->iters = it;
-    s->rr = rr;
-    if (hist) hist[it] = rr;
-    if (!isfinite(rr)) {
-      s->done = 1;
-      s->status = -6;
-    } else if (rr <= s->tol2 * s->bnorm2) {
-      s->done = 1;
-      s->status = 1;
-    } else if (it >= s->maxit) {
-      s->done = 1;
-      s->status = 2;
+__global__ __launch_bounds__(kBlock) void k_pcg_conv(Scal *s, const double *p, int64_t np) {
+  if (s->all_done) return;
+  for (int k = 0; k < s->K; ++k) {
+    double rr = sum_partials(p, np, s->K, k);
+    if (threadIdx.x == 0 && !s->done[k]) {
+      int it = s->iters[k] + 1;
+      s->iters[k] = it;
+      s->rr[k] = rr;
+      if (!isfinite(rr)) {
+        s->done[k] = 1;
+        s->status[k] = -6;
+      } else if (rr <= s->tol2 * s->bnorm2[k]) {
+        s->done[k] = 1;
+        s->status[k] = 1;
+      } else if (it >= s->maxit) {
+        s->done[k] = 1;
+        s->status[k] = 2;
+      }
     }
   }
+  if (threadIdx.x == 0) update_all_done(s);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pcg_beta(Scal *s, const double *p, int64_t np) {
-  if (s->done) return;
-  double rz = sum_partials(p, np);
-  if (threadIdx.x == 0) {
-    s->beta = rz / s->rho;
-    s->rho = rz;
+  if (s->all_done) return;
+  for (int k = 0; k < s->K; ++k) {
+    double rz = sum_partials(p, np, s->K, k);
+    if (threadIdx.x == 0 && !s->done[k]) {
+      s->beta[k] = rz / s->rho[k];
+      s->rho[k] = rz;
+    }
   }
 }
 
-__global__ void k_pcg_p(const Scal *s, double *__restrict__ p, const double *__restrict__ z, int64_t n) {
-  if (s->done) return;
-  const double b = s->beta;
+template <class T, int K>
+__global__ void k_pcg_p(const Scal *s, T *__restrict__ p, const T *__restrict__ z, int64_t n) {
+  if (s->all_done) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = z[i] + b * p[i];
+  if (i >= n) return;
+  Row<T, K> pi = ld<T, K>(p, i);
+  const Row<T, K> zi = ld<T, K>(z, i);
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (!s->done[k]) pi.v[k] = zi.v[k] + (T)s->beta[k] * pi.v[k];
+  st<T, K>(p, i, pi);
 }
 
-__global__ void k_pcg_resume(Scal *s) {
+__global__ void k_pcg_resume(Scal *s, unsigned keep) {
   if (threadIdx.x == 0) {
-    s->done = 0;
-    s->status = 0;
+    for (int k = 0; k < s->K; ++k)
+      if (!((keep >> k) & 1u)) {
+        s->done[k] = 0;
+        s->status[k] = 0;
+      }
+    update_all_done(s);
   }
 }
 
@@ -389,157 +600,257 @@ inline dim3 grid(int64_t nb) { return dim3((unsigned)nb); }
 
 }  // namespace
 
-void launch_spmv(hipStream_t st, const Sell &A, bool diff, int mode, int64_t r0, int64_t r1, const double *x,
-                 const double *g, double *y, double *partial, const int *done) {
+#define VEMG_K_SWITCH(K, ...) \
+  switch (K) {                \
+    case 1: {                 \
+      constexpr int KK = 1;   \
+      __VA_ARGS__;            \
+    } break;                  \
+    case 2: {                 \
+      constexpr int KK = 2;   \
+      __VA_ARGS__;            \
+    } break;                  \
+    case 4: {                 \
+      constexpr int KK = 4;   \
+      __VA_ARGS__;            \
+    } break;                  \
+    default: {                \
+      constexpr int KK = 8;   \
+      __VA_ARGS__;            \
+    } break;                  \
+  }
+
+#define VEMG_G_SWITCH(G, ...) \
+  switch (G) {                \
+    case 4: {                 \
+      constexpr int GG = 4;   \
+      __VA_ARGS__;            \
+    } break;                  \
+    case 8: {                 \
+      constexpr int GG = 8;   \
+      __VA_ARGS__;            \
+    } break;                  \
+    case 16: {                \
+      constexpr int GG = 16;  \
+      __VA_ARGS__;            \
+    } break;                  \
+    case 32: {                \
+      constexpr int GG = 32;  \
+      __VA_ARGS__;            \
+    } break;                  \
+    default: {                \
+      constexpr int GG = 64;  \
+      __VA_ARGS__;            \
+    } break;                  \
+  }
+
+template <class T>
+void launch_spmv(hipStream_t stm, int K, const Sell &A, int mode, int64_t r0, int64_t r1, const T *x, const T *g,
+                 T *y, double *partial, const int *done) {
   int64_t nb = sell_blocks(r0, r1);
   if (!nb) return;
   int64_t sf = r0 / kWave;
-#define VEMG_SPMV(D, M, T) hipLaunchKernelGGL((k_spmv<D, M, T>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, sf, nb, x, g, y, partial, done)
-  if (diff) {
+  VEMG_K_SWITCH(K, {
     if (mode == 0) {
-      if (partial) VEMG_SPMV(true, 0, true); else VEMG_SPMV(true, 0, false);
+      if (partial)
+        hipLaunchKernelGGL((k_spmv<T, KK, 0, true>), grid(nb), dim3(kBlock), 0, stm, A, r0, r1, sf, nb, x, g, y,
+                           partial, done);
+      else
+        hipLaunchKernelGGL((k_spmv<T, KK, 0, false>), grid(nb), dim3(kBlock), 0, stm, A, r0, r1, sf, nb, x, g, y,
+                           partial, done);
     } else {
-      if (partial) VEMG_SPMV(true, 1, true); else VEMG_SPMV(true, 1, false);
+      hipLaunchKernelGGL((k_spmv<T, KK, 1, false>), grid(nb), dim3(kBlock), 0, stm, A, r0, r1, sf, nb, x, g, y,
+                         partial, done);
     }
-  } else {
-    if (mode == 0) {
-      if (partial) VEMG_SPMV(false, 0, true); else VEMG_SPMV(false, 0, false);
-    } else {
-      if (partial) VEMG_SPMV(false, 1, true); else VEMG_SPMV(false, 1, false);
-    }
-  }
-#undef VEMG_SPMV
+  })
 }
 
-void launch_gs(hipStream_t st, const Sell &A, bool diff, int64_t a0, int64_t a1, int64_t b0, int64_t b1,
-               const double *g, double *x, const int *done) {
+template <class T>
+void launch_gs(hipStream_t stm, int K, const Sell &A, int64_t a0, int64_t a1, int64_t b0, int64_t b1, const T *g,
+               T *x, const int *done) {
   int64_t nba = sell_blocks(a0, a1), nbb = sell_blocks(b0, b1);
   int64_t nbt = nba + nbb;
   if (!nbt) return;
   int64_t sa = a0 / kWave, sb = b0 / kWave;
-  if (diff)
-    hipLaunchKernelGGL((k_gs<true>), grid(nbt), dim3(kBlock), 0, st, A, a0, a1, sa, nba, b0, b1, sb, nbt, g, x, done);
-  else
-    hipLaunchKernelGGL((k_gs<false>), grid(nbt), dim3(kBlock), 0, st, A, a0, a1, sa, nba, b0, b1, sb, nbt, g, x, done);
+  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_gs<T, KK>), grid(nbt), dim3(kBlock), 0, stm, A, a0, a1, sa, nba, b0, b1, sb,
+                                      nbt, g, x, done))
 }
 
-void launch_rect(hipStream_t st, const Sell &P, bool accumulate, const double *x, double *y, const int *done) {
-  int64_t nb = sell_blocks(0, P.nrows);
-  if (!nb) return;
-  if (accumulate)
-    hipLaunchKernelGGL((k_rect<true>), grid(nb), dim3(kBlock), 0, st, P, nb, x, y, done);
-  else
-    hipLaunchKernelGGL((k_rect<false>), grid(nb), dim3(kBlock), 0, st, P, nb, x, y, done);
-}
-
-void launch_prolong_sum(hipStream_t st, const Sell &E, int64_t n_top, const double *y, const double *w,
-                        const double *r, double *z, double *partial, const int *done) {
+template <class T>
+void launch_rect(hipStream_t stm, int K, const Sell &E, bool accumulate, const T *x, T *y, const int *done) {
   int64_t nb = sell_blocks(0, E.nrows);
   if (!nb) return;
-  hipLaunchKernelGGL(k_prolong_sum, grid(nb), dim3(kBlock), 0, st, E, n_top, nb, y, w, r, z, partial, done);
+  VEMG_K_SWITCH(K, {
+    if (accumulate)
+      hipLaunchKernelGGL((k_rect<T, KK, true>), grid(nb), dim3(kBlock), 0, stm, E, nb, x, y, done);
+    else
+      hipLaunchKernelGGL((k_rect<T, KK, false>), grid(nb), dim3(kBlock), 0, stm, E, nb, x, y, done);
+  })
 }
 
-void launch_dense(hipStream_t st, const double *Cinv, int64_t m, const double *g, double *x, const int *done) {
+template <class T>
+void launch_prolong_sum(hipStream_t stm, int K, const Sell &E, int64_t n_top, const T *y, const T *w, const T *r,
+                        T *z, double *partial, const int *done) {
+  int64_t nb = sell_blocks(0, E.nrows);
+  if (!nb) return;
+  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_prolong_sum<T, KK>), grid(nb), dim3(kBlock), 0, stm, E, n_top, nb, y, w, r,
+                                      z, partial, done))
+}
+
+template <class T>
+static void csr_launch(hipStream_t stm, int K, int mode, const CsrG &A, int64_t r0, int64_t r1, const T *x,
+                       const T *g, T *y, const int *done) {
+  int64_t rows = r1 - r0;
+  if (rows <= 0) return;
+  int64_t nb = (rows * A.G + kBlock - 1) / kBlock;
+  VEMG_K_SWITCH(K, VEMG_G_SWITCH(A.G, {
+    switch (mode) {
+      case 0:
+        hipLaunchKernelGGL((k_csr_spmv<T, KK, GG, 0>), grid(nb), dim3(kBlock), 0, stm, A, r0, r1, x, g, y, done);
+        break;
+      case 1:
+        hipLaunchKernelGGL((k_csr_spmv<T, KK, GG, 1>), grid(nb), dim3(kBlock), 0, stm, A, r0, r1, x, g, y, done);
+        break;
+      case 2:
+        hipLaunchKernelGGL((k_csr_spmv<T, KK, GG, 2>), grid(nb), dim3(kBlock), 0, stm, A, r0, r1, x, g, y, done);
+        break;
+      default:
+        hipLaunchKernelGGL((k_csr_spmv<T, KK, GG, 3>), grid(nb), dim3(kBlock), 0, stm, A, r0, r1, x, g, y, done);
+        break;
+    }
+  }))
+}
+
+template <class T>
+void launch_csr_spmv(hipStream_t stm, int K, const CsrG &A, int mode, int64_t r0, int64_t r1, const T *x,
+                     const T *g, T *y, const int *done) {
+  csr_launch<T>(stm, K, mode == 0 ? 0 : 1, A, r0, r1, x, g, y, done);
+}
+
+template <class T>
+void launch_csr_rect(hipStream_t stm, int K, const CsrG &P, bool accumulate, const T *x, T *y, const int *done) {
+  csr_launch<T>(stm, K, accumulate ? 3 : 2, P, 0, P.nrows, x, nullptr, y, done);
+}
+
+template <class T>
+void launch_csr_gs(hipStream_t stm, int K, const CsrG &A, int64_t r0, int64_t r1, const T *g, T *x, const int *done) {
+  int64_t rows = r1 - r0;
+  if (rows <= 0) return;
+  int64_t nb = (rows * A.G + kBlock - 1) / kBlock;
+  VEMG_K_SWITCH(K, VEMG_G_SWITCH(A.G, hipLaunchKernelGGL((k_csr_gs<T, KK, GG>), grid(nb), dim3(kBlock), 0, stm, A,
+                                                          r0, r1, g, x, done)))
+}
+
+template <class T>
+void launch_dense(hipStream_t stm, int K, const double *Cinv, int64_t m, const T *g, T *x, const int *done) {
   if (m <= 0) return;
-  hipLaunchKernelGGL(k_dense, grid((m + kSlicesPerBlock - 1) / kSlicesPerBlock), dim3(kBlock), 0, st, Cinv, m, g, x,
-                     done);
+  int64_t nb = (m + kSlicesPerBlock - 1) / kSlicesPerBlock;
+  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_dense<T, KK>), grid(nb), dim3(kBlock), 0, stm, Cinv, m, g, x, done))
 }
 
-void launch_fill(hipStream_t st, double *x, int64_t n, double v, const int *done) {
+template <class T>
+void launch_fill(hipStream_t stm, T *x, int64_t n, T v, const int *done) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_fill, grid(vec_blocks(n)), dim3(kBlock), 0, st, x, n, v, done);
+  hipLaunchKernelGGL((k_fill<T>), grid(vec_blocks(n)), dim3(kBlock), 0, stm, x, n, v, done);
 }
 
-void launch_copy(hipStream_t st, const double *a, double *b, int64_t n, const int *done) {
+template <class T>
+void launch_copy(hipStream_t stm, const T *a, T *b, int64_t n, const int *done) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_copy, grid(vec_blocks(n)), dim3(kBlock), 0, st, a, b, n, done);
+  hipLaunchKernelGGL((k_copy<T>), grid(vec_blocks(n)), dim3(kBlock), 0, stm, a, b, n, done);
 }
 
-void launch_dot(hipStream_t st, const double *a, const double *b, int64_t n, double *partial, const int *done) {
+template <class T>
+void launch_dot(hipStream_t stm, int K, const T *a, const T *b, int64_t n, double *partial, const int *done) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_dot, grid(vec_blocks(n)), dim3(kBlock), 0, st, a, b, n, partial, done);
+  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_dot<T, KK>), grid(vec_blocks(n)), dim3(kBlock), 0, stm, a, b, n, partial,
+                                      done))
 }
 
-void launch_jacobi(hipStream_t st, const double *r, const double *diag, double *z, int64_t n, const int *done) {
+template <class T>
+void launch_jacobi(hipStream_t stm, int K, const T *r, const double *diag, T *z, int64_t n, const int *done) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_jacobi, grid(vec_blocks(n)), dim3(kBlock), 0, st, r, diag, z, n, done);
+  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_jacobi<T, KK>), grid(vec_blocks(n)), dim3(kBlock), 0, stm, r, diag, z, n,
+                                      done))
 }
 
-void launch_gather(hipStream_t st, const double *nat, const int64_t *perm, double *sto, int64_t n) {
+void launch_gather(hipStream_t stm, int K, int k, const double *nat, const int64_t *perm, double *sto, int64_t n) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_gather, grid(vec_blocks(n)), dim3(kBlock), 0, st, nat, perm, sto, n);
+  hipLaunchKernelGGL(k_gather, grid(vec_blocks(n)), dim3(kBlock), 0, stm, nat, perm, sto, n, K, k);
 }
 
-void launch_scatter(hipStream_t st, const double *sto, const int64_t *perm, double *nat, int64_t n) {
+void launch_scatter(hipStream_t stm, int K, int k, const double *sto, const int64_t *perm, double *nat, int64_t n) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_scatter, grid(vec_blocks(n)), dim3(kBlock), 0, st, sto, perm, nat, n);
+  hipLaunchKernelGGL(k_scatter, grid(vec_blocks(n)), dim3(kBlock), 0, stm, sto, perm, nat, n, K, k);
 }
 
-template <int MODE>
-static void csr_dispatch(hipStream_t st, const CsrG &A, int64_t r0, int64_t r1, const double *x, const double *g,
-                         double *y, const int *done) {
-  int64_t rows = r1 - r0;
-  if (rows <= 0) return;
-  int64_t nb = (rows * A.G + kBlock - 1) / kBlock;
-  switch (A.G) {
-    case 4: hipLaunchKernelGGL((k_csr_spmv<4, MODE>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, x, g, y, done); break;
-    case 8: hipLaunchKernelGGL((k_csr_spmv<8, MODE>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, x, g, y, done); break;
-    case 16: hipLaunchKernelGGL((k_csr_spmv<16, MODE>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, x, g, y, done); break;
-    case 32: hipLaunchKernelGGL((k_csr_spmv<32, MODE>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, x, g, y, done); break;
-    default: hipLaunchKernelGGL((k_csr_spmv<64, MODE>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, x, g, y, done); break;
-  }
-}
-
-void launch_csr_spmv(hipStream_t st, const CsrG &A, int mode, int64_t r0, int64_t r1, const double *x,
-                     const double *g, double *y, const int *done) {
-  if (mode == 0) csr_dispatch<0>(st, A, r0, r1, x, g, y, done);
-  else csr_dispatch<1>(st, A, r0, r1, x, g, y, done);
-}
-
-void launch_csr_rect(hipStream_t st, const CsrG &P, bool accumulate, const double *x, double *y, const int *done) {
-  if (accumulate) csr_dispatch<3>(st, P, 0, P.nrows, x, nullptr, y, done);
-  else csr_dispatch<2>(st, P, 0, P.nrows, x, nullptr, y, done);
-}
-
-void launch_csr_gs(hipStream_t st, const CsrG &A, int64_t r0, int64_t r1, const double *g, double *x,
+void launch_demote(hipStream_t stm, int K, const double *r64, const double *scale, float *r32, int64_t n,
                    const int *done) {
-  int64_t rows = r1 - r0;
-  if (rows <= 0) return;
-  int64_t nb = (rows * A.G + kBlock - 1) / kBlock;
-  switch (A.G) {
-    case 4: hipLaunchKernelGGL((k_csr_gs<4>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, g, x, done); break;
-    case 8: hipLaunchKernelGGL((k_csr_gs<8>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, g, x, done); break;
-    case 16: hipLaunchKernelGGL((k_csr_gs<16>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, g, x, done); break;
-    case 32: hipLaunchKernelGGL((k_csr_gs<32>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, g, x, done); break;
-    default: hipLaunchKernelGGL((k_csr_gs<64>), grid(nb), dim3(kBlock), 0, st, A, r0, r1, g, x, done); break;
-  }
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_demote, grid(vec_blocks(n * K)), dim3(kBlock), 0, stm, r64, scale, r32, n, K, done);
 }
 
-void launch_pcg_init(hipStream_t st, Scal *s, const double *pb, int64_t npb, double tol, int maxit) {
-  hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(kBlock), 0, st, s, pb, npb, tol, maxit);
+void launch_promote(hipStream_t stm, int K, const float *d32, const double *scale, double *x64, int64_t n,
+                    bool accumulate, const int *done) {
+  if (n <= 0) return;
+  if (accumulate)
+    hipLaunchKernelGGL((k_promote<true>), grid(vec_blocks(n * K)), dim3(kBlock), 0, stm, d32, scale, x64, n, K, done);
+  else
+    hipLaunchKernelGGL((k_promote<false>), grid(vec_blocks(n * K)), dim3(kBlock), 0, stm, d32, scale, x64, n, K, done);
 }
-void launch_pcg_set_rho(hipStream_t st, Scal *s, const double *p, int64_t np) {
-  hipLaunchKernelGGL(k_pcg_set_rho, dim3(1), dim3(kBlock), 0, st, s, p, np);
+
+void launch_pcg_init(hipStream_t stm, int K, Scal *s, const double *pb, int64_t npb, double tol, int maxit) {
+  hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(kBlock), 0, stm, s, pb, npb, K, tol, maxit);
 }
-void launch_pcg_alpha(hipStream_t st, Scal *s, const double *p, int64_t np) {
-  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(kBlock), 0, st, s, p, np);
+void launch_pcg_set_rho(hipStream_t stm, int, Scal *s, const double *p, int64_t np) {
+  hipLaunchKernelGGL(k_pcg_set_rho, dim3(1), dim3(kBlock), 0, stm, s, p, np);
 }
-void launch_pcg_xr(hipStream_t st, Scal *s, double *x, double *r, const double *p, const double *q, int64_t n,
-                   double *partial) {
-  hipLaunchKernelGGL(k_pcg_xr, grid(vec_blocks(n)), dim3(kBlock), 0, st, s, x, r, p, q, n, partial);
+void launch_pcg_alpha(hipStream_t stm, int, Scal *s, const double *p, int64_t np) {
+  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(kBlock), 0, stm, s, p, np);
 }
-void launch_pcg_conv(hipStream_t st, Scal *s, const double *p, int64_t np, double *hist) {
-  hipLaunchKernelGGL(k_pcg_conv, dim3(1), dim3(kBlock), 0, st, s, p, np, hist);
+template <class T>
+void launch_pcg_xr(hipStream_t stm, int K, Scal *s, T *x, T *r, const T *p, const T *q, int64_t n, double *partial) {
+  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_pcg_xr<T, KK>), grid(vec_blocks(n)), dim3(kBlock), 0, stm, s, x, r, p, q, n,
+                                      partial))
 }
-void launch_pcg_beta(hipStream_t st, Scal *s, const double *p, int64_t np) {
-  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(kBlock), 0, st, s, p, np);
+void launch_pcg_conv(hipStream_t stm, int, Scal *s, const double *p, int64_t np) {
+  hipLaunchKernelGGL(k_pcg_conv, dim3(1), dim3(kBlock), 0, stm, s, p, np);
 }
-void launch_pcg_p(hipStream_t st, Scal *s, double *pvec, const double *z, int64_t n) {
-  hipLaunchKernelGGL(k_pcg_p, grid(vec_blocks(n)), dim3(kBlock), 0, st, s, pvec, z, n);
+void launch_pcg_beta(hipStream_t stm, int, Scal *s, const double *p, int64_t np) {
+  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(kBlock), 0, stm, s, p, np);
 }
-void launch_pcg_resume(hipStream_t st, Scal *s) { hipLaunchKernelGGL(k_pcg_resume, dim3(1), dim3(64), 0, st, s); }
-void launch_reduce(hipStream_t st, const double *p, int64_t np, double *out) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, p, np, out);
+template <class T>
+void launch_pcg_p(hipStream_t stm, int K, Scal *s, T *pvec, const T *z, int64_t n) {
+  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_pcg_p<T, KK>), grid(vec_blocks(n)), dim3(kBlock), 0, stm, s, pvec, z, n))
 }
+void launch_reduce(hipStream_t stm, int K, const double *p, int64_t np, double *out) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, stm, p, np, K, out);
+}
+void launch_pcg_resume(hipStream_t stm, int, Scal *s, unsigned keep) {
+  hipLaunchKernelGGL(k_pcg_resume, dim3(1), dim3(64), 0, stm, s, keep);
+}
+
+#define VEMG_INSTANTIATE(T)                                                                                          \
+  template void launch_spmv<T>(hipStream_t, int, const Sell &, int, int64_t, int64_t, const T *, const T *, T *,      \
+                               double *, const int *);                                                               \
+  template void launch_gs<T>(hipStream_t, int, const Sell &, int64_t, int64_t, int64_t, int64_t, const T *, T *,       \
+                             const int *);                                                                           \
+  template void launch_rect<T>(hipStream_t, int, const Sell &, bool, const T *, T *, const int *);                    \
+  template void launch_prolong_sum<T>(hipStream_t, int, const Sell &, int64_t, const T *, const T *, const T *, T *,   \
+                                      double *, const int *);                                                        \
+  template void launch_csr_spmv<T>(hipStream_t, int, const CsrG &, int, int64_t, int64_t, const T *, const T *, T *,   \
+                                   const int *);                                                                     \
+  template void launch_csr_gs<T>(hipStream_t, int, const CsrG &, int64_t, int64_t, const T *, T *, const int *);      \
+  template void launch_csr_rect<T>(hipStream_t, int, const CsrG &, bool, const T *, T *, const int *);                \
+  template void launch_dense<T>(hipStream_t, int, const double *, int64_t, const T *, T *, const int *);              \
+  template void launch_fill<T>(hipStream_t, T *, int64_t, T, const int *);                                           \
+  template void launch_copy<T>(hipStream_t, const T *, T *, int64_t, const int *);                                   \
+  template void launch_dot<T>(hipStream_t, int, const T *, const T *, int64_t, double *, const int *);                \
+  template void launch_jacobi<T>(hipStream_t, int, const T *, const double *, T *, int64_t, const int *);             \
+  template void launch_pcg_xr<T>(hipStream_t, int, Scal *, T *, T *, const T *, const T *, int64_t, double *);        \
+  template void launch_pcg_p<T>(hipStream_t, int, Scal *, T *, const T *, int64_t);
+
+VEMG_INSTANTIATE(double)
+VEMG_INSTANTIATE(float)
 
 }  // namespace vemg

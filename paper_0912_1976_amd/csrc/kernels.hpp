@@ -1,5 +1,11 @@
 // Device kernels of the PCG hot path (gfx950, wave64) and their launchers.
 // All launchers enqueue on the given stream and never synchronise.
+//
+// Every vector kernel works on K right-hand sides at once (K in {1,2,4,8}):
+// vectors are stored row-major as [n][K], so a matrix entry is read once
+// for all K columns and the K values of a gathered row are contiguous.
+// The vector type T is double (FP64 path) or float (inner solve of the
+// mixed-precision path); reductions always accumulate in double.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,18 +17,23 @@ namespace vemg {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kSlicesPerBlock = kBlock / kWave;
+constexpr int kMaxBatch = 8;
 
 // SELL-64 matrix: 64 consecutive rows form a slice stored column-major and
 // padded to the slice's longest row, so lane t of a wavefront reads entry k
 // of row 64 s + t at sptr[s] + 64 k + t (coalesced).  Only off-diagonal
-// entries are stored; `d` holds the per-row diagonal term (the deficit for
-// the difference form, a_ii for the standard form).  Padding entries have
-// value 0 and point at the row itself (square) or column 0 (rectangular).
+// entries are stored; padding entries have value 0 and point at the row
+// itself (square) or column 0 (rectangular).
+//   fine A (difference form): FP64 values a_ij with the deficit d64;
+//   FP32 copy: row-scaled values a_ij / a_ii with s32 = a_ii and
+//   dh32 = d_i / a_ii, so (A x)_i = s_i (sum_j w_ij (x_j - x_i) + dh_i x_i).
 struct Sell {
   const int64_t *sptr = nullptr;  // nslices + 1 entry offsets
   const int32_t *col = nullptr;
-  const double *val = nullptr;
-  const double *d = nullptr;
+  const double *val64 = nullptr;
+  const float *val32 = nullptr;
+  const double *d64 = nullptr;
+  const float *s32 = nullptr, *dh32 = nullptr;
   int64_t nrows = 0;
 };
 
@@ -30,23 +41,29 @@ struct Sell {
 // two chosen from the mean row length): the group reads consecutive entries
 // of its row (coalesced) and reduces with cross-lane shuffles, so long rows
 // (coarse multigrid operators, restrictions) cost a few memory round trips
-// instead of one per entry.  `d` as for Sell (square standard form only).
+// instead of one per entry.  Square operators store off-diagonals only:
+// FP64 values with d64 = a_ii; FP32 values a_ij / a_ii with s32 = a_ii.
 struct CsrG {
   const int32_t *ptr = nullptr;  // nrows + 1
   const int32_t *col = nullptr;
-  const double *val = nullptr;
-  const double *d = nullptr;
+  const double *val64 = nullptr;
+  const float *val32 = nullptr;
+  const double *d64 = nullptr;
+  const float *s32 = nullptr;
   int64_t nrows = 0;
   int G = 4;
 };
 
-// Device scalars of one PCG solve.
+// Device scalars of one batched PCG solve (one set per column).
 struct Scal {
-  double rho, alpha, beta, bnorm2, tol2, rr, pq, dot;
-  int done, iters, maxit, status;  // status: 0 running, 1 converged, 2 max_iter, -6 breakdown
+  double rho[kMaxBatch], alpha[kMaxBatch], beta[kMaxBatch], bnorm2[kMaxBatch], rr[kMaxBatch],
+      pq[kMaxBatch];
+  double tol2;
+  int done[kMaxBatch], iters[kMaxBatch], status[kMaxBatch];  // status: 0 running, 1 converged,
+                                                            // 2 max_iter, -6 breakdown
+  int all_done, maxit, K;
 };
 
-// number of blocks covering rows [r0, r1)
 inline int64_t sell_blocks(int64_t r0, int64_t r1) {
   if (r1 <= r0) return 0;
   int64_t s0 = r0 / kWave, s1 = (r1 + kWave - 1) / kWave;
@@ -54,52 +71,70 @@ inline int64_t sell_blocks(int64_t r0, int64_t r1) {
 }
 inline int64_t vec_blocks(int64_t n) { return (n + kBlock - 1) / kBlock; }
 
-// y = A x (mode 0) or y = g - A x (mode 1) on rows [r0, r1); difference form
-// y_i = sum_j a_ij (x_j - x_i) + d_i x_i when diff, else d_i x_i + sum_j a_ij x_j.
-// With partial != null, partial[block] = sum over the block's rows of x_i y_i.
-void launch_spmv(hipStream_t st, const Sell &A, bool diff, int mode, int64_t r0, int64_t r1,
-                 const double *x, const double *g, double *y, double *partial, const int *done);
+// ---- fine matrix (SELL, difference form) ---------------------------------
+// y = A x (mode 0) or y = g - A x (mode 1) on rows [r0, r1).  With partial,
+// partial[block * K + k] = sum over the block's rows of x_ik y_ik.
+template <class T>
+void launch_spmv(hipStream_t st, int K, const Sell &A, int mode, int64_t r0, int64_t r1, const T *x, const T *g,
+                 T *y, double *partial, const int *done);
 // One multicolour Gauss-Seidel step on the rows [a0,a1) and [b0,b1) (rows of
 // one colour): x_i += (g_i - (A x)_i) / a_ii.
-void launch_gs(hipStream_t st, const Sell &A, bool diff, int64_t a0, int64_t a1, int64_t b0, int64_t b1,
-               const double *g, double *x, const int *done);
-// y = P x (accumulate: y += P x) for a rectangular SELL matrix, rows [0, nrows).
-void launch_rect(hipStream_t st, const Sell &P, bool accumulate, const double *x, double *y,
-                 const int *done);
-// z_i = (E~ y)_i + (i >= n_top ? w_i : 0); partial[block] = sum r_i z_i.
-void launch_prolong_sum(hipStream_t st, const Sell &E, int64_t n_top, const double *y, const double *w,
-                        const double *r, double *z, double *partial, const int *done);
-// x = Cinv g (dense m x m, row-major).
-void launch_dense(hipStream_t st, const double *Cinv, int64_t m, const double *g, double *x, const int *done);
-void launch_fill(hipStream_t st, double *x, int64_t n, double v, const int *done);
-void launch_copy(hipStream_t st, const double *a, double *b, int64_t n, const int *done);
-// partial[block] = sum a_i b_i
-void launch_dot(hipStream_t st, const double *a, const double *b, int64_t n, double *partial, const int *done);
-// z = r / diag
-void launch_jacobi(hipStream_t st, const double *r, const double *diag, double *z, int64_t n, const int *done);
-// storage <-> natural order
-void launch_gather(hipStream_t st, const double *nat, const int64_t *perm, double *sto, int64_t n);
-void launch_scatter(hipStream_t st, const double *sto, const int64_t *perm, double *nat, int64_t n);
+template <class T>
+void launch_gs(hipStream_t st, int K, const Sell &A, int64_t a0, int64_t a1, int64_t b0, int64_t b1, const T *g,
+               T *x, const int *done);
+// y = E x (accumulate: y += E x) for a rectangular SELL matrix, rows [0, nrows).
+template <class T>
+void launch_rect(hipStream_t st, int K, const Sell &E, bool accumulate, const T *x, T *y, const int *done);
+// z_i = (E~ y)_i + (i >= n_top ? w_i : 0); partial[block * K + k] = sum r_ik z_ik.
+template <class T>
+void launch_prolong_sum(hipStream_t st, int K, const Sell &E, int64_t n_top, const T *y, const T *w, const T *r,
+                        T *z, double *partial, const int *done);
 
-// CsrG versions.  mode 0: y = A x, 1: y = g - A x (square, standard form);
-// rect: y = P x or y += P x over rows [0, nrows).
-void launch_csr_spmv(hipStream_t st, const CsrG &A, int mode, int64_t r0, int64_t r1, const double *x,
-                     const double *g, double *y, const int *done);
-void launch_csr_gs(hipStream_t st, const CsrG &A, int64_t r0, int64_t r1, const double *g, double *x,
+// ---- coarse operators and transfers (CsrG) -------------------------------
+// mode 0: y = A x, 1: y = g - A x (square); rect: y = P x or y += P x.
+template <class T>
+void launch_csr_spmv(hipStream_t st, int K, const CsrG &A, int mode, int64_t r0, int64_t r1, const T *x,
+                     const T *g, T *y, const int *done);
+template <class T>
+void launch_csr_gs(hipStream_t st, int K, const CsrG &A, int64_t r0, int64_t r1, const T *g, T *x, const int *done);
+template <class T>
+void launch_csr_rect(hipStream_t st, int K, const CsrG &P, bool accumulate, const T *x, T *y, const int *done);
+// x = Cinv g (dense m x m FP64, row-major), K columns.
+template <class T>
+void launch_dense(hipStream_t st, int K, const double *Cinv, int64_t m, const T *g, T *x, const int *done);
+
+// ---- vectors ([n][K]) ----------------------------------------------------
+template <class T>
+void launch_fill(hipStream_t st, T *x, int64_t count, T v, const int *done);
+template <class T>
+void launch_copy(hipStream_t st, const T *a, T *b, int64_t count, const int *done);
+// partial[block * K + k] = sum a_ik b_ik
+template <class T>
+void launch_dot(hipStream_t st, int K, const T *a, const T *b, int64_t n, double *partial, const int *done);
+template <class T>
+void launch_jacobi(hipStream_t st, int K, const T *r, const double *diag, T *z, int64_t n, const int *done);
+// natural <-> storage order for column k of a batch (stride K)
+void launch_gather(hipStream_t st, int K, int k, const double *nat, const int64_t *perm, double *sto, int64_t n);
+void launch_scatter(hipStream_t st, int K, int k, const double *sto, const int64_t *perm, double *nat, int64_t n);
+// mixed precision: r32 = r64 * scale[k];  x64 (+)= scale[k] * d32
+void launch_demote(hipStream_t st, int K, const double *r64, const double *scale, float *r32, int64_t n,
                    const int *done);
-void launch_csr_rect(hipStream_t st, const CsrG &P, bool accumulate, const double *x, double *y, const int *done);
+void launch_promote(hipStream_t st, int K, const float *d32, const double *scale, double *x64, int64_t n,
+                    bool accumulate, const int *done);
 
-// PCG pieces (single-block scalar kernels sum the partials in index order).
-void launch_pcg_init(hipStream_t st, Scal *s, const double *pb, int64_t npb, double tol, int maxit);
-void launch_pcg_set_rho(hipStream_t st, Scal *s, const double *p, int64_t np);
-void launch_pcg_alpha(hipStream_t st, Scal *s, const double *p, int64_t np);
-void launch_pcg_xr(hipStream_t st, Scal *s, double *x, double *r, const double *p, const double *q, int64_t n,
-                   double *partial);
-void launch_pcg_conv(hipStream_t st, Scal *s, const double *p, int64_t np, double *hist);
-void launch_pcg_beta(hipStream_t st, Scal *s, const double *p, int64_t np);
-void launch_pcg_p(hipStream_t st, Scal *s, double *pvec, const double *z, int64_t n);
-void launch_reduce(hipStream_t st, const double *p, int64_t np, double *out);
-// clears the done flag before a restart (keeps the iteration count)
-void launch_pcg_resume(hipStream_t st, Scal *s);
+// ---- PCG scalars (single-block kernels sum partials in index order) ------
+void launch_pcg_init(hipStream_t st, int K, Scal *s, const double *pb, int64_t npb, double tol, int maxit);
+void launch_pcg_set_rho(hipStream_t st, int K, Scal *s, const double *p, int64_t np);
+void launch_pcg_alpha(hipStream_t st, int K, Scal *s, const double *p, int64_t np);
+template <class T>
+void launch_pcg_xr(hipStream_t st, int K, Scal *s, T *x, T *r, const T *p, const T *q, int64_t n, double *partial);
+void launch_pcg_conv(hipStream_t st, int K, Scal *s, const double *p, int64_t np);
+void launch_pcg_beta(hipStream_t st, int K, Scal *s, const double *p, int64_t np);
+template <class T>
+void launch_pcg_p(hipStream_t st, int K, Scal *s, T *pvec, const T *z, int64_t n);
+// out[k] = sum of the partials of column k
+void launch_reduce(hipStream_t st, int K, const double *p, int64_t np, double *out);
+// before a restart: clears done/status of the columns whose bit in keep is 0
+void launch_pcg_resume(hipStream_t st, int K, Scal *s, unsigned keep);
 
 }  // namespace vemg

@@ -131,15 +131,20 @@ def test_manufactured_solution(mode):
     assert np.max(np.abs(x[free] - xs[free])) / np.max(np.abs(xs[free])) < 1e-8
 
 
-def test_deterministic_and_batched_equals_single():
+@pytest.mark.parametrize("nrhs", [3, 8, 11])
+def test_deterministic_and_batched_equals_single(nrhs):
+    # every column of a batch (widths 4, 8 and 8+4 here) reproduces its
+    # single-column solve bit for bit, and repeated solves are identical
     m, s, o = _build(RAGGED, "N")
-    B = np.stack([s.rhs(fourier_field(m.xyz, RAGGED["H"], 200 + k)) for k in range(3)])
-    x1, it1, r1, _ = s.solve(B[1], rtol=1e-9)
-    x1b, _, _, _ = s.solve(B[1], rtol=1e-9)
-    assert torch.equal(x1, x1b)
+    B = np.stack([s.rhs(fourier_field(m.xyz, RAGGED["H"], 200 + k)) for k in range(nrhs)])
     xb, itb, rb, st = s.solve(B, rtol=1e-9)
-    assert torch.equal(xb[1], x1)
-    assert itb[1] == it1[0]
+    assert st == 0
+    for k in (0, nrhs // 2, nrhs - 1):
+        x1, it1, r1, _ = s.solve(B[k], rtol=1e-9)
+        x1b, _, _, _ = s.solve(B[k], rtol=1e-9)
+        assert torch.equal(x1, x1b)
+        assert itb[k] == it1[0]
+        assert torch.equal(xb[k], x1)
 
 
 def test_edge_cases():
@@ -166,6 +171,39 @@ def test_graph_replay_equals_eager():
         xb, ib, _, _ = s2.solve(b, rtol=1e-9)
         assert ia == ib
         assert torch.equal(xa, xb)
+
+
+@pytest.mark.parametrize("precision", ["mixed_ir", "mixed_pc"])
+@pytest.mark.parametrize("mode", ["N", "D"])
+def test_mixed_precision_matches_fp64_oracle(precision, mode):
+    # FP32 operators / preconditioner inside FP64 refinement or FP64 CG:
+    # the solution must match the FP64 oracle within 1e-6 (relative L2)
+    m, s, o = _build(RAGGED, mode, precision=precision)
+    b_nat = s.rhs(fourier_field(m.xyz, RAGGED["H"], 100))
+    xo, _, _, ok = osolver.solve(o, b_nat[o.perm], 1e-11, "vl_as", max_iter=5000)
+    B = np.stack([b_nat, 2.0 * b_nat, s.rhs(fourier_field(m.xyz, RAGGED["H"], 101))])
+    x, its, rels, st = s.solve(B, rtol=1e-9, max_iter=5000)
+    _print(precision, mode, "iters", its, "relres", rels, "status", st)
+    assert st == 0 and max(rels) <= 1e-9
+    x = x.cpu().numpy()
+    assert _rel(x[0][o.perm], xo) < 1e-6
+    assert _rel(x[1][o.perm], 2.0 * xo) < 1e-6
+
+
+def test_mixed_operators_fp32():
+    # FP32 versions of the hot-path operators against the FP64 oracle
+    m, s, o = _build(RAGGED, "N", precision="mixed_ir")
+    rng = np.random.default_rng(5)
+    n, nt = o.n, o.n_top
+    x = rng.standard_normal(n)
+    y = s.apply(lib.OP_A, x, n).cpu().numpy()
+    ref = osolver.apply_A(o, x)
+    scale = np.abs(o.Aoff).sum(axis=1).A.ravel() * np.abs(x).max()
+    assert np.max(np.abs(y - ref) / scale) < 1e-6
+    et = s.apply(lib.OP_ET, x, nt).cpu().numpy()
+    assert _rel(et, o.E.T @ x) < 1e-6
+    z = s.apply(lib.OP_PRECOND, x, n).cpu().numpy()
+    assert _rel(z, precond.make(o, "vl_as")(x)) < 1e-4
 
 
 def test_full_size_config2_residual_and_sampled_rows():
