@@ -200,6 +200,59 @@ const char *vemg_status_string(vemg_status st);
 /* Message of the last error on this handle ("" if none). */
 const char *vemg_last_error(vemg_solver s);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of solve requests over several resident
+ * meshes.  A scheduler thread owns one lane per mesh with 8 right-hand-side
+ * slots whose Krylov state stays in HBM.  Queued right-hand sides join free
+ * slots whenever the lane's current chunk of PCG iterations ends, converged
+ * columns retire after an FP64 true-residual check (so a column's result
+ * does not depend on what else shares its batch), and the chunks of
+ * different meshes run concurrently on their own streams.  Meshes are made
+ * resident (uploaded) against an HBM budget; idle meshes are evicted
+ * least-recently-used first.  Solves use the handle options given at
+ * creation (VEMG_MIXED_IR is served as VEMG_MIXED_PC: its FP64 CG keeps
+ * per-column state that can join and retire at any chunk boundary).
+ * ------------------------------------------------------------------------ */
+typedef struct vemg_server_s *vemg_server;
+
+typedef struct {
+  int64_t requests_done, columns_done, requests_queued;
+  double p50_ms, p99_ms, mean_ms, max_ms;  /* request latency, submit -> result written */
+  double solves_per_s;                     /* right-hand sides completed per second of busy time */
+  double busy_s;                           /* first submit -> last completion */
+  double mean_slot_occupancy;              /* active slots / 8, averaged over chunks */
+  int64_t chunks, uploads, evictions;
+  size_t resident_bytes, budget_bytes;
+} vemg_server_stats;
+
+/* hbm_budget: device bytes the resident meshes may use (0 = no limit). */
+vemg_status vemg_server_create(int device, size_t hbm_budget, const vemg_options *o, vemg_server *out);
+/* Registers a mesh (host setup now; same arguments as vemg_setup).  Fails
+ * with VEMG_ERR_OOM if the mesh alone exceeds the budget. */
+vemg_status vemg_server_add_mesh(vemg_server s, int64_t n_nodes, const double *xyz, int64_t n_tets,
+                                 const int64_t *tets, const uint8_t *top_mask, int *mesh_id);
+/* vemg_rhs for a registered mesh (host arrays). */
+vemg_status vemg_server_rhs(vemg_server s, int mesh_id, const double *f_host, double *b_host);
+/* Queues nrhs right-hand sides ([nrhs][n_nodes], device, natural order,
+ * fully written before the call) and returns at once.  x ([nrhs][n_nodes],
+ * device) is written when the request completes; both buffers must stay
+ * valid until then. */
+vemg_status vemg_server_submit(vemg_server s, int mesh_id, int nrhs, const double *b_dev, double *x_dev,
+                               double rtol, int max_iter, uint64_t *req_id);
+/* Ids of requests completed since the last poll (at most cap). */
+vemg_status vemg_server_poll(vemg_server s, uint64_t *done_ids, int cap, int *n_done);
+/* Blocks until the request is complete (timeout_s <= 0: no timeout). */
+vemg_status vemg_server_wait(vemg_server s, uint64_t req_id, double timeout_s);
+/* Result of a completed request: worst column status, and per column the
+ * iterations and true relative residual (arrays of nrhs, may be NULL). */
+vemg_status vemg_server_result(vemg_server s, uint64_t req_id, int *status, int *iters, double *relres,
+                               double *latency_ms);
+vemg_status vemg_server_get_stats(vemg_server s, vemg_server_stats *st);
+/* Finishes queued work, stops the scheduler and frees every mesh. */
+vemg_status vemg_server_destroy(vemg_server s);
+/* Message of the last server error ("" if none). */
+const char *vemg_server_last_error(vemg_server s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,6 +6,6 @@ gfx950); this package is a thin ctypes binding over its C ABI (include/vemg.h)
 that passes PyTorch device tensors as raw pointers.
 """
 from ._lib import (  # noqa: F401
-    Solver, VemgError, load_library, library_path, OP_A, OP_PRECOND, OP_ET, OP_E,
+    Solver, Server, VemgError, load_library, library_path, OP_A, OP_PRECOND, OP_ET, OP_E,
     OP_VCYCLE_S, OP_VCYCLE_ABAR, OP_GS_FWD, STATUS,
 )

@@ -46,6 +46,14 @@ class Info(C.Structure):
                 ("device_bytes", C.c_size_t)]
 
 
+class ServerStats(C.Structure):
+    _fields_ = [("requests_done", C.c_int64), ("columns_done", C.c_int64), ("requests_queued", C.c_int64),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("max_ms", C.c_double),
+                ("solves_per_s", C.c_double), ("busy_s", C.c_double), ("mean_slot_occupancy", C.c_double),
+                ("chunks", C.c_int64), ("uploads", C.c_int64), ("evictions", C.c_int64),
+                ("resident_bytes", C.c_size_t), ("budget_bytes", C.c_size_t)]
+
+
 def library_path():
     return os.path.join(_HERE, "libvemg.so")
 
@@ -75,6 +83,22 @@ def load_library():
     lib.vemg_status_string.restype = C.c_char_p
     lib.vemg_last_error.argtypes = [P]
     lib.vemg_last_error.restype = C.c_char_p
+    U64 = C.c_uint64
+    lib.vemg_server_create.argtypes = [I32, C.c_size_t, C.POINTER(Options), C.POINTER(P)]
+    lib.vemg_server_add_mesh.argtypes = [P, I64, P, I64, P, P, C.POINTER(I32)]
+    lib.vemg_server_rhs.argtypes = [P, I32, P, P]
+    lib.vemg_server_submit.argtypes = [P, I32, I32, P, P, D, I32, C.POINTER(U64)]
+    lib.vemg_server_poll.argtypes = [P, C.POINTER(U64), I32, C.POINTER(I32)]
+    lib.vemg_server_wait.argtypes = [P, U64, D]
+    lib.vemg_server_result.argtypes = [P, U64, C.POINTER(I32), P, P, C.POINTER(D)]
+    lib.vemg_server_get_stats.argtypes = [P, C.POINTER(ServerStats)]
+    lib.vemg_server_destroy.argtypes = [P]
+    lib.vemg_server_last_error.argtypes = [P]
+    lib.vemg_server_last_error.restype = C.c_char_p
+    for f in ("vemg_server_create", "vemg_server_add_mesh", "vemg_server_rhs", "vemg_server_submit",
+              "vemg_server_poll", "vemg_server_wait", "vemg_server_result", "vemg_server_get_stats",
+              "vemg_server_destroy"):
+        getattr(lib, f).restype = I32
     for f in ("vemg_create", "vemg_setup", "vemg_rhs", "vemg_matvec", "vemg_solve", "vemg_apply",
               "vemg_get_info", "vemg_export", "vemg_destroy", "vemg_time_op"):
         getattr(lib, f).restype = I32
@@ -206,3 +230,103 @@ class Solver:
         out = self._torch.empty(out_len, dtype=self._torch.float64, device=self.dev)
         self._check(self._lib.vemg_apply(self._h, op, _ptr(v), _ptr(out)), self._h)
         return out
+
+
+class Server:
+    """Continuous-batching solve server over several resident meshes.
+
+    Device buffers of every submitted request are kept alive here until the
+    request is collected with result()."""
+
+    def __init__(self, *, device=0, hbm_budget=0, top_bc="pinned", pc="vl_as", precision="mixed_pc",
+                 poll_every=8, coarse_max=2048, max_restarts=5):
+        import torch
+        self._torch = torch
+        self._lib = load_library()
+        opt = Options()
+        self._lib.vemg_default_options(C.byref(opt))
+        opt.top_bc = _TOP[top_bc]
+        opt.pc = _PC[pc]
+        opt.precision = _PREC[precision]
+        opt.poll_every = poll_every
+        opt.coarse_max = coarse_max
+        opt.max_restarts = max_restarts
+        self.dev = torch.device("cuda", device)
+        h = C.c_void_p()
+        self._check(self._lib.vemg_server_create(device, hbm_budget, C.byref(opt), C.byref(h)))
+        self._h = h
+        self._live = {}
+        self.n_nodes = []
+
+    def _check(self, st):
+        if st < 0:
+            msg = self._lib.vemg_server_last_error(self._h).decode() if getattr(self, "_h", None) else ""
+            raise VemgError(st, msg)
+        return st
+
+    def add_mesh(self, xyz, tets, top):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tets = np.ascontiguousarray(tets, dtype=np.int64)
+        top = np.ascontiguousarray(top, dtype=np.uint8)
+        mid = C.c_int(0)
+        self._check(self._lib.vemg_server_add_mesh(self._h, xyz.shape[0], xyz.ctypes.data, tets.shape[0],
+                                                   tets.ctypes.data, top.ctypes.data, C.byref(mid)))
+        self.n_nodes.append(xyz.shape[0])
+        return mid.value
+
+    def rhs(self, mesh_id, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        b = np.empty_like(f)
+        self._check(self._lib.vemg_server_rhs(self._h, mesh_id, f.ctypes.data, b.ctypes.data))
+        return b
+
+    def submit(self, mesh_id, b, rtol=1e-8, max_iter=5000):
+        """b: CUDA float64 tensor [nrhs, n_nodes] (written and synchronised)."""
+        torch = self._torch
+        b = b.to(device=self.dev, dtype=torch.float64).contiguous()
+        if b.dim() == 1:
+            b = b[None]
+        x = torch.empty_like(b)
+        torch.cuda.synchronize(self.dev)
+        rid = C.c_uint64(0)
+        self._check(self._lib.vemg_server_submit(self._h, mesh_id, b.shape[0], _ptr(b), _ptr(x), rtol, max_iter,
+                                                 C.byref(rid)))
+        self._live[rid.value] = (b, x)
+        return rid.value
+
+    def poll(self, cap=1024):
+        ids = (C.c_uint64 * cap)()
+        n = C.c_int(0)
+        self._check(self._lib.vemg_server_poll(self._h, ids, cap, C.byref(n)))
+        return [ids[i] for i in range(n.value)]
+
+    def wait(self, rid, timeout=0.0):
+        self._check(self._lib.vemg_server_wait(self._h, rid, timeout))
+
+    def result(self, rid):
+        """(x tensor [nrhs, n_nodes], status, iters, relres, latency_ms); releases the request."""
+        b, x = self._live.pop(rid)
+        nrhs = b.shape[0]
+        st = C.c_int(0)
+        its = (C.c_int * nrhs)()
+        rel = (C.c_double * nrhs)()
+        lat = C.c_double(0.0)
+        self._check(self._lib.vemg_server_result(self._h, rid, C.byref(st), its, rel, C.byref(lat)))
+        return x, st.value, list(its), list(rel), lat.value
+
+    def stats(self):
+        s = ServerStats()
+        self._check(self._lib.vemg_server_get_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.vemg_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -11,9 +11,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
 #include <map>
+#include <mutex>
+#include <thread>
 #include <memory>
 #include <string>
 #include <type_traits>
@@ -709,6 +714,9 @@ void upload(Handle *h) {
   h->scale_in = h->ar.alloc<double>(kMaxBatch);
   h->scale_out = h->ar.alloc<double>(kMaxBatch);
   h->scal = h->ar.alloc<Scal>(1);
+  // every column starts finished (no right-hand side yet)
+  launch_fill<double>(st, h->part_b, kMaxBatch, 0.0, nullptr);
+  launch_pcg_init(st, kMaxBatch, h->scal, h->part_b, 1, 1.0, 1);
   // the top block of the smoother vectors stays zero
   launch_fill<double>(st, h->v64.w, (int64_t)cnt, 0.0, nullptr);
   launch_fill<float>(st, h->v32.w, (int64_t)cnt, 0.0f, nullptr);
@@ -984,6 +992,282 @@ int guarded(Handle *h, F &&f) {
 }  // namespace
 }  // namespace vemg
 
+
+// ============================================================== serving
+namespace vemg {
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct SReq {
+  uint64_t id = 0;
+  int mesh = 0, nrhs = 0, max_iter = 0;
+  const double *b = nullptr;
+  double *x = nullptr;
+  double rtol = 0.0, t_submit = 0.0, t_done = 0.0;
+  int cols_left = 0, status = VEMG_OK;
+  bool done = false;
+  std::vector<int> iters;
+  std::vector<double> rel;
+};
+
+struct SSlot {
+  int64_t req = -1;  // index into Server::reqs
+  int col = 0, restarts = 0;
+  double prev = INFINITY;
+};
+
+struct Lane {
+  vemg_solver_s *h = nullptr;
+  bool resident = false;
+  size_t footprint = 0;
+  std::deque<std::pair<int64_t, int>> queue;  // (request, column)
+  SSlot slot[kMaxBatch];
+  bool launched = false;
+  uint64_t last_used = 0;
+  bool busy() const {
+    if (!queue.empty()) return true;
+    for (auto &s : slot)
+      if (s.req >= 0) return true;
+    return false;
+  }
+};
+
+}  // namespace
+}  // namespace vemg
+
+struct vemg_server_s {
+  int device = 0;
+  size_t budget = 0, used = 0;
+  vemg_options opt;
+  std::vector<std::unique_ptr<vemg::Lane>> lanes;
+  std::vector<std::unique_ptr<vemg::SReq>> reqs;
+  std::map<uint64_t, int64_t> by_id;
+  std::deque<int64_t> incoming, completed;
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  std::thread worker;
+  bool stop = false, started = false;
+  uint64_t next_id = 1, tick = 0;
+  std::string err;
+  double first_submit = -1.0, last_done = -1.0;
+  int64_t chunks = 0, uploads = 0, evictions = 0, cols_done = 0;
+  double occupancy_sum = 0.0;
+  int64_t queued_cols = 0;
+};
+
+namespace vemg {
+namespace {
+
+using Server = vemg_server_s;
+
+void lane_release(Server *sv, Lane &L) {
+  destroy_graphs(L.h);
+  L.h->ar.release();
+  L.resident = false;
+  sv->used -= L.footprint;
+  sv->evictions++;
+}
+
+// make a lane resident, evicting idle lanes (least recently used first)
+bool lane_admit(Server *sv, Lane &L) {
+  if (L.resident) return true;
+  while (sv->budget && sv->used + L.footprint > sv->budget) {
+    Lane *victim = nullptr;
+    for (auto &o : sv->lanes)
+      if (o->resident && !o->busy() && (!victim || o->last_used < victim->last_used)) victim = o.get();
+    if (!victim) return false;
+    lane_release(sv, *victim);
+  }
+  upload(L.h);
+  L.footprint = L.h->ar.bytes;
+  L.resident = true;
+  sv->used += L.footprint;
+  sv->uploads++;
+  return true;
+}
+
+double lane_tol(Server *sv, Lane &L) {
+  double t = 1.0;
+  for (auto &sl : L.slot)
+    if (sl.req >= 0) t = std::min(t, sv->reqs[sl.req]->rtol);
+  return t;
+}
+
+int lane_maxit(Server *sv, Lane &L) {
+  int m = 1;
+  for (auto &sl : L.slot)
+    if (sl.req >= 0) m = std::max(m, sv->reqs[sl.req]->max_iter);
+  return std::min(m, 1 << 20);
+}
+
+// (re)start the slot columns in mask: join (x = 0, r = b) or restart (r = res)
+void lane_start(Server *sv, Lane &L, unsigned mask, bool restart) {
+  Handle *h = L.h;
+  hipStream_t st = h->work;
+  int64_t n = h->P.n, N = h->P.n_nodes;
+  if (!restart)
+    for (int k = 0; k < kMaxBatch; ++k)
+      if ((mask >> k) & 1u) {
+        SReq &q = *sv->reqs[L.slot[k].req];
+        launch_gather(st, kMaxBatch, k, q.b + (int64_t)L.slot[k].col * N, h->perm, h->b, n);
+      }
+  launch_slot_vectors(st, mask, restart, h->b, h->v64.res, h->v64.x, h->v64.r, n);
+  launch_dot<double>(st, kMaxBatch, h->b, h->b, n, h->part_b, nullptr);
+  launch_slot_scalars(st, mask, restart, h->scal, h->part_b, vec_blocks(n), lane_tol(sv, L), lane_maxit(sv, L),
+                      h->scale_in, h->scale_out);
+  int64_t np = 0;
+  if (h->opt.precision != VEMG_FP64)
+    np = precond_mixed(h, kMaxBatch, h->v64.r, h->v64.z, nullptr);
+  else
+    precond<double>(h, kMaxBatch, h->v64.r, h->v64.z, h->part_rz, &np, nullptr);
+  launch_slot_rho(st, mask, h->scal, h->part_rz, np);
+  launch_slot_copy(st, mask, h->v64.z, h->v64.p, n);
+}
+
+void finish_request(Server *sv, SReq &q) {
+  std::lock_guard<std::mutex> lk(sv->mu);
+  q.done = true;
+  q.t_done = now_s();
+  sv->completed.push_back(sv->by_id[q.id]);
+  sv->last_done = q.t_done;
+  sv->cv_done.notify_all();
+}
+
+// columns that finished their chunk: confirm on the FP64 true residual and
+// retire them, or restart them from the true residual
+void lane_collect(Server *sv, Lane &L) {
+  Handle *h = L.h;
+  hipStream_t st = h->work;
+  Scal hs = read_scal(h);
+  unsigned fin = 0;
+  for (int k = 0; k < kMaxBatch; ++k)
+    if (L.slot[k].req >= 0 && hs.done[k]) fin |= 1u << k;
+  if (!fin) return;
+  double rr[kMaxBatch];
+  true_residual(h, kMaxBatch, rr);
+  unsigned restart = 0;
+  std::vector<SReq *> finished;
+  int64_t n = h->P.n, N = h->P.n_nodes;
+  for (int k = 0; k < kMaxBatch; ++k) {
+    if (!((fin >> k) & 1u)) continue;
+    SSlot &sl = L.slot[k];
+    SReq &q = *sv->reqs[sl.req];
+    double bb = hs.bnorm2[k];
+    double rel;
+    int status;
+    if (bb == 0.0) {
+      rel = 0.0;
+      status = VEMG_OK;
+    } else if (hs.status[k] == -6 || !std::isfinite(bb)) {
+      rel = NAN;
+      status = VEMG_ERR_BREAKDOWN;
+    } else {
+      rel = std::sqrt(rr[k] / bb);
+      if (rel <= q.rtol) status = VEMG_OK;
+      else if (hs.iters[k] >= q.max_iter) status = VEMG_WARN_MAXITER;
+      else if (sl.restarts >= h->opt.max_restarts || rel > 0.5 * sl.prev) status = VEMG_WARN_FLOOR;
+      else {
+        sl.prev = rel;
+        sl.restarts++;
+        restart |= 1u << k;
+        continue;
+      }
+    }
+    double *xk = q.x + (int64_t)sl.col * N;
+    launch_fill<double>(st, xk, N, 0.0, nullptr);
+    launch_scatter(st, kMaxBatch, k, h->v64.x, h->perm, xk, n);
+    q.iters[sl.col] = hs.iters[k];
+    q.rel[sl.col] = rel;
+    if (status < 0 || (q.status >= 0 && status > q.status)) q.status = status;
+    if (--q.cols_left == 0) finished.push_back(&q);
+    sl = SSlot();
+    sv->cols_done++;
+  }
+  if (restart) lane_start(sv, L, restart, true);
+  HIPCHK(hipStreamSynchronize(st));
+  for (SReq *q : finished) finish_request(sv, *q);
+}
+
+void server_loop(Server *sv) {
+  (void)hipSetDevice(sv->device);
+  while (true) {
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      auto has_work = [&]() {
+        if (!sv->incoming.empty()) return true;
+        for (auto &L : sv->lanes)
+          if (L->busy()) return true;
+        return false;
+      };
+      sv->cv.wait(lk, [&]() { return sv->stop || has_work(); });
+      if (sv->stop && !has_work()) break;
+      while (!sv->incoming.empty()) {
+        int64_t ri = sv->incoming.front();
+        sv->incoming.pop_front();
+        SReq &q = *sv->reqs[ri];
+        for (int c = 0; c < q.nrhs; ++c) sv->lanes[q.mesh]->queue.emplace_back(ri, c);
+      }
+    }
+    try {
+      // admission, joins and launches: every lane's chunk is queued before
+      // any lane is waited on, so different meshes overlap on the device
+      for (auto &Lp : sv->lanes) {
+        Lane &L = *Lp;
+        L.launched = false;
+        if (!L.busy()) continue;
+        if (!lane_admit(sv, L)) continue;
+        L.last_used = ++sv->tick;
+        unsigned mask = 0;
+        for (int k = 0; k < kMaxBatch && !L.queue.empty(); ++k)
+          if (L.slot[k].req < 0) {
+            L.slot[k] = SSlot();
+            L.slot[k].req = L.queue.front().first;
+            L.slot[k].col = L.queue.front().second;
+            L.queue.pop_front();
+            mask |= 1u << k;
+          }
+        if (mask) lane_start(sv, L, mask, false);
+        int active = 0;
+        for (auto &sl : L.slot) active += sl.req >= 0;
+        if (!active) continue;
+        int kind = L.h->opt.precision != VEMG_FP64 ? kGraphMixedPC : kGraphFP64;
+        for (int it = 0; it < L.h->opt.poll_every; ++it) run_iteration<double>(L.h, kMaxBatch, kind);
+        L.launched = true;
+        sv->chunks++;
+        sv->occupancy_sum += active / (double)kMaxBatch;
+      }
+      for (auto &Lp : sv->lanes)
+        if (Lp->launched) lane_collect(sv, *Lp);
+    } catch (const std::exception &e) {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->err = e.what();
+      sv->stop = true;
+      // fail every pending request so that waiters return
+      for (auto &q : sv->reqs)
+        if (!q->done) {
+          q->done = true;
+          q->status = VEMG_ERR_DEVICE;
+          q->t_done = now_s();
+          sv->completed.push_back(sv->by_id[q->id]);
+        }
+      for (auto &L : sv->lanes) {
+        L->queue.clear();
+        for (auto &sl : L->slot) sl = SSlot();
+      }
+      sv->incoming.clear();
+      sv->cv_done.notify_all();
+      break;
+    }
+  }
+}
+
+}  // namespace
+}  // namespace vemg
+
 using vemg::guarded;
 
 extern "C" {
@@ -1178,5 +1462,198 @@ const char *vemg_status_string(vemg_status st) {
 }
 
 const char *vemg_last_error(vemg_solver s) { return s ? s->err.c_str() : ""; }
+
+
+vemg_status vemg_server_create(int device, size_t hbm_budget, const vemg_options *o, vemg_server *out) {
+  if (!out || device < 0) return VEMG_ERR_INVALID_ARG;
+  *out = nullptr;
+  auto *sv = new (std::nothrow) vemg_server_s();
+  if (!sv) return VEMG_ERR_OOM;
+  if (o)
+    sv->opt = *o;
+  else
+    vemg_default_options(&sv->opt);
+  if (sv->opt.precision == VEMG_MIXED_IR) sv->opt.precision = VEMG_MIXED_PC;
+  sv->device = device;
+  sv->budget = hbm_budget;
+  *out = sv;
+  return VEMG_OK;
+}
+
+vemg_status vemg_server_add_mesh(vemg_server sv, int64_t n_nodes, const double *xyz, int64_t n_tets,
+                                 const int64_t *tets, const uint8_t *top_mask, int *mesh_id) {
+  if (!sv || !mesh_id) return VEMG_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (sv->started) {
+    sv->err = "meshes must be added before the first submit";
+    return VEMG_ERR_STATE;
+  }
+  vemg_solver h = nullptr;
+  vemg_status st = vemg_create(&sv->opt, sv->device, nullptr, &h);
+  if (st != VEMG_OK) return st;
+  st = vemg_setup(h, n_nodes, xyz, n_tets, tets, top_mask);
+  if (st != VEMG_OK) {
+    sv->err = h->err;
+    vemg_destroy(h);
+    return st;
+  }
+  auto L = std::make_unique<vemg::Lane>();
+  L->h = h;
+  L->footprint = h->ar.bytes;
+  L->resident = true;
+  sv->used += L->footprint;
+  sv->uploads++;
+  if (sv->budget && L->footprint > sv->budget) {
+    sv->err = "mesh needs more device memory than the budget";
+    vemg_destroy(h);
+    sv->used -= L->footprint;
+    return VEMG_ERR_OOM;
+  }
+  if (sv->budget && sv->used > sv->budget) {
+    // keep the host setup; the scheduler uploads the mesh when it is needed
+    int r = guarded(h, [&]() -> int {
+      vemg::lane_release(sv, *L);
+      sv->evictions--;
+      return VEMG_OK;
+    });
+    if (r != VEMG_OK) return (vemg_status)r;
+  }
+  *mesh_id = (int)sv->lanes.size();
+  sv->lanes.push_back(std::move(L));
+  return VEMG_OK;
+}
+
+vemg_status vemg_server_rhs(vemg_server sv, int mesh_id, const double *f_host, double *b_host) {
+  if (!sv || mesh_id < 0 || mesh_id >= (int)sv->lanes.size()) return VEMG_ERR_INVALID_ARG;
+  return vemg_rhs(sv->lanes[mesh_id]->h, f_host, b_host);
+}
+
+vemg_status vemg_server_submit(vemg_server sv, int mesh_id, int nrhs, const double *b_dev, double *x_dev, double rtol,
+                               int max_iter, uint64_t *req_id) {
+  if (!sv || !b_dev || !x_dev || nrhs < 1 || !(rtol >= 0.0) || max_iter < 1) return VEMG_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (mesh_id < 0 || mesh_id >= (int)sv->lanes.size()) return VEMG_ERR_INVALID_ARG;
+  if (sv->stop) return VEMG_ERR_STATE;
+  if (!sv->started) {
+    sv->started = true;
+    sv->worker = std::thread(vemg::server_loop, sv);
+  }
+  auto q = std::make_unique<vemg::SReq>();
+  q->id = sv->next_id++;
+  q->mesh = mesh_id;
+  q->nrhs = nrhs;
+  q->b = b_dev;
+  q->x = x_dev;
+  q->rtol = rtol;
+  q->max_iter = max_iter;
+  q->t_submit = vemg::now_s();
+  q->cols_left = nrhs;
+  q->iters.assign(nrhs, 0);
+  q->rel.assign(nrhs, 0.0);
+  if (sv->first_submit < 0) sv->first_submit = q->t_submit;
+  if (req_id) *req_id = q->id;
+  sv->by_id[q->id] = (int64_t)sv->reqs.size();
+  sv->incoming.push_back((int64_t)sv->reqs.size());
+  sv->reqs.push_back(std::move(q));
+  sv->cv.notify_all();
+  return VEMG_OK;
+}
+
+vemg_status vemg_server_poll(vemg_server sv, uint64_t *done_ids, int cap, int *n_done) {
+  if (!sv || !n_done || (cap > 0 && !done_ids)) return VEMG_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  int k = 0;
+  while (k < cap && !sv->completed.empty()) {
+    done_ids[k++] = sv->reqs[sv->completed.front()]->id;
+    sv->completed.pop_front();
+  }
+  *n_done = k;
+  return sv->err.empty() ? VEMG_OK : VEMG_ERR_DEVICE;
+}
+
+vemg_status vemg_server_wait(vemg_server sv, uint64_t req_id, double timeout_s) {
+  if (!sv) return VEMG_ERR_INVALID_ARG;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->by_id.find(req_id);
+  if (it == sv->by_id.end()) return VEMG_ERR_INVALID_ARG;
+  vemg::SReq *q = sv->reqs[it->second].get();
+  auto pred = [&]() { return q->done; };
+  if (timeout_s > 0) {
+    if (!sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) return VEMG_ERR_STATE;
+  } else {
+    sv->cv_done.wait(lk, pred);
+  }
+  return sv->err.empty() ? VEMG_OK : VEMG_ERR_DEVICE;
+}
+
+vemg_status vemg_server_result(vemg_server sv, uint64_t req_id, int *status, int *iters, double *relres,
+                               double *latency_ms) {
+  if (!sv) return VEMG_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->by_id.find(req_id);
+  if (it == sv->by_id.end()) return VEMG_ERR_INVALID_ARG;
+  vemg::SReq &q = *sv->reqs[it->second];
+  if (!q.done) return VEMG_ERR_STATE;
+  if (status) *status = q.status;
+  for (int c = 0; c < q.nrhs; ++c) {
+    if (iters) iters[c] = q.iters[c];
+    if (relres) relres[c] = q.rel[c];
+  }
+  if (latency_ms) *latency_ms = 1e3 * (q.t_done - q.t_submit);
+  return VEMG_OK;
+}
+
+vemg_status vemg_server_get_stats(vemg_server sv, vemg_server_stats *st) {
+  if (!sv || !st) return VEMG_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  std::memset(st, 0, sizeof(*st));
+  std::vector<double> lat;
+  for (auto &q : sv->reqs)
+    if (q->done) lat.push_back(1e3 * (q->t_done - q->t_submit));
+  std::sort(lat.begin(), lat.end());
+  st->requests_done = (int64_t)lat.size();
+  st->requests_queued = (int64_t)sv->reqs.size() - st->requests_done;
+  st->columns_done = sv->cols_done;
+  if (!lat.empty()) {
+    auto pct = [&](double p) {
+      double pos = p * (double)(lat.size() - 1);
+      size_t i = (size_t)pos;
+      double f = pos - (double)i;
+      return i + 1 < lat.size() ? lat[i] * (1.0 - f) + lat[i + 1] * f : lat[i];
+    };
+    st->p50_ms = pct(0.50);
+    st->p99_ms = pct(0.99);
+    double sum = 0.0;
+    for (double v : lat) sum += v;
+    st->mean_ms = sum / (double)lat.size();
+    st->max_ms = lat.back();
+  }
+  if (sv->last_done > sv->first_submit && sv->first_submit >= 0) {
+    st->busy_s = sv->last_done - sv->first_submit;
+    st->solves_per_s = (double)sv->cols_done / st->busy_s;
+  }
+  st->mean_slot_occupancy = sv->chunks ? sv->occupancy_sum / (double)sv->chunks : 0.0;
+  st->chunks = sv->chunks;
+  st->uploads = sv->uploads;
+  st->evictions = sv->evictions;
+  st->resident_bytes = sv->used;
+  st->budget_bytes = sv->budget;
+  return VEMG_OK;
+}
+
+vemg_status vemg_server_destroy(vemg_server sv) {
+  if (!sv) return VEMG_ERR_INVALID_ARG;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+    sv->cv.notify_all();
+  }
+  if (sv->worker.joinable()) sv->worker.join();
+  for (auto &L : sv->lanes) vemg_destroy(L->h);
+  delete sv;
+  return VEMG_OK;
+}
+
+const char *vemg_server_last_error(vemg_server sv) { return sv ? sv->err.c_str() : ""; }
 
 }  // extern "C"

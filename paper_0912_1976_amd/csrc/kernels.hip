@@ -596,9 +596,92 @@ __global__ void k_pcg_resume(Scal *s, unsigned keep) {
   }
 }
 
+__global__ void k_slot_vectors(unsigned mask, int restart, const double *__restrict__ b, const double *__restrict__ res,
+                               double *__restrict__ x, double *__restrict__ r, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * kMaxBatch) return;
+  int k = (int)(i % kMaxBatch);
+  if (!((mask >> k) & 1u)) return;
+  if (restart) {
+    r[i] = res[i];
+  } else {
+    x[i] = 0.0;
+    r[i] = b[i];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_slot_scalars(unsigned mask, int restart, Scal *s, const double *pb,
+                                                         int64_t npb, double tol, int maxit, double *scale_in,
+                                                         double *scale_out) {
+  for (int k = 0; k < kMaxBatch; ++k) {
+    if (!((mask >> k) & 1u)) continue;
+    double t = restart ? 0.0 : sum_partials(pb, npb, kMaxBatch, k);
+    if (threadIdx.x == 0) {
+      if (!restart) {
+        s->bnorm2[k] = t;
+        s->iters[k] = 0;
+        double nb = sqrt(t);
+        bool ok = t > 0.0 && isfinite(t);
+        scale_in[k] = ok ? 1.0 / nb : 0.0;
+        scale_out[k] = ok ? nb : 0.0;
+      }
+      const double bb = s->bnorm2[k];
+      if (bb == 0.0) {
+        s->done[k] = 1;
+        s->status[k] = 1;
+      } else if (!isfinite(bb)) {
+        s->done[k] = 1;
+        s->status[k] = -6;
+      } else {
+        s->done[k] = 0;
+        s->status[k] = 0;
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    s->K = kMaxBatch;
+    s->tol2 = tol * tol;
+    s->maxit = maxit;
+    update_all_done(s);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_slot_rho(unsigned mask, Scal *s, const double *p, int64_t np) {
+  for (int k = 0; k < kMaxBatch; ++k) {
+    if (!((mask >> k) & 1u)) continue;
+    double t = sum_partials(p, np, kMaxBatch, k);
+    if (threadIdx.x == 0) s->rho[k] = t;
+  }
+}
+
+__global__ void k_slot_copy(unsigned mask, const double *__restrict__ z, double *__restrict__ p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * kMaxBatch) return;
+  if ((mask >> (int)(i % kMaxBatch)) & 1u) p[i] = z[i];
+}
+
 inline dim3 grid(int64_t nb) { return dim3((unsigned)nb); }
 
 }  // namespace
+
+void launch_slot_vectors(hipStream_t stm, unsigned mask, bool restart, const double *b, const double *res, double *x,
+                         double *r, int64_t n) {
+  if (n <= 0 || !mask) return;
+  hipLaunchKernelGGL(k_slot_vectors, grid(vec_blocks(n * kMaxBatch)), dim3(kBlock), 0, stm, mask, (int)restart, b, res,
+                     x, r, n);
+}
+void launch_slot_scalars(hipStream_t stm, unsigned mask, bool restart, Scal *s, const double *pb, int64_t npb,
+                         double tol, int maxit, double *scale_in, double *scale_out) {
+  hipLaunchKernelGGL(k_slot_scalars, dim3(1), dim3(kBlock), 0, stm, mask, (int)restart, s, pb, npb, tol, maxit,
+                     scale_in, scale_out);
+}
+void launch_slot_rho(hipStream_t stm, unsigned mask, Scal *s, const double *p, int64_t np) {
+  hipLaunchKernelGGL(k_slot_rho, dim3(1), dim3(kBlock), 0, stm, mask, s, p, np);
+}
+void launch_slot_copy(hipStream_t stm, unsigned mask, const double *z, double *p, int64_t n) {
+  if (n <= 0 || !mask) return;
+  hipLaunchKernelGGL(k_slot_copy, grid(vec_blocks(n * kMaxBatch)), dim3(kBlock), 0, stm, mask, z, p, n);
+}
 
 #define VEMG_K_SWITCH(K, ...) \
   switch (K) {                \

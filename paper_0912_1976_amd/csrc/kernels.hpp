@@ -137,4 +137,19 @@ void launch_reduce(hipStream_t st, int K, const double *p, int64_t np, double *o
 // before a restart: clears done/status of the columns whose bit in keep is 0
 void launch_pcg_resume(hipStream_t st, int K, Scal *s, unsigned keep);
 
+// Continuous batching (K = kMaxBatch slots): columns in `mask` (re)start
+// while the others keep their state.
+//   join: x_k = 0, r_k = b_k;   restart: r_k = res_k (x_k kept)
+void launch_slot_vectors(hipStream_t st, unsigned mask, bool restart, const double *b, const double *res,
+                         double *x, double *r, int64_t n);
+// join: bnorm2_k from the partials of b.b, iters_k = 0; both: done_k = 0
+// (1 for a zero right-hand side), status_k = 0, and the FP32 scaling of the
+// preconditioner input scale_in_k = 1/||b_k||, scale_out_k = ||b_k||
+void launch_slot_scalars(hipStream_t st, unsigned mask, bool restart, Scal *s, const double *pb, int64_t npb,
+                         double tol, int maxit, double *scale_in, double *scale_out);
+// rho_k from the partials of r.z, for the columns in mask
+void launch_slot_rho(hipStream_t st, unsigned mask, Scal *s, const double *p, int64_t np);
+// p_k = z_k for the columns in mask
+void launch_slot_copy(hipStream_t st, unsigned mask, const double *z, double *p, int64_t n);
+
 }  // namespace vemg

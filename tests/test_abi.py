@@ -1,0 +1,62 @@
+"""The C ABI (include/vemg.h) without a GPU: every declared function is
+exported, options and status strings behave, and host-only handles reject
+compute calls."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+lib_mod = pytest.importorskip("paper_0912_1976_amd")
+
+from inputs import box_mesh  # noqa: E402
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "vemg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vemg_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = lib_mod.load_library()
+    names = declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_default_options_are_the_papers_parameters():
+    lib = lib_mod.load_library()
+    o = lib_mod._lib.Options()
+    lib.vemg_default_options(C.byref(o))
+    assert o.theta == 0.01 and abs(o.prolong_omega - 2.0 / 3.0) < 1e-15
+    assert o.pc == 0 and o.top_bc == 0 and o.precision == 0
+
+
+def test_status_strings_and_invalid_arguments():
+    lib = lib_mod.load_library()
+    for st in range(-7, 3):
+        assert lib.vemg_status_string(st)
+    o = lib_mod._lib.Options()
+    lib.vemg_default_options(C.byref(o))
+    o.theta = -1.0
+    h = C.c_void_p()
+    assert lib.vemg_create(C.byref(o), -1, None, C.byref(h)) == -1
+    assert lib.vemg_create(None, -1, None, None) == -1
+
+
+def test_host_only_handle_rejects_compute():
+    m = box_mesh(5, 5, 3, 0.01)
+    s = lib_mod.Solver(m.xyz, m.tets, m.top, device=-1)
+    lib = s._lib
+    dummy = C.c_void_p(16)
+    assert lib.vemg_solve(s._h, 1, dummy, dummy, 1e-8, 10, None, None) == -7
+    assert lib.vemg_matvec(s._h, dummy, dummy) == -7
+    assert lib.vemg_apply(s._h, 0, dummy, dummy) == -7
+    # rhs is host-side and works
+    b = s.rhs(np.ones(m.n))
+    assert np.isfinite(b).all()
