@@ -1,13 +1,18 @@
-"""Benchmark: FP64 vertical-extrapolation multigrid PCG on one MI355X.
+"""Benchmark of the vertical-extrapolation multigrid PCG on one MI355X.
 
-Workload (default): thin box 129 x 129 x 33 vertices (549,152 free unknowns),
+Headline workload: thin box 129 x 129 x 33 vertices (549,152 free unknowns),
 aspect ratio 1e-3, bathymetric floor z = -H(1 + 0.3 sin 2 pi x sin 2 pi y),
 +-0.3 h seeded horizontal jitter of every interior vertex on every layer,
 6 P1 tetrahedra per cell, point condition on the top (Neumann elsewhere),
 right-hand side b = M f for a seeded 16-mode smooth random field, relative
-residual tolerance 1e-8, preconditioner = vertical lumping + additive
-smoother.  One step = one complete solve (setup excluded), inputs resident
-in HBM.  Prints one JSON line.
+residual tolerance 1e-8, vertical lumping + additive smoother, FP64.  One
+step = one complete solve (setup excluded), inputs resident in HBM.
+
+Also measured (reported beside the headline in the same JSON line): eight
+right-hand sides per launch, the two mixed-precision forms, the serving
+stream over six resident meshes (continuous batching; saturated and Poisson
+arrivals; mixed precision vs FP64), live kernel timings for the roofline,
+and the CPU oracle on a bounded sample of the headline solve.
 """
 from __future__ import annotations
 
@@ -25,36 +30,59 @@ WORKLOADS = {
     "thinbox-257x257x33-eps1e-4": dict(nx=257, nz=33, H=1e-4, jitter=0.3, seed=4, bathymetry=True, rhs_seed=200),
     "thinbox-17x17x9-eps1e-2": dict(nx=17, nz=9, H=1e-2, jitter=0.2, seed=1, bathymetry=False, rhs_seed=100),
 }
+# serving meshes: (n, layers, H), seeds 5..10 -> 10,625 ... 2,179,617 nodes
+SERVE_MESHES = [(25, 17, 1e-2), (49, 21, 4e-3), (97, 21, 1.6e-3), (129, 33, 6.3e-4), (177, 33, 2.5e-4),
+                (257, 33, 1e-4)]
 HBM_PEAK_GBS = 8000.0
 
 
-def spmv_bytes(info):
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def spmv_bytes(info, K=1, elt=8, val=8):
     """Algorithmic bytes of one difference-form SpMV over all rows: every
-    stored off-diagonal (8-byte value, 4-byte column), and per row the
-    deficit d_i, x_i, y_i and one read of x_j (gathers counted once)."""
-    return info["nnz_offdiag"] * 12 + info["n"] * 32
+    stored off-diagonal (value + 4-byte column), per row the deficit (or the
+    two FP32 row factors) and, per column of the batch, x_i, y_i and one
+    gathered x_j."""
+    return info["nnz_offdiag"] * (val + 4) + info["n"] * (8 + 3 * elt * K)
 
 
-def gs_sweep_bytes(info):
-    """One forward multicolour sweep: every off-diagonal once (12 B), and
-    per row d_i, g_i, the read and write of x_i and one gathered x_j."""
-    return info["nnz_offdiag"] * 12 + info["n"] * 40
+def gs_sweep_bytes(info, K=1, elt=8, val=8):
+    """One forward multicolour sweep: every off-diagonal once, per row the
+    row factors and, per column, g_i, the read and write of x_i and one
+    gathered x_j."""
+    return info["nnz_offdiag"] * (val + 4) + info["n"] * (8 + 4 * elt * K)
+
+
+def timed_solves(s, b, steps, warmup, rtol):
+    import torch
+    for _ in range(warmup):
+        s.solve(b, rtol=rtol, max_iter=5000)
+    torch.cuda.synchronize()
+    times, iters, rels, sts = [], [], [], []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, its, rel, st = s.solve(b, rtol=rtol, max_iter=5000)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        iters.append(its)
+        rels.append(rel)
+        sts.append(st)
+    return x, times, iters, rels, sts
 
 
 def cpu_baseline(mesh, wl, iters):
     """The oracle as it stands, single-threaded, timed over `iters` PCG
-    iterations of the same solve (setup untimed)."""
-    try:
-        from threadpoolctl import threadpool_limits
-    except ImportError:  # pragma: no cover
-        threadpool_limits = None
-    import numpy as np
+    iterations of the headline solve (its setup untimed)."""
+    import numpy as np  # noqa: F401
+    from threadpoolctl import threadpool_limits
 
     from inputs import fourier_field
     from oracle import pcg, precond, solver as osolver
 
-    ctx = threadpool_limits(limits=1) if threadpool_limits else None
-    try:
+    with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         o = osolver.setup(mesh, "N")
         t_setup = time.perf_counter() - t0
@@ -63,11 +91,9 @@ def cpu_baseline(mesh, wl, iters):
         t0 = time.perf_counter()
         _, it, _, _ = pcg.pcg(lambda v: osolver.apply_A(o, v), M, b, 0.0, max_iter=iters)
         t = time.perf_counter() - t0
-    finally:
-        if ctx is not None:
-            ctx.unregister() if hasattr(ctx, "unregister") else None
     return {"value": o.n * it / t, "unit": "DOF*iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{it} PCG iterations of the same solve (oracle setup {t_setup:.1f} s untimed)",
+            "sample": f"{it} PCG iterations (VL + additive smoother) of the headline solve, oracle setup "
+                      f"{t_setup:.1f} s untimed",
             "seconds": round(t, 3), "cpu": _cpu_model(), "host_cpus": os.cpu_count()}
 
 
@@ -82,6 +108,70 @@ def _cpu_model():
     return "unknown"
 
 
+def serving(nreq, seed, rtol, dev):
+    """Stream of solve requests over six resident meshes: each request picks a
+    mesh uniformly and 1..8 right-hand sides (seeded).  Run saturated (all
+    submitted at once) and with Poisson arrivals at 0.8x the saturated
+    request rate, in mixed precision and in FP64."""
+    import numpy as np
+    import torch
+
+    import paper_0912_1976_amd as vemg
+    from inputs import box_mesh, fourier_field
+
+    rng = np.random.default_rng(seed)
+    srv = vemg.Server(device=0, precision="mixed_pc")
+    meshes, pools, sizes = [], [], []
+    t0 = time.perf_counter()
+    for i, (nx, nz, H) in enumerate(SERVE_MESHES):
+        m = box_mesh(nx, nx, nz, H, jitter=0.3, seed=5 + i, bathymetry=True)
+        mid = srv.add_mesh(m.xyz, m.tets, m.top)
+        pool = np.stack([srv.rhs(mid, fourier_field(m.xyz, H, 1000 + 16 * i + k)) for k in range(8)])
+        pools.append(torch.as_tensor(pool, device=dev))
+        meshes.append(mid)
+        sizes.append(m.n)
+        log(f"serving mesh {i}: {m.n} nodes")
+    t_setup = time.perf_counter() - t0
+    plan = [(int(rng.integers(0, len(meshes))), int(rng.integers(1, 9))) for _ in range(nreq)]
+    cols = [rng.permutation(8)[:k] for _, k in plan]
+
+    def run(rate):
+        rids = []
+        gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, nreq) if rate else np.zeros(nreq)
+        t_start = time.perf_counter()
+        t_next = t_start
+        for (mi, k), c, gap in zip(plan, cols, gaps):
+            t_next += gap
+            d = t_next - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            rids.append(srv.submit(meshes[mi], pools[mi][torch.as_tensor(c, device=dev)], rtol=rtol))
+        worst, floor = 0, 0
+        for rid in rids:
+            srv.wait(rid, timeout=600.0)
+            x, st, its, rel, lat = srv.result(rid)
+            worst = min(worst, st) if st < 0 else max(worst, st)
+            floor += int(st == 2)
+        s = srv.stats()
+        return {"requests": nreq, "columns": int(s["columns_done"]), "solves_per_s": s["solves_per_s"],
+                "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"], "mean_ms": s["mean_ms"], "max_ms": s["max_ms"],
+                "busy_s": s["busy_s"], "slot_occupancy": s["mean_slot_occupancy"], "worst_status": worst,
+                "requests_at_floor": floor, "arrival_rate_per_s": rate}
+
+    out = {"meshes_nodes": sizes, "setup_s": t_setup, "rtol": rtol}
+    for prec in ("mixed_pc", "fp64"):
+        srv.set_precision(prec)
+        sat = run(0.0)
+        log(f"serving {prec} saturated: {sat['solves_per_s']:.1f} solves/s p50 {sat['p50_ms']:.1f} ms")
+        rate = 0.8 * sat["requests"] / sat["busy_s"]
+        srv.set_precision(prec)
+        poi = run(rate)
+        log(f"serving {prec} poisson {rate:.1f}/s: p50 {poi['p50_ms']:.1f} ms p99 {poi['p99_ms']:.1f} ms")
+        out[prec] = {"saturated": sat, "poisson": poi}
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +182,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="headline solve and roofline only")
+    ap.add_argument("--serve-requests", type=int, default=96)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -106,50 +198,67 @@ def main():
 
     wl = WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
-    print(f"[bench] workload {args.workload}: building mesh", file=sys.stderr, flush=True)
+    log(f"workload {args.workload}: building mesh")
     mesh = box_mesh(wl["nx"], wl["nx"], wl["nz"], wl["H"], jitter=wl["jitter"], seed=wl["seed"],
                     bathymetry=wl["bathymetry"])
     t0 = time.perf_counter()
     s = vemg.Solver(mesh.xyz, mesh.tets, mesh.top, top_bc="pinned", pc=args.pc, device=0)
     t_setup = time.perf_counter() - t0
     info = s.info()
-    b = torch.as_tensor(s.rhs(fourier_field(mesh.xyz, wl["H"], wl["rhs_seed"])), device=dev)
-    print(f"[bench] setup {t_setup:.2f} s, n={info['n']}; warmup", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        x, its, rel, st = s.solve(b, rtol=args.rtol, max_iter=5000)
-    torch.cuda.synchronize()
-    times, iters, rels = [], [], []
-    for _ in range(args.steps):
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        x, its, rel, st = s.solve(b, rtol=args.rtol, max_iter=5000)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t1)
-        iters.append(its[0])
-        rels.append(rel[0])
-    total = sum(times)
     n = info["n"]
-    value = n * sum(iters) / total
-    print(f"[bench] {args.steps} solves, iters {iters[0]}, {1e3 * total / args.steps:.2f} ms/solve",
-          file=sys.stderr, flush=True)
+    b1 = torch.as_tensor(s.rhs(fourier_field(mesh.xyz, wl["H"], wl["rhs_seed"])), device=dev)
+    log(f"setup {t_setup:.2f} s, n={n}; timing {args.steps} FP64 solves")
+    x64, times, iters, rels, sts = timed_solves(s, b1, args.steps, args.warmup, args.rtol)
+    total = sum(times)
+    its = iters[0][0]
+    value = n * sum(i[0] for i in iters) / total
+    log(f"FP64: {its} iterations, {1e3 * total / args.steps:.2f} ms/solve, relres {rels[0][0]:.2e}")
 
     # live per-kernel timing (HIP events on the library's stream)
     ms_spmv, _ = s.time_op(vemg.OP_A, reps=50)
     ms_gs, nl_gs = s.time_op(vemg.OP_GS_FWD, reps=20)
-    bw_spmv = spmv_bytes(info) / (ms_spmv * 1e-3) / 1e9
-    bw_gs = gs_sweep_bytes(info) / (ms_gs * 1e-3) / 1e9
-    # per iteration the fine A is swept twice by SOR (pre and post smoothing)
-    # and applied twice as SpMV (CG product and smoother residual)
-    if 2 * ms_gs >= 2 * ms_spmv:
-        dom = {"kernel": "k_gs<true> (fine multicolour SOR sweep)", "bytes": gs_sweep_bytes(info) / nl_gs,
-               "ms": ms_gs / nl_gs, "launches_per_sweep": nl_gs}
+    # per PCG iteration the fine A is swept twice by SOR (the A_bar smoother)
+    # and applied twice as an SpMV (CG product, smoother residual)
+    if ms_gs >= ms_spmv:
+        dom = {"kernel": "k_gs<double,1> (fine multicolour SOR, one colour per launch)",
+               "bytes": gs_sweep_bytes(info) / nl_gs, "ms": ms_gs / nl_gs}
     else:
-        dom = {"kernel": "k_spmv<true,*> (fine difference-form SpMV)", "bytes": spmv_bytes(info), "ms": ms_spmv}
+        dom = {"kernel": "k_spmv<double,1,0,true> (fine difference-form SpMV)", "bytes": spmv_bytes(info),
+               "ms": ms_spmv}
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+
+    extras = {}
+    if not args.no_extras:
+        B8 = torch.as_tensor(np.stack([s.rhs(fourier_field(mesh.xyz, wl["H"], wl["rhs_seed"] + k))
+                                       for k in range(8)]), device=dev)
+        xb, tb, ib, rb, _ = timed_solves(s, B8, 3, 1, args.rtol)
+        extras["fp64_batch8"] = {"solves_per_s": 8 * 3 / sum(tb), "ms_per_batch": 1e3 * sum(tb) / 3,
+                                 "iterations": ib[0], "max_relres": max(rb[0])}
+        ms8, _ = s.time_op(vemg.OP_A, reps=20, nrhs=8)
+        extras["kernels_batch8"] = {"spmv_ms": ms8, "spmv_GBs": spmv_bytes(info, 8) / (ms8 * 1e-3) / 1e9}
+        log(f"FP64 x8: {extras['fp64_batch8']['solves_per_s']:.1f} solves/s")
+        for prec in ("mixed_ir", "mixed_pc"):
+            sm = vemg.Solver(mesh.xyz, mesh.tets, mesh.top, top_bc="pinned", pc=args.pc, device=0, precision=prec)
+            xm, tm, im, rm, stm = timed_solves(sm, b1, max(3, args.steps // 2), 1, args.rtol)
+            err = float(torch.linalg.norm(xm - x64) / torch.linalg.norm(x64))
+            xmb, tmb, imb, rmb, _ = timed_solves(sm, B8, 3, 1, args.rtol)
+            errb = float(torch.linalg.norm(xmb - xb) / torch.linalg.norm(xb))
+            rec = {"time_to_tol_ms": 1e3 * float(np.median(tm)), "iterations": im[0][0], "relres": rm[0][0],
+                   "status": stm[0], "rel_err_vs_fp64": err, "batch8_solves_per_s": 8 * 3 / sum(tmb),
+                   "batch8_rel_err_vs_fp64": errb}
+            if prec == "mixed_ir":
+                ms32, _ = sm.time_op(vemg.OP_A, reps=50)
+                rec["spmv32_ms"] = ms32
+                rec["spmv32_GBs"] = spmv_bytes(info, 1, 4, 4) / (ms32 * 1e-3) / 1e9
+            extras[prec] = rec
+            log(f"{prec}: {rec['time_to_tol_ms']:.1f} ms, iters {rec['iterations']}, err {err:.1e}")
+            sm.close()
+        log("serving stream")
+        extras["serving"] = serving(args.serve_requests, 11, args.rtol, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        log("cpu baseline (oracle)")
         cpu = cpu_baseline(mesh, wl, args.cpu_iters)
 
     line = {
@@ -166,17 +275,19 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n_dof": n, "rtol": args.rtol, "precond": args.pc,
-                   "top": "point condition (Neumann elsewhere)", "precision": "fp64"},
-        "iterations": iters[0],
+                   "top": "point condition (Neumann elsewhere)", "precision": "fp64", "rhs_per_solve": 1},
+        "iterations": its,
         "time_to_tol_ms": 1e3 * float(np.median(times)),
         "solves_per_s": args.steps / total,
-        "relres": max(rels),
+        "relres": max(r[0] for r in rels),
         "setup_s": t_setup,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom["kernel"],
                      "bytes_per_launch": dom["bytes"], "ms_per_launch": dom["ms"]},
-        "kernels": {"spmv_ms": ms_spmv, "spmv_GBs": bw_spmv, "gs_sweep_ms": ms_gs, "gs_sweep_GBs": bw_gs,
+        "kernels": {"spmv_ms": ms_spmv, "spmv_GBs": spmv_bytes(info) / (ms_spmv * 1e-3) / 1e9,
+                    "gs_sweep_ms": ms_gs, "gs_sweep_GBs": gs_sweep_bytes(info) / (ms_gs * 1e-3) / 1e9,
                     "gs_launches": nl_gs},
+        "extras": extras,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -248,6 +248,10 @@ vemg_status vemg_server_wait(vemg_server s, uint64_t req_id, double timeout_s);
 vemg_status vemg_server_result(vemg_server s, uint64_t req_id, int *status, int *iters, double *relres,
                                double *latency_ms);
 vemg_status vemg_server_get_stats(vemg_server s, vemg_server_stats *st);
+/* Switches the precision of later solves (VEMG_FP64 or VEMG_MIXED_PC) and
+ * resets the statistics; only while no request is queued or running
+ * (VEMG_ERR_STATE otherwise). */
+vemg_status vemg_server_set_precision(vemg_server s, int precision);
 /* Finishes queued work, stops the scheduler and frees every mesh. */
 vemg_status vemg_server_destroy(vemg_server s);
 /* Message of the last server error ("" if none). */

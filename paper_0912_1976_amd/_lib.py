@@ -93,11 +93,12 @@ def load_library():
     lib.vemg_server_result.argtypes = [P, U64, C.POINTER(I32), P, P, C.POINTER(D)]
     lib.vemg_server_get_stats.argtypes = [P, C.POINTER(ServerStats)]
     lib.vemg_server_destroy.argtypes = [P]
+    lib.vemg_server_set_precision.argtypes = [P, I32]
     lib.vemg_server_last_error.argtypes = [P]
     lib.vemg_server_last_error.restype = C.c_char_p
     for f in ("vemg_server_create", "vemg_server_add_mesh", "vemg_server_rhs", "vemg_server_submit",
               "vemg_server_poll", "vemg_server_wait", "vemg_server_result", "vemg_server_get_stats",
-              "vemg_server_destroy"):
+              "vemg_server_destroy", "vemg_server_set_precision"):
         getattr(lib, f).restype = I32
     for f in ("vemg_create", "vemg_setup", "vemg_rhs", "vemg_matvec", "vemg_solve", "vemg_apply",
               "vemg_get_info", "vemg_export", "vemg_destroy", "vemg_time_op"):
@@ -313,6 +314,9 @@ class Server:
         lat = C.c_double(0.0)
         self._check(self._lib.vemg_server_result(self._h, rid, C.byref(st), its, rel, C.byref(lat)))
         return x, st.value, list(its), list(rel), lat.value
+
+    def set_precision(self, precision):
+        self._check(self._lib.vemg_server_set_precision(self._h, _PREC[precision]))
 
     def stats(self):
         s = ServerStats()

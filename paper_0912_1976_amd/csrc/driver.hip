@@ -247,6 +247,9 @@ struct vemg_solver_s {
   vemg::Scal *scal = nullptr;
   int64_t nnz_A = 0, nnz_E = 0;
   std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;  // key: kind * 16 + K
+  // false for server lanes once the scheduler runs: a capture on one thread
+  // must not coincide with device-wide synchronisation on another
+  bool allow_capture = true;
 };
 
 namespace vemg {
@@ -443,24 +446,30 @@ void destroy_graphs(Handle *h) {
   h->graphs.clear();
 }
 
+// graph of one iteration for (kind, K), captured on first use when allowed
 template <class T>
-void run_iteration(Handle *h, int K, int kind) {
-  if (!h->opt.use_graphs) {
-    pcg_iteration<T>(h, K, kind);
-    return;
-  }
+hipGraphExec_t iteration_graph(Handle *h, int K, int kind) {
   int key = kind * 16 + K;
   auto it = h->graphs.find(key);
-  if (it == h->graphs.end()) {
-    HIPCHK(hipStreamBeginCapture(h->work, hipStreamCaptureModeThreadLocal));
+  if (it != h->graphs.end()) return it->second.second;
+  if (!h->allow_capture) return nullptr;
+  HIPCHK(hipStreamBeginCapture(h->work, hipStreamCaptureModeThreadLocal));
+  pcg_iteration<T>(h, K, kind);
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamEndCapture(h->work, &g));
+  hipGraphExec_t ge = nullptr;
+  HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+  h->graphs.emplace(key, std::make_pair(g, ge));
+  return ge;
+}
+
+template <class T>
+void run_iteration(Handle *h, int K, int kind) {
+  hipGraphExec_t ge = h->opt.use_graphs ? iteration_graph<T>(h, K, kind) : nullptr;
+  if (ge)
+    HIPCHK(hipGraphLaunch(ge, h->work));
+  else
     pcg_iteration<T>(h, K, kind);
-    hipGraph_t g = nullptr;
-    HIPCHK(hipStreamEndCapture(h->work, &g));
-    hipGraphExec_t ge = nullptr;
-    HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-    it = h->graphs.emplace(key, std::make_pair(g, ge)).first;
-  }
-  HIPCHK(hipGraphLaunch(it->second.second, h->work));
 }
 
 Scal read_scal(Handle *h) {
@@ -1056,7 +1065,7 @@ struct vemg_server_s {
   double first_submit = -1.0, last_done = -1.0;
   int64_t chunks = 0, uploads = 0, evictions = 0, cols_done = 0;
   double occupancy_sum = 0.0;
-  int64_t queued_cols = 0;
+  int64_t reqs_base = 0;  // requests before the last statistics reset
 };
 
 namespace vemg {
@@ -1308,8 +1317,11 @@ vemg_status vemg_create(const vemg_options *o, int device, void *hip_stream, vem
   h->user = (hipStream_t)hip_stream;
   int st = guarded(h, [&]() -> int {
     if (device >= 0) {
-      HIPCHK(hipStreamCreate(&h->work));
-      HIPCHK(hipStreamCreate(&h->work2));
+      // non-blocking streams: no implicit ordering with the legacy null
+      // stream, so another thread's work cannot join a graph being captured
+      // here (ordering with the caller's stream is explicit, see sync_in)
+      HIPCHK(hipStreamCreateWithFlags(&h->work, hipStreamNonBlocking));
+      HIPCHK(hipStreamCreateWithFlags(&h->work2, hipStreamNonBlocking));
       HIPCHK(hipEventCreateWithFlags(&h->ev, hipEventDisableTiming));
       HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
       HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
@@ -1497,6 +1509,21 @@ vemg_status vemg_server_add_mesh(vemg_server sv, int64_t n_nodes, const double *
     vemg_destroy(h);
     return st;
   }
+  // capture both iteration graphs now, while no other thread uses the device
+  int gst = guarded(h, [&]() -> int {
+    if (h->opt.use_graphs) {
+      vemg::iteration_graph<double>(h, vemg::kMaxBatch, vemg::kGraphFP64);
+      vemg::iteration_graph<double>(h, vemg::kMaxBatch, vemg::kGraphMixedPC);
+      HIPCHK(hipStreamSynchronize(h->work));
+    }
+    h->allow_capture = false;
+    return VEMG_OK;
+  });
+  if (gst != VEMG_OK) {
+    sv->err = h->err;
+    vemg_destroy(h);
+    return (vemg_status)gst;
+  }
   auto L = std::make_unique<vemg::Lane>();
   L->h = h;
   L->footprint = h->ar.bytes;
@@ -1608,11 +1635,14 @@ vemg_status vemg_server_get_stats(vemg_server sv, vemg_server_stats *st) {
   std::lock_guard<std::mutex> lk(sv->mu);
   std::memset(st, 0, sizeof(*st));
   std::vector<double> lat;
-  for (auto &q : sv->reqs)
-    if (q->done) lat.push_back(1e3 * (q->t_done - q->t_submit));
+  int64_t pending = 0;
+  for (size_t i = (size_t)sv->reqs_base; i < sv->reqs.size(); ++i) {
+    if (sv->reqs[i]->done) lat.push_back(1e3 * (sv->reqs[i]->t_done - sv->reqs[i]->t_submit));
+    else ++pending;
+  }
   std::sort(lat.begin(), lat.end());
   st->requests_done = (int64_t)lat.size();
-  st->requests_queued = (int64_t)sv->reqs.size() - st->requests_done;
+  st->requests_queued = pending;
   st->columns_done = sv->cols_done;
   if (!lat.empty()) {
     auto pct = [&](double p) {
@@ -1638,6 +1668,25 @@ vemg_status vemg_server_get_stats(vemg_server sv, vemg_server_stats *st) {
   st->evictions = sv->evictions;
   st->resident_bytes = sv->used;
   st->budget_bytes = sv->budget;
+  return VEMG_OK;
+}
+
+vemg_status vemg_server_set_precision(vemg_server sv, int precision) {
+  if (!sv || precision < 0 || precision > 2) return VEMG_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (!sv->incoming.empty()) return VEMG_ERR_STATE;
+  for (auto &L : sv->lanes)
+    if (L->busy()) return VEMG_ERR_STATE;
+  for (auto &q : sv->reqs)
+    if (!q->done) return VEMG_ERR_STATE;
+  int p = precision == VEMG_MIXED_IR ? VEMG_MIXED_PC : precision;
+  sv->opt.precision = p;
+  for (auto &L : sv->lanes) L->h->opt.precision = p;
+  sv->first_submit = sv->last_done = -1.0;
+  sv->chunks = sv->cols_done = 0;
+  sv->occupancy_sum = 0.0;
+  for (auto &q : sv->reqs) q->t_done = q->t_submit = 0.0;
+  sv->reqs_base = (int64_t)sv->reqs.size();
   return VEMG_OK;
 }
 
