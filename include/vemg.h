@@ -169,13 +169,15 @@ typedef enum {
   VEMG_OP_E = 3,
   VEMG_OP_VCYCLE_S = 4,
   VEMG_OP_VCYCLE_ABAR = 5,
-  VEMG_OP_GS_FWD = 6
+  VEMG_OP_GS_FWD = 6,
+  VEMG_OP_GS_COARSE = 7  /* vemg_time_op only: one forward sweep on the first coarse level of A_bar */
 } vemg_op;
 vemg_status vemg_apply(vemg_solver s, int op, const double *in_dev, double *out_dev);
 
 /* Benchmark support: average device time in milliseconds of one
- * application of VEMG_OP_A (one SpMV launch) or VEMG_OP_GS_FWD (one forward
- * multicolour sweep over all rows, one launch per colour) to nrhs (1..8)
+ * application of VEMG_OP_A (one SpMV launch), VEMG_OP_GS_FWD (one forward
+ * multicolour sweep over all rows, one launch per colour) or
+ * VEMG_OP_GS_COARSE (the same on A_bar's first coarse level) to nrhs (1..8)
  * columns, in the handle's inner precision (FP32 for VEMG_MIXED_IR, FP64
  * otherwise), measured with HIP events on the handle's own stream around
  * `reps` back-to-back applications on internal buffers, after one untimed

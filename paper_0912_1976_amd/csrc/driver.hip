@@ -872,6 +872,12 @@ void time_once(Handle *h, int op, int K) {
     launch_spmv<T>(st, K, h->A, 0, 0, n, v.p, (const T *)nullptr, v.q, h->part_pq, nullptr);
     return;
   }
+  if (op == VEMG_OP_GS_COARSE) {
+    DLevel &L = h->Ab[1];
+    for (size_t c = 0; c + 1 < L.cstart.size(); ++c)
+      launch_csr_gs<T>(st, K, L.Ac, L.cstart[c], L.cstart[c + 1], L.g<T>(), L.x<T>(), nullptr);
+    return;
+  }
   int nct = (int)P.top_colour_start.size() - 1, ncb = (int)P.bar_colour_start.size() - 1;
   for (int c = 0; c < std::max(nct, ncb); ++c) {
     int64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
@@ -891,9 +897,21 @@ int do_time(Handle *h, int op, int K, int reps, double *avg_ms, int *launches) {
   hipStream_t st = h->work;
   const Problem &P = h->P;
   int64_t n = P.n;
-  if (op != VEMG_OP_A && op != VEMG_OP_GS_FWD) return VEMG_ERR_INVALID_ARG;
+  if (op != VEMG_OP_A && op != VEMG_OP_GS_FWD && op != VEMG_OP_GS_COARSE) return VEMG_ERR_INVALID_ARG;
+  if (op == VEMG_OP_GS_COARSE && (h->Ab.size() < 2 || h->Ab[1].coarsest)) return VEMG_ERR_STATE;
   if (K != 1 && K != 2 && K != 4 && K != 8) return VEMG_ERR_INVALID_ARG;
   int nc = std::max((int)P.top_colour_start.size() - 1, (int)P.bar_colour_start.size() - 1);
+  if (op == VEMG_OP_GS_COARSE) {
+    nc = (int)h->Ab[1].cstart.size() - 1;
+    DLevel &L = h->Ab[1];
+    if (h->opt.precision == VEMG_MIXED_IR) {
+      launch_fill<float>(st, L.g32, L.n * K, 1.0f, nullptr);
+      launch_fill<float>(st, L.x32, L.n * K, 0.0f, nullptr);
+    } else {
+      launch_fill<double>(st, L.g64, L.n * K, 1.0, nullptr);
+      launch_fill<double>(st, L.x64, L.n * K, 0.0, nullptr);
+    }
+  }
   bool f32 = h->opt.precision == VEMG_MIXED_IR;
   if (f32) {
     launch_fill<float>(st, h->v32.p, n * K, 1.0f, nullptr);

@@ -152,8 +152,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Sell A, int64_t r0, int64_t r1,
   if (DOT) block_sum_store<K>(prod, partial + blk * K);
 }
 
+// one wavefront (one slice) per block: a colour holds few rows, so small
+// blocks spread them over every CU
 template <class T, int K>
-__global__ __launch_bounds__(kBlock) void k_gs(Sell A, int64_t a0, int64_t a1, int64_t sa, int64_t nba, int64_t b0,
+__global__ __launch_bounds__(kWave) void k_gs(Sell A, int64_t a0, int64_t a1, int64_t sa, int64_t nba, int64_t b0,
                                                int64_t b1, int64_t sb, int64_t nbt, const T *__restrict__ g,
                                                T *__restrict__ x, const int *__restrict__ done) {
   if (done && *done) return;
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_gs(Sell A, int64_t a0, int64_t a1, i
     sf = sb;
   }
   const int lane = threadIdx.x & 63;
-  const int64_t s = sf + blk * kSlicesPerBlock + (threadIdx.x >> 6);
+  const int64_t s = sf + blk;
   const int64_t r = s * 64 + lane;
   if (r < r0 || r >= r1) return;
   const Row<T, K> xr = ld<T, K>(x, r);
@@ -268,12 +270,12 @@ __device__ __forceinline__ void group_row(const CsrG &A, int64_t r, int gl, cons
 
 // MODE 0: y = A x, 1: y = g - A x (square); 2: y = P x, 3: y += P x
 template <class T, int K, int G, int MODE>
-__global__ __launch_bounds__(kBlock) void k_csr_spmv(CsrG A, int64_t r0, int64_t r1, const T *__restrict__ x,
+__global__ __launch_bounds__(kWave) void k_csr_spmv(CsrG A, int64_t r0, int64_t r1, const T *__restrict__ x,
                                                      const T *__restrict__ g, T *__restrict__ y,
                                                      const int *__restrict__ done) {
   if (done && *done) return;
   const int gl = threadIdx.x & (G - 1);
-  const int64_t r = r0 + ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+  const int64_t r = r0 + ((int64_t)blockIdx.x * kWave + threadIdx.x) / G;
   if (r >= r1) return;
   T acc[K];
   group_row<T, K, G>(A, r, gl, x, acc);
@@ -307,11 +309,11 @@ __global__ __launch_bounds__(kBlock) void k_csr_spmv(CsrG A, int64_t r0, int64_t
 }
 
 template <class T, int K, int G>
-__global__ __launch_bounds__(kBlock) void k_csr_gs(CsrG A, int64_t r0, int64_t r1, const T *__restrict__ g,
+__global__ __launch_bounds__(kWave) void k_csr_gs(CsrG A, int64_t r0, int64_t r1, const T *__restrict__ g,
                                                    T *__restrict__ x, const int *__restrict__ done) {
   if (done && *done) return;
   const int gl = threadIdx.x & (G - 1);
-  const int64_t r = r0 + ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+  const int64_t r = r0 + ((int64_t)blockIdx.x * kWave + threadIdx.x) / G;
   if (r >= r1) return;
   T acc[K];
   group_row<T, K, G>(A, r, gl, x, acc);  // off-diagonal part only
@@ -748,14 +750,18 @@ void launch_spmv(hipStream_t stm, int K, const Sell &A, int mode, int64_t r0, in
   })
 }
 
+static inline int64_t slices(int64_t r0, int64_t r1) {
+  return r1 <= r0 ? 0 : (r1 + kWave - 1) / kWave - r0 / kWave;
+}
+
 template <class T>
 void launch_gs(hipStream_t stm, int K, const Sell &A, int64_t a0, int64_t a1, int64_t b0, int64_t b1, const T *g,
                T *x, const int *done) {
-  int64_t nba = sell_blocks(a0, a1), nbb = sell_blocks(b0, b1);
+  int64_t nba = slices(a0, a1), nbb = slices(b0, b1);
   int64_t nbt = nba + nbb;
   if (!nbt) return;
   int64_t sa = a0 / kWave, sb = b0 / kWave;
-  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_gs<T, KK>), grid(nbt), dim3(kBlock), 0, stm, A, a0, a1, sa, nba, b0, b1, sb,
+  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_gs<T, KK>), grid(nbt), dim3(kWave), 0, stm, A, a0, a1, sa, nba, b0, b1, sb,
                                       nbt, g, x, done))
 }
 
@@ -785,20 +791,20 @@ static void csr_launch(hipStream_t stm, int K, int mode, const CsrG &A, int64_t 
                        const T *g, T *y, const int *done) {
   int64_t rows = r1 - r0;
   if (rows <= 0) return;
-  int64_t nb = (rows * A.G + kBlock - 1) / kBlock;
+  int64_t nb = (rows * A.G + kWave - 1) / kWave;
   VEMG_K_SWITCH(K, VEMG_G_SWITCH(A.G, {
     switch (mode) {
       case 0:
-        hipLaunchKernelGGL((k_csr_spmv<T, KK, GG, 0>), grid(nb), dim3(kBlock), 0, stm, A, r0, r1, x, g, y, done);
+        hipLaunchKernelGGL((k_csr_spmv<T, KK, GG, 0>), grid(nb), dim3(kWave), 0, stm, A, r0, r1, x, g, y, done);
         break;
       case 1:
-        hipLaunchKernelGGL((k_csr_spmv<T, KK, GG, 1>), grid(nb), dim3(kBlock), 0, stm, A, r0, r1, x, g, y, done);
+        hipLaunchKernelGGL((k_csr_spmv<T, KK, GG, 1>), grid(nb), dim3(kWave), 0, stm, A, r0, r1, x, g, y, done);
         break;
       case 2:
-        hipLaunchKernelGGL((k_csr_spmv<T, KK, GG, 2>), grid(nb), dim3(kBlock), 0, stm, A, r0, r1, x, g, y, done);
+        hipLaunchKernelGGL((k_csr_spmv<T, KK, GG, 2>), grid(nb), dim3(kWave), 0, stm, A, r0, r1, x, g, y, done);
         break;
       default:
-        hipLaunchKernelGGL((k_csr_spmv<T, KK, GG, 3>), grid(nb), dim3(kBlock), 0, stm, A, r0, r1, x, g, y, done);
+        hipLaunchKernelGGL((k_csr_spmv<T, KK, GG, 3>), grid(nb), dim3(kWave), 0, stm, A, r0, r1, x, g, y, done);
         break;
     }
   }))
@@ -819,8 +825,8 @@ template <class T>
 void launch_csr_gs(hipStream_t stm, int K, const CsrG &A, int64_t r0, int64_t r1, const T *g, T *x, const int *done) {
   int64_t rows = r1 - r0;
   if (rows <= 0) return;
-  int64_t nb = (rows * A.G + kBlock - 1) / kBlock;
-  VEMG_K_SWITCH(K, VEMG_G_SWITCH(A.G, hipLaunchKernelGGL((k_csr_gs<T, KK, GG>), grid(nb), dim3(kBlock), 0, stm, A,
+  int64_t nb = (rows * A.G + kWave - 1) / kWave;
+  VEMG_K_SWITCH(K, VEMG_G_SWITCH(A.G, hipLaunchKernelGGL((k_csr_gs<T, KK, GG>), grid(nb), dim3(kWave), 0, stm, A,
                                                           r0, r1, g, x, done)))
 }
 

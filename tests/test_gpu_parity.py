@@ -117,6 +117,24 @@ def test_solution_matches_oracle(pc):
     assert abs(its[0] - it_o) <= max(3, 0.1 * it_o)
 
 
+@pytest.mark.parametrize("pc", ["vl_as", "vl_sor"])
+def test_graded_multiscale_mesh_matches_oracle(pc):
+    # the centre-refined multiscale mesh (stand-in for the paper's Mesh B)
+    from inputs import graded_mesh
+    _dev()
+    m = graded_mesh(1 / 60, 1e-3, jitter=0.25, seed=3)
+    _print("case graded", m.n, pc)
+    s = lib.Solver(m.xyz, m.tets, m.top, pc=pc, device=0, coarse_max=64)
+    o = osolver.setup(m, "N", coarse_max=64)
+    b_nat = s.rhs(fourier_field(m.xyz, 1e-3, 7))
+    xo, it_o, rel_o, ok = osolver.solve(o, b_nat[o.perm], 1e-11, pc, max_iter=5000)
+    x, its, rels, st = s.solve(b_nat, rtol=1e-11, max_iter=5000)
+    _print("iters gpu", its, "oracle", it_o)
+    assert st == 0
+    assert _rel(x.cpu().numpy()[o.perm], xo) < 1e-8
+    assert abs(its[0] - it_o) <= max(3, 0.1 * it_o)
+
+
 @pytest.mark.parametrize("mode", ["N", "D"])
 def test_manufactured_solution(mode):
     # the paper's protocol: b = A x*, so the exact discrete solution is known
