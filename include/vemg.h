@@ -14,14 +14,19 @@
  * the free nodes and solves A phi = b by preconditioned conjugate gradients.
  *
  * Preconditioners (Section 6):
- *   VEMG_PC_VL_ADDITIVE  E~ Vcyc_S(E~^T r) + Z Vcyc_Abar(Z^T r), eq.
- *                        ourpreconditioner: vertical extrapolation E~
- *                        (Section 5.4) to the surface, the Galerkin surface
- *                        operator S = E~^T A E~ approximated by a smoothed
- *                        aggregation V-cycle, plus the additive smoother, an
- *                        SA V-cycle on the Dirichlet-top block A_bar.
- *   VEMG_PC_VL_SOR       E~ as the first coarsening of a multigrid cycle
- *                        with one forward / one backward SOR sweep on A.
+ *   VEMG_PC_VL_SOR       vertical lumping as the first coarsening of a
+ *                        multigrid cycle: one forward multicolour SOR sweep
+ *                        on A, the coarse correction E~ Vcyc_S(E~^T res)
+ *                        with the vertical extrapolation E~ (Section 5.4)
+ *                        and a smoothed aggregation V-cycle on the Galerkin
+ *                        surface operator S = E~^T A E~, one backward sweep.
+ *   VEMG_PC_VL_ADDITIVE  that cycle with the additive smoother included:
+ *                        M^{-1} r = VL_SOR(r) + Z Vcyc_Abar(Z^T r), where
+ *                        Vcyc_Abar is one SA V-cycle on the Dirichlet-top
+ *                        block A_bar and Z = [0; I] (the combination run in
+ *                        the experiments of Section 6).
+ *   VEMG_PC_VL_ADDITIVE_ONLY  eq. ourpreconditioner on its own:
+ *                        E~ Vcyc_S(E~^T r) + Z Vcyc_Abar(Z^T r), no SOR.
  *   VEMG_PC_JACOBI, VEMG_PC_NONE  baselines.
  *
  * Conventions
@@ -66,7 +71,8 @@ typedef enum {
   VEMG_PC_VL_ADDITIVE = 0,
   VEMG_PC_VL_SOR = 1,
   VEMG_PC_JACOBI = 2,
-  VEMG_PC_NONE = 3
+  VEMG_PC_NONE = 3,
+  VEMG_PC_VL_ADDITIVE_ONLY = 4
 } vemg_pc;
 
 /* Precision of the solve.
@@ -140,11 +146,18 @@ vemg_status vemg_matvec(vemg_solver s, const double *x_dev, double *y_dev);
 /* Solves A x = b for nrhs right-hand sides stored one after another
  * ([nrhs][n_nodes], device).  Right-hand sides are solved in batches of up
  * to 8 that share every matrix read (SpMM-style launches); each column
- * converges on its own.  Stops when ||b - A x||_2 <= rtol ||b||_2 on the
- * FP64 true residual or after max_iter iterations (products with A; for
- * VEMG_MIXED_IR the inner FP32 iterations summed over refinement steps).
- * iters and relres (host, length nrhs, may be NULL) receive the iteration
- * count and the final true relative residual of each right-hand side.
+ * converges on its own.  PCG restarts from the true residual: each restart
+ * solves for a correction from zero, and the solution is kept on the device
+ * as an unevaluated sum hi + lo of two doubles into which every correction
+ * is added without rounding error.  The true residual b - A (hi + lo) is
+ * evaluated with error-free products and double-double sums, so the FP64
+ * accuracy floor that grows with the condition number (Section 6) does not
+ * stop the refinement.  Stops when ||b - A (hi + lo)||_2 <= rtol ||b||_2 or
+ * after max_iter iterations (products with A; for VEMG_MIXED_IR the inner
+ * FP32 iterations summed over refinement steps).  x receives hi + lo rounded
+ * to FP64, which changes each residual entry by at most u (|A| |x|)_i,
+ * u = 2^-53.  iters and relres (host, length nrhs, may be NULL) receive the
+ * iteration count and that final relative residual of each right-hand side.
  * Returns the worst status: VEMG_WARN_MAXITER / VEMG_WARN_FLOOR with the
  * last iterate when rtol was not reached, VEMG_ERR_BREAKDOWN on p.Ap <= 0 or
  * NaN (that column only; the others are still solved). */

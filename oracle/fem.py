@@ -222,6 +222,30 @@ def apply_difference_form(Aoff, d, x):
     return np.bincount(rows, weights=contrib, minlength=Aoff.shape[0]) + d * x
 
 
+def residual_extended(Aoff, d, b, hi, lo):
+    """b - A_UU (hi + lo) for a solution held as the unevaluated sum of two
+    doubles, in the difference form, evaluated in numpy.longdouble (x87
+    extended precision, 64-bit significand) and rounded to FP64 once.
+
+    Not part of the paper: Section 6 attributes the accuracy floor of its
+    FP64 runs to round-off growing with the condition number; evaluating the
+    restart residual of PCG this way removes that floor (see pcg.py)."""
+    L = np.longdouble
+    if np.finfo(L).nmant < 63:
+        raise RuntimeError("numpy.longdouble is not an extended-precision type on this platform")
+    h = np.asarray(hi, dtype=L)
+    l = np.asarray(lo, dtype=L)
+    rows = np.repeat(np.arange(Aoff.shape[0]), np.diff(Aoff.indptr))
+    # the differences are taken part by part: for neighbouring values the
+    # difference of the high parts is exact, so no rounding of hi + lo itself
+    # enters (it would be amplified by the large vertical couplings)
+    diff = (h[Aoff.indices] - h[rows]) + (l[Aoff.indices] - l[rows])
+    acc = np.zeros(Aoff.shape[0], dtype=L)
+    np.add.at(acc, rows, Aoff.data.astype(L) * diff)
+    dl = np.asarray(d, dtype=L)
+    return (np.asarray(b, dtype=L) - (acc + (dl * h + dl * l))).astype(np.float64)
+
+
 def diagonal_of(Aoff, d):
     """a_ii = d_i - sum_{j in U} a_ij (ascending j)."""
     return d - row_sums(Aoff)

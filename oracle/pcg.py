@@ -49,34 +49,55 @@ def pcg(apply_A, apply_M, b, tol, max_iter=1000):
     return x, max_iter, hist, False
 
 
-def pcg_restarted(apply_A, apply_M, b, tol, max_iter=1000, max_restarts=5):
+def two_sum(a, b):
+    """Error-free sum (Knuth): s = fl(a + b) and e with s + e = a + b exactly."""
+    s = a + b
+    bb = s - a
+    return s, (a - (s - bb)) + (b - bb)
+
+
+def pcg_restarted(apply_A, apply_M, b, tol, max_iter=1000, max_restarts=5, residual=None):
     """PCG whose stopping test is confirmed on the true residual b - A x.
 
     When the recurrence residual reaches tol but the true one does not, PCG
-    restarts from the current iterate with the true residual (at most
-    max_restarts times, and only while each restart at least halves the true
-    residual).  Below the level where rounding of x itself dominates (it
-    grows like eps^-2, as Section 6 observes), no FP64 iterate can do better;
-    the solve then ends at that floor with converged = False.
-    Returns (x, iterations, true relative residual, converged, restarts)."""
+    restarts with the true residual as right-hand side and solves for a
+    correction from zero (at most max_restarts times, and only while each
+    restart at least halves the true residual).
+
+    The solution is held as the unevaluated sum hi + lo of two doubles: each
+    correction is added with an error-free sum, its rounding error kept in
+    lo.  residual(hi, lo) returns b - A (hi + lo); the default evaluates A hi
+    and A lo in FP64.  Section 6 observes an accuracy floor that grows with
+    the condition number and ascribes it to FP64 round-off; with an
+    extended-precision residual (fem.residual_extended) the refinement
+    removes it and the solution becomes accurate to FP64 rounding, while a
+    plain FP64 residual leaves the floor where rounding the iterate puts it.
+    Returns (fl(hi + lo), iterations, relative residual of hi + lo,
+    converged, restarts); converged = False at the floor, at max_iter or
+    after max_restarts."""
     b = np.asarray(b, dtype=np.float64)
     bnorm = float(np.sqrt(b @ b))
-    x = np.zeros_like(b)
+    hi = np.zeros_like(b)
+    lo = np.zeros_like(b)
     if bnorm == 0.0:
-        return x, 0, 0.0, True, 0
+        return hi, 0, 0.0, True, 0
+    if residual is None:
+        def residual(h, l):
+            return (b - apply_A(h)) - apply_A(l)
     total = 0
     prev = np.inf
     restarts = 0
     while True:
-        r = b - apply_A(x)
+        r = residual(hi, lo)
         rel = float(np.sqrt(r @ r)) / bnorm
         if rel <= tol:
-            return x, total, rel, True, restarts
+            return hi + lo, total, rel, True, restarts
         if total >= max_iter or restarts > max_restarts or rel > 0.5 * prev:
-            return x, total, rel, False, restarts
+            return hi + lo, total, rel, False, restarts
         if total > 0:
             restarts += 1
         prev = rel
         dx, it, _, _ = pcg(apply_A, apply_M, r, tol * bnorm / (rel * bnorm), max_iter - total)
-        x = x + dx
+        hi, e = two_sum(hi, dx)
+        lo = lo + e
         total += it

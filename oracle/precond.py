@@ -2,21 +2,32 @@
 
 Test infrastructure only.
 
-* 'vl_as'  -- vertical lumping + additive smoother, eq. ourpreconditioner:
-              z = E~ Vcyc_S(E~^T r) + Z Vcyc_Abar(Z^T r), Z = [0; I].
-              The two terms are independent; with exact solves in both and
-              the exact extrapolation E this is A^{-1} (eq. E multigrid).
 * 'vl_sor' -- vertical lumping as the first coarsening of an ordinary
               multigrid cycle with one forward SOR sweep on A before and one
               backward sweep after (Section 6, second preconditioner):
               x = GS_fwd(A, r); x += E~ Vcyc_S(E~^T (r - A x)); x = GS_bwd(A, r, x).
+* 'vl_as'  -- that cycle with the additive smoother included (Section 6,
+              third preconditioner; Section 5.5 for the smoother):
+              z = vl_sor(r) + Z Vcyc_Abar(Z^T r), Z = [0; I].
+              Reading: Section 6 describes the third preconditioner as the
+              vertical-lumping cycle combined with the smoother and compares
+              the preconditioner with and without it; taking the sum keeps
+              the SOR cycle of the second preconditioner and adds the second
+              term of eq. ourpreconditioner with A_bar^{-1} replaced by one
+              V-cycle.  The sum of two symmetric positive definite operators
+              is one, so CG applies.
+* 'vl_add' -- eq. ourpreconditioner on its own, no SOR:
+              z = E~ Vcyc_S(E~^T r) + Z Vcyc_Abar(Z^T r).
+              The two terms are independent; with exact solves in both and
+              the exact extrapolation E this is A^{-1} (eq. E multigrid).
 * 'sa'     -- one smoothed aggregation V-cycle on the whole A (the first
               preconditioner of Section 6, the paper's baseline, which shows
               eps-dependent plateaus).
 * 'jacobi' -- z = r / diag(A).
 * 'none'   -- z = r.
-In mode D the surface branch is empty (all top values are fixed) and
-'vl_as' reduces to the additive smoother alone.
+In mode D the surface branch is empty (all top values are fixed): 'vl_sor'
+is then one symmetric Gauss-Seidel sweep and 'vl_add' the additive smoother
+alone.
 """
 from __future__ import annotations
 
@@ -25,13 +36,27 @@ import numpy as np
 from . import amg
 
 
-def _vl_as(s):
+def _additive_smoother(s, r):
+    """Z Vcyc_Abar(Z^T r): one V-cycle on the non-top block, zero on top."""
+    z = np.zeros_like(r)
+    z[s.n_top:] = amg.vcycle(s.Abar_levels, r[s.n_top:])
+    return z
+
+
+def _vl_add(s):
     def apply(r):
-        z = np.zeros_like(r)
+        z = _additive_smoother(s, r)
         if s.n_top > 0:
             z += s.E @ amg.vcycle(s.S_levels, s.E.T @ r)
-        z[s.n_top:] += amg.vcycle(s.Abar_levels, r[s.n_top:])
         return z
+    return apply
+
+
+def _vl_as(s):
+    sor = _vl_sor(s)
+
+    def apply(r):
+        return sor(r) + _additive_smoother(s, r)
     return apply
 
 
@@ -66,6 +91,8 @@ def make(s, pc):
         return _sa(s)
     if pc == "vl_as":
         return _vl_as(s)
+    if pc == "vl_add":
+        return _vl_add(s)
     if pc == "vl_sor":
         return _vl_sor(s)
     if pc == "jacobi":

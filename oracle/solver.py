@@ -136,7 +136,9 @@ def to_natural(s: OracleSetup, x):
 
 def solve(s: OracleSetup, b, tol=1e-8, pc="vl_as", max_iter=1000):
     """PCG on A_UU x = b (storage order), stopping test confirmed on the true
-    residual.  Returns (x, iterations, true relative residual, converged)."""
+    residual of the extended iterate, evaluated in extended precision.
+    Returns (x, iterations, that relative residual, converged)."""
     M = precond.make(s, pc)
-    x, it, rel, ok, _ = pcg.pcg_restarted(lambda v: apply_A(s, v), M, b, tol, max_iter)
+    x, it, rel, ok, _ = pcg.pcg_restarted(lambda v: apply_A(s, v), M, b, tol, max_iter,
+                                          residual=lambda hi, lo: fem.residual_extended(s.Aoff, s.d, b, hi, lo))
     return x, it, rel, ok

@@ -13,7 +13,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvemg.so")
 
 HOST_SOURCES = ["setup.cpp", "sparse.cpp"]
-HIP_SOURCES = ["kernels.hip", "driver.hip"]
+HIP_SOURCES = ["kernels.hip", "refine.hip", "driver.hip"]
+# error-free transformations need every operation rounded as written
+FILE_FLAGS = {"refine.hip": ["-ffp-contract=off"]}
 
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-sign-compare"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -36,7 +38,7 @@ def build(verbose: bool = True) -> str:
         objs.append(obj)
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        _run([hipcc, *HIP_FLAGS, *FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = LIB + ".tmp"
     _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])

@@ -193,6 +193,9 @@ template <class T>
 struct Work {
   T *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *res = nullptr,
     *resA = nullptr, *tmp = nullptr;
+  // FP64 only: the solution as the unevaluated sum xs + xl, into which each
+  // restart's correction x is folded
+  T *xs = nullptr, *xl = nullptr;
 };
 
 struct DLevel {
@@ -229,7 +232,7 @@ enum GraphKind { kGraphFP64 = 0, kGraphFP32 = 1, kGraphMixedPC = 2 };
 struct vemg_solver_s {
   vemg_options opt;
   int device = -1;
-  hipStream_t user = nullptr, work = nullptr, work2 = nullptr;  // work2: surface branch
+  hipStream_t user = nullptr, work = nullptr, work2 = nullptr;  // work2: parallel preconditioner branch
   hipEvent_t ev = nullptr, ev_fork = nullptr, ev_join = nullptr;
   std::string err;
   bool ready = false;
@@ -331,6 +334,49 @@ void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *
   for (int c = nc - 1; c >= 0; --c) gs(c);
 }
 
+// One vertical-lumping multigrid cycle on stream st (Section 6, second
+// preconditioner): forward multicolour SOR on A from zero, E~ coarse
+// correction through one V-cycle on the surface operator, backward SOR.
+template <class T>
+void sor_cycle(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *done) {
+  const Problem &P = h->P;
+  int64_t n = P.n, m = P.n_top;
+  Work<T> &v = work_of<T>(h);
+  launch_fill<T>(st, zz, n * K, T(0), done);
+  int nct = (int)P.top_colour_start.size() - 1, ncb = (int)P.bar_colour_start.size() - 1;
+  int nc = std::max(nct, ncb);
+  auto sweep = [&](int c) {
+    int64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    if (c < nct) {
+      a0 = P.top_colour_start[c];
+      a1 = P.top_colour_start[c + 1];
+    }
+    if (c < ncb) {
+      b0 = P.bar_colour_start[c];
+      b1 = P.bar_colour_start[c + 1];
+    }
+    launch_gs<T>(st, K, h->A, a0, a1, b0, b1, rr, zz, done);
+  };
+  for (int c = 0; c < nc; ++c) sweep(c);
+  if (m > 0) {
+    launch_spmv<T>(st, K, h->A, 1, 0, n, zz, rr, v.res, nullptr, done);
+    launch_csr_rect<T>(st, K, h->Et, false, v.res, h->S[0].g<T>(), done);
+    vcycle<T>(st, K, h->S, 0, done);
+    launch_rect<T>(st, K, h->E, true, h->S[0].x<T>(), zz, done);
+  }
+  for (int c = nc - 1; c >= 0; --c) sweep(c);
+}
+
+// w = Z Vcyc_Abar(Z^T rr) on stream st (the additive smoother; rows of the top
+// block of w stay zero)
+template <class T>
+void additive_smoother(Handle *h, hipStream_t st, int K, const T *rr, const int *done) {
+  T *saved = h->Ab[0].g<T>();
+  h->Ab[0].g<T>() = const_cast<T *>(rr);
+  vcycle<T>(st, K, h->Ab, 0, done);
+  h->Ab[0].g<T>() = saved;
+}
+
 // z = M^{-1} rr in precision T; partial sums of rr . z go to part (blocks in *np)
 template <class T>
 void precond(Handle *h, int K, const T *rr, T *zz, double *part, int64_t *np, const int *done) {
@@ -340,8 +386,21 @@ void precond(Handle *h, int K, const T *rr, T *zz, double *part, int64_t *np, co
   Work<T> &v = work_of<T>(h);
   switch (h->opt.pc) {
     case VEMG_PC_VL_ADDITIVE: {
-      // the two terms of the additive preconditioner are independent: the
-      // surface branch runs on a second stream (a parallel graph branch)
+      // the lumping cycle and the additive smoother are independent: the
+      // smoother runs on the second stream (a parallel graph branch)
+      HIPCHK(hipEventRecord(h->ev_fork, st));
+      HIPCHK(hipStreamWaitEvent(h->work2, h->ev_fork, 0));
+      additive_smoother<T>(h, h->work2, K, rr, done);
+      HIPCHK(hipEventRecord(h->ev_join, h->work2));
+      sor_cycle<T>(h, st, K, rr, zz, done);
+      HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
+      launch_add_dot<T>(st, K, v.w, rr, zz, m, n, part, done);
+      *np = vec_blocks(n);
+      break;
+    }
+    case VEMG_PC_VL_ADDITIVE_ONLY: {
+      // the two terms of eq. ourpreconditioner are independent: the surface
+      // branch runs on the second stream
       if (m > 0) {
         HIPCHK(hipEventRecord(h->ev_fork, st));
         HIPCHK(hipStreamWaitEvent(h->work2, h->ev_fork, 0));
@@ -349,10 +408,7 @@ void precond(Handle *h, int K, const T *rr, T *zz, double *part, int64_t *np, co
         vcycle<T>(h->work2, K, h->S, 0, done);
         HIPCHK(hipEventRecord(h->ev_join, h->work2));
       }
-      T *saved = h->Ab[0].g<T>();
-      h->Ab[0].g<T>() = const_cast<T *>(rr);
-      vcycle<T>(st, K, h->Ab, 0, done);
-      h->Ab[0].g<T>() = saved;
+      additive_smoother<T>(h, st, K, rr, done);
       if (m > 0) {
         HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
         launch_prolong_sum<T>(st, K, h->E, m, h->S[0].x<T>(), v.w, rr, zz, part, done);
@@ -364,34 +420,11 @@ void precond(Handle *h, int K, const T *rr, T *zz, double *part, int64_t *np, co
       }
       break;
     }
-    case VEMG_PC_VL_SOR: {
-      launch_fill<T>(st, zz, n * K, T(0), done);
-      int nct = (int)P.top_colour_start.size() - 1, ncb = (int)P.bar_colour_start.size() - 1;
-      int nc = std::max(nct, ncb);
-      auto sweep = [&](int c) {
-        int64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-        if (c < nct) {
-          a0 = P.top_colour_start[c];
-          a1 = P.top_colour_start[c + 1];
-        }
-        if (c < ncb) {
-          b0 = P.bar_colour_start[c];
-          b1 = P.bar_colour_start[c + 1];
-        }
-        launch_gs<T>(st, K, h->A, a0, a1, b0, b1, rr, zz, done);
-      };
-      for (int c = 0; c < nc; ++c) sweep(c);
-      if (m > 0) {
-        launch_spmv<T>(st, K, h->A, 1, 0, n, zz, rr, v.res, nullptr, done);
-        launch_csr_rect<T>(st, K, h->Et, false, v.res, h->S[0].g<T>(), done);
-        vcycle<T>(st, K, h->S, 0, done);
-        launch_rect<T>(st, K, h->E, true, h->S[0].x<T>(), zz, done);
-      }
-      for (int c = nc - 1; c >= 0; --c) sweep(c);
+    case VEMG_PC_VL_SOR:
+      sor_cycle<T>(h, st, K, rr, zz, done);
       launch_dot<T>(st, K, rr, zz, n, part, done);
       *np = vec_blocks(n);
       break;
-    }
     case VEMG_PC_JACOBI:
       launch_jacobi<T>(st, K, rr, h->diag, zz, n, done);
       launch_dot<T>(st, K, rr, zz, n, part, done);
@@ -490,11 +523,12 @@ Scal iterate(Handle *h, int K, int kind) {
   }
 }
 
-// FP64 true residual res = b - A x and its squared column norms (host)
+// true residual res = b - A (xs + xl) of the extended iterate, evaluated in
+// extended precision, and its squared column norms (host)
 void true_residual(Handle *h, int K, double *rr_host) {
   hipStream_t st = h->work;
   int64_t n = h->P.n;
-  launch_spmv<double>(st, K, h->A, 1, 0, n, h->v64.x, h->b, h->v64.res, nullptr, nullptr);
+  launch_residual_ext(st, K, h->A, h->b, h->v64.xs, h->v64.xl, h->v64.res);
   launch_dot<double>(st, K, h->v64.res, h->v64.res, n, h->part_t, nullptr);
   launch_reduce(st, K, h->part_t, vec_blocks(n), h->dscal);
   HIPCHK(hipMemcpyAsync(rr_host, h->dscal, K * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -543,9 +577,12 @@ void solve_cg(Handle *h, int K, double rtol, int max_iter, ColResult *res) {
     upload_scales(h, K, sin, sout);
   }
   launch_fill<double>(st, v.x, n * K, 0.0, nullptr);
+  launch_fill<double>(st, v.xs, n * K, 0.0, nullptr);
+  launch_fill<double>(st, v.xl, n * K, 0.0, nullptr);
   launch_copy<double>(st, h->b, v.r, n * K, nullptr);
   launch_dot<double>(st, K, h->b, h->b, n, h->part_b, nullptr);
   launch_pcg_init(st, K, h->scal, h->part_b, vec_blocks(n), rtol, max_iter);
+  const unsigned all = (1u << K) - 1u;
   double prev[kMaxBatch];
   bool final_[kMaxBatch];
   int restarts = 0;
@@ -562,6 +599,8 @@ void solve_cg(Handle *h, int K, double rtol, int max_iter, ColResult *res) {
     launch_pcg_set_rho(st, K, h->scal, h->part_rz, np);
     launch_copy<double>(st, v.z, v.p, n * K, nullptr);
     Scal hs = iterate<double>(h, K, kind);
+    // columns already final hold x = 0 and are not updated: folding all is exact for them
+    launch_fold(st, K, all, v.xs, v.xl, v.x, n);
     double rr[kMaxBatch];
     true_residual(h, K, rr);
     unsigned keep = 0;
@@ -598,6 +637,7 @@ void solve_cg(Handle *h, int K, double rtol, int max_iter, ColResult *res) {
     launch_copy<double>(st, v.res, v.r, n * K, nullptr);
     launch_pcg_resume(st, K, h->scal, keep);
   }
+  launch_round(st, v.xs, v.xl, v.x, n * K);
 }
 
 // FP64 iterative refinement with FP32 inner PCG; h->b holds K columns.
@@ -607,6 +647,8 @@ void solve_ir(Handle *h, int K, double rtol, int max_iter, ColResult *res) {
   double bb[kMaxBatch];
   rhs_norms(h, K, bb);
   launch_fill<double>(st, h->v64.x, n * K, 0.0, nullptr);
+  launch_fill<double>(st, h->v64.xs, n * K, 0.0, nullptr);
+  launch_fill<double>(st, h->v64.xl, n * K, 0.0, nullptr);
   double prev[kMaxBatch];
   bool fin[kMaxBatch];
   for (int k = 0; k < K; ++k) {
@@ -616,7 +658,7 @@ void solve_ir(Handle *h, int K, double rtol, int max_iter, ColResult *res) {
   }
   for (int outer = 0;; ++outer) {
     double rr[kMaxBatch];
-    true_residual(h, K, rr);  // v64.res = b - A x
+    true_residual(h, K, rr);  // v64.res = b - A (xs + xl)
     double sin[kMaxBatch], sout[kMaxBatch];
     bool any = false;
     for (int k = 0; k < K; ++k) {
@@ -671,8 +713,11 @@ void solve_ir(Handle *h, int K, double rtol, int max_iter, ColResult *res) {
     Scal hs = iterate<float>(h, K, kGraphFP32);
     for (int k = 0; k < K; ++k)
       if (!fin[k]) res[k].iters += hs.iters[k];
-    launch_promote(st, K, v.x, h->scale_out, h->v64.x, n, true, nullptr);
+    // the FP64 correction d = ||r|| d32, folded into the extended solution
+    launch_promote(st, K, v.x, h->scale_out, h->v64.x, n, false, nullptr);
+    launch_fold(st, K, (1u << K) - 1u, h->v64.xs, h->v64.xl, h->v64.x, n);
   }
+  launch_round(st, h->v64.xs, h->v64.xl, h->v64.x, n * K);
 }
 
 void upload(Handle *h) {
@@ -696,6 +741,8 @@ void upload(Handle *h) {
     v.res = h->ar.alloc<double>(cnt);
     v.resA = h->ar.alloc<double>(cnt);
     v.tmp = h->ar.alloc<double>(cnt);
+    v.xs = h->ar.alloc<double>(cnt);
+    v.xl = h->ar.alloc<double>(cnt);
   };
   auto mk32 = [&](Work<float> &v) {
     v.x = h->ar.alloc<float>(cnt);
@@ -1142,7 +1189,7 @@ void lane_start(Server *sv, Lane &L, unsigned mask, bool restart) {
         SReq &q = *sv->reqs[L.slot[k].req];
         launch_gather(st, kMaxBatch, k, q.b + (int64_t)L.slot[k].col * N, h->perm, h->b, n);
       }
-  launch_slot_vectors(st, mask, restart, h->b, h->v64.res, h->v64.x, h->v64.r, n);
+  launch_slot_vectors(st, mask, restart, h->b, h->v64.res, h->v64.xs, h->v64.xl, h->v64.x, h->v64.r, n);
   launch_dot<double>(st, kMaxBatch, h->b, h->b, n, h->part_b, nullptr);
   launch_slot_scalars(st, mask, restart, h->scal, h->part_b, vec_blocks(n), lane_tol(sv, L), lane_maxit(sv, L),
                       h->scale_in, h->scale_out);
@@ -1174,8 +1221,10 @@ void lane_collect(Server *sv, Lane &L) {
   for (int k = 0; k < kMaxBatch; ++k)
     if (L.slot[k].req >= 0 && hs.done[k]) fin |= 1u << k;
   if (!fin) return;
+  launch_fold(st, kMaxBatch, fin, h->v64.xs, h->v64.xl, h->v64.x, h->P.n);
   double rr[kMaxBatch];
   true_residual(h, kMaxBatch, rr);
+  launch_round(st, h->v64.xs, h->v64.xl, h->v64.tmp, h->P.n * kMaxBatch);
   unsigned restart = 0;
   std::vector<SReq *> finished;
   int64_t n = h->P.n, N = h->P.n_nodes;
@@ -1206,7 +1255,7 @@ void lane_collect(Server *sv, Lane &L) {
     }
     double *xk = q.x + (int64_t)sl.col * N;
     launch_fill<double>(st, xk, N, 0.0, nullptr);
-    launch_scatter(st, kMaxBatch, k, h->v64.x, h->perm, xk, n);
+    launch_scatter(st, kMaxBatch, k, h->v64.tmp, h->perm, xk, n);
     q.iters[sl.col] = hs.iters[k];
     q.rel[sl.col] = rel;
     if (status < 0 || (q.status >= 0 && status > q.status)) q.status = status;
@@ -1324,7 +1373,7 @@ vemg_status vemg_create(const vemg_options *o, int device, void *hip_stream, vem
     opt = *o;
   else
     vemg_default_options(&opt);
-  if (opt.top_bc < 0 || opt.top_bc > 1 || opt.pc < 0 || opt.pc > 3 || opt.max_levels < 1 || opt.max_levels > 16 ||
+  if (opt.top_bc < 0 || opt.top_bc > 1 || opt.pc < 0 || opt.pc > 4 || opt.max_levels < 1 || opt.max_levels > 16 ||
       opt.coarse_max < 1 || opt.coarse_max > 8192 || !(opt.theta >= 0.0) || opt.poll_every < 1 ||
       opt.precision < 0 || opt.precision > 2 || !(opt.inner_rtol > 0.0 && opt.inner_rtol < 1.0) || opt.max_outer < 1)
     return VEMG_ERR_INVALID_ARG;

@@ -386,6 +386,31 @@ __global__ __launch_bounds__(kBlock) void k_dot(const T *__restrict__ a, const T
   block_sum_store<K>(t, partial + (int64_t)blockIdx.x * K);
 }
 
+// z_i += w_i on the rows i >= row0, then the block partials of r . z
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void k_add_dot(const T *__restrict__ w, const T *__restrict__ r,
+                                                    T *__restrict__ z, int64_t row0, int64_t n,
+                                                    double *__restrict__ partial, const int *__restrict__ done) {
+  if (done && *done) return;
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double t[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) t[k] = 0.0;
+  if (i < n) {
+    Row<T, K> zi = ld<T, K>(z, i);
+    const Row<T, K> ri = ld<T, K>(r, i);
+    if (i >= row0) {
+      const Row<T, K> wi = ld<T, K>(w, i);
+#pragma unroll
+      for (int k = 0; k < K; ++k) zi.v[k] += wi.v[k];
+      st<T, K>(z, i, zi);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) t[k] = (double)ri.v[k] * (double)zi.v[k];
+  }
+  block_sum_store<K>(t, partial + (int64_t)blockIdx.x * K);
+}
+
 template <class T, int K>
 __global__ void k_jacobi(const T *__restrict__ r, const double *__restrict__ dg, T *__restrict__ z, int64_t n,
                          const int *__restrict__ done) {
@@ -599,7 +624,8 @@ __global__ void k_pcg_resume(Scal *s, unsigned keep) {
 }
 
 __global__ void k_slot_vectors(unsigned mask, int restart, const double *__restrict__ b, const double *__restrict__ res,
-                               double *__restrict__ x, double *__restrict__ r, int64_t n) {
+                               double *__restrict__ hi, double *__restrict__ lo, double *__restrict__ x,
+                               double *__restrict__ r, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * kMaxBatch) return;
   int k = (int)(i % kMaxBatch);
@@ -607,6 +633,8 @@ __global__ void k_slot_vectors(unsigned mask, int restart, const double *__restr
   if (restart) {
     r[i] = res[i];
   } else {
+    hi[i] = 0.0;
+    lo[i] = 0.0;
     x[i] = 0.0;
     r[i] = b[i];
   }
@@ -666,11 +694,11 @@ inline dim3 grid(int64_t nb) { return dim3((unsigned)nb); }
 
 }  // namespace
 
-void launch_slot_vectors(hipStream_t stm, unsigned mask, bool restart, const double *b, const double *res, double *x,
-                         double *r, int64_t n) {
+void launch_slot_vectors(hipStream_t stm, unsigned mask, bool restart, const double *b, const double *res, double *hi,
+                         double *lo, double *x, double *r, int64_t n) {
   if (n <= 0 || !mask) return;
   hipLaunchKernelGGL(k_slot_vectors, grid(vec_blocks(n * kMaxBatch)), dim3(kBlock), 0, stm, mask, (int)restart, b, res,
-                     x, r, n);
+                     hi, lo, x, r, n);
 }
 void launch_slot_scalars(hipStream_t stm, unsigned mask, bool restart, Scal *s, const double *pb, int64_t npb,
                          double tol, int maxit, double *scale_in, double *scale_out) {
@@ -857,6 +885,14 @@ void launch_dot(hipStream_t stm, int K, const T *a, const T *b, int64_t n, doubl
 }
 
 template <class T>
+void launch_add_dot(hipStream_t stm, int K, const T *w, const T *r, T *z, int64_t row0, int64_t n, double *partial,
+                    const int *done) {
+  if (n <= 0) return;
+  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_add_dot<T, KK>), grid(vec_blocks(n)), dim3(kBlock), 0, stm, w, r, z, row0, n,
+                                      partial, done))
+}
+
+template <class T>
 void launch_jacobi(hipStream_t stm, int K, const T *r, const double *diag, T *z, int64_t n, const int *done) {
   if (n <= 0) return;
   VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_jacobi<T, KK>), grid(vec_blocks(n)), dim3(kBlock), 0, stm, r, diag, z, n,
@@ -935,6 +971,8 @@ void launch_pcg_resume(hipStream_t stm, int, Scal *s, unsigned keep) {
   template void launch_fill<T>(hipStream_t, T *, int64_t, T, const int *);                                           \
   template void launch_copy<T>(hipStream_t, const T *, T *, int64_t, const int *);                                   \
   template void launch_dot<T>(hipStream_t, int, const T *, const T *, int64_t, double *, const int *);                \
+  template void launch_add_dot<T>(hipStream_t, int, const T *, const T *, T *, int64_t, int64_t, double *,             \
+                                  const int *);                                                                      \
   template void launch_jacobi<T>(hipStream_t, int, const T *, const double *, T *, int64_t, const int *);             \
   template void launch_pcg_xr<T>(hipStream_t, int, Scal *, T *, T *, const T *, const T *, int64_t, double *);        \
   template void launch_pcg_p<T>(hipStream_t, int, Scal *, T *, const T *, int64_t);

@@ -111,6 +111,10 @@ void launch_copy(hipStream_t st, const T *a, T *b, int64_t count, const int *don
 // partial[block * K + k] = sum a_ik b_ik
 template <class T>
 void launch_dot(hipStream_t st, int K, const T *a, const T *b, int64_t n, double *partial, const int *done);
+// z_i += w_i for rows i >= row0; partial[block * K + k] = sum r_ik z_ik (updated z)
+template <class T>
+void launch_add_dot(hipStream_t st, int K, const T *w, const T *r, T *z, int64_t row0, int64_t n, double *partial,
+                    const int *done);
 template <class T>
 void launch_jacobi(hipStream_t st, int K, const T *r, const double *diag, T *z, int64_t n, const int *done);
 // natural <-> storage order for column k of a batch (stride K)
@@ -137,11 +141,23 @@ void launch_reduce(hipStream_t st, int K, const double *p, int64_t np, double *o
 // before a restart: clears done/status of the columns whose bit in keep is 0
 void launch_pcg_resume(hipStream_t st, int K, Scal *s, unsigned keep);
 
+// ---- extended iterate across restarts (refine.hip) ----------------------
+// The solution is the unevaluated sum hi + lo ([n][K] each); a restart's
+// correction x is folded in without rounding error for the columns in mask
+// (hi + x rounded, its error added to lo; x = 0 afterwards).
+void launch_fold(hipStream_t st, int K, unsigned mask, double *hi, double *lo, double *x, int64_t n);
+// res = b - A (hi + lo) on the fine difference-form matrix, with error-free
+// products and double-double sums, rounded once (K in {1,2,4,8}).
+void launch_residual_ext(hipStream_t st, int K, const Sell &A, const double *b, const double *hi, const double *lo,
+                         double *res);
+// out = hi + lo (rounded), count entries
+void launch_round(hipStream_t st, const double *hi, const double *lo, double *out, int64_t count);
+
 // Continuous batching (K = kMaxBatch slots): columns in `mask` (re)start
 // while the others keep their state.
-//   join: x_k = 0, r_k = b_k;   restart: r_k = res_k (x_k kept)
+//   join: hi_k = lo_k = x_k = 0, r_k = b_k;   restart: r_k = res_k (after a fold)
 void launch_slot_vectors(hipStream_t st, unsigned mask, bool restart, const double *b, const double *res,
-                         double *x, double *r, int64_t n);
+                         double *hi, double *lo, double *x, double *r, int64_t n);
 // join: bnorm2_k from the partials of b.b, iters_k = 0; both: done_k = 0
 // (1 for a zero right-hand side), status_k = 0, and the FP32 scaling of the
 // preconditioner input scale_in_k = 1/||b_k||, scale_out_k = ||b_k||

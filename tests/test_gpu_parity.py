@@ -103,7 +103,19 @@ def test_operators_match_oracle(built):
     assert e < tol
 
 
-@pytest.mark.parametrize("pc", ["vl_as", "vl_sor", "jacobi"])
+@pytest.mark.parametrize("pc", ["vl_sor", "vl_add"])
+@pytest.mark.parametrize("mode", ["N", "D"])
+def test_other_preconditioners_match_oracle(pc, mode):
+    m, s, o = _build(CFG1, mode, pc)
+    r = np.random.default_rng(2).standard_normal(o.n)
+    z = s.apply(lib.OP_PRECOND, r, o.n).cpu().numpy()
+    tol = max(_cycle_tol(o.Abar_levels), _cycle_tol(o.S_levels) if o.n_top > 0 else 0.0)
+    e = _rel(z, precond.make(o, pc)(r))
+    _print("precond", pc, mode, "rel", e, "tol", tol)
+    assert e < tol
+
+
+@pytest.mark.parametrize("pc", ["vl_as", "vl_sor", "vl_add", "jacobi"])
 def test_solution_matches_oracle(pc):
     m, s, o = _build(CFG1, "N", pc)
     b_nat = s.rhs(fourier_field(m.xyz, 0.01, 100))
@@ -127,10 +139,13 @@ def test_graded_multiscale_mesh_matches_oracle(pc):
     s = lib.Solver(m.xyz, m.tets, m.top, pc=pc, device=0, coarse_max=64)
     o = osolver.setup(m, "N", coarse_max=64)
     b_nat = s.rhs(fourier_field(m.xyz, 1e-3, 7))
+    # the small elements put the residual of any FP64-rounded solution near
+    # 6e-9 here; both sides refine an extended iterate with an exact
+    # residual, so 1e-11 is reachable
     xo, it_o, rel_o, ok = osolver.solve(o, b_nat[o.perm], 1e-11, pc, max_iter=5000)
     x, its, rels, st = s.solve(b_nat, rtol=1e-11, max_iter=5000)
-    _print("iters gpu", its, "oracle", it_o)
-    assert st == 0
+    _print("iters gpu", its, "oracle", it_o, "relres", rels, rel_o)
+    assert ok and st == 0 and rels[0] <= 1e-11
     assert _rel(x.cpu().numpy()[o.perm], xo) < 1e-8
     assert abs(its[0] - it_o) <= max(3, 0.1 * it_o)
 
@@ -240,12 +255,44 @@ def test_full_size_config2_residual_and_sampled_rows():
     _, Aoff = fem.assemble_stiffness(m.xyz, m.tets)
     D = fem.dirichlet_set(m.xyz, m.top, "N")
     U, Auu, d = fem.reduce_to_unknowns(Aoff, D)
-    r = b[U] - fem.apply_difference_form(Auu, d, x[U])
+    assert st == 0 and rels[0] <= 1e-8
+    # the library reports the residual of its extended iterate; the returned
+    # FP64 solution is that iterate rounded, which moves each residual entry
+    # by at most u (|A| |x|)_i, u = 2^-53
+    r = fem.residual_extended(Auu, d, b[U], x[U], np.zeros(U.size))
     rel = np.linalg.norm(r) / np.linalg.norm(b[U])
-    assert st == 0 and rel <= 1.05e-8
+    absA_x = np.abs(Auu) @ np.abs(x[U]) + np.abs(fem.diagonal_of(Auu, d)) * np.abs(x[U])
+    bound = 1e-8 + 2.0 ** -53 * np.linalg.norm(absA_x) / np.linalg.norm(b[U])
+    _print("residual of the rounded solution", rel, "bound", bound)
+    assert rel <= bound
     xr = np.random.default_rng(3).standard_normal(m.n)
     y = s.matvec(xr).cpu().numpy()
     ref = fem.apply_difference_form(Auu, d, xr[U])
     rows = np.random.default_rng(4).choice(U.size, 2000, replace=False)
     scale = np.abs(Auu).sum(axis=1).A.ravel()[rows] * np.abs(xr).max()
     assert np.max(np.abs(y[U][rows] - ref[rows]) / scale) < 1e-14
+
+
+@pytest.mark.timeout(400)
+def test_full_size_config4_mixed_batch8_reaches_tolerance():
+    # 257 x 257 x 33 thin box, eps 1e-4 (about 2.2M unknowns), eight seeded
+    # smooth right-hand sides per solve, FP32 preconditioner inside FP64 CG:
+    # every column reaches 1e-8 (the extended iterate removes the FP64
+    # accuracy floor that this aspect ratio would otherwise impose) and
+    # matches the FP64 path within 1e-6.
+    _dev()
+    m = box_mesh(257, 257, 33, 1e-4, bathymetry=True, jitter=0.3, seed=4)
+    _print("case config-4 full size", m.n)
+    sm = lib.Solver(m.xyz, m.tets, m.top, device=0, precision="mixed_pc")
+    B = np.stack([sm.rhs(fourier_field(m.xyz, 1e-4, 200 + k)) for k in range(8)])
+    xm, itm, relm, stm = sm.solve(B, rtol=1e-8, max_iter=3000)
+    _print("mixed iters", itm, "relres", relm, "status", stm)
+    assert stm == 0 and max(relm) <= 1e-8
+    sm.close()
+    s = lib.Solver(m.xyz, m.tets, m.top, device=0)
+    x, its, rels, st = s.solve(B, rtol=1e-8, max_iter=3000)
+    _print("fp64 iters", its, "relres", rels, "status", st)
+    assert st == 0 and max(rels) <= 1e-8
+    errs = [float(torch.linalg.norm(xm[k] - x[k]) / torch.linalg.norm(x[k])) for k in range(8)]
+    _print("mixed vs fp64", errs)
+    assert max(errs) <= 1e-6
