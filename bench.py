@@ -55,6 +55,105 @@ def gs_sweep_bytes(info, K=1, elt=8, val=8):
     return info["nnz_offdiag"] * (val + 4) + info["n"] * (8 + 4 * elt * K)
 
 
+def coarse_gs_bytes(info, level=1, K=1, elt=8, val=8):
+    """One forward multicolour sweep on a coarse A_bar level (CSR, standard
+    form without the diagonal): every off-diagonal once (value + column), per
+    row the row pointer, the diagonal and, per column, g_i, the read and
+    write of x_i and one gathered x_j."""
+    off = info["abar_nnz"][level] - info["abar_rows"][level]
+    return off * (val + 4) + info["abar_rows"][level] * (4 + 8 + 4 * elt * K)
+
+
+# Fine-level sweeps, fine SpMVs and coarse (first coarse level of A_bar and
+# the surface operator) sweeps per PCG iteration, by preconditioner:
+#   vl_as:  SOR cycle (2 fine sweeps, 1 residual SpMV, 2 sweeps on S) and the
+#           A_bar V-cycle (2 fine sweeps over the non-top rows, 1 residual
+#           SpMV, 2 sweeps on A_bar level 1), plus the CG product
+#   vl_sor: the SOR cycle alone plus the CG product
+#   vl_add: both V-cycles without the SOR cycle plus the CG product
+PER_ITERATION = {"vl_as": (4, 3, 4), "vl_sor": (2, 2, 2), "vl_add": (2, 2, 4), "jacobi": (0, 1, 0),
+                 "none": (0, 1, 0)}
+KERNEL_NAMES = {"gs": "k_gs<double, 1> (fine multicolour SOR, one colour per launch)",
+                "spmv": "k_spmv<double, 1, 0, true> (fine difference-form SpMV fused with p.q)",
+                "cgs": "k_csr_gs<double, 1, 32> (coarse multicolour SOR, one colour per launch)"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+
+
+def _kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_0912_1976_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key, workload):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 PMC
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel's reading),
+    or None when there is none for this kernel and workload or the kernel
+    sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != _kernel_source_hash() or rec.get("workload") != workload:
+        return None
+    k = rec.get("kernels", {}).get(kernel_key)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def profile_kernels(workload):
+    """The hot kernels of one PCG iteration, each repeated, plus a plain
+    copy of known size (the calibration of the PMC byte counters): the
+    command profiled by the rocprofv3 --pmc passes."""
+    import torch
+
+    import paper_0912_1976_amd as vemg
+    from inputs import box_mesh
+
+    wl = WORKLOADS[workload]
+    mesh = box_mesh(wl["nx"], wl["nx"], wl["nz"], wl["H"], jitter=wl["jitter"], seed=wl["seed"],
+                    bathymetry=wl["bathymetry"])
+    s = vemg.Solver(mesh.xyz, mesh.tets, mesh.top, top_bc="pinned", pc="vl_as", device=0)
+    info = s.info()
+    for name, op in (("fine sweep", vemg.OP_GS_FWD), ("fine spmv", vemg.OP_A), ("coarse sweep", vemg.OP_GS_COARSE)):
+        ms, nl = s.time_op(op, reps=10)
+        print(f"[profile] {name}: {ms:.4f} ms per application, {nl} launches", flush=True)
+    nbytes = 512 << 20
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"[profile] copy calibration: 5 copies of {nbytes} bytes; n={info['n']} "
+          f"nnz_offdiag={info['nnz_offdiag']}", flush=True)
+
+
+def pmc_summary(paths):
+    """Mean of each PMC counter per kernel over the dispatches of rocprofv3
+    counter-collection CSV files (values as the counters report them)."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    acc = defaultdict(lambda: [0.0, 0])
+    for p in paths:
+        files = [p] if p.endswith(".csv") else glob.glob(os.path.join(p, "**", "*counter_collection.csv"),
+                                                        recursive=True)
+        for f in files:
+            with open(f, newline="") as fh:
+                for row in csv.DictReader(fh):
+                    key = (row["Kernel_Name"], row["Counter_Name"])
+                    acc[key][0] += float(row["Counter_Value"])
+                    acc[key][1] += 1
+    print("| dispatches | mean value | counter | kernel |")
+    print("|---:|---:|---|---|")
+    for (kern, ctr), (tot, cnt) in sorted(acc.items(), key=lambda kv: -kv[1][0]):
+        print(f"| {cnt} | {tot / cnt:.1f} | {ctr} | `{kern[:110]}` |")
+
+
 def timed_solves(s, b, steps, warmup, rtol):
     import torch
     for _ in range(warmup):
@@ -178,17 +277,28 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="thinbox-129x129x33-eps1e-3", choices=sorted(WORKLOADS))
-    ap.add_argument("--pc", default="vl_as", choices=["vl_as", "vl_sor", "jacobi", "none"])
+    ap.add_argument("--pc", default="vl_as", choices=sorted(PER_ITERATION))
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline solve and roofline only")
     ap.add_argument("--serve-requests", type=int, default=96)
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="run only the hot kernels and a copy calibration (for rocprofv3 --pmc)")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="DIR_OR_CSV",
+                    help="summarise rocprofv3 counter-collection output and exit (no GPU)")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
               "(the multi-GPU decomposition is described in DESIGN.md, not built).", file=sys.stderr)
         sys.exit(2)
+
+    if args.profile_kernels:
+        profile_kernels(args.workload)
+        return
 
     import numpy as np
     import torch
@@ -217,15 +327,18 @@ def main():
     # live per-kernel timing (HIP events on the library's stream)
     ms_spmv, _ = s.time_op(vemg.OP_A, reps=50)
     ms_gs, nl_gs = s.time_op(vemg.OP_GS_FWD, reps=20)
-    # per PCG iteration the fine A is swept twice by SOR (the A_bar smoother)
-    # and applied twice as an SpMV (CG product, smoother residual)
-    if ms_gs >= ms_spmv:
-        dom = {"kernel": "k_gs<double,1> (fine multicolour SOR, one colour per launch)",
-               "bytes": gs_sweep_bytes(info) / nl_gs, "ms": ms_gs / nl_gs}
-    else:
-        dom = {"kernel": "k_spmv<double,1,0,true> (fine difference-form SpMV)", "bytes": spmv_bytes(info),
-               "ms": ms_spmv}
-    achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+    try:
+        ms_cgs, nl_cgs = s.time_op(vemg.OP_GS_COARSE, reps=20)
+    except vemg.VemgError:  # A_bar has no coarse level above the coarsest
+        ms_cgs, nl_cgs = 0.0, 1
+    n_gs, n_spmv, n_cgs = PER_ITERATION[args.pc]
+    share = {"gs": n_gs * ms_gs, "spmv": n_spmv * ms_spmv, "cgs": n_cgs * ms_cgs}
+    dom_key = max(share, key=share.get)
+    dom = {"gs": (gs_sweep_bytes(info) / nl_gs, ms_gs / nl_gs),
+           "spmv": (spmv_bytes(info), ms_spmv),
+           "cgs": (coarse_gs_bytes(info) / nl_cgs, ms_cgs / nl_cgs)}[dom_key]
+    achieved = dom[0] / (dom[1] * 1e-3) / 1e9
+    traffic = measured_traffic(dom_key, args.workload)
 
     extras = {}
     if not args.no_extras:
@@ -282,11 +395,14 @@ def main():
         "relres": max(r[0] for r in rels),
         "setup_s": t_setup,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom["kernel"],
-                     "bytes_per_launch": dom["bytes"], "ms_per_launch": dom["ms"]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": KERNEL_NAMES[dom_key],
+                     "bytes_per_launch": dom[0], "ms_per_launch": dom[1]},
         "kernels": {"spmv_ms": ms_spmv, "spmv_GBs": spmv_bytes(info) / (ms_spmv * 1e-3) / 1e9,
                     "gs_sweep_ms": ms_gs, "gs_sweep_GBs": gs_sweep_bytes(info) / (ms_gs * 1e-3) / 1e9,
-                    "gs_launches": nl_gs},
+                    "gs_launches": nl_gs, "coarse_sweep_ms": ms_cgs,
+                    "coarse_sweep_GBs": coarse_gs_bytes(info) / (ms_cgs * 1e-3) / 1e9 if ms_cgs else None,
+                    "coarse_launches": nl_cgs,
+                    "ms_per_iteration_estimate": share},
         "extras": extras,
         "cpu_baseline": cpu,
     }
