@@ -121,14 +121,61 @@ def profile_kernels(workload):
     for name, op in (("fine sweep", vemg.OP_GS_FWD), ("fine spmv", vemg.OP_A), ("coarse sweep", vemg.OP_GS_COARSE)):
         ms, nl = s.time_op(op, reps=10)
         print(f"[profile] {name}: {ms:.4f} ms per application, {nl} launches", flush=True)
-    nbytes = 512 << 20
-    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    a = torch.ones(CALIBRATION_BYTES // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(5):
-        b.copy_(a)
+    for _ in range(3):
+        torch.mul(a, 2.0, out=b)
     torch.cuda.synchronize()
-    print(f"[profile] copy calibration: 5 copies of {nbytes} bytes; n={info['n']} "
-          f"nnz_offdiag={info['nnz_offdiag']}", flush=True)
+    print(f"[profile] calibration: 3 elementwise products reading and writing {CALIBRATION_BYTES} bytes each; "
+          f"n={info['n']} nnz_offdiag={info['nnz_offdiag']}", flush=True)
+
+
+CALIBRATION_BYTES = 512 << 20
+PMC_KERNELS = {"gs": "k_gs<double, 1>", "spmv": "k_spmv<double, 1, 0, true>", "cgs": "k_csr_gs<double, 1, 32>",
+               "calibration": "MulFunctor"}
+
+
+def _pmc_means(path, counter):
+    import csv
+    import glob
+    files = [path] if path.endswith(".csv") else glob.glob(os.path.join(path, "**", "*counter_collection.csv"),
+                                                          recursive=True)
+    out = {}
+    for f in files:
+        with open(f, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] != counter:
+                    continue
+                for key, pat in PMC_KERNELS.items():
+                    if pat in row["Kernel_Name"]:
+                        t = out.setdefault(key, [0.0, 0])
+                        t[0] += float(row["Counter_Value"])
+                        t[1] += 1
+    return {k: v[0] / v[1] for k, v in out.items()}
+
+
+def pmc_traffic(fetch_dir, write_dir, workload):
+    """HBM-side bytes per launch of the hot kernels from the two PMC passes:
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each divided by what the
+    same counter reads for the calibration product (CALIBRATION_BYTES read
+    and written once) relative to its true size."""
+    fetch = _pmc_means(fetch_dir, "FETCH_SIZE")
+    write = _pmc_means(write_dir, "WRITE_SIZE")
+    kib = CALIBRATION_BYTES / 1024.0
+    ff, wf = fetch["calibration"] / kib, write["calibration"] / kib
+    rec = {"workload": workload, "source_hash": _kernel_source_hash(),
+           "calibration": {"bytes": CALIBRATION_BYTES, "fetch_factor": ff, "write_factor": wf},
+           "commands": [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o run -- "
+                        f"python3 -u bench.py --profile-kernels --workload {workload}",
+                        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {write_dir} -o run -- "
+                        f"python3 -u bench.py --profile-kernels --workload {workload}",
+                        f"python3 bench.py --pmc-traffic {fetch_dir} {write_dir} --workload {workload}"],
+           "kernels": {}}
+    for key in ("gs", "spmv", "cgs"):
+        if key in fetch and key in write:
+            rec["kernels"][key] = {"kernel": KERNEL_NAMES[key], "fetch_kib": fetch[key], "write_kib": write[key],
+                                   "hbm_bytes_per_launch": 1024.0 * (fetch[key] / ff + write[key] / wf)}
+    print(json.dumps(rec, indent=1))
 
 
 def pmc_summary(paths):
@@ -287,9 +334,14 @@ def main():
                     help="run only the hot kernels and a copy calibration (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-summary", nargs="+", metavar="DIR_OR_CSV",
                     help="summarise rocprofv3 counter-collection output and exit (no GPU)")
+    ap.add_argument("--pmc-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="per-launch HBM bytes of the hot kernels from the two PMC passes, as JSON (no GPU)")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args.pmc_summary)
+        return
+    if args.pmc_traffic:
+        pmc_traffic(*args.pmc_traffic, args.workload)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
