@@ -140,9 +140,9 @@ class Level:
 
 
 def colour_level(A):
-    """Greedy colouring in index order, then stable sort by colour.
+    """Greedy colouring in smallest-last order, then stable sort by colour.
     Returns (permutation new->old, colours in new order)."""
-    col = ordering.greedy_colouring(A)
+    col = ordering.colouring(A)
     perm = np.argsort(col, kind="stable")
     return perm, col[perm]
 

@@ -6,8 +6,11 @@ The paper orders the unknowns top block first, phi = (phi'; phi_bar)
 (eqs. phi_decomposition / equation_decomposition).  Within each block the
 order used here is a locality order followed by a colour sort, so that the
 symmetric Gauss-Seidel (SOR, omega = 1) sweeps of Section 6 can update one
-colour class at a time.  These are readings of the paper (it does not fix an
-order); they are pinned by the validity tests (permutation, valid colouring)
+colour class at a time.  Colours are greedy in smallest-last vertex order,
+which keeps the number of colour classes (sequential sweep stages) small:
+four on a Kuhn-split box, whose tetrahedra are 4-cliques.  These are
+readings of the paper (it does not fix an order); they are pinned by the
+validity tests (permutation, valid colouring, the smallest-last property)
 and, for the GPU library, by bit-exact comparison.
 
 Locality key of a free node (x, y, z):
@@ -41,6 +44,44 @@ def locality_order(xyz, top, free):
     idx = np.nonzero(free)[0]
     order = np.lexsort((idx, -z[idx], fine[idx], tile[idx], block[idx]))
     return idx[order]
+
+
+def smallest_last_order(A):
+    """Smallest-last vertex order of the off-diagonal pattern of the square
+    CSR matrix A (Matula and Beck): repeatedly remove the vertex of smallest
+    degree among the vertices not yet removed (degree counted over those
+    vertices only; ties to the smallest index), and return the removal
+    sequence reversed.  Greedy colouring in this order uses at most one more
+    colour than the graph's degeneracy.  Plain Python with a lazy heap."""
+    import heapq
+    n = A.shape[0]
+    indptr = A.indptr.tolist()
+    indices = A.indices.tolist()
+    deg = [0] * n
+    for i in range(n):
+        deg[i] = sum(1 for jj in range(indptr[i], indptr[i + 1]) if indices[jj] != i)
+    heap = [(deg[i], i) for i in range(n)]
+    heapq.heapify(heap)
+    removed = [False] * n
+    seq = []
+    while heap:
+        d, i = heapq.heappop(heap)
+        if removed[i] or d != deg[i]:
+            continue            # stale entry: i was removed or its degree has dropped
+        removed[i] = True
+        seq.append(i)
+        for jj in range(indptr[i], indptr[i + 1]):
+            j = indices[jj]
+            if j != i and not removed[j]:
+                deg[j] -= 1
+                heapq.heappush(heap, (deg[j], j))
+    seq.reverse()
+    return np.array(seq, dtype=np.int64)
+
+
+def colouring(A):
+    """The colouring used for every SOR sweep: greedy in smallest-last order."""
+    return greedy_colouring(A, smallest_last_order(A))
 
 
 def greedy_colouring(A, order=None):

@@ -4,11 +4,11 @@ Test infrastructure only.
 
 Order of the free unknowns ("storage order"): top block first (paper
 eq. phi_decomposition), each block in locality order, then stably sorted by
-the greedy colour of A_UU computed in locality order (see ordering.py).  The
+the colour of A_UU (greedy in smallest-last order, see ordering.py).  The
 non-top block is the matrix A_bar of eq. equation_decomposition; its colouring
 is the restriction of the colouring of A_UU.  The surface operator
-S = E~^T A E~ is coloured in the top block's storage order and stored colour
-by colour as well; E~'s columns follow that order.
+S = E~^T A E~ (indexed in the top block's storage order) is coloured the same
+way and stored colour by colour as well; E~'s columns follow that order.
 """
 from __future__ import annotations
 
@@ -59,7 +59,7 @@ def setup(mesh, mode="N", coarse_max=2048, max_levels=10):
     pos_in_U = np.full(n_nodes, -1, dtype=np.int64)
     pos_in_U[U] = np.arange(U.size)
     loc_u = pos_in_U[loc]
-    colour_u = ordering.greedy_colouring(Auu_nat, loc_u)
+    colour_u = ordering.colouring(Auu_nat)
     block = np.where(top[U], 0, 1)
     order_u = ordering.colour_sorted(loc_u, colour_u, block)
     perm = U[order_u]

@@ -8,7 +8,9 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <numeric>
+#include <queue>
 #include <sstream>
 #include <tuple>
 
@@ -117,6 +119,40 @@ std::vector<int32_t> greedy_colouring(const Csr &A, const std::vector<int64_t> &
   }
   return col;
 }
+
+// Smallest-last vertex order of the off-diagonal pattern: repeatedly remove a
+// vertex of smallest remaining degree (ties to the smallest index), then
+// reverse.  A lazy min-heap of (degree, index); entries whose degree has since
+// dropped, or whose vertex is gone, are skipped when popped.
+std::vector<int64_t> smallest_last_order(const Csr &A) {
+  const int64_t n = A.nrows;
+  std::vector<int64_t> deg(n, 0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) deg[i] += (A.idx[k] != i);
+  using Entry = std::pair<int64_t, int64_t>;
+  std::priority_queue<Entry, std::vector<Entry>, std::greater<Entry>> heap;
+  for (int64_t i = 0; i < n; ++i) heap.emplace(deg[i], i);
+  std::vector<char> removed(n, 0);
+  std::vector<int64_t> seq;
+  seq.reserve(n);
+  while (!heap.empty()) {
+    const Entry e = heap.top();
+    heap.pop();
+    const int64_t i = e.second;
+    if (removed[i] || e.first != deg[i]) continue;
+    removed[i] = 1;
+    seq.push_back(i);
+    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      const int64_t j = A.idx[k];
+      if (j != i && !removed[j]) heap.emplace(--deg[j], j);
+    }
+  }
+  std::reverse(seq.begin(), seq.end());
+  return seq;
+}
+
+// the colouring of every SOR sweep: greedy in smallest-last order
+std::vector<int32_t> sweep_colouring(const Csr &A) { return greedy_colouring(A, smallest_last_order(A)); }
 
 std::vector<int64_t> colour_ranges(const std::vector<int32_t> &col, int64_t a, int64_t b) {
   int32_t nc = 0;
@@ -375,9 +411,7 @@ void build_hierarchy(std::vector<Level> &levels, const SetupOptions &opt) {
     Csr P = spgemm(jacobi_smoother(L.A, opt.prolong_omega), P0);
     Csr Pt = transpose(P);
     Csr Ac = spgemm(Pt, spgemm(L.A, P));
-    std::vector<int64_t> ident(nc);
-    std::iota(ident.begin(), ident.end(), 0);
-    std::vector<int32_t> ccol = greedy_colouring(Ac, ident);
+    std::vector<int32_t> ccol = sweep_colouring(Ac);
     std::vector<int64_t> cperm = stable_colour_sort(ccol);
     std::vector<int64_t> cinv(nc);
     for (int64_t i = 0; i < nc; ++i) cinv[cperm[i]] = i;
@@ -588,7 +622,7 @@ void build_problem(Problem &P, const SetupOptions &opt, int64_t n_nodes, const d
     const Key &p = keys[a], &q = keys[b];
     return std::tie(p.block, p.tile, p.fine, p.negz, p.node) < std::tie(q.block, q.tile, q.fine, q.negz, q.node);
   });
-  std::vector<int32_t> colu = greedy_colouring(Auu, loc);
+  std::vector<int32_t> colu = sweep_colouring(Auu);
   std::vector<int64_t> order = loc;
   std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
     return std::make_pair(keys[a].block, colu[a]) < std::make_pair(keys[b].block, colu[b]);
@@ -697,9 +731,7 @@ void build_problem(Problem &P, const SetupOptions &opt, int64_t n_nodes, const d
     }
     Csr E0t = transpose(E0);
     Csr S0 = spgemm(E0t, spgemm(A, E0));
-    std::vector<int64_t> ident(m);
-    std::iota(ident.begin(), ident.end(), 0);
-    std::vector<int32_t> scol = greedy_colouring(S0, ident);
+    std::vector<int32_t> scol = sweep_colouring(S0);
     P.S_perm = stable_colour_sort(scol);
     std::vector<int64_t> sinv(m);
     for (int64_t i = 0; i < m; ++i) sinv[P.S_perm[i]] = i;

@@ -89,6 +89,46 @@ def test_colourings_and_aggregates_valid():
             assert L.agg.min() == 0 and np.unique(L.agg).size == L.agg.max() + 1
 
 
+def _brute_smallest_last(A):
+    # the definition, by recomputation from scratch at every step
+    n = A.shape[0]
+    Ad = (A.tocsr() != 0).astype(int).tolil()
+    Ad.setdiag(0)
+    G = sp.csr_matrix(Ad)
+    G = ((G + G.T) > 0).astype(int)
+    alive = np.ones(n, bool)
+    seq = []
+    for _ in range(n):
+        deg = np.asarray(G[:, alive].sum(axis=1)).ravel()
+        cand = np.nonzero(alive)[0]
+        i = cand[np.argmin(deg[cand])]      # first minimum = smallest index
+        seq.append(i)
+        alive[i] = False
+    return np.array(seq[::-1])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_smallest_last_order_matches_definition(seed):
+    rng = np.random.default_rng(seed)
+    n = 60
+    R = sp.random(n, n, density=0.08, random_state=rng, format="csr")
+    A = (R + R.T + sp.eye(n)).tocsr()
+    A.sort_indices()
+    assert np.array_equal(ordering.smallest_last_order(A), _brute_smallest_last(A))
+    col = ordering.colouring(A)
+    assert ordering.is_valid_colouring(A, col)
+
+
+def test_kuhn_box_needs_exactly_four_colours():
+    # every tetrahedron is a 4-clique of the matrix graph, so four colours are
+    # the minimum; the Kuhn split admits four ((i + j + k) mod 4 differs along
+    # every edge), and the smallest-last greedy colouring finds that minimum
+    m = box_mesh(9, 8, 6, 1e-3, jitter=0.3, seed=4, bathymetry=True)
+    s = solver.setup(m, "N")
+    assert ordering.is_valid_colouring(s.A, s.colour)
+    assert int(s.colour.max()) + 1 == 4
+
+
 def test_multicolour_gs_equals_sequential_gs():
     # forward sweep with zero initial guess = (D + L)^{-1} g in colour-sorted order
     m, s = _hier()
