@@ -226,6 +226,13 @@ struct DLevel {
 
 enum GraphKind { kGraphFP64 = 0, kGraphFP32 = 1, kGraphMixedPC = 2 };
 
+// the captured graphs of one PCG iteration: a single graph, or four segments
+struct IterGraphs {
+  hipGraph_t graph[4] = {};
+  hipGraphExec_t exec[4] = {};
+  int parts = 0;
+};
+
 }  // namespace
 }  // namespace vemg
 
@@ -249,7 +256,7 @@ struct vemg_solver_s {
   int64_t *perm = nullptr;
   vemg::Scal *scal = nullptr;
   int64_t nnz_A = 0, nnz_E = 0;
-  std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;  // key: kind * 16 + K
+  std::map<int, vemg::IterGraphs> graphs;  // key: kind * 16 + K
   // false for server lanes once the scheduler runs: a capture on one thread
   // must not coincide with device-wide synchronisation on another
   bool allow_capture = true;
@@ -377,49 +384,70 @@ void additive_smoother(Handle *h, hipStream_t st, int K, const T *rr, const int 
   h->Ab[0].g<T>() = saved;
 }
 
+// The two VL+additive forms have a second, independent branch: the additive
+// smoother beside the SOR cycle (VEMG_PC_VL_ADDITIVE), or the surface branch
+// beside the smoother (VEMG_PC_VL_ADDITIVE_ONLY with a non-empty surface).
+bool has_branch(const Handle *h) {
+  return h->opt.pc == VEMG_PC_VL_ADDITIVE || (h->opt.pc == VEMG_PC_VL_ADDITIVE_ONLY && h->P.n_top > 0);
+}
+
+// second branch, on stream st2
+template <class T>
+void precond_branch(Handle *h, hipStream_t st2, int K, const T *rr, const int *done) {
+  if (h->opt.pc == VEMG_PC_VL_ADDITIVE) {
+    additive_smoother<T>(h, st2, K, rr, done);
+  } else {
+    launch_csr_rect<T>(st2, K, h->Et, false, rr, h->S[0].g<T>(), done);
+    vcycle<T>(st2, K, h->S, 0, done);
+  }
+}
+
+// first branch, on stream st
+template <class T>
+void precond_main(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *done) {
+  if (h->opt.pc == VEMG_PC_VL_ADDITIVE)
+    sor_cycle<T>(h, st, K, rr, zz, done);
+  else
+    additive_smoother<T>(h, st, K, rr, done);
+}
+
+// after both branches: z = sum of the two, partials of rr . z (returns their count)
+template <class T>
+int64_t precond_join(Handle *h, hipStream_t st, int K, const T *rr, T *zz, double *part, const int *done) {
+  const int64_t n = h->P.n, m = h->P.n_top;
+  Work<T> &v = work_of<T>(h);
+  if (h->opt.pc == VEMG_PC_VL_ADDITIVE) {
+    launch_add_dot<T>(st, K, v.w, rr, zz, m, n, part, done);
+    return vec_blocks(n);
+  }
+  launch_prolong_sum<T>(st, K, h->E, m, h->S[0].x<T>(), v.w, rr, zz, part, done);
+  return sell_blocks(0, n);
+}
+
 // z = M^{-1} rr in precision T; partial sums of rr . z go to part (blocks in *np)
 template <class T>
 void precond(Handle *h, int K, const T *rr, T *zz, double *part, int64_t *np, const int *done) {
   hipStream_t st = h->work;
   const Problem &P = h->P;
-  int64_t n = P.n, m = P.n_top;
+  int64_t n = P.n;
   Work<T> &v = work_of<T>(h);
+  if (has_branch(h)) {
+    HIPCHK(hipEventRecord(h->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(h->work2, h->ev_fork, 0));
+    precond_branch<T>(h, h->work2, K, rr, done);
+    HIPCHK(hipEventRecord(h->ev_join, h->work2));
+    precond_main<T>(h, st, K, rr, zz, done);
+    HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
+    *np = precond_join<T>(h, st, K, rr, zz, part, done);
+    return;
+  }
   switch (h->opt.pc) {
-    case VEMG_PC_VL_ADDITIVE: {
-      // the lumping cycle and the additive smoother are independent: the
-      // smoother runs on the second stream (a parallel graph branch)
-      HIPCHK(hipEventRecord(h->ev_fork, st));
-      HIPCHK(hipStreamWaitEvent(h->work2, h->ev_fork, 0));
-      additive_smoother<T>(h, h->work2, K, rr, done);
-      HIPCHK(hipEventRecord(h->ev_join, h->work2));
-      sor_cycle<T>(h, st, K, rr, zz, done);
-      HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
-      launch_add_dot<T>(st, K, v.w, rr, zz, m, n, part, done);
+    case VEMG_PC_VL_ADDITIVE_ONLY:  // empty surface: the additive smoother alone
+      additive_smoother<T>(h, st, K, rr, done);
+      launch_copy<T>(st, v.w, zz, n * K, done);
+      launch_dot<T>(st, K, rr, zz, n, part, done);
       *np = vec_blocks(n);
       break;
-    }
-    case VEMG_PC_VL_ADDITIVE_ONLY: {
-      // the two terms of eq. ourpreconditioner are independent: the surface
-      // branch runs on the second stream
-      if (m > 0) {
-        HIPCHK(hipEventRecord(h->ev_fork, st));
-        HIPCHK(hipStreamWaitEvent(h->work2, h->ev_fork, 0));
-        launch_csr_rect<T>(h->work2, K, h->Et, false, rr, h->S[0].g<T>(), done);
-        vcycle<T>(h->work2, K, h->S, 0, done);
-        HIPCHK(hipEventRecord(h->ev_join, h->work2));
-      }
-      additive_smoother<T>(h, st, K, rr, done);
-      if (m > 0) {
-        HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
-        launch_prolong_sum<T>(st, K, h->E, m, h->S[0].x<T>(), v.w, rr, zz, part, done);
-        *np = sell_blocks(0, n);
-      } else {
-        launch_copy<T>(st, v.w, zz, n * K, done);
-        launch_dot<T>(st, K, rr, zz, n, part, done);
-        *np = vec_blocks(n);
-      }
-      break;
-    }
     case VEMG_PC_VL_SOR:
       sor_cycle<T>(h, st, K, rr, zz, done);
       launch_dot<T>(st, K, rr, zz, n, part, done);
@@ -449,14 +477,81 @@ int64_t precond_mixed(Handle *h, int K, const double *rr, double *zz, const int 
   return vec_blocks(n);
 }
 
-// one PCG iteration in precision T (kind FP64/FP32) or FP64 with an FP32
-// preconditioner (kind MixedPC)
+// One PCG iteration in precision T (kind FP64/FP32) or FP64 with an FP32
+// preconditioner (kind MixedPC), in four segments: the Krylov part up to the
+// convergence test (and the FP32 demotion), the preconditioner's second
+// branch (stream work2), its first branch, and the join plus the rest of the
+// Krylov update.  Eagerly they run back to back with an event fork and join;
+// as graphs each segment is captured on its own and launched on its stream,
+// so that the two branches overlap on the device.
+enum Segment { kSegPre = 0, kSegBranch = 1, kSegMain = 2, kSegPost = 3 };
+
+template <class T>
+void pcg_segment(Handle *h, int K, int kind, int seg) {
+  hipStream_t st = h->work;
+  int64_t n = h->P.n;
+  Work<T> &v = work_of<T>(h);
+  const int *done = &h->scal->all_done;
+  const bool mixed = kind == kGraphMixedPC;
+  switch (seg) {
+    case kSegPre:
+      launch_spmv<T>(st, K, h->A, 0, 0, n, v.p, (const T *)nullptr, v.q, h->part_pq, done);
+      launch_pcg_alpha(st, K, h->scal, h->part_pq, sell_blocks(0, n));
+      launch_pcg_xr<T>(st, K, h->scal, v.x, v.r, v.p, v.q, n, h->part_rr);
+      launch_pcg_conv(st, K, h->scal, h->part_rr, vec_blocks(n));
+      if constexpr (std::is_same<T, double>::value)
+        if (mixed) launch_demote(st, K, v.r, h->scale_in, h->v32.tmp, n, done);
+      break;
+    case kSegBranch:
+      if (mixed)
+        precond_branch<float>(h, h->work2, K, h->v32.tmp, done);
+      else
+        precond_branch<T>(h, h->work2, K, v.r, done);
+      break;
+    case kSegMain:
+      if (mixed)
+        precond_main<float>(h, st, K, h->v32.tmp, h->v32.z, done);
+      else
+        precond_main<T>(h, st, K, v.r, v.z, done);
+      break;
+    case kSegPost: {
+      int64_t np;
+      if constexpr (std::is_same<T, double>::value) {
+        if (mixed) {
+          precond_join<float>(h, st, K, h->v32.tmp, h->v32.z, h->part_t, done);
+          launch_promote(st, K, h->v32.z, h->scale_out, v.z, n, false, done);
+          launch_dot<double>(st, K, v.r, v.z, n, h->part_rz, done);
+          np = vec_blocks(n);
+        } else {
+          np = precond_join<T>(h, st, K, v.r, v.z, h->part_rz, done);
+        }
+      } else {
+        np = precond_join<T>(h, st, K, v.r, v.z, h->part_rz, done);
+      }
+      launch_pcg_beta(st, K, h->scal, h->part_rz, np);
+      launch_pcg_p<T>(st, K, h->scal, v.p, v.z, n);
+      break;
+    }
+  }
+}
+
 template <class T>
 void pcg_iteration(Handle *h, int K, int kind) {
   hipStream_t st = h->work;
   int64_t n = h->P.n;
   Work<T> &v = work_of<T>(h);
   const int *done = &h->scal->all_done;
+  if (has_branch(h)) {
+    pcg_segment<T>(h, K, kind, kSegPre);
+    HIPCHK(hipEventRecord(h->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(h->work2, h->ev_fork, 0));
+    pcg_segment<T>(h, K, kind, kSegBranch);
+    HIPCHK(hipEventRecord(h->ev_join, h->work2));
+    pcg_segment<T>(h, K, kind, kSegMain);
+    HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
+    pcg_segment<T>(h, K, kind, kSegPost);
+    return;
+  }
   launch_spmv<T>(st, K, h->A, 0, 0, n, v.p, (const T *)nullptr, v.q, h->part_pq, done);
   launch_pcg_alpha(st, K, h->scal, h->part_pq, sell_blocks(0, n));
   launch_pcg_xr<T>(st, K, h->scal, v.x, v.r, v.p, v.q, n, h->part_rr);
@@ -472,37 +567,60 @@ void pcg_iteration(Handle *h, int K, int kind) {
 }
 
 void destroy_graphs(Handle *h) {
-  for (auto &kv : h->graphs) {
-    if (kv.second.second) (void)hipGraphExecDestroy(kv.second.second);
-    if (kv.second.first) (void)hipGraphDestroy(kv.second.first);
-  }
+  for (auto &kv : h->graphs)
+    for (int i = 0; i < 4; ++i) {
+      if (kv.second.exec[i]) (void)hipGraphExecDestroy(kv.second.exec[i]);
+      if (kv.second.graph[i]) (void)hipGraphDestroy(kv.second.graph[i]);
+    }
   h->graphs.clear();
 }
 
-// graph of one iteration for (kind, K), captured on first use when allowed
+template <class F>
+void capture(hipStream_t st, hipGraph_t *g, hipGraphExec_t *ge, F &&record) {
+  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  record();
+  HIPCHK(hipStreamEndCapture(st, g));
+  HIPCHK(hipGraphInstantiate(ge, *g, nullptr, nullptr, 0));
+}
+
+// graphs of one iteration for (kind, K), captured on first use when allowed:
+// one graph, or the four segments when the preconditioner has two branches
 template <class T>
-hipGraphExec_t iteration_graph(Handle *h, int K, int kind) {
+const IterGraphs *iteration_graphs(Handle *h, int K, int kind) {
   int key = kind * 16 + K;
   auto it = h->graphs.find(key);
-  if (it != h->graphs.end()) return it->second.second;
+  if (it != h->graphs.end()) return &it->second;
   if (!h->allow_capture) return nullptr;
-  HIPCHK(hipStreamBeginCapture(h->work, hipStreamCaptureModeThreadLocal));
-  pcg_iteration<T>(h, K, kind);
-  hipGraph_t g = nullptr;
-  HIPCHK(hipStreamEndCapture(h->work, &g));
-  hipGraphExec_t ge = nullptr;
-  HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-  h->graphs.emplace(key, std::make_pair(g, ge));
-  return ge;
+  IterGraphs ig;
+  if (has_branch(h)) {
+    ig.parts = 4;
+    for (int seg = 0; seg < 4; ++seg)
+      capture(seg == kSegBranch ? h->work2 : h->work, &ig.graph[seg], &ig.exec[seg],
+              [&]() { pcg_segment<T>(h, K, kind, seg); });
+  } else {
+    ig.parts = 1;
+    capture(h->work, &ig.graph[0], &ig.exec[0], [&]() { pcg_iteration<T>(h, K, kind); });
+  }
+  return &h->graphs.emplace(key, ig).first->second;
 }
 
 template <class T>
 void run_iteration(Handle *h, int K, int kind) {
-  hipGraphExec_t ge = h->opt.use_graphs ? iteration_graph<T>(h, K, kind) : nullptr;
-  if (ge)
-    HIPCHK(hipGraphLaunch(ge, h->work));
-  else
+  const IterGraphs *ig = h->opt.use_graphs ? iteration_graphs<T>(h, K, kind) : nullptr;
+  if (!ig) {
     pcg_iteration<T>(h, K, kind);
+  } else if (ig->parts == 1) {
+    HIPCHK(hipGraphLaunch(ig->exec[0], h->work));
+  } else {
+    HIPCHK(hipGraphLaunch(ig->exec[kSegPre], h->work));
+    HIPCHK(hipEventRecord(h->ev_fork, h->work));
+    HIPCHK(hipStreamWaitEvent(h->work2, h->ev_fork, 0));
+    HIPCHK(hipGraphLaunch(ig->exec[kSegBranch], h->work2));
+    HIPCHK(hipEventRecord(h->ev_join, h->work2));
+    HIPCHK(hipGraphLaunch(ig->exec[kSegMain], h->work));
+    HIPCHK(hipStreamWaitEvent(h->work, h->ev_join, 0));
+    HIPCHK(hipGraphLaunch(ig->exec[kSegPost], h->work));
+  }
 }
 
 Scal read_scal(Handle *h) {
@@ -1579,8 +1697,8 @@ vemg_status vemg_server_add_mesh(vemg_server sv, int64_t n_nodes, const double *
   // capture both iteration graphs now, while no other thread uses the device
   int gst = guarded(h, [&]() -> int {
     if (h->opt.use_graphs) {
-      vemg::iteration_graph<double>(h, vemg::kMaxBatch, vemg::kGraphFP64);
-      vemg::iteration_graph<double>(h, vemg::kMaxBatch, vemg::kGraphMixedPC);
+      vemg::iteration_graphs<double>(h, vemg::kMaxBatch, vemg::kGraphFP64);
+      vemg::iteration_graphs<double>(h, vemg::kMaxBatch, vemg::kGraphMixedPC);
       HIPCHK(hipStreamSynchronize(h->work));
     }
     h->allow_capture = false;

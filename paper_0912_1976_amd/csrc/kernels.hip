@@ -111,6 +111,36 @@ __device__ __forceinline__ void sell_row(const Sell &A, int64_t s, int lane, con
 }
 
 // ------------------------------------------------------------- fine matrix
+// (A x)_r in difference form (MODE 0), or g_r - (A x)_r (MODE 1)
+template <class T, int K, int MODE>
+__device__ __forceinline__ Row<T, K> fine_apply(const Sell &A, int64_t r, const Row<T, K> &xr, const T (&acc)[K],
+                                                const T *__restrict__ g) {
+  Row<T, K> out;
+  if constexpr (std::is_same<T, double>::value) {
+    const double dr = A.d64[r];
+#pragma unroll
+    for (int k = 0; k < K; ++k) out.v[k] = acc[k] + dr * xr.v[k];
+  } else {
+    const float sr = A.s32[r], dh = A.dh32[r];
+#pragma unroll
+    for (int k = 0; k < K; ++k) out.v[k] = sr * (acc[k] + dh * xr.v[k]);
+  }
+  if (MODE == 1) {
+    const Row<T, K> gr = ld<T, K>(g, r);
+#pragma unroll
+    for (int k = 0; k < K; ++k) out.v[k] = gr.v[k] - out.v[k];
+  }
+  return out;
+}
+
+template <class T, int K, int MODE>
+__device__ __forceinline__ Row<T, K> fine_row(const Sell &A, int64_t s, int lane, int64_t r, const T *__restrict__ x,
+                                              const Row<T, K> &xr, const T *__restrict__ g) {
+  T acc[K], off;
+  sell_row<T, K, true>(A, s, lane, x, xr, acc, off);
+  return fine_apply<T, K, MODE>(A, r, xr, acc, g);
+}
+
 template <class T, int K, int MODE, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmv(Sell A, int64_t r0, int64_t r1, int64_t s_first, int64_t nb,
                                                  const T *__restrict__ x, const T *__restrict__ g,
@@ -126,23 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Sell A, int64_t r0, int64_t r1,
   for (int k = 0; k < K; ++k) prod[k] = 0.0;
   if (r >= r0 && r < r1) {
     const Row<T, K> xr = ld<T, K>(x, r);
-    T acc[K], off;
-    sell_row<T, K, true>(A, s, lane, x, xr, acc, off);
-    Row<T, K> out;
-    if constexpr (std::is_same<T, double>::value) {
-      const double dr = A.d64[r];
-#pragma unroll
-      for (int k = 0; k < K; ++k) out.v[k] = acc[k] + dr * xr.v[k];
-    } else {
-      const float sr = A.s32[r], dh = A.dh32[r];
-#pragma unroll
-      for (int k = 0; k < K; ++k) out.v[k] = sr * (acc[k] + dh * xr.v[k]);
-    }
-    if (MODE == 1) {
-      const Row<T, K> gr = ld<T, K>(g, r);
-#pragma unroll
-      for (int k = 0; k < K; ++k) out.v[k] = gr.v[k] - out.v[k];
-    }
+    const Row<T, K> out = fine_row<T, K, MODE>(A, s, lane, r, x, xr, g);
     st<T, K>(y, r, out);
     if (DOT) {
 #pragma unroll
@@ -152,29 +166,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Sell A, int64_t r0, int64_t r1,
   if (DOT) block_sum_store<K>(prod, partial + blk * K);
 }
 
-// one wavefront (one slice) per block: a colour holds few rows, so small
-// blocks spread them over every CU
+// device form of the row ranges of one multicolour step
+template <class T>
+struct GsDev {
+  int64_t r0[2], r1[2], sf[2], nb[2];
+  T *x;
+  int n;
+  int64_t nbt;
+};
+
+// one Gauss-Seidel step of row r: x_r + (g_r - (A x)_r) / a_rr
 template <class T, int K>
-__global__ __launch_bounds__(kWave) void k_gs(Sell A, int64_t a0, int64_t a1, int64_t sa, int64_t nba, int64_t b0,
-                                               int64_t b1, int64_t sb, int64_t nbt, const T *__restrict__ g,
-                                               T *__restrict__ x, const int *__restrict__ done) {
-  if (done && *done) return;
-  int64_t blk = xcd_block(blockIdx.x, nbt);
-  int64_t r0 = a0, r1 = a1, sf = sa;
-  if (blk >= nba) {
-    blk -= nba;
-    r0 = b0;
-    r1 = b1;
-    sf = sb;
-  }
-  const int lane = threadIdx.x & 63;
-  const int64_t s = sf + blk;
-  const int64_t r = s * 64 + lane;
-  if (r < r0 || r >= r1) return;
-  const Row<T, K> xr = ld<T, K>(x, r);
-  const Row<T, K> gr = ld<T, K>(g, r);
-  T acc[K], off;
-  sell_row<T, K, true>(A, s, lane, x, xr, acc, off);
+__device__ __forceinline__ Row<T, K> gs_apply(const Sell &A, int64_t r, const Row<T, K> &xr, const Row<T, K> &gr,
+                                              const T (&acc)[K], T off) {
   Row<T, K> out;
   if constexpr (std::is_same<T, double>::value) {
     const double dr = A.d64[r], diag = dr - off;
@@ -185,7 +189,33 @@ __global__ __launch_bounds__(kWave) void k_gs(Sell A, int64_t a0, int64_t a1, in
 #pragma unroll
     for (int k = 0; k < K; ++k) out.v[k] = xr.v[k] + (gr.v[k] * inv_s - (acc[k] + dh * xr.v[k])) / diag;
   }
-  st<T, K>(x, r, out);
+  return out;
+}
+
+// one wavefront (one slice) per block: a colour holds few rows, so small
+// blocks spread them over every CU; up to two row ranges (the top and the
+// non-top rows of one colour)
+template <class T, int K>
+__global__ __launch_bounds__(kWave) void k_gs(Sell A, GsDev<T> J, const T *__restrict__ g,
+                                               const int *__restrict__ done) {
+  if (done && *done) return;
+  int64_t blk = xcd_block(blockIdx.x, J.nbt);
+  int j = 0;
+  while (j + 1 < J.n && blk >= J.nb[j]) {
+    blk -= J.nb[j];
+    ++j;
+  }
+  const int64_t r0 = J.r0[j], r1 = J.r1[j];
+  T *x = J.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t s = J.sf[j] + blk;
+  const int64_t r = s * 64 + lane;
+  if (r < r0 || r >= r1) return;
+  const Row<T, K> xr = ld<T, K>(x, r);
+  const Row<T, K> gr = ld<T, K>(g, r);
+  T acc[K], off;
+  sell_row<T, K, true>(A, s, lane, x, xr, acc, off);
+  st<T, K>(x, r, gs_apply<T, K>(A, r, xr, gr, acc, off));
 }
 
 template <class T, int K, bool ACC>
@@ -268,20 +298,27 @@ __device__ __forceinline__ void group_row(const CsrG &A, int64_t r, int gl, cons
   }
 }
 
-// MODE 0: y = A x, 1: y = g - A x (square); 2: y = P x, 3: y += P x
+// Row r of a CsrG operation, by its group of G lanes (lane 0 of the group
+// writes).  MODE 0: y = A x, 1: y = g - A x (square); 2: y = P x, 3: y += P x;
+// 4: one Gauss-Seidel step y_r = (g_r - sum_j a_rj x_j) / a_rr (y = x).
 template <class T, int K, int G, int MODE>
-__global__ __launch_bounds__(kWave) void k_csr_spmv(CsrG A, int64_t r0, int64_t r1, const T *__restrict__ x,
-                                                     const T *__restrict__ g, T *__restrict__ y,
-                                                     const int *__restrict__ done) {
-  if (done && *done) return;
-  const int gl = threadIdx.x & (G - 1);
-  const int64_t r = r0 + ((int64_t)blockIdx.x * kWave + threadIdx.x) / G;
-  if (r >= r1) return;
+__device__ __forceinline__ void csr_row_op(const CsrG &A, int64_t r, int gl, const T *x, const T *g, T *y) {
   T acc[K];
-  group_row<T, K, G>(A, r, gl, x, acc);
+  group_row<T, K, G>(A, r, gl, x, acc);  // off-diagonal part only
   if (gl != 0) return;
   Row<T, K> out;
-  if (MODE <= 1) {
+  if (MODE == 4) {
+    const Row<T, K> gr = ld<T, K>(g, r);
+    if constexpr (std::is_same<T, double>::value) {
+      const double dr = A.d64[r];
+#pragma unroll
+      for (int k = 0; k < K; ++k) out.v[k] = (gr.v[k] - acc[k]) / dr;
+    } else {
+      const float inv_s = 1.0f / A.s32[r];
+#pragma unroll
+      for (int k = 0; k < K; ++k) out.v[k] = gr.v[k] * inv_s - acc[k];
+    }
+  } else if (MODE <= 1) {
     const Row<T, K> xr = ld<T, K>(x, r);
     if constexpr (std::is_same<T, double>::value) {
       const double dr = A.d64[r];
@@ -308,6 +345,17 @@ __global__ __launch_bounds__(kWave) void k_csr_spmv(CsrG A, int64_t r0, int64_t 
   st<T, K>(y, r, out);
 }
 
+template <class T, int K, int G, int MODE>
+__global__ __launch_bounds__(kWave) void k_csr_spmv(CsrG A, int64_t r0, int64_t r1, const T *__restrict__ x,
+                                                     const T *__restrict__ g, T *__restrict__ y,
+                                                     const int *__restrict__ done) {
+  if (done && *done) return;
+  const int gl = threadIdx.x & (G - 1);
+  const int64_t r = r0 + ((int64_t)blockIdx.x * kWave + threadIdx.x) / G;
+  if (r >= r1) return;
+  csr_row_op<T, K, G, MODE>(A, r, gl, x, g, y);
+}
+
 template <class T, int K, int G>
 __global__ __launch_bounds__(kWave) void k_csr_gs(CsrG A, int64_t r0, int64_t r1, const T *__restrict__ g,
                                                    T *__restrict__ x, const int *__restrict__ done) {
@@ -315,31 +363,13 @@ __global__ __launch_bounds__(kWave) void k_csr_gs(CsrG A, int64_t r0, int64_t r1
   const int gl = threadIdx.x & (G - 1);
   const int64_t r = r0 + ((int64_t)blockIdx.x * kWave + threadIdx.x) / G;
   if (r >= r1) return;
-  T acc[K];
-  group_row<T, K, G>(A, r, gl, x, acc);  // off-diagonal part only
-  if (gl != 0) return;
-  const Row<T, K> gr = ld<T, K>(g, r);
-  Row<T, K> out;
-  if constexpr (std::is_same<T, double>::value) {
-    const double dr = A.d64[r];
-#pragma unroll
-    for (int k = 0; k < K; ++k) out.v[k] = (gr.v[k] - acc[k]) / dr;
-  } else {
-    const float inv_s = 1.0f / A.s32[r];
-#pragma unroll
-    for (int k = 0; k < K; ++k) out.v[k] = gr.v[k] * inv_s - acc[k];
-  }
-  st<T, K>(x, r, out);
+  csr_row_op<T, K, G, 4>(A, r, gl, x, g, x);
 }
 
 // one wavefront per row of the dense FP64 coarsest inverse
 template <class T, int K>
-__global__ __launch_bounds__(kBlock) void k_dense(const double *__restrict__ C, int64_t m, const T *__restrict__ g,
-                                                  T *__restrict__ x, const int *__restrict__ done) {
-  if (done && *done) return;
-  const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
-  if (i >= m) return;
+__device__ __forceinline__ void dense_row(const double *__restrict__ C, int64_t m, int64_t i, int lane,
+                                          const T *__restrict__ g, T *__restrict__ x) {
   double t[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) t[k] = 0.0;
@@ -353,6 +383,15 @@ __global__ __launch_bounds__(kBlock) void k_dense(const double *__restrict__ C, 
 #pragma unroll
   for (int k = 0; k < K; ++k) out.v[k] = (T)wave_sum(t[k]);
   if (lane == 0) st<T, K>(x, i, out);
+}
+
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void k_dense(const double *__restrict__ C, int64_t m, const T *__restrict__ g,
+                                                  T *__restrict__ x, const int *__restrict__ done) {
+  if (done && *done) return;
+  const int64_t i = (int64_t)blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
+  if (i >= m) return;
+  dense_row<T, K>(C, m, i, threadIdx.x & 63, g, x);
 }
 
 // ------------------------------------------------------------- vectors
@@ -785,12 +824,21 @@ static inline int64_t slices(int64_t r0, int64_t r1) {
 template <class T>
 void launch_gs(hipStream_t stm, int K, const Sell &A, int64_t a0, int64_t a1, int64_t b0, int64_t b1, const T *g,
                T *x, const int *done) {
-  int64_t nba = slices(a0, a1), nbb = slices(b0, b1);
-  int64_t nbt = nba + nbb;
-  if (!nbt) return;
-  int64_t sa = a0 / kWave, sb = b0 / kWave;
-  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_gs<T, KK>), grid(nbt), dim3(kWave), 0, stm, A, a0, a1, sa, nba, b0, b1, sb,
-                                      nbt, g, x, done))
+  GsDev<T> J{};
+  J.x = x;
+  const int64_t ra[2] = {a0, b0}, rb[2] = {a1, b1};
+  for (int i = 0; i < 2; ++i) {
+    const int64_t nb = slices(ra[i], rb[i]);
+    if (!nb) continue;
+    J.r0[J.n] = ra[i];
+    J.r1[J.n] = rb[i];
+    J.sf[J.n] = ra[i] / kWave;
+    J.nb[J.n] = nb;
+    J.nbt += nb;
+    ++J.n;
+  }
+  if (!J.nbt) return;
+  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_gs<T, KK>), grid(J.nbt), dim3(kWave), 0, stm, A, J, g, done))
 }
 
 template <class T>
