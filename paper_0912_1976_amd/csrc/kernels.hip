@@ -112,33 +112,35 @@ __device__ __forceinline__ void sell_row(const Sell &A, int64_t s, int lane, con
 
 // ------------------------------------------------------------- fine matrix
 // (A x)_r in difference form (MODE 0), or g_r - (A x)_r (MODE 1)
+// (A x)_r in difference form (MODE 0), or g_r - (A x)_r (MODE 1); the row's
+// own operands are loaded before its entries
 template <class T, int K, int MODE>
-__device__ __forceinline__ Row<T, K> fine_apply(const Sell &A, int64_t r, const Row<T, K> &xr, const T (&acc)[K],
-                                                const T *__restrict__ g) {
+__device__ __forceinline__ Row<T, K> fine_row(const Sell &A, int64_t s, int lane, int64_t r, const T *__restrict__ x,
+                                              const Row<T, K> &xr, const T *__restrict__ g) {
+  Row<T, K> gr;
+  if (MODE == 1) gr = ld<T, K>(g, r);
+  T d0, d1 = T(0);
+  if constexpr (std::is_same<T, double>::value) {
+    d0 = A.d64[r];
+  } else {
+    d0 = A.s32[r];
+    d1 = A.dh32[r];
+  }
+  T acc[K], off;
+  sell_row<T, K, true>(A, s, lane, x, xr, acc, off);
   Row<T, K> out;
   if constexpr (std::is_same<T, double>::value) {
-    const double dr = A.d64[r];
 #pragma unroll
-    for (int k = 0; k < K; ++k) out.v[k] = acc[k] + dr * xr.v[k];
+    for (int k = 0; k < K; ++k) out.v[k] = acc[k] + d0 * xr.v[k];
   } else {
-    const float sr = A.s32[r], dh = A.dh32[r];
 #pragma unroll
-    for (int k = 0; k < K; ++k) out.v[k] = sr * (acc[k] + dh * xr.v[k]);
+    for (int k = 0; k < K; ++k) out.v[k] = d0 * (acc[k] + d1 * xr.v[k]);
   }
   if (MODE == 1) {
-    const Row<T, K> gr = ld<T, K>(g, r);
 #pragma unroll
     for (int k = 0; k < K; ++k) out.v[k] = gr.v[k] - out.v[k];
   }
   return out;
-}
-
-template <class T, int K, int MODE>
-__device__ __forceinline__ Row<T, K> fine_row(const Sell &A, int64_t s, int lane, int64_t r, const T *__restrict__ x,
-                                              const Row<T, K> &xr, const T *__restrict__ g) {
-  T acc[K], off;
-  sell_row<T, K, true>(A, s, lane, x, xr, acc, off);
-  return fine_apply<T, K, MODE>(A, r, xr, acc, g);
 }
 
 template <class T, int K, int MODE, bool DOT>
@@ -175,17 +177,18 @@ struct GsDev {
   int64_t nbt;
 };
 
-// one Gauss-Seidel step of row r: x_r + (g_r - (A x)_r) / a_rr
+// one Gauss-Seidel step of row r: x_r + (g_r - (A x)_r) / a_rr, with the
+// row's diagonal data d0, d1 loaded by the caller
 template <class T, int K>
-__device__ __forceinline__ Row<T, K> gs_apply(const Sell &A, int64_t r, const Row<T, K> &xr, const Row<T, K> &gr,
+__device__ __forceinline__ Row<T, K> gs_apply(T d0, T d1, const Row<T, K> &xr, const Row<T, K> &gr,
                                               const T (&acc)[K], T off) {
   Row<T, K> out;
   if constexpr (std::is_same<T, double>::value) {
-    const double dr = A.d64[r], diag = dr - off;
+    const double dr = d0, diag = dr - off;
 #pragma unroll
     for (int k = 0; k < K; ++k) out.v[k] = xr.v[k] + (gr.v[k] - (acc[k] + dr * xr.v[k])) / diag;
   } else {
-    const float inv_s = 1.0f / A.s32[r], dh = A.dh32[r], diag = dh - off;
+    const float inv_s = 1.0f / d0, dh = d1, diag = dh - off;
 #pragma unroll
     for (int k = 0; k < K; ++k) out.v[k] = xr.v[k] + (gr.v[k] * inv_s - (acc[k] + dh * xr.v[k])) / diag;
   }
@@ -213,9 +216,16 @@ __global__ __launch_bounds__(kWave) void k_gs(Sell A, GsDev<T> J, const T *__res
   if (r < r0 || r >= r1) return;
   const Row<T, K> xr = ld<T, K>(x, r);
   const Row<T, K> gr = ld<T, K>(g, r);
+  T d0, d1 = T(0);
+  if constexpr (std::is_same<T, double>::value) {
+    d0 = A.d64[r];
+  } else {
+    d0 = A.s32[r];
+    d1 = A.dh32[r];
+  }
   T acc[K], off;
   sell_row<T, K, true>(A, s, lane, x, xr, acc, off);
-  st<T, K>(x, r, gs_apply<T, K>(A, r, xr, gr, acc, off));
+  st<T, K>(x, r, gs_apply<T, K>(d0, d1, xr, gr, acc, off));
 }
 
 template <class T, int K, bool ACC>
@@ -303,34 +313,41 @@ __device__ __forceinline__ void group_row(const CsrG &A, int64_t r, int gl, cons
 // 4: one Gauss-Seidel step y_r = (g_r - sum_j a_rj x_j) / a_rr (y = x).
 template <class T, int K, int G, int MODE>
 __device__ __forceinline__ void csr_row_op(const CsrG &A, int64_t r, int gl, const T *x, const T *g, T *y) {
+  // the row's own operands are loaded first, so that their latency overlaps
+  // the row-pointer -> entries -> gathered values chain of group_row
+  Row<T, K> gr, xr, yr;
+  T dr = T(0);
+  if (MODE == 1 || MODE == 4) gr = ld<T, K>(g, r);
+  if (MODE <= 1) xr = ld<T, K>(x, r);
+  if (MODE == 3) yr = ld<T, K>(y, r);
+  if (MODE <= 1 || MODE == 4) {
+    if constexpr (std::is_same<T, double>::value)
+      dr = A.d64[r];
+    else
+      dr = A.s32[r];
+  }
   T acc[K];
   group_row<T, K, G>(A, r, gl, x, acc);  // off-diagonal part only
   if (gl != 0) return;
   Row<T, K> out;
   if (MODE == 4) {
-    const Row<T, K> gr = ld<T, K>(g, r);
     if constexpr (std::is_same<T, double>::value) {
-      const double dr = A.d64[r];
 #pragma unroll
       for (int k = 0; k < K; ++k) out.v[k] = (gr.v[k] - acc[k]) / dr;
     } else {
-      const float inv_s = 1.0f / A.s32[r];
+      const float inv_s = 1.0f / dr;
 #pragma unroll
       for (int k = 0; k < K; ++k) out.v[k] = gr.v[k] * inv_s - acc[k];
     }
   } else if (MODE <= 1) {
-    const Row<T, K> xr = ld<T, K>(x, r);
     if constexpr (std::is_same<T, double>::value) {
-      const double dr = A.d64[r];
 #pragma unroll
       for (int k = 0; k < K; ++k) out.v[k] = acc[k] + dr * xr.v[k];
     } else {
-      const float sr = A.s32[r];
 #pragma unroll
-      for (int k = 0; k < K; ++k) out.v[k] = sr * (acc[k] + xr.v[k]);
+      for (int k = 0; k < K; ++k) out.v[k] = dr * (acc[k] + xr.v[k]);
     }
     if (MODE == 1) {
-      const Row<T, K> gr = ld<T, K>(g, r);
 #pragma unroll
       for (int k = 0; k < K; ++k) out.v[k] = gr.v[k] - out.v[k];
     }
@@ -338,7 +355,7 @@ __device__ __forceinline__ void csr_row_op(const CsrG &A, int64_t r, int gl, con
 #pragma unroll
     for (int k = 0; k < K; ++k) out.v[k] = acc[k];
   } else {
-    out = ld<T, K>(y, r);
+    out = yr;
 #pragma unroll
     for (int k = 0; k < K; ++k) out.v[k] += acc[k];
   }
