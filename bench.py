@@ -318,6 +318,67 @@ def serving(nreq, seed, rtol, dev):
     return out
 
 
+def config_runs(dev, rtol):
+    """The two other single-GPU configurations at full size.
+    * 257 x 257 x 33 thin box, eps 1e-4 (2.18M unknowns), eight seeded smooth
+      right-hand sides per solve: FP32 preconditioner in FP64 CG against FP64,
+      solves/s and the error of every column against the FP64 solution.
+    * Centre-refined multiscale thin box (h_min 1/900, 16-64 layers, eps 1e-3,
+      about 3.5M unknowns), b = A x* for the manufactured x*: VL + additive
+      smoother against VL + SOR (the paper's Mesh B comparison), iterations,
+      time to tolerance and the relative max-norm error against x*."""
+    import numpy as np
+    import torch
+
+    import paper_0912_1976_amd as vemg
+    from inputs import box_mesh, fourier_field, graded_mesh, manufactured_u
+
+    out = {}
+    t0 = time.perf_counter()
+    m = box_mesh(257, 257, 33, 1e-4, jitter=0.3, seed=4, bathymetry=True)
+    s = vemg.Solver(m.xyz, m.tets, m.top, top_bc="pinned", pc="vl_as", device=0)
+    B = torch.as_tensor(np.stack([s.rhs(fourier_field(m.xyz, 1e-4, 200 + k)) for k in range(8)]), device=dev)
+    rec = {"workload": "thinbox-257x257x33-eps1e-4", "n_dof": s.info()["n"], "rhs_per_solve": 8,
+           "setup_s": time.perf_counter() - t0}
+    x64 = None
+    for prec in ("fp64", "mixed_pc"):
+        s.set_precision(prec)
+        x, t, it, rel, st = timed_solves(s, B, 2, 1, rtol)
+        r = {"ms_per_batch": 1e3 * float(np.median(t)), "solves_per_s": 8 / float(np.median(t)),
+             "iterations": it[0], "max_relres": max(rel[0]), "status": st[0]}
+        if x64 is None:
+            x64 = x
+        else:
+            r["max_rel_err_vs_fp64"] = max(float(torch.linalg.norm(x[k] - x64[k]) / torch.linalg.norm(x64[k]))
+                                           for k in range(8))
+        rec[prec] = r
+        log(f"config 4 {prec}: {r['solves_per_s']:.1f} solves/s, iterations {max(r['iterations'])}")
+    s.close()
+    out["thinbox_257_eps1e-4_batch8"] = rec
+
+    t0 = time.perf_counter()
+    m = graded_mesh(1 / 900, 1e-3, jitter=0.25, seed=3)
+    s = vemg.Solver(m.xyz, m.tets, m.top, top_bc="pinned", pc="vl_as", device=0)
+    info = s.info()
+    rec = {"workload": "graded-hmin1/900-eps1e-3", "n_dof": info["n"], "setup_s": time.perf_counter() - t0}
+    xs = manufactured_u(m.xyz, 1e-3)
+    b = s.matvec(xs)
+    free = np.zeros(m.n, bool)
+    free[s.export("perm", np.int64)] = True
+    for pc in ("vl_as", "vl_sor"):
+        s.set_preconditioner(pc)
+        x, t, it, rel, st = timed_solves(s, b, 2, 1, rtol)
+        xh = x.cpu().numpy()
+        err = float(np.max(np.abs(xh[free] - xs[free])) / np.max(np.abs(xs[free])))
+        rec[pc] = {"time_to_tol_ms": 1e3 * float(np.median(t)), "iterations": it[0][0], "relres": rel[0][0],
+                   "status": st[0], "dof_iters_per_s": info["n"] * it[0][0] / float(np.median(t)),
+                   "max_rel_err_vs_manufactured": err}
+        log(f"config 3 {pc}: {rec[pc]['iterations']} iterations, {rec[pc]['time_to_tol_ms']:.1f} ms")
+    s.close()
+    out["graded_multiscale"] = rec
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,6 +391,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline solve and roofline only")
     ap.add_argument("--serve-requests", type=int, default=96)
+    ap.add_argument("--no-configs", action="store_true", help="skip the full-size 257^2 and graded configurations")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="run only the hot kernels and a copy calibration (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-summary", nargs="+", metavar="DIR_OR_CSV",
@@ -420,6 +482,8 @@ def main():
             sm.close()
         log("serving stream")
         extras["serving"] = serving(args.serve_requests, 11, args.rtol, dev)
+        if not args.no_configs:
+            extras["configs"] = config_runs(dev, args.rtol)
 
     cpu = None
     if not args.no_cpu_baseline:

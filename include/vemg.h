@@ -199,6 +199,17 @@ vemg_status vemg_time_op(vemg_solver s, int op, int nrhs, int reps, double *avg_
 
 vemg_status vemg_get_info(vemg_solver s, vemg_info *info);
 
+/* Switches the preconditioner (vemg_pc) of a set-up handle; the setup (E~,
+ * both hierarchies, packed operators) serves every preconditioner, so only
+ * the captured iteration graphs are dropped.  Waits for the handle's pending
+ * work.  VEMG_ERR_INVALID_ARG for an unknown value. */
+vemg_status vemg_set_preconditioner(vemg_solver s, int pc);
+
+/* Switches the precision (vemg_precision) of later solves; the FP32 operator
+ * copies are built at setup, so nothing is rebuilt.  VEMG_ERR_INVALID_ARG
+ * for an unknown value. */
+vemg_status vemg_set_precision(vemg_solver s, int precision);
+
 /* Copies a setup array to host memory for inspection (bit-exact tests).
  * name: "perm" (int64 [n], storage -> natural), "colour" (int32 [n]),
  * "Aoff.ptr" (int64), "Aoff.idx" (int32), "Aoff.val", "d", "diag" (double),

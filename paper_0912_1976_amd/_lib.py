@@ -76,6 +76,8 @@ def load_library():
     lib.vemg_solve.argtypes = [P, I32, P, P, D, I32, P, P]
     lib.vemg_apply.argtypes = [P, I32, P, P]
     lib.vemg_get_info.argtypes = [P, C.POINTER(Info)]
+    lib.vemg_set_preconditioner.argtypes = [P, I32]
+    lib.vemg_set_precision.argtypes = [P, I32]
     lib.vemg_time_op.argtypes = [P, I32, I32, I32, C.POINTER(C.c_double), C.POINTER(C.c_int)]
     lib.vemg_export.argtypes = [P, C.c_char_p, P, C.POINTER(C.c_size_t)]
     lib.vemg_destroy.argtypes = [P]
@@ -170,6 +172,15 @@ class Solver:
             pass
 
     # ---------------------------------------------------------------- info
+    def set_preconditioner(self, pc):
+        """Switch the preconditioner ('vl_as', 'vl_sor', 'vl_add', 'jacobi',
+        'none') without repeating the setup."""
+        self._check(self._lib.vemg_set_preconditioner(self._h, _PC[pc]), self._h)
+
+    def set_precision(self, precision):
+        """Switch between 'fp64', 'mixed_ir' and 'mixed_pc' for later solves."""
+        self._check(self._lib.vemg_set_precision(self._h, _PREC[precision]), self._h)
+
     def info(self):
         inf = Info()
         self._check(self._lib.vemg_get_info(self._h, C.byref(inf)), self._h)

@@ -1589,6 +1589,25 @@ vemg_status vemg_time_op(vemg_solver s, int op, int nrhs, int reps, double *avg_
   return (vemg_status)guarded(s, [&]() -> int { return vemg::do_time(s, op, nrhs, reps, avg_ms, launches); });
 }
 
+vemg_status vemg_set_preconditioner(vemg_solver s, int pc) {
+  if (!s || pc < 0 || pc > 4) return VEMG_ERR_INVALID_ARG;
+  return (vemg_status)guarded(s, [&]() -> int {
+    if (s->device >= 0) {
+      if (s->work) HIPCHK(hipStreamSynchronize(s->work));
+      if (s->work2) HIPCHK(hipStreamSynchronize(s->work2));
+    }
+    vemg::destroy_graphs(s);
+    s->opt.pc = pc;
+    return VEMG_OK;
+  });
+}
+
+vemg_status vemg_set_precision(vemg_solver s, int precision) {
+  if (!s || precision < 0 || precision > 2) return VEMG_ERR_INVALID_ARG;
+  s->opt.precision = precision;
+  return VEMG_OK;
+}
+
 vemg_status vemg_get_info(vemg_solver s, vemg_info *info) {
   if (!s || !info) return VEMG_ERR_INVALID_ARG;
   if (!s->ready) return VEMG_ERR_STATE;

@@ -206,6 +206,27 @@ def test_graph_replay_equals_eager():
         assert torch.equal(xa, xb)
 
 
+def test_switching_preconditioner_and_precision_equals_fresh_handles():
+    # one setup serves every preconditioner and precision: a switched handle
+    # reproduces a freshly built one bit for bit
+    m, s, o = _build(RAGGED, "N")
+    b = s.rhs(fourier_field(m.xyz, RAGGED["H"], 21))
+    for pc in ("vl_sor", "vl_add", "vl_as"):
+        s.set_preconditioner(pc)
+        x1, it1, _, _ = s.solve(b, rtol=1e-9)
+        f = lib.Solver(m.xyz, m.tets, m.top, pc=pc, device=0, coarse_max=64)
+        x2, it2, _, _ = f.solve(b, rtol=1e-9)
+        assert it1 == it2 and torch.equal(x1, x2), pc
+        f.close()
+    s.set_precision("mixed_pc")
+    x1, it1, _, _ = s.solve(b, rtol=1e-9)
+    f = lib.Solver(m.xyz, m.tets, m.top, device=0, coarse_max=64, precision="mixed_pc")
+    x2, it2, _, _ = f.solve(b, rtol=1e-9)
+    assert it1 == it2 and torch.equal(x1, x2)
+    with pytest.raises(lib.VemgError):
+        s._check(s._lib.vemg_set_preconditioner(s._h, 9), s._h)
+
+
 @pytest.mark.parametrize("precision", ["mixed_ir", "mixed_pc"])
 @pytest.mark.parametrize("mode", ["N", "D"])
 def test_mixed_precision_matches_fp64_oracle(precision, mode):
