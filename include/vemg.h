@@ -8,10 +8,18 @@
  * conditions on the floor and the vertical coasts, and on the top surface
  * either
  *   VEMG_TOP_PINNED     Neumann plus the point condition phi(x_0) = 0 with
- *                       x_0 a top node (eq. point condition), or
- *   VEMG_TOP_DIRICHLET  phi = 0 on the whole top surface (eq. dirichlet).
- * The library assembles the P1 stiffness matrix A (eq. Ax=b) restricted to
- * the free nodes and solves A phi = b by preconditioned conjugate gradients.
+ *                       x_0 a top node (eq. point condition),
+ *   VEMG_TOP_DIRICHLET  phi = 0 on the whole top surface (eq. dirichlet), or
+ *   VEMG_TOP_ROBIN      the free-surface condition of Section 2 under
+ *                       backward Euler, d phi/dn + alpha phi = 0 with
+ *                       alpha = (n.k)/(g dt^2) > 0 (vemg_options.robin_alpha);
+ *                       its weak form adds alpha times the P1 mass matrix of
+ *                       the top triangles projected onto (x, y), and no node
+ *                       is fixed.  Small alpha approaches the pinned
+ *                       Neumann problem, large alpha the Dirichlet top.
+ * The library assembles the P1 stiffness matrix A (eq. Ax=b), plus the
+ * Robin term, restricted to the free nodes and solves A phi = b by
+ * preconditioned conjugate gradients.
  *
  * Preconditioners (Section 6):
  *   VEMG_PC_VL_SOR       vertical lumping as the first coarsening of a
@@ -65,7 +73,7 @@ typedef enum {
   VEMG_ERR_STATE = -7         /* call out of order (e.g. solve before setup) */
 } vemg_status;
 
-typedef enum { VEMG_TOP_PINNED = 0, VEMG_TOP_DIRICHLET = 1 } vemg_top_bc;
+typedef enum { VEMG_TOP_PINNED = 0, VEMG_TOP_DIRICHLET = 1, VEMG_TOP_ROBIN = 2 } vemg_top_bc;
 
 typedef enum {
   VEMG_PC_VL_ADDITIVE = 0,
@@ -99,6 +107,7 @@ typedef struct {
   int precision;       /* vemg_precision, VEMG_FP64 */
   double inner_rtol;   /* VEMG_MIXED_IR: relative tolerance of each inner FP32 solve, 1e-4 */
   int max_outer;       /* VEMG_MIXED_IR: refinement steps, 30 */
+  double robin_alpha;  /* VEMG_TOP_ROBIN: alpha > 0 (ignored otherwise), 0 */
 } vemg_options;
 
 typedef struct {

@@ -171,6 +171,56 @@ def assemble_mass(xyz, tets):
     return M
 
 
+def top_surface_mass(xyz, tri):
+    """Robin term of the free-surface condition (Section 2).  Backward Euler
+    applied to the kinematic condition turns the top condition into
+    d phi/dn + alpha phi = 0 with alpha = (n.k)/(g dt^2) >= 0 (the printed
+    form has its sign garbled; this is the reading that gives an SPD
+    problem).  Its weak form adds alpha int_top (n.k) phi psi dS, and
+    (n.k) dS is the horizontally projected area element, so the term is the
+    P1 mass matrix of the top triangles projected onto (x, y).
+
+    tri: top triangles (sorted vertex triples in ascending order).  Returns
+    (Moff, L): Moff the off-diagonal part on the triangles' edges, each value
+    a left-to-right sum of area/12 over the triangles holding the edge in
+    ascending order (symmetric CSR, sorted indices, no diagonal, shape n x n
+    with n = number of nodes); L_i the left-to-right sum of area/3 over the
+    triangles holding node i (the row sums of the mass matrix)."""
+    n = xyz.shape[0]
+    tri = np.asarray(tri, dtype=np.int64)
+    x1, y1 = xyz[tri[:, 0], 0], xyz[tri[:, 0], 1]
+    x2, y2 = xyz[tri[:, 1], 0], xyz[tri[:, 1], 1]
+    x3, y3 = xyz[tri[:, 2], 0], xyz[tri[:, 2], 1]
+    area = 0.5 * np.abs((x2 - x1) * (y3 - y1) - (x3 - x1) * (y2 - y1))
+    pairs = ((0, 1), (0, 2), (1, 2))
+    lo = np.stack([np.minimum(tri[:, a], tri[:, b]) for a, b in pairs], axis=1)
+    hi = np.stack([np.maximum(tri[:, a], tri[:, b]) for a, b in pairs], axis=1)
+    key = (lo * n + hi).ravel()
+    ukey, inv = np.unique(key, return_inverse=True)
+    w = _sequential_sum_by_key(inv, np.repeat(area / 12.0, 3), ukey.size)
+    ei, ej = ukey // n, ukey % n
+    Moff = sp.csr_matrix((np.concatenate([w, w]), (np.concatenate([ei, ej]), np.concatenate([ej, ei]))),
+                         shape=(n, n))
+    Moff.sort_indices()
+    L = _sequential_sum_by_key(tri.ravel(), np.repeat(area / 3.0, 3), n)
+    return Moff, L
+
+
+def add_robin(Aoff, Moff, L, alpha):
+    """A + alpha M_top in difference form: off-diagonals a_ij + alpha m_ij on
+    the pattern of Aoff (which contains every top edge), and the deficit
+    alpha L_i that the Robin term adds (M_top applied to a constant)."""
+    Aoff = Aoff.tocsr()
+    M = Moff.tocsr()
+    rows = np.repeat(np.arange(Aoff.shape[0]), np.diff(Aoff.indptr))
+    m_on = np.asarray(M[rows, Aoff.indices]).ravel()
+    if abs(M.sum() - m_on.sum()) > 1e-12 * abs(M.sum()):
+        raise ValueError("a top edge is not a mesh edge")
+    out = Aoff.copy()
+    out.data = Aoff.data + alpha * m_on
+    return out, alpha * L
+
+
 def pin_node(xyz, top):
     """Point condition phi(x_0) = 0 with x_0 on the top surface (eq. point
     condition).  Reading: the top node closest to the origin corner, ties to
@@ -186,6 +236,8 @@ def dirichlet_set(xyz, top, mode, pin=-1):
     mode 'N': the Neumann problem with the point condition (Section 3,
     eq. point condition) -- only x_0 is fixed.
     mode 'D': Dirichlet condition on the whole top surface (eq. dirichlet).
+    mode 'R': the Robin condition of the free surface (see top_surface_mass)
+    -- nothing is fixed.
     """
     n = xyz.shape[0]
     D = np.zeros(n, dtype=bool)
@@ -193,7 +245,7 @@ def dirichlet_set(xyz, top, mode, pin=-1):
         D[pin if pin >= 0 else pin_node(xyz, top)] = True
     elif mode == "D":
         D[top] = True
-    else:
+    elif mode != "R":
         raise ValueError(mode)
     return D
 

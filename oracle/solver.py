@@ -45,17 +45,26 @@ class OracleSetup:
         return self.perm.size
 
 
-def setup(mesh, mode="N", coarse_max=2048, max_levels=10):
-    """Assembly (Section 3), E~ (Section 5.4) and both SA hierarchies (Section 6)."""
+def setup(mesh, mode="N", coarse_max=2048, max_levels=10, alpha=0.0):
+    """Assembly (Section 3), E~ (Section 5.4) and both SA hierarchies (Section 6).
+    mode 'N' (point condition), 'D' (Dirichlet top) or 'R' (Robin top with
+    coefficient alpha > 0, the free-surface condition of Section 2)."""
     xyz, tets, top = mesh.xyz, mesh.tets, mesh.top
     n_nodes = xyz.shape[0]
     _, Aoff_full = fem.assemble_stiffness(xyz, tets)
+    d_robin = np.zeros(n_nodes)
+    if mode == "R":
+        if not alpha > 0.0:
+            raise ValueError("the Robin coefficient must be positive")
+        Moff, L = fem.top_surface_mass(xyz, extrap.top_triangles(tets, top))
+        Aoff_full, d_robin = fem.add_robin(Aoff_full, Moff, L, alpha)
     pin = fem.pin_node(xyz, top) if mode == "N" else -1
     D = fem.dirichlet_set(xyz, top, mode, pin)
     free = ~D
     # locality order and colouring of A_UU (indices in natural numbering)
     loc = ordering.locality_order(xyz, top, free)
     U, Auu_nat, d_nat = fem.reduce_to_unknowns(Aoff_full, D)
+    d_nat = d_nat + d_robin[U]
     pos_in_U = np.full(n_nodes, -1, dtype=np.int64)
     pos_in_U[U] = np.arange(U.size)
     loc_u = pos_in_U[loc]

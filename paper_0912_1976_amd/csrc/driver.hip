@@ -1481,6 +1481,7 @@ void vemg_default_options(vemg_options *o) {
   o->precision = VEMG_FP64;
   o->inner_rtol = 1e-4;
   o->max_outer = 30;
+  o->robin_alpha = 0.0;
 }
 
 vemg_status vemg_create(const vemg_options *o, int device, void *hip_stream, vemg_solver *out) {
@@ -1491,7 +1492,9 @@ vemg_status vemg_create(const vemg_options *o, int device, void *hip_stream, vem
     opt = *o;
   else
     vemg_default_options(&opt);
-  if (opt.top_bc < 0 || opt.top_bc > 1 || opt.pc < 0 || opt.pc > 4 || opt.max_levels < 1 || opt.max_levels > 16 ||
+  if (opt.top_bc < 0 || opt.top_bc > 2 ||
+      (opt.top_bc == VEMG_TOP_ROBIN && !(opt.robin_alpha > 0.0 && std::isfinite(opt.robin_alpha))) ||
+      opt.pc < 0 || opt.pc > 4 || opt.max_levels < 1 || opt.max_levels > 16 ||
       opt.coarse_max < 1 || opt.coarse_max > 8192 || !(opt.theta >= 0.0) || opt.poll_every < 1 ||
       opt.precision < 0 || opt.precision > 2 || !(opt.inner_rtol > 0.0 && opt.inner_rtol < 1.0) || opt.max_outer < 1)
     return VEMG_ERR_INVALID_ARG;
@@ -1529,7 +1532,9 @@ vemg_status vemg_setup(vemg_solver s, int64_t n_nodes, const double *xyz, int64_
     vemg::destroy_graphs(s);
     s->ar.release();
     vemg::SetupOptions so;
-    so.top_dirichlet = s->opt.top_bc;
+    so.top_dirichlet = s->opt.top_bc == VEMG_TOP_DIRICHLET;
+    so.robin = s->opt.top_bc == VEMG_TOP_ROBIN;
+    so.robin_alpha = s->opt.robin_alpha;
     so.pin_node = s->opt.pin_node;
     so.theta = s->opt.theta;
     so.prolong_omega = s->opt.prolong_omega;

@@ -517,6 +517,61 @@ struct Locator {
 }  // namespace
 
 // ---------------------------------------------------------------- driver
+// Top-surface triangles: tetrahedron faces with three top nodes, each as its
+// sorted vertex triple, in ascending lexicographic order without repeats.
+std::vector<std::array<int64_t, 3>> top_triangles(int64_t n_tets, const int64_t *tets, const std::vector<uint8_t> &top) {
+  std::vector<std::array<int64_t, 3>> tri;
+  static const int faces[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
+  for (int64_t e = 0; e < n_tets; ++e)
+    for (auto &f : faces) {
+      std::array<int64_t, 3> t = {tets[4 * e + f[0]], tets[4 * e + f[1]], tets[4 * e + f[2]]};
+      if (top[t[0]] && top[t[1]] && top[t[2]]) {
+        std::sort(t.begin(), t.end());
+        tri.push_back(t);
+      }
+    }
+  std::sort(tri.begin(), tri.end());
+  tri.erase(std::unique(tri.begin(), tri.end()), tri.end());
+  return tri;
+}
+
+// Robin term of the free-surface condition: alpha times the P1 mass matrix
+// of the top triangles projected onto (x, y).  Its off-diagonal values
+// (left-to-right sums of area/12 over the triangles holding an edge, in
+// ascending triangle order) are scaled by alpha and added to the entries of
+// A (every top edge is a mesh edge); L_i (the sum of area/3 over the
+// triangles holding node i) times alpha is the deficit the term adds.
+void add_robin(Csr &A, const double *xyz, const std::vector<std::array<int64_t, 3>> &tri, double alpha,
+               std::vector<double> &dR) {
+  const int64_t n = A.nrows;
+  std::vector<double> m(A.idx.size(), 0.0), L(n, 0.0);
+  auto find = [&](int64_t i, int64_t j) {
+    auto b = A.idx.begin() + A.ptr[i], e = A.idx.begin() + A.ptr[i + 1];
+    auto it = std::lower_bound(b, e, (int32_t)j);
+    if (it == e || *it != (int32_t)j) fail(-2, "a top-surface edge is not an edge of the mesh");
+    return (int64_t)(it - A.idx.begin());
+  };
+  static const int pairs[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+  for (auto &t : tri) {
+    const double x1 = xyz[3 * t[0]], y1 = xyz[3 * t[0] + 1];
+    const double x2 = xyz[3 * t[1]], y2 = xyz[3 * t[1] + 1];
+    const double x3 = xyz[3 * t[2]], y3 = xyz[3 * t[2] + 1];
+    const double area = 0.5 * std::fabs((x2 - x1) * (y3 - y1) - (x3 - x1) * (y2 - y1));
+    for (auto &p : pairs) {
+      const int64_t i = std::min(t[p[0]], t[p[1]]), j = std::max(t[p[0]], t[p[1]]);
+      m[find(i, j)] += area / 12.0;
+    }
+    for (int a = 0; a < 3; ++a) L[t[a]] += area / 3.0;
+  }
+  // mirror the upper triangle (i < j) to the lower one, then add alpha m
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+      if (A.idx[k] < i) m[k] = m[find(A.idx[k], i)];
+  for (size_t k = 0; k < m.size(); ++k) A.val[k] = A.val[k] + alpha * m[k];
+  dR.assign(n, 0.0);
+  for (int64_t i = 0; i < n; ++i) dR[i] = alpha * L[i];
+}
+
 void build_problem(Problem &P, const SetupOptions &opt, int64_t n_nodes, const double *xyz,
                    int64_t n_tets, const int64_t *tets, const uint8_t *top) {
   if (n_nodes < 4 || n_tets < 1 || !xyz || !tets || !top) fail(-1, "empty mesh or null pointer");
@@ -538,9 +593,11 @@ void build_problem(Problem &P, const SetupOptions &opt, int64_t n_nodes, const d
   }
   if (m_top < 3) fail(-2, "the top surface needs at least 3 nodes");
 
-  // Dirichlet set
+  // Dirichlet set (empty for the Robin top)
   std::vector<uint8_t> fixed(n_nodes, 0);
-  if (opt.top_dirichlet) {
+  if (opt.robin) {
+    if (!(opt.robin_alpha > 0.0)) fail(-1, "the Robin coefficient must be positive");
+  } else if (opt.top_dirichlet) {
     for (int64_t i = 0; i < n_nodes; ++i) fixed[i] = P.top[i];
   } else {
     int64_t pin = opt.pin_node;
@@ -563,6 +620,8 @@ void build_problem(Problem &P, const SetupOptions &opt, int64_t n_nodes, const d
 
   // assembly (natural numbering)
   Csr Afull = assemble_offdiag(n_nodes, xyz, n_tets, tets);
+  std::vector<double> dR;
+  if (opt.robin) add_robin(Afull, xyz, top_triangles(n_tets, tets, P.top), opt.robin_alpha, dR);
 
   // free nodes U (ascending natural index), A_UU and the deficit
   std::vector<int64_t> U;
@@ -590,6 +649,7 @@ void build_problem(Problem &P, const SetupOptions &opt, int64_t n_nodes, const d
       }
     }
     dnat[u] = -s + 0.0;
+    if (opt.robin) dnat[u] = dnat[u] + dR[i];
     Auu.ptr[u + 1] = (int64_t)Auu.idx.size();
   }
   Afull = Csr();
@@ -680,19 +740,7 @@ void build_problem(Problem &P, const SetupOptions &opt, int64_t n_nodes, const d
   // vertical extrapolation E~ and the surface hierarchy
   int64_t m = P.n_top;
   if (m > 0) {
-    std::vector<std::array<int64_t, 3>> tri;
-    for (int64_t e = 0; e < n_tets; ++e) {
-      static const int faces[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
-      for (auto &f : faces) {
-        std::array<int64_t, 3> t = {tets[4 * e + f[0]], tets[4 * e + f[1]], tets[4 * e + f[2]]};
-        if (P.top[t[0]] && P.top[t[1]] && P.top[t[2]]) {
-          std::sort(t.begin(), t.end());
-          tri.push_back(t);
-        }
-      }
-    }
-    std::sort(tri.begin(), tri.end());
-    tri.erase(std::unique(tri.begin(), tri.end()), tri.end());
+    std::vector<std::array<int64_t, 3>> tri = top_triangles(n_tets, tets, P.top);
     if (tri.empty()) fail(-2, "no top-surface triangles (faces with three top nodes)");
     Locator loc2(xyz, tri, xmin, ymin, xmax, ymax);
     Csr E0;
@@ -796,7 +844,7 @@ void mass_rhs(const Problem &P, const double *f, double *b) {
       w[t[a]] += vol / 20.0 * 5.0;
     }
   }
-  if (!P.opt.top_dirichlet) {
+  if (!P.opt.top_dirichlet && !P.opt.robin) {  // the pure Neumann problem needs int f = 0
     double sb = 0.0, sw = 0.0;
     for (int64_t i = 0; i < N; ++i) {
       sb += bf[i];

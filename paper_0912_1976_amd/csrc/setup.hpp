@@ -33,6 +33,8 @@ struct Level {
 
 struct SetupOptions {
   int top_dirichlet = 0;     // 0: point condition at pin_node, 1: Dirichlet on the whole top
+  int robin = 0;             // 1: Robin top d phi/dn + robin_alpha phi = 0, nothing fixed
+  double robin_alpha = 0.0;
   int64_t pin_node = -1;     // -1: top node closest to the origin corner
   double theta = 0.01;
   double prolong_omega = 2.0 / 3.0;

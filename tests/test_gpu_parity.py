@@ -31,6 +31,9 @@ CFG1 = dict(nx=17, ny=17, nz=9, H=0.01, jitter=0.2, seed=1, bathymetry=False)
 RAGGED = dict(nx=23, ny=13, nz=6, H=1e-3, jitter=0.3, seed=7, bathymetry=True)
 
 
+ROBIN_ALPHA = 20.0
+
+
 def _build(cfg, mode, pc="vl_as", **kw):
     # small coarsest level so that these meshes exercise several levels
     kw.setdefault("coarse_max", 64)
@@ -38,12 +41,13 @@ def _build(cfg, mode, pc="vl_as", **kw):
     c = dict(cfg)
     m = box_mesh(c.pop("nx"), c.pop("ny"), c.pop("nz"), c.pop("H"), **c)
     _print("case", cfg, mode, pc)
-    s = lib.Solver(m.xyz, m.tets, m.top, top_bc=mode, pc=pc, device=0, **kw)
-    o = osolver.setup(m, mode, coarse_max=kw["coarse_max"])
+    alpha = ROBIN_ALPHA if mode == "R" else 0.0
+    s = lib.Solver(m.xyz, m.tets, m.top, top_bc=mode, pc=pc, device=0, robin_alpha=alpha, **kw)
+    o = osolver.setup(m, mode, coarse_max=kw["coarse_max"], alpha=alpha)
     return m, s, o
 
 
-@pytest.fixture(scope="module", params=[("cfg1", "N"), ("cfg1", "D"), ("ragged", "N")])
+@pytest.fixture(scope="module", params=[("cfg1", "N"), ("cfg1", "D"), ("ragged", "N"), ("ragged", "R")])
 def built(request):
     name, mode = request.param
     return _build(CFG1 if name == "cfg1" else RAGGED, mode)
@@ -113,6 +117,19 @@ def test_other_preconditioners_match_oracle(pc, mode):
     e = _rel(z, precond.make(o, pc)(r))
     _print("precond", pc, mode, "rel", e, "tol", tol)
     assert e < tol
+
+
+@pytest.mark.parametrize("pc", ["vl_as", "vl_sor"])
+def test_robin_solution_matches_oracle(pc):
+    # the free-surface (Robin) top: nothing fixed, A + alpha M_top
+    m, s, o = _build(RAGGED, "R", pc)
+    b_nat = s.rhs(fourier_field(m.xyz, RAGGED["H"], 33))
+    xo, it_o, rel_o, ok = osolver.solve(o, b_nat[o.perm], 1e-11, pc, max_iter=5000)
+    x, its, rels, st = s.solve(b_nat, rtol=1e-11, max_iter=5000)
+    _print("robin iters gpu", its, "oracle", it_o, "relres", rels, rel_o)
+    assert ok and st == 0 and rels[0] <= 1e-11
+    assert _rel(x.cpu().numpy()[o.perm], xo) < 1e-8
+    assert abs(its[0] - it_o) <= max(3, 0.1 * it_o)
 
 
 @pytest.mark.parametrize("pc", ["vl_as", "vl_sor", "vl_add", "jacobi"])

@@ -19,14 +19,17 @@ CASES = [
     ("D", dict(nx=9, ny=8, nz=5, H=0.01, jitter=0.3, seed=11, bathymetry=True)),
     ("N", dict(nx=17, ny=17, nz=9, H=0.01, jitter=0.2, seed=1, bathymetry=False)),
     ("N", dict(nx=21, ny=19, nz=7, H=1e-4, jitter=0.3, seed=5, bathymetry=True)),
+    ("R", dict(nx=9, ny=8, nz=5, H=0.01, jitter=0.3, seed=11, bathymetry=True)),
 ]
+ROBIN_ALPHA = 7.5
 
 
 def _mk(mode, kw):
     kw = dict(kw)
     m = box_mesh(kw.pop("nx"), kw.pop("ny"), kw.pop("nz"), kw.pop("H"), **kw)
-    s = lib.Solver(m.xyz, m.tets, m.top, top_bc=mode, device=-1, coarse_max=40)
-    o = osolver.setup(m, mode, coarse_max=40)
+    alpha = ROBIN_ALPHA if mode == "R" else 0.0
+    s = lib.Solver(m.xyz, m.tets, m.top, top_bc=mode, device=-1, coarse_max=40, robin_alpha=alpha)
+    o = osolver.setup(m, mode, coarse_max=40, alpha=alpha)
     return m, s, o
 
 
