@@ -379,6 +379,58 @@ def config_runs(dev, rtol):
     return out
 
 
+def sa_baseline_runs(dev, rtol):
+    """The paper's comparison (Section 6, Figs. iso_no_vl_eps and iso_vl_eps)
+    at the headline size: plain smoothed aggregation PCG against the
+    VL + additive smoother preconditioner on the 129 x 129 x 33 box at aspect
+    ratios 1e-2, 1e-3 and 1e-4 (same seeds and field as the headline)."""
+    import numpy as np
+    import torch
+
+    import paper_0912_1976_amd as vemg
+    from inputs import box_mesh, fourier_field
+
+    out = {}
+    for H in (1e-2, 1e-3, 1e-4):
+        m = box_mesh(129, 129, 33, H, jitter=0.3, seed=2, bathymetry=True)
+        s = vemg.Solver(m.xyz, m.tets, m.top, top_bc="pinned", pc="sa", device=0)
+        b = torch.as_tensor(s.rhs(fourier_field(m.xyz, H, 100)), device=dev)
+        rec = {}
+        for pc in ("sa", "vl_as"):
+            s.set_preconditioner(pc)
+            x, t, it, rel, st = timed_solves(s, b, 2, 1, rtol)
+            rec[pc] = {"iterations": it[0][0], "time_to_tol_ms": 1e3 * float(np.median(t)), "relres": rel[0][0],
+                       "status": st[0]}
+        out[f"eps={H:g}"] = rec
+        log(f"eps {H:g}: SA {rec['sa']['iterations']} iterations ({rec['sa']['time_to_tol_ms']:.0f} ms), "
+            f"VL+AS {rec['vl_as']['iterations']} ({rec['vl_as']['time_to_tol_ms']:.0f} ms)")
+        s.close()
+    return out
+
+
+def robin_runs(mesh, wl, dev, rtol):
+    """The headline mesh with the free-surface (Robin) top instead of the point
+    condition: alpha H = H / (g dt^2) of 3e-5 (a 4 km ocean and a one-hour
+    step: close to the Neumann limit) and 3e-2 (a step of a few minutes)."""
+    import numpy as np
+    import torch
+
+    import paper_0912_1976_amd as vemg
+    from inputs import fourier_field
+
+    out = {}
+    for aH in (3e-5, 3e-2):
+        alpha = aH / wl["H"]
+        s = vemg.Solver(mesh.xyz, mesh.tets, mesh.top, top_bc="robin", robin_alpha=alpha, pc="vl_as", device=0)
+        b = torch.as_tensor(s.rhs(fourier_field(mesh.xyz, wl["H"], wl["rhs_seed"])), device=dev)
+        x, t, it, rel, st = timed_solves(s, b, 3, 1, rtol)
+        out[f"alphaH={aH:g}"] = {"alpha": alpha, "iterations": it[0][0], "time_to_tol_ms": 1e3 * float(np.median(t)),
+                                 "relres": rel[0][0], "status": st[0]}
+        log(f"robin alpha H = {aH:g}: {it[0][0]} iterations, {1e3 * float(np.median(t)):.1f} ms")
+        s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -482,6 +534,8 @@ def main():
             sm.close()
         log("serving stream")
         extras["serving"] = serving(args.serve_requests, 11, args.rtol, dev)
+        extras["robin_top"] = robin_runs(mesh, wl, dev, args.rtol)
+        extras["sa_baseline"] = sa_baseline_runs(dev, args.rtol)
         if not args.no_configs:
             extras["configs"] = config_runs(dev, args.rtol)
 

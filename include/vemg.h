@@ -35,6 +35,11 @@
  *                        the experiments of Section 6).
  *   VEMG_PC_VL_ADDITIVE_ONLY  eq. ourpreconditioner on its own:
  *                        E~ Vcyc_S(E~^T r) + Z Vcyc_Abar(Z^T r), no SOR.
+ *   VEMG_PC_SA           the paper's baseline (Section 6, first
+ *                        preconditioner): one smoothed aggregation V-cycle
+ *                        on the whole A, forward SOR before and backward SOR
+ *                        after each coarse correction; its hierarchy is built
+ *                        only when the handle is set up with this value.
  *   VEMG_PC_JACOBI, VEMG_PC_NONE  baselines.
  *
  * Conventions
@@ -80,7 +85,8 @@ typedef enum {
   VEMG_PC_VL_SOR = 1,
   VEMG_PC_JACOBI = 2,
   VEMG_PC_NONE = 3,
-  VEMG_PC_VL_ADDITIVE_ONLY = 4
+  VEMG_PC_VL_ADDITIVE_ONLY = 4,
+  VEMG_PC_SA = 5
 } vemg_pc;
 
 /* Precision of the solve.
@@ -211,7 +217,8 @@ vemg_status vemg_get_info(vemg_solver s, vemg_info *info);
 /* Switches the preconditioner (vemg_pc) of a set-up handle; the setup (E~,
  * both hierarchies, packed operators) serves every preconditioner, so only
  * the captured iteration graphs are dropped.  Waits for the handle's pending
- * work.  VEMG_ERR_INVALID_ARG for an unknown value. */
+ * work.  VEMG_ERR_INVALID_ARG for an unknown value; VEMG_ERR_STATE for
+ * VEMG_PC_SA on a handle set up without that hierarchy. */
 vemg_status vemg_set_preconditioner(vemg_solver s, int pc);
 
 /* Switches the precision (vemg_precision) of later solves; the FP32 operator

@@ -71,18 +71,22 @@ def _vl_sor(s):
     return apply
 
 
-def _sa(s):
+def sa_levels(s, coarse_max=None, max_levels=None):
+    """The smoothed aggregation hierarchy of the whole A_UU, built in the
+    storage order (top block first, each block colour-sorted; the fine-level
+    sweeps take colour c of both blocks at once).  Reading: the paper fixes no
+    node order for its baseline; this is the order of the lumping method."""
     if getattr(s, "_sa_levels", None) is None:
-        # colour-sorted order over the whole A_UU: stable sort by colour
-        perm = np.argsort(s.colour, kind="stable")
-        A = amg.permute(s.A, perm)
-        s._sa_levels = (perm, amg.build_hierarchy(A, s.colour[perm]))
-    perm, levels = s._sa_levels
+        s._sa_levels = amg.build_hierarchy(s.A, s.colour, None, coarse_max or s.coarse_max,
+                                           max_levels or s.max_levels)
+    return s._sa_levels
+
+
+def _sa(s):
+    levels = sa_levels(s)
 
     def apply(r):
-        z = np.zeros_like(r)
-        z[perm] = amg.vcycle(levels, r[perm])
-        return z
+        return amg.vcycle(levels, r)
     return apply
 
 

@@ -39,6 +39,8 @@ class OracleSetup:
     mass: sp.csr_matrix       # full consistent mass matrix, natural order
     xyz: np.ndarray
     top: np.ndarray
+    coarse_max: int = 2048    # hierarchy parameters (also for the SA baseline)
+    max_levels: int = 10
 
     @property
     def n(self):
@@ -105,7 +107,8 @@ def setup(mesh, mode="N", coarse_max=2048, max_levels=10, alpha=0.0):
     return OracleSetup(mode=mode, n_nodes=n_nodes, pin=pin, perm=perm, n_top=n_top,
                        Aoff=Aoff, d=d, A=A, diag=diag, colour=colour, E=E, S_perm=S_perm,
                        S_levels=S_levels, Abar_levels=Abar_levels,
-                       mass=fem.assemble_mass(xyz, tets), xyz=xyz, top=top)
+                       mass=fem.assemble_mass(xyz, tets), xyz=xyz, top=top, coarse_max=coarse_max,
+                       max_levels=max_levels)
 
 
 def ordering_permute(A, order):

@@ -204,6 +204,7 @@ struct DLevel {
   bool fine = false;
   int64_t n = 0, row0 = 0;
   std::vector<int64_t> cstart;  // colour ranges, global row indices
+  std::vector<int64_t> cstart_top;  // fine level of the whole A_UU: top-block range of each colour
   CsrG P, Pt;                   // prolongation (n x n_next) and restriction
   double *Cinv = nullptr;       // coarsest level only
   bool coarsest = false;
@@ -248,7 +249,7 @@ struct vemg_solver_s {
   vemg::Sell A;                           // fine A_UU, difference form
   vemg::Sell E;
   vemg::CsrG Et;
-  std::vector<vemg::DLevel> S, Ab;
+  std::vector<vemg::DLevel> S, Ab, SA;  // SA: baseline hierarchy of the whole A_UU (may be empty)
   vemg::Work<double> v64;
   vemg::Work<float> v32;
   double *b = nullptr, *diag = nullptr, *scale_in = nullptr, *scale_out = nullptr, *dscal = nullptr;
@@ -272,7 +273,9 @@ Work<T> &work_of(Handle *h) {
   if constexpr (std::is_same<T, double>::value) return h->v64; else return h->v32;
 }
 
-void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, bool is_abar) {
+enum LevelsOf { kLevelsS = 0, kLevelsAbar = 1, kLevelsSA = 2 };
+
+void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, int of) {
   hipStream_t st = h->work;
   D.clear();
   for (size_t l = 0; l < H.size(); ++l) {
@@ -280,11 +283,19 @@ void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, bool
     DLevel dl;
     dl.n = L.n();
     dl.coarsest = (l + 1 == H.size());
-    if (is_abar && l == 0) {
+    if (of != kLevelsS && l == 0) {
+      // fine level: rows of the fine SELL matrix (non-top rows for A_bar,
+      // all rows for the whole A_UU), colour ranges in global rows
       dl.fine = true;
       dl.As = h->A;
-      dl.row0 = h->P.n_top;
-      dl.cstart = h->P.bar_colour_start;  // already global
+      dl.row0 = of == kLevelsAbar ? h->P.n_top : 0;
+      dl.cstart = h->P.bar_colour_start;
+      if (of == kLevelsSA) {
+        const int nc = std::max((int)h->P.top_colour_start.size(), (int)h->P.bar_colour_start.size()) - 1;
+        dl.cstart_top = h->P.top_colour_start;
+        dl.cstart_top.resize(nc + 1, dl.cstart_top.back());
+        dl.cstart.resize(nc + 1, dl.cstart.back());
+      }
       dl.x64 = h->v64.w;
       dl.g64 = h->v64.r;
       dl.r64 = h->v64.resA;
@@ -324,7 +335,9 @@ void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *
   launch_fill<T>(st, x + o, L.n * K, T(0), done);
   int nc = (int)L.cstart.size() - 1;
   auto gs = [&](int c) {
-    if (L.fine)
+    if (L.fine && !L.cstart_top.empty())
+      launch_gs<T>(st, K, L.As, L.cstart_top[c], L.cstart_top[c + 1], L.cstart[c], L.cstart[c + 1], g, x, done);
+    else if (L.fine)
       launch_gs<T>(st, K, L.As, L.cstart[c], L.cstart[c + 1], 0, 0, g, x, done);
     else
       launch_csr_gs<T>(st, K, L.Ac, L.cstart[c], L.cstart[c + 1], g, x, done);
@@ -453,6 +466,19 @@ void precond(Handle *h, int K, const T *rr, T *zz, double *part, int64_t *np, co
       launch_dot<T>(st, K, rr, zz, n, part, done);
       *np = vec_blocks(n);
       break;
+    case VEMG_PC_SA: {
+      // one V-cycle of the baseline hierarchy, its fine level on rr -> zz
+      DLevel &F = h->SA[0];
+      T *sx = F.x<T>(), *sg = F.g<T>();
+      F.x<T>() = zz;
+      F.g<T>() = const_cast<T *>(rr);
+      vcycle<T>(st, K, h->SA, 0, done);
+      F.x<T>() = sx;
+      F.g<T>() = sg;
+      launch_dot<T>(st, K, rr, zz, n, part, done);
+      *np = vec_blocks(n);
+      break;
+    }
     case VEMG_PC_JACOBI:
       launch_jacobi<T>(st, K, rr, h->diag, zz, n, done);
       launch_dot<T>(st, K, rr, zz, n, part, done);
@@ -894,8 +920,10 @@ void upload(Handle *h) {
   // the top block of the smoother vectors stays zero
   launch_fill<double>(st, h->v64.w, (int64_t)cnt, 0.0, nullptr);
   launch_fill<float>(st, h->v32.w, (int64_t)cnt, 0.0f, nullptr);
-  if (m > 0) build_levels(h, P.S, h->S, false);
-  build_levels(h, P.Abar, h->Ab, true);
+  if (m > 0) build_levels(h, P.S, h->S, kLevelsS);
+  build_levels(h, P.Abar, h->Ab, kLevelsAbar);
+  h->SA.clear();
+  if (!P.SA.empty()) build_levels(h, P.SA, h->SA, kLevelsSA);
   HIPCHK(hipStreamSynchronize(st));
 }
 
@@ -1139,8 +1167,8 @@ int do_export(Handle *h, const std::string &name, void *buf, size_t *bytes) {
   std::string head = name.substr(0, dot), rest = name.substr(dot + 1);
   if (head == "Aoff") return export_csr(P.Aoff, rest, buf, bytes);
   if (head == "E") return export_csr(P.E, rest, buf, bytes);
-  if (head == "S" || head == "Abar") {
-    const std::vector<Level> &H = head == "S" ? P.S : P.Abar;
+  if (head == "S" || head == "Abar" || head == "SA") {
+    const std::vector<Level> &H = head == "S" ? P.S : head == "Abar" ? P.Abar : P.SA;
     auto dot2 = rest.find('.');
     if (dot2 == std::string::npos) return VEMG_ERR_INVALID_ARG;
     size_t l = (size_t)std::stoul(rest.substr(0, dot2));
@@ -1494,7 +1522,7 @@ vemg_status vemg_create(const vemg_options *o, int device, void *hip_stream, vem
     vemg_default_options(&opt);
   if (opt.top_bc < 0 || opt.top_bc > 2 ||
       (opt.top_bc == VEMG_TOP_ROBIN && !(opt.robin_alpha > 0.0 && std::isfinite(opt.robin_alpha))) ||
-      opt.pc < 0 || opt.pc > 4 || opt.max_levels < 1 || opt.max_levels > 16 ||
+      opt.pc < 0 || opt.pc > 5 || opt.max_levels < 1 || opt.max_levels > 16 ||
       opt.coarse_max < 1 || opt.coarse_max > 8192 || !(opt.theta >= 0.0) || opt.poll_every < 1 ||
       opt.precision < 0 || opt.precision > 2 || !(opt.inner_rtol > 0.0 && opt.inner_rtol < 1.0) || opt.max_outer < 1)
     return VEMG_ERR_INVALID_ARG;
@@ -1535,6 +1563,7 @@ vemg_status vemg_setup(vemg_solver s, int64_t n_nodes, const double *xyz, int64_
     so.top_dirichlet = s->opt.top_bc == VEMG_TOP_DIRICHLET;
     so.robin = s->opt.top_bc == VEMG_TOP_ROBIN;
     so.robin_alpha = s->opt.robin_alpha;
+    so.build_sa = s->opt.pc == VEMG_PC_SA;
     so.pin_node = s->opt.pin_node;
     so.theta = s->opt.theta;
     so.prolong_omega = s->opt.prolong_omega;
@@ -1595,7 +1624,11 @@ vemg_status vemg_time_op(vemg_solver s, int op, int nrhs, int reps, double *avg_
 }
 
 vemg_status vemg_set_preconditioner(vemg_solver s, int pc) {
-  if (!s || pc < 0 || pc > 4) return VEMG_ERR_INVALID_ARG;
+  if (!s || pc < 0 || pc > 5) return VEMG_ERR_INVALID_ARG;
+  if (pc == VEMG_PC_SA && s->P.SA.empty()) {
+    s->err = "the smoothed aggregation baseline hierarchy is built only when the handle is set up with it";
+    return VEMG_ERR_STATE;
+  }
   return (vemg_status)guarded(s, [&]() -> int {
     if (s->device >= 0) {
       if (s->work) HIPCHK(hipStreamSynchronize(s->work));

@@ -826,6 +826,21 @@ void build_problem(Problem &P, const SetupOptions &opt, int64_t n_nodes, const d
   P.Abar.clear();
   P.Abar.push_back(std::move(B0));
   build_hierarchy(P.Abar, opt);
+
+  // the paper's baseline: smoothed aggregation on the whole A_UU, in the
+  // storage order (colour c of the fine level = its top and non-top ranges)
+  P.SA.clear();
+  if (opt.build_sa) {
+    Level F;
+    F.A = A;
+    F.colour = P.colour;
+    F.node.resize(n);
+    std::iota(F.node.begin(), F.node.end(), 0);
+    F.k = 1;
+    F.B.assign(n, 1.0);
+    P.SA.push_back(std::move(F));
+    build_hierarchy(P.SA, opt);
+  }
 }
 
 void mass_rhs(const Problem &P, const double *f, double *b) {

@@ -35,6 +35,7 @@ struct SetupOptions {
   int top_dirichlet = 0;     // 0: point condition at pin_node, 1: Dirichlet on the whole top
   int robin = 0;             // 1: Robin top d phi/dn + robin_alpha phi = 0, nothing fixed
   double robin_alpha = 0.0;
+  int build_sa = 0;          // 1: also the smoothed aggregation hierarchy of the whole A_UU
   int64_t pin_node = -1;     // -1: top node closest to the origin corner
   double theta = 0.01;
   double prolong_omega = 2.0 / 3.0;
@@ -58,6 +59,7 @@ struct Problem {
   Csr E, Et;                          // E~ (n x m') and its transpose
   std::vector<int64_t> S_perm;        // S storage position -> top-block position
   std::vector<Level> S, Abar;         // hierarchies (S empty when m' = 0)
+  std::vector<Level> SA;              // SA on the whole A_UU (baseline; only with opt.build_sa)
 };
 
 // Builds the whole problem.  Throws SetupError with a status code on

@@ -119,6 +119,25 @@ def test_other_preconditioners_match_oracle(pc, mode):
     assert e < tol
 
 
+@pytest.mark.parametrize("mode", ["N", "R"])
+def test_sa_baseline_matches_oracle(mode):
+    # the paper's baseline: one smoothed aggregation V-cycle on the whole A
+    m, s, o = _build(RAGGED, mode, "sa")
+    r = np.random.default_rng(4).standard_normal(o.n)
+    z = s.apply(lib.OP_PRECOND, r, o.n).cpu().numpy()
+    levels = precond.sa_levels(o)
+    e, tol = _rel(z, precond.make(o, "sa")(r)), _cycle_tol(levels)
+    _print("sa precond rel", e, "tol", tol)
+    assert e < tol
+    b_nat = s.rhs(fourier_field(m.xyz, RAGGED["H"], 44))
+    xo, it_o, rel_o, ok = osolver.solve(o, b_nat[o.perm], 1e-11, "sa", max_iter=5000)
+    x, its, rels, st = s.solve(b_nat, rtol=1e-11, max_iter=5000)
+    _print("sa iters gpu", its, "oracle", it_o)
+    assert ok and st == 0
+    assert _rel(x.cpu().numpy()[o.perm], xo) < 1e-8
+    assert abs(its[0] - it_o) <= max(3, 0.1 * it_o)
+
+
 @pytest.mark.parametrize("pc", ["vl_as", "vl_sor"])
 def test_robin_solution_matches_oracle(pc):
     # the free-surface (Robin) top: nothing fixed, A + alpha M_top

@@ -113,6 +113,31 @@ def test_hierarchies(pair, which):
             assert np.abs(Cinv @ L.A.toarray() - np.eye(L.n)).max() < 1e-7
 
 
+@pytest.mark.parametrize("mode", ["N", "R"])
+def test_sa_baseline_hierarchy(mode):
+    # the paper's baseline hierarchy on the whole A_UU (built on request)
+    from oracle import precond
+    kw = dict(nx=9, ny=8, nz=5, H=0.01, jitter=0.3, seed=11, bathymetry=True)
+    m = box_mesh(kw.pop("nx"), kw.pop("ny"), kw.pop("nz"), kw.pop("H"), **kw)
+    alpha = ROBIN_ALPHA if mode == "R" else 0.0
+    s = lib.Solver(m.xyz, m.tets, m.top, top_bc=mode, device=-1, coarse_max=40, robin_alpha=alpha, pc="sa")
+    o = osolver.setup(m, mode, coarse_max=40, alpha=alpha)
+    levels = precond.sa_levels(o, coarse_max=40)
+    assert len(levels) >= 2
+    for l, L in enumerate(levels):
+        pre = f"SA.{l}."
+        assert np.array_equal(s.export(pre + "colour", np.int32), L.colour)
+        assert np.array_equal(s.export(pre + "node", np.int32), L.node)
+        A = _csr(s, pre + "A")
+        _same_pattern(A, L.A)
+        _close(A[2], L.A.data)
+        if l + 1 < len(levels):
+            assert np.array_equal(s.export(pre + "agg", np.int32), L.agg)
+            P = _csr(s, pre + "P")
+            _same_pattern(P, L.P)
+            _close(P[2], L.P.data, 1e-12)
+
+
 def test_mass_rhs_matches_oracle(pair):
     m, s, o = pair
     f = np.cos(3 * m.xyz[:, 0]) + m.xyz[:, 1] ** 2
