@@ -1536,8 +1536,15 @@ vemg_status vemg_create(const vemg_options *o, int device, void *hip_stream, vem
       // non-blocking streams: no implicit ordering with the legacy null
       // stream, so another thread's work cannot join a graph being captured
       // here (ordering with the caller's stream is explicit, see sync_in)
-      HIPCHK(hipStreamCreateWithFlags(&h->work, hipStreamNonBlocking));
-      HIPCHK(hipStreamCreateWithFlags(&h->work2, hipStreamNonBlocking));
+      // Both work streams get dedicated hardware queues: a stream created with
+      // a CU mask (here every CU, so nothing is restricted) does not share its
+      // queue, so the two preconditioner branches cannot end up serialised
+      // behind each other or behind another stream's work.
+      hipDeviceProp_t prop;
+      HIPCHK(hipGetDeviceProperties(&prop, device));
+      std::vector<uint32_t> mask((prop.multiProcessorCount + 31) / 32, 0xffffffffu);
+      HIPCHK(hipExtStreamCreateWithCUMask(&h->work, (uint32_t)mask.size(), mask.data()));
+      HIPCHK(hipExtStreamCreateWithCUMask(&h->work2, (uint32_t)mask.size(), mask.data()));
       HIPCHK(hipEventCreateWithFlags(&h->ev, hipEventDisableTiming));
       HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
       HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
