@@ -321,8 +321,9 @@ def serving(nreq, seed, rtol, dev):
 def config_runs(dev, rtol):
     """The two other single-GPU configurations at full size.
     * 257 x 257 x 33 thin box, eps 1e-4 (2.18M unknowns), eight seeded smooth
-      right-hand sides per solve: FP32 preconditioner in FP64 CG against FP64,
-      solves/s and the error of every column against the FP64 solution.
+      right-hand sides per solve: FP64, FP32 inner PCG inside FP64 iterative
+      refinement, and FP32 preconditioner in FP64 CG; solves/s and the error
+      of every column against the FP64 solution.
     * Centre-refined multiscale thin box (h_min 1/900, 16-64 layers, eps 1e-3,
       about 3.5M unknowns), b = A x* for the manufactured x*: VL + additive
       smoother against VL + SOR (the paper's Mesh B comparison), iterations,
@@ -341,7 +342,7 @@ def config_runs(dev, rtol):
     rec = {"workload": "thinbox-257x257x33-eps1e-4", "n_dof": s.info()["n"], "rhs_per_solve": 8,
            "setup_s": time.perf_counter() - t0}
     x64 = None
-    for prec in ("fp64", "mixed_pc"):
+    for prec in ("fp64", "mixed_ir", "mixed_pc"):
         s.set_precision(prec)
         x, t, it, rel, st = timed_solves(s, B, 2, 1, rtol)
         r = {"ms_per_batch": 1e3 * float(np.median(t)), "solves_per_s": 8 / float(np.median(t)),
