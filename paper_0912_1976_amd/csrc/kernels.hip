@@ -309,7 +309,9 @@ __device__ __forceinline__ void group_row(const CsrG &A, int64_t r, int gl, cons
 }
 
 // Row r of a CsrG operation, by its group of G lanes (lane 0 of the group
-// writes).  MODE 0: y = A x, 1: y = g - A x (square); 2: y = P x, 3: y += P x;
+// writes).  The kernels below renumber their blocks like the fine ones, so
+// that each XCD works on a contiguous range of rows and the vector values
+// those rows gather stay in that XCD's L2.  MODE 0: y = A x, 1: y = g - A x (square); 2: y = P x, 3: y += P x;
 // 4: one Gauss-Seidel step y_r = (g_r - sum_j a_rj x_j) / a_rr (y = x).
 template <class T, int K, int G, int MODE>
 __device__ __forceinline__ void csr_row_op(const CsrG &A, int64_t r, int gl, const T *x, const T *g, T *y) {
@@ -368,7 +370,7 @@ __global__ __launch_bounds__(kWave) void k_csr_spmv(CsrG A, int64_t r0, int64_t 
                                                      const int *__restrict__ done) {
   if (done && *done) return;
   const int gl = threadIdx.x & (G - 1);
-  const int64_t r = r0 + ((int64_t)blockIdx.x * kWave + threadIdx.x) / G;
+  const int64_t r = r0 + (xcd_block(blockIdx.x, gridDim.x) * kWave + threadIdx.x) / G;
   if (r >= r1) return;
   csr_row_op<T, K, G, MODE>(A, r, gl, x, g, y);
 }
@@ -378,7 +380,7 @@ __global__ __launch_bounds__(kWave) void k_csr_gs(CsrG A, int64_t r0, int64_t r1
                                                    T *__restrict__ x, const int *__restrict__ done) {
   if (done && *done) return;
   const int gl = threadIdx.x & (G - 1);
-  const int64_t r = r0 + ((int64_t)blockIdx.x * kWave + threadIdx.x) / G;
+  const int64_t r = r0 + (xcd_block(blockIdx.x, gridDim.x) * kWave + threadIdx.x) / G;
   if (r >= r1) return;
   csr_row_op<T, K, G, 4>(A, r, gl, x, g, x);
 }
