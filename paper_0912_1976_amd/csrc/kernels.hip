@@ -89,6 +89,13 @@ __device__ __forceinline__ const float *csr_vals<float>(const CsrG &A) {
 
 // Off-diagonal terms of one SELL row for K columns: acc = sum_j v_j (x_j - x_r)
 // (DIFF) or sum_j v_j x_j, and off = sum_j v_j.
+// entries of a row kept in flight per lane: fewer as the gathered rows of K
+// values grow, so that the registers they take still allow several waves
+template <class T, int K>
+constexpr int sell_unroll() {
+  return sizeof(T) * K >= 64 ? 1 : sizeof(T) * K >= 32 ? 2 : 4;
+}
+
 template <class T, int K, bool DIFF>
 __device__ __forceinline__ void sell_row(const Sell &A, int64_t s, int lane, const T *__restrict__ x,
                                          const Row<T, K> &xr, T (&acc)[K], T &off) {
@@ -99,7 +106,8 @@ __device__ __forceinline__ void sell_row(const Sell &A, int64_t s, int lane, con
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = T(0);
   off = T(0);
-#pragma unroll 4
+  constexpr int U = sell_unroll<T, K>();
+#pragma unroll U
   for (int e = 0; e < len; ++e) {
     const int32_t c = cp[(int64_t)e * 64];
     const T v = vp[(int64_t)e * 64];
@@ -513,19 +521,36 @@ __global__ void k_promote(const float *__restrict__ d32, const double *__restric
 }
 
 // ------------------------------------------------------------- PCG scalars
-// fixed-order sum over np partials of column k by one block
-__device__ __forceinline__ double sum_partials(const double *__restrict__ p, int64_t np, int K, int k) {
-  double t = 0.0;
-  for (int64_t j = threadIdx.x; j < np; j += kBlock) t += p[j * K + k];
-  __shared__ double buf[kBlock];
+// Fixed-order sums of the K columns of np partials (row-major [np][K]) by one
+// block, all columns at once: thread t adds rows t, t + kBlock, ... in turn,
+// then a pairwise tree over the threads.  The order for column k does not
+// depend on K, so a column's sum is the same alone and in a batch.
+__device__ __forceinline__ void sum_partials(const double *__restrict__ p, int64_t np, int K,
+                                             double (&res)[kMaxBatch]) {
+  double t[kMaxBatch];
+#pragma unroll
+  for (int k = 0; k < kMaxBatch; ++k) t[k] = 0.0;
+  for (int64_t j = threadIdx.x; j < np; j += kBlock) {
+#pragma unroll
+    for (int k = 0; k < kMaxBatch; ++k)
+      if (k < K) t[k] += p[j * K + k];
+  }
+  __shared__ double buf[kMaxBatch][kBlock];
   __syncthreads();
-  buf[threadIdx.x] = t;
+#pragma unroll
+  for (int k = 0; k < kMaxBatch; ++k)
+    if (k < K) buf[k][threadIdx.x] = t[k];
   __syncthreads();
   for (int o = kBlock / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) buf[threadIdx.x] += buf[threadIdx.x + o];
+    if ((int)threadIdx.x < o) {
+#pragma unroll
+      for (int k = 0; k < kMaxBatch; ++k)
+        if (k < K) buf[k][threadIdx.x] += buf[k][threadIdx.x + o];
+    }
     __syncthreads();
   }
-  return buf[0];
+#pragma unroll
+  for (int k = 0; k < kMaxBatch; ++k) res[k] = (k < K) ? buf[k][0] : 0.0;
 }
 
 __device__ __forceinline__ void update_all_done(Scal *s) {
@@ -535,16 +560,18 @@ __device__ __forceinline__ void update_all_done(Scal *s) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce(const double *p, int64_t np, int K, double *out) {
-  for (int k = 0; k < K; ++k) {
-    double t = sum_partials(p, np, K, k);
-    if (threadIdx.x == 0) out[k] = t;
-  }
+  double t[kMaxBatch];
+  sum_partials(p, np, K, t);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < K; ++k) out[k] = t[k];
 }
 
 __global__ __launch_bounds__(kBlock) void k_pcg_init(Scal *s, const double *pb, int64_t npb, int K, double tol,
                                                      int maxit) {
+  double sums[kMaxBatch];
+  sum_partials(pb, npb, K, sums);
   for (int k = 0; k < kMaxBatch; ++k) {
-    double t = (k < K) ? sum_partials(pb, npb, K, k) : 0.0;
+    const double t = sums[k];
     if (threadIdx.x == 0) {
       s->bnorm2[k] = t;
       s->iters[k] = 0;
@@ -572,16 +599,18 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Scal *s, const double *pb, 
 }
 
 __global__ __launch_bounds__(kBlock) void k_pcg_set_rho(Scal *s, const double *p, int64_t np) {
-  for (int k = 0; k < s->K; ++k) {
-    double t = sum_partials(p, np, s->K, k);
-    if (threadIdx.x == 0) s->rho[k] = t;
-  }
+  double t[kMaxBatch];
+  sum_partials(p, np, s->K, t);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < s->K; ++k) s->rho[k] = t[k];
 }
 
 __global__ __launch_bounds__(kBlock) void k_pcg_alpha(Scal *s, const double *p, int64_t np) {
   if (s->all_done) return;
+  double sums[kMaxBatch];
+  sum_partials(p, np, s->K, sums);
   for (int k = 0; k < s->K; ++k) {
-    double pq = sum_partials(p, np, s->K, k);
+    const double pq = sums[k];
     if (threadIdx.x == 0 && !s->done[k]) {
       s->pq[k] = pq;
       if (!(pq > 0.0) || !isfinite(pq) || !isfinite(s->rho[k])) {
@@ -625,8 +654,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr(const Scal *s, T *__restrict_
 
 __global__ __launch_bounds__(kBlock) void k_pcg_conv(Scal *s, const double *p, int64_t np) {
   if (s->all_done) return;
+  double sums[kMaxBatch];
+  sum_partials(p, np, s->K, sums);
   for (int k = 0; k < s->K; ++k) {
-    double rr = sum_partials(p, np, s->K, k);
+    const double rr = sums[k];
     if (threadIdx.x == 0 && !s->done[k]) {
       int it = s->iters[k] + 1;
       s->iters[k] = it;
@@ -648,8 +679,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_conv(Scal *s, const double *p, i
 
 __global__ __launch_bounds__(kBlock) void k_pcg_beta(Scal *s, const double *p, int64_t np) {
   if (s->all_done) return;
+  double sums[kMaxBatch];
+  sum_partials(p, np, s->K, sums);
   for (int k = 0; k < s->K; ++k) {
-    double rz = sum_partials(p, np, s->K, k);
+    const double rz = sums[k];
     if (threadIdx.x == 0 && !s->done[k]) {
       s->beta[k] = rz / s->rho[k];
       s->rho[k] = rz;
@@ -701,9 +734,11 @@ __global__ void k_slot_vectors(unsigned mask, int restart, const double *__restr
 __global__ __launch_bounds__(kBlock) void k_slot_scalars(unsigned mask, int restart, Scal *s, const double *pb,
                                                          int64_t npb, double tol, int maxit, double *scale_in,
                                                          double *scale_out) {
+  double sums[kMaxBatch];
+  sum_partials(pb, npb, kMaxBatch, sums);
   for (int k = 0; k < kMaxBatch; ++k) {
     if (!((mask >> k) & 1u)) continue;
-    double t = restart ? 0.0 : sum_partials(pb, npb, kMaxBatch, k);
+    const double t = restart ? 0.0 : sums[k];
     if (threadIdx.x == 0) {
       if (!restart) {
         s->bnorm2[k] = t;
@@ -735,11 +770,11 @@ __global__ __launch_bounds__(kBlock) void k_slot_scalars(unsigned mask, int rest
 }
 
 __global__ __launch_bounds__(kBlock) void k_slot_rho(unsigned mask, Scal *s, const double *p, int64_t np) {
-  for (int k = 0; k < kMaxBatch; ++k) {
-    if (!((mask >> k) & 1u)) continue;
-    double t = sum_partials(p, np, kMaxBatch, k);
-    if (threadIdx.x == 0) s->rho[k] = t;
-  }
+  double t[kMaxBatch];
+  sum_partials(p, np, kMaxBatch, t);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kMaxBatch; ++k)
+      if ((mask >> k) & 1u) s->rho[k] = t[k];
 }
 
 __global__ void k_slot_copy(unsigned mask, const double *__restrict__ z, double *__restrict__ p, int64_t n) {
