@@ -151,3 +151,45 @@ def vertical_extrapolation(xyz, tets, top, node_order, dirichlet):
     tri_of_row = np.full(n_free, -1, dtype=np.int64)
     tri_of_row[r_in] = which
     return E, tri_of_row
+
+
+def sspai_refit(E0, A, n_top):
+    """The sparse-approximate-inverse alternative to the projection (Section
+    5.4, second approach): E~ = [I; F] keeps the pattern of the projected
+    E~, and the entries of F are refitted from the operator.
+
+    The exact extrapolation is E = [I; -A_bar^{-1} C^T] (Section 5.3), with
+    A_bar the non-top block of A_UU and C^T its coupling block (non-top rows,
+    top columns).  Column i of F is fitted on its own: with J the non-top
+    rows where column i of the pattern is non-empty, v = F[J, i] solves the
+    restriction of A_bar f_i = -C^T e_i to J,
+        A_bar[J, J] v = -C^T[J, i],
+    entries outside J staying zero.  Reading: the text writes the fitting
+    objective as |F^T A_bar - C| while its decoupled column systems carry
+    -r_i on the right; the exact E above fixes the sign, and the column
+    systems are what is solved here.  Each dense system is solved by
+    Cholesky (A_bar[J, J] is a principal submatrix of a symmetric positive
+    definite matrix).
+
+    E0: n x m' CSR in storage order (top rows first, identity there); A: the
+    standard-form A_UU in the same order.  Returns a new CSR with the same
+    pattern."""
+    import scipy.linalg
+
+    E = E0.tocsr().copy()
+    E.sort_indices()
+    A = A.tocsr()
+    Ec = E.tocsc()
+    Ec.sort_indices()
+    for i in range(E.shape[1]):
+        rows = Ec.indices[Ec.indptr[i]:Ec.indptr[i + 1]]
+        J = rows[rows >= n_top]
+        if J.size == 0:
+            continue
+        G = A[J][:, J].toarray()
+        rhs = -A[J, i].toarray().ravel()
+        v = scipy.linalg.cho_solve(scipy.linalg.cho_factor(G, lower=True), rhs)
+        for r, val in zip(J, v):
+            k = E.indptr[r] + np.searchsorted(E.indices[E.indptr[r]:E.indptr[r + 1]], i)
+            E.data[k] = val
+    return E

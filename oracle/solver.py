@@ -41,16 +41,22 @@ class OracleSetup:
     top: np.ndarray
     coarse_max: int = 2048    # hierarchy parameters (also for the SA baseline)
     max_levels: int = 10
+    extrapolation: str = "projection"
 
     @property
     def n(self):
         return self.perm.size
 
 
-def setup(mesh, mode="N", coarse_max=2048, max_levels=10, alpha=0.0):
+def setup(mesh, mode="N", coarse_max=2048, max_levels=10, alpha=0.0, extrapolation="projection"):
     """Assembly (Section 3), E~ (Section 5.4) and both SA hierarchies (Section 6).
     mode 'N' (point condition), 'D' (Dirichlet top) or 'R' (Robin top with
-    coefficient alpha > 0, the free-surface condition of Section 2)."""
+    coefficient alpha > 0, the free-surface condition of Section 2).
+    extrapolation: 'projection' (the vertical projection of Section 5.4) or
+    'sspai' (its pattern with F refitted from A, the second approach of
+    Section 5.4)."""
+    if extrapolation not in ("projection", "sspai"):
+        raise ValueError(extrapolation)
     xyz, tets, top = mesh.xyz, mesh.tets, mesh.top
     n_nodes = xyz.shape[0]
     _, Aoff_full = fem.assemble_stiffness(xyz, tets)
@@ -88,6 +94,8 @@ def setup(mesh, mode="N", coarse_max=2048, max_levels=10, alpha=0.0):
     S_levels = None
     if n_top > 0:
         E0, _ = extrap.vertical_extrapolation(xyz, tets, top, perm, D)
+        if extrapolation == "sspai":
+            E0 = extrap.sspai_refit(E0, A, n_top)
         S0 = amg.structural_product(E0.T.tocsr(), A, E0)
         S_perm, S_col = amg.colour_level(S0)
         E = E0[:, S_perm].tocsr()
@@ -108,7 +116,7 @@ def setup(mesh, mode="N", coarse_max=2048, max_levels=10, alpha=0.0):
                        Aoff=Aoff, d=d, A=A, diag=diag, colour=colour, E=E, S_perm=S_perm,
                        S_levels=S_levels, Abar_levels=Abar_levels,
                        mass=fem.assemble_mass(xyz, tets), xyz=xyz, top=top, coarse_max=coarse_max,
-                       max_levels=max_levels)
+                       max_levels=max_levels, extrapolation=extrapolation)
 
 
 def ordering_permute(A, order):
