@@ -99,6 +99,22 @@ typedef enum {
  *                    preconditioner (transfers, smoothers, V-cycles) runs in FP32. */
 typedef enum { VEMG_FP64 = 0, VEMG_MIXED_IR = 1, VEMG_MIXED_PC = 2 } vemg_precision;
 
+/* Extrapolation operator E~ = [I; F] of the surface branch (Section 5.4).
+ *   VEMG_EXTRAP_PROJECTION  each node below the top takes the linear
+ *                           interpolant of the surface triangle its vertical
+ *                           projection lands in (at most three entries a row).
+ *   VEMG_EXTRAP_SSPAI       the same pattern, F refitted from the operator
+ *                           (the sparse approximate inverse alternative of
+ *                           Section 5.4): column i of F solves the exact
+ *                           extrapolation's column system A_bar f = -C^T e_i
+ *                           restricted to its pattern, one dense Cholesky
+ *                           solve per surface unknown at setup.  With
+ *                           vertical columns it tends to the projection as
+ *                           eps^2; on meshes with broken columns it loses the
+ *                           constants and converges far more slowly at small
+ *                           eps. */
+typedef enum { VEMG_EXTRAP_PROJECTION = 0, VEMG_EXTRAP_SSPAI = 1 } vemg_extrapolation;
+
 typedef struct {
   int top_bc;          /* vemg_top_bc */
   int64_t pin_node;    /* pinned top node (natural index); -1: top node closest to the origin */
@@ -114,6 +130,7 @@ typedef struct {
   double inner_rtol;   /* VEMG_MIXED_IR: relative tolerance of each inner FP32 solve, 1e-4 */
   int max_outer;       /* VEMG_MIXED_IR: refinement steps, 30 */
   double robin_alpha;  /* VEMG_TOP_ROBIN: alpha > 0 (ignored otherwise), 0 */
+  int extrapolation;   /* vemg_extrapolation, VEMG_EXTRAP_PROJECTION */
 } vemg_options;
 
 typedef struct {

@@ -20,6 +20,7 @@ OP_A, OP_PRECOND, OP_ET, OP_E, OP_VCYCLE_S, OP_VCYCLE_ABAR, OP_GS_FWD, OP_GS_COA
 _PC = {"vl_as": 0, "vl_sor": 1, "jacobi": 2, "none": 3, "vl_add": 4, "sa": 5}
 _TOP = {"pinned": 0, "N": 0, "dirichlet": 1, "D": 1, "robin": 2, "R": 2}
 _PREC = {"fp64": 0, "mixed": 1, "mixed_ir": 1, "mixed_pc": 2}
+_EXTRAP = {"projection": 0, "sspai": 1}
 
 
 class VemgError(RuntimeError):
@@ -33,7 +34,7 @@ class Options(C.Structure):
                 ("theta", C.c_double), ("prolong_omega", C.c_double), ("max_levels", C.c_int),
                 ("coarse_max", C.c_int64), ("poll_every", C.c_int), ("max_restarts", C.c_int),
                 ("use_graphs", C.c_int), ("precision", C.c_int), ("inner_rtol", C.c_double),
-                ("max_outer", C.c_int), ("robin_alpha", C.c_double)]
+                ("max_outer", C.c_int), ("robin_alpha", C.c_double), ("extrapolation", C.c_int)]
 
 
 class Info(C.Structure):
@@ -121,12 +122,14 @@ class Solver:
 
     def __init__(self, xyz, tets, top, *, top_bc="pinned", pc="vl_as", device=0, pin_node=-1,
                  use_graphs=True, poll_every=8, coarse_max=2048, max_levels=10, max_restarts=5,
-                 precision="fp64", inner_rtol=1e-4, max_outer=30, robin_alpha=0.0):
+                 precision="fp64", inner_rtol=1e-4, max_outer=30, robin_alpha=0.0,
+                 extrapolation="projection"):
         self._lib = load_library()
         opt = Options()
         self._lib.vemg_default_options(C.byref(opt))
         opt.top_bc = _TOP[top_bc]
         opt.robin_alpha = robin_alpha
+        opt.extrapolation = _EXTRAP[extrapolation]
         opt.pc = _PC[pc]
         opt.pin_node = pin_node
         opt.use_graphs = int(bool(use_graphs))
@@ -252,7 +255,7 @@ class Server:
     request is collected with result()."""
 
     def __init__(self, *, device=0, hbm_budget=0, top_bc="pinned", pc="vl_as", precision="mixed_pc",
-                 poll_every=8, coarse_max=2048, max_restarts=5, robin_alpha=0.0):
+                 poll_every=8, coarse_max=2048, max_restarts=5, robin_alpha=0.0, extrapolation="projection"):
         import torch
         self._torch = torch
         self._lib = load_library()
@@ -260,6 +263,7 @@ class Server:
         self._lib.vemg_default_options(C.byref(opt))
         opt.top_bc = _TOP[top_bc]
         opt.robin_alpha = robin_alpha
+        opt.extrapolation = _EXTRAP[extrapolation]
         opt.pc = _PC[pc]
         opt.precision = _PREC[precision]
         opt.poll_every = poll_every

@@ -1510,6 +1510,7 @@ void vemg_default_options(vemg_options *o) {
   o->inner_rtol = 1e-4;
   o->max_outer = 30;
   o->robin_alpha = 0.0;
+  o->extrapolation = VEMG_EXTRAP_PROJECTION;
 }
 
 vemg_status vemg_create(const vemg_options *o, int device, void *hip_stream, vemg_solver *out) {
@@ -1524,7 +1525,8 @@ vemg_status vemg_create(const vemg_options *o, int device, void *hip_stream, vem
       (opt.top_bc == VEMG_TOP_ROBIN && !(opt.robin_alpha > 0.0 && std::isfinite(opt.robin_alpha))) ||
       opt.pc < 0 || opt.pc > 5 || opt.max_levels < 1 || opt.max_levels > 16 ||
       opt.coarse_max < 1 || opt.coarse_max > 8192 || !(opt.theta >= 0.0) || opt.poll_every < 1 ||
-      opt.precision < 0 || opt.precision > 2 || !(opt.inner_rtol > 0.0 && opt.inner_rtol < 1.0) || opt.max_outer < 1)
+      opt.precision < 0 || opt.precision > 2 || !(opt.inner_rtol > 0.0 && opt.inner_rtol < 1.0) || opt.max_outer < 1 ||
+      opt.extrapolation < 0 || opt.extrapolation > 1)
     return VEMG_ERR_INVALID_ARG;
   auto *h = new (std::nothrow) vemg_solver_s();
   if (!h) return VEMG_ERR_OOM;
@@ -1571,6 +1573,7 @@ vemg_status vemg_setup(vemg_solver s, int64_t n_nodes, const double *xyz, int64_
     so.robin = s->opt.top_bc == VEMG_TOP_ROBIN;
     so.robin_alpha = s->opt.robin_alpha;
     so.build_sa = s->opt.pc == VEMG_PC_SA;
+    so.extrapolation = s->opt.extrapolation;
     so.pin_node = s->opt.pin_node;
     so.theta = s->opt.theta;
     so.prolong_omega = s->opt.prolong_omega;

@@ -6,12 +6,14 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <functional>
 #include <numeric>
 #include <queue>
 #include <sstream>
+#include <thread>
 #include <tuple>
 
 namespace vemg {
@@ -391,6 +393,99 @@ void spd_inverse(std::vector<double> &M, int64_t n) {
       double *mi = &M[i * n];
       for (int64_t j = 0; j <= k; ++j) mi[j] += a * wk[j];
     }
+  }
+}
+
+// The sparse approximate inverse alternative to the projection (Section 5.4,
+// second approach).  The exact extrapolation is E = [I; -A_bar^{-1} C^T]
+// (Section 5.3); E~ keeps the projection's pattern, and column i of its
+// non-top block F is refitted on its own: with J the non-top rows of the
+// column's pattern, v = F[J, i] solves A_bar[J, J] v = -C^T[J, i] (entries
+// outside J stay zero).  A_bar[J, J] is a principal submatrix of a symmetric
+// positive definite matrix: one dense Cholesky factorisation per column.
+// Columns are independent and are shared among host threads.
+void sspai_refit(Csr &E, const Csr &A, int64_t m) {
+  const int64_t n = E.nrows, nc = E.ncols;
+  // non-top entries of every column, rows ascending, with their position in E
+  std::vector<int64_t> cptr(nc + 1, 0);
+  for (int64_t r = m; r < n; ++r)
+    for (int64_t k = E.ptr[r]; k < E.ptr[r + 1]; ++k) ++cptr[E.idx[k] + 1];
+  for (int64_t i = 0; i < nc; ++i) cptr[i + 1] += cptr[i];
+  std::vector<int64_t> crow(cptr[nc]), cpos(cptr[nc]), next(cptr.begin(), cptr.end() - 1);
+  for (int64_t r = m; r < n; ++r)
+    for (int64_t k = E.ptr[r]; k < E.ptr[r + 1]; ++k) {
+      int64_t c = E.idx[k];
+      crow[next[c]] = r;
+      cpos[next[c]] = k;
+      ++next[c];
+    }
+  std::atomic<int64_t> next_col{0}, bad{-1};
+  auto work = [&]() {
+    std::vector<double> L, v;
+    for (;;) {
+      int64_t c = next_col.fetch_add(1);
+      if (c >= nc) return;
+      const int64_t b = cptr[c], q = cptr[c + 1] - b;
+      if (q == 0) continue;
+      const int64_t *J = &crow[b];
+      L.assign(q * q, 0.0);
+      v.assign(q, 0.0);
+      for (int64_t a = 0; a < q; ++a) {
+        const int64_t r = J[a];
+        for (int64_t k = A.ptr[r]; k < A.ptr[r + 1]; ++k) {
+          const int64_t j = A.idx[k];
+          if (j == c) {
+            v[a] = -A.val[k];
+          } else if (j >= m) {
+            const int64_t *p = std::lower_bound(J, J + q, j);
+            if (p != J + q && *p == j) L[a * q + (p - J)] = A.val[k];
+          }
+        }
+      }
+      // lower Cholesky factor in place (row-major, lower triangle)
+      bool ok = true;
+      for (int64_t j = 0; j < q && ok; ++j) {
+        double s = L[j * q + j];
+        for (int64_t k = 0; k < j; ++k) s -= L[j * q + k] * L[j * q + k];
+        if (!(s > 0.0)) {
+          ok = false;
+          break;
+        }
+        const double ljj = std::sqrt(s);
+        L[j * q + j] = ljj;
+        for (int64_t i = j + 1; i < q; ++i) {
+          double t = L[i * q + j];
+          for (int64_t k = 0; k < j; ++k) t -= L[i * q + k] * L[j * q + k];
+          L[i * q + j] = t / ljj;
+        }
+      }
+      if (!ok) {
+        int64_t none = -1;
+        bad.compare_exchange_strong(none, c);
+        return;
+      }
+      for (int64_t i = 0; i < q; ++i) {  // L y = rhs
+        double t = v[i];
+        for (int64_t k = 0; k < i; ++k) t -= L[i * q + k] * v[k];
+        v[i] = t / L[i * q + i];
+      }
+      for (int64_t i = q - 1; i >= 0; --i) {  // L^T x = y
+        double t = v[i];
+        for (int64_t k = i + 1; k < q; ++k) t -= L[k * q + i] * v[k];
+        v[i] = t / L[i * q + i];
+      }
+      for (int64_t a = 0; a < q; ++a) E.val[cpos[b + a]] = v[a];
+    }
+  };
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (unsigned t = 1; t < nt; ++t) pool.emplace_back(work);
+  work();
+  for (auto &t : pool) t.join();
+  if (bad.load() >= 0) {
+    std::ostringstream os;
+    os << "extrapolation refit: the system of surface column " << bad.load() << " is not positive definite";
+    fail(-3, os.str());
   }
 }
 
@@ -777,6 +872,7 @@ void build_problem(Problem &P, const SetupOptions &opt, int64_t n_nodes, const d
       }
       E0.ptr[s + 1] = (int64_t)E0.idx.size();
     }
+    if (opt.extrapolation == 1) sspai_refit(E0, A, m);
     Csr E0t = transpose(E0);
     Csr S0 = spgemm(E0t, spgemm(A, E0));
     std::vector<int32_t> scol = sweep_colouring(S0);

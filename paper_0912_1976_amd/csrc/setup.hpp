@@ -36,6 +36,7 @@ struct SetupOptions {
   int robin = 0;             // 1: Robin top d phi/dn + robin_alpha phi = 0, nothing fixed
   double robin_alpha = 0.0;
   int build_sa = 0;          // 1: also the smoothed aggregation hierarchy of the whole A_UU
+  int extrapolation = 0;     // 0: vertical projection, 1: F refitted on its pattern (SSPAI)
   int64_t pin_node = -1;     // -1: top node closest to the origin corner
   double theta = 0.01;
   double prolong_omega = 2.0 / 3.0;

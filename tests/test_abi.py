@@ -47,6 +47,10 @@ def test_status_strings_and_invalid_arguments():
     h = C.c_void_p()
     assert lib.vemg_create(C.byref(o), -1, None, C.byref(h)) == -1
     assert lib.vemg_create(None, -1, None, None) == -1
+    lib.vemg_default_options(C.byref(o))
+    assert o.extrapolation == 0
+    o.extrapolation = 2
+    assert lib.vemg_create(C.byref(o), -1, None, C.byref(h)) == -1
 
 
 def test_host_only_handle_rejects_compute():

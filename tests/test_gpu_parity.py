@@ -40,10 +40,11 @@ def _build(cfg, mode, pc="vl_as", **kw):
     _dev()
     c = dict(cfg)
     m = box_mesh(c.pop("nx"), c.pop("ny"), c.pop("nz"), c.pop("H"), **c)
-    _print("case", cfg, mode, pc)
+    _print("case", cfg, mode, pc, kw)
     alpha = ROBIN_ALPHA if mode == "R" else 0.0
+    ex = kw.get("extrapolation", "projection")
     s = lib.Solver(m.xyz, m.tets, m.top, top_bc=mode, pc=pc, device=0, robin_alpha=alpha, **kw)
-    o = osolver.setup(m, mode, coarse_max=kw["coarse_max"], alpha=alpha)
+    o = osolver.setup(m, mode, coarse_max=kw["coarse_max"], alpha=alpha, extrapolation=ex)
     return m, s, o
 
 
@@ -146,6 +147,20 @@ def test_robin_solution_matches_oracle(pc):
     xo, it_o, rel_o, ok = osolver.solve(o, b_nat[o.perm], 1e-11, pc, max_iter=5000)
     x, its, rels, st = s.solve(b_nat, rtol=1e-11, max_iter=5000)
     _print("robin iters gpu", its, "oracle", it_o, "relres", rels, rel_o)
+    assert ok and st == 0 and rels[0] <= 1e-11
+    assert _rel(x.cpu().numpy()[o.perm], xo) < 1e-8
+    assert abs(its[0] - it_o) <= max(3, 0.1 * it_o)
+
+
+@pytest.mark.parametrize("mode,pc", [("N", "vl_as"), ("N", "vl_add"), ("R", "vl_sor")])
+def test_sspai_extrapolation_matches_oracle(mode, pc):
+    # E~ with F refitted on the projection's pattern (Section 5.4, second
+    # approach); eps = 0.1, where the refit is competitive
+    m, s, o = _build(dict(CFG1, H=0.1), mode, pc, extrapolation="sspai")
+    b_nat = s.rhs(fourier_field(m.xyz, 0.1, 41))
+    xo, it_o, rel_o, ok = osolver.solve(o, b_nat[o.perm], 1e-11, pc, max_iter=5000)
+    x, its, rels, st = s.solve(b_nat, rtol=1e-11, max_iter=5000)
+    _print("sspai iters gpu", its, "oracle", it_o, "relres", rels, rel_o)
     assert ok and st == 0 and rels[0] <= 1e-11
     assert _rel(x.cpu().numpy()[o.perm], xo) < 1e-8
     assert abs(its[0] - it_o) <= max(3, 0.1 * it_o)

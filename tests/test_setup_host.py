@@ -169,3 +169,36 @@ def test_setup_errors():
     with pytest.raises(lib.VemgError) as e:
         lib.Solver(m.xyz, t2, m.top, device=-1)
     assert e.value.status == -2
+
+
+@pytest.mark.parametrize("mode", ["N", "R"])
+def test_sspai_extrapolation_and_surface_hierarchy(mode):
+    # E~ refitted on the projection's pattern (Section 5.4, second approach):
+    # same pattern and permutation, values from per-column dense solves
+    # (Cholesky on both sides, different summation orders), then the surface
+    # hierarchy built on the new S = E~^T A E~
+    kw = dict(nx=9, ny=8, nz=5, H=0.01, jitter=0.3, seed=11, bathymetry=True)
+    m = box_mesh(kw.pop("nx"), kw.pop("ny"), kw.pop("nz"), kw.pop("H"), **kw)
+    alpha = ROBIN_ALPHA if mode == "R" else 0.0
+    s = lib.Solver(m.xyz, m.tets, m.top, top_bc=mode, device=-1, coarse_max=40, robin_alpha=alpha,
+                   extrapolation="sspai")
+    o = osolver.setup(m, mode, coarse_max=40, alpha=alpha, extrapolation="sspai")
+    assert np.array_equal(s.export("S_perm", np.int64), o.S_perm)
+    E = _csr(s, "E")
+    _same_pattern(E, o.E)
+    _close(E[2], o.E.data, 1e-12)
+    levels = o.S_levels
+    assert s.info()["s_levels"] == len(levels)
+    for l, L in enumerate(levels[:-1]):
+        pre = f"S.{l}."
+        assert np.array_equal(s.export(pre + "colour", np.int32), L.colour)
+        assert np.array_equal(s.export(pre + "agg", np.int32), L.agg)
+        A = _csr(s, pre + "A")
+        _same_pattern(A, L.A)
+        _close(A[2], L.A.data, 1e-12)
+
+
+def test_unknown_extrapolation_rejected():
+    m = box_mesh(5, 4, 3, 0.1)
+    with pytest.raises(KeyError):
+        lib.Solver(m.xyz, m.tets, m.top, device=-1, extrapolation="harmonic")
