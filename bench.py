@@ -494,7 +494,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(the multi-GPU decomposition is described in DESIGN.md, not built).", file=sys.stderr)
+              "(the decomposition over several GPUs is designed, not built).", file=sys.stderr)
         sys.exit(2)
 
     if args.profile_kernels:
