@@ -64,6 +64,36 @@ def coarse_gs_bytes(info, level=1, K=1, elt=8, val=8):
     return off * (val + 4) + info["abar_rows"][level] * (4 + 8 + 4 * elt * K)
 
 
+def restrict_bytes(info, K=1, elt=8, val=8):
+    """The restriction g = E~^T r (CSR of E~^T): every stored entry (value +
+    column), r read once, per surface row the row pointer and the output."""
+    return info["e_nnz"] * (val + 4) + info["n"] * elt * K + info["n_top"] * (4 + elt * K)
+
+
+def prolong_bytes(info, K=1, elt=8, val=8):
+    """The prolongation z += E~ y: every stored entry (value + column), z read
+    and written once, y read once."""
+    return info["e_nnz"] * (val + 4) + 2 * info["n"] * elt * K + info["n_top"] * elt * K
+
+
+def kernel_rates(s, info, vemg, K=1, reps=20):
+    """Live per-application times of the hot operators of one iteration
+    (HIP events on the library's stream) and their algorithmic rates."""
+    out = {}
+    for name, op, nbytes in (("spmv", vemg.OP_A, spmv_bytes(info, K)),
+                             ("fine_sweep", vemg.OP_GS_FWD, gs_sweep_bytes(info, K)),
+                             ("coarse_sweep", vemg.OP_GS_COARSE, coarse_gs_bytes(info, K=K)),
+                             ("restrict_Et", vemg.OP_ET, restrict_bytes(info, K)),
+                             ("prolong_E", vemg.OP_E, prolong_bytes(info, K))):
+        try:
+            ms, nl = s.time_op(op, reps=reps, nrhs=K)
+        except vemg.VemgError:
+            continue
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out[name] = {"ms": ms, "launches": nl, "bytes": nbytes, "GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    return out
+
+
 # Fine-level sweeps, fine SpMVs and coarse (first coarse level of A_bar and
 # the surface operator) sweeps per PCG iteration, by preconditioner:
 #   vl_as:  SOR cycle (2 fine sweeps, 1 residual SpMV, 2 sweeps on S) and the
@@ -341,6 +371,7 @@ def config_runs(dev, rtol):
     B = torch.as_tensor(np.stack([s.rhs(fourier_field(m.xyz, 1e-4, 200 + k)) for k in range(8)]), device=dev)
     rec = {"workload": "thinbox-257x257x33-eps1e-4", "n_dof": s.info()["n"], "rhs_per_solve": 8,
            "setup_s": time.perf_counter() - t0}
+    rec["kernels"] = {"K1": kernel_rates(s, s.info(), vemg, 1), "K8": kernel_rates(s, s.info(), vemg, 8, reps=10)}
     x64 = None
     for prec in ("fp64", "mixed_ir", "mixed_pc"):
         s.set_precision(prec)
@@ -548,8 +579,9 @@ def main():
         xb, tb, ib, rb, _ = timed_solves(s, B8, 3, 1, args.rtol)
         extras["fp64_batch8"] = {"solves_per_s": 8 * 3 / sum(tb), "ms_per_batch": 1e3 * sum(tb) / 3,
                                  "iterations": ib[0], "max_relres": max(rb[0])}
-        ms8, _ = s.time_op(vemg.OP_A, reps=20, nrhs=8)
-        extras["kernels_batch8"] = {"spmv_ms": ms8, "spmv_GBs": spmv_bytes(info, 8) / (ms8 * 1e-3) / 1e9}
+        extras["kernels_batch8"] = kernel_rates(s, info, vemg, 8, reps=10)
+        extras["transfers"] = {k: v for k, v in kernel_rates(s, info, vemg, 1).items()
+                               if k in ("restrict_Et", "prolong_E")}
         log(f"FP64 x8: {extras['fp64_batch8']['solves_per_s']:.1f} solves/s")
         for prec in ("mixed_ir", "mixed_pc"):
             sm = vemg.Solver(mesh.xyz, mesh.tets, mesh.top, top_bc="pinned", pc=args.pc, device=0, precision=prec)

@@ -221,8 +221,10 @@ vemg_status vemg_apply(vemg_solver s, int op, const double *in_dev, double *out_
 
 /* Benchmark support: average device time in milliseconds of one
  * application of VEMG_OP_A (one SpMV launch), VEMG_OP_GS_FWD (one forward
- * multicolour sweep over all rows, one launch per colour) or
- * VEMG_OP_GS_COARSE (the same on A_bar's first coarse level) to nrhs (1..8)
+ * multicolour sweep over all rows, one launch per colour),
+ * VEMG_OP_GS_COARSE (the same on A_bar's first coarse level), VEMG_OP_ET
+ * (the restriction E~^T, one launch) or VEMG_OP_E (the prolongation E~
+ * added into an n-vector, as the SOR cycle applies it, one launch) to nrhs (1..8)
  * columns, in the handle's inner precision (FP32 for VEMG_MIXED_IR, FP64
  * otherwise), measured with HIP events on the handle's own stream around
  * `reps` back-to-back applications on internal buffers, after one untimed

@@ -1065,6 +1065,14 @@ void time_once(Handle *h, int op, int K) {
     launch_spmv<T>(st, K, h->A, 0, 0, n, v.p, (const T *)nullptr, v.q, h->part_pq, nullptr);
     return;
   }
+  if (op == VEMG_OP_ET) {
+    launch_csr_rect<T>(st, K, h->Et, false, v.r, h->S[0].g<T>(), nullptr);
+    return;
+  }
+  if (op == VEMG_OP_E) {
+    launch_rect<T>(st, K, h->E, true, h->S[0].x<T>(), v.z, nullptr);
+    return;
+  }
   if (op == VEMG_OP_GS_COARSE) {
     DLevel &L = h->Ab[1];
     for (size_t c = 0; c + 1 < L.cstart.size(); ++c)
@@ -1090,8 +1098,10 @@ int do_time(Handle *h, int op, int K, int reps, double *avg_ms, int *launches) {
   hipStream_t st = h->work;
   const Problem &P = h->P;
   int64_t n = P.n;
-  if (op != VEMG_OP_A && op != VEMG_OP_GS_FWD && op != VEMG_OP_GS_COARSE) return VEMG_ERR_INVALID_ARG;
+  if (op != VEMG_OP_A && op != VEMG_OP_GS_FWD && op != VEMG_OP_GS_COARSE && op != VEMG_OP_ET && op != VEMG_OP_E)
+    return VEMG_ERR_INVALID_ARG;
   if (op == VEMG_OP_GS_COARSE && (h->Ab.size() < 2 || h->Ab[1].coarsest)) return VEMG_ERR_STATE;
+  if ((op == VEMG_OP_ET || op == VEMG_OP_E) && (P.n_top == 0 || h->S.empty())) return VEMG_ERR_STATE;
   if (K != 1 && K != 2 && K != 4 && K != 8) return VEMG_ERR_INVALID_ARG;
   int nc = std::max((int)P.top_colour_start.size() - 1, (int)P.bar_colour_start.size() - 1);
   if (op == VEMG_OP_GS_COARSE) {
@@ -1106,6 +1116,12 @@ int do_time(Handle *h, int op, int K, int reps, double *avg_ms, int *launches) {
     }
   }
   bool f32 = h->opt.precision == VEMG_MIXED_IR;
+  if (op == VEMG_OP_E) {
+    if (f32)
+      launch_fill<float>(st, h->S[0].x32, P.n_top * K, 1.0f, nullptr);
+    else
+      launch_fill<double>(st, h->S[0].x64, P.n_top * K, 1.0, nullptr);
+  }
   if (f32) {
     launch_fill<float>(st, h->v32.p, n * K, 1.0f, nullptr);
     launch_fill<float>(st, h->v32.r, n * K, 1.0f, nullptr);
@@ -1131,7 +1147,7 @@ int do_time(Handle *h, int op, int K, int reps, double *avg_ms, int *launches) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *avg_ms = (double)ms / reps;
-  if (launches) *launches = (op == VEMG_OP_A) ? 1 : nc;
+  if (launches) *launches = (op == VEMG_OP_A || op == VEMG_OP_ET || op == VEMG_OP_E) ? 1 : nc;
   return VEMG_OK;
 }
 
