@@ -153,7 +153,7 @@ def permute(A, perm):
     return A
 
 
-def node_strength_graph(A, node, nnodes):
+def node_strength_graph(A, node, nnodes, theta=THETA):
     """Strong node graph: nodes I != J are strongly connected when
     ||A_IJ||_F > theta sqrt(||A_II||_F ||A_JJ||_F), with A_IJ the block of
     entries whose row belongs to I and column to J.  For one unknown per
@@ -168,7 +168,7 @@ def node_strength_graph(A, node, nnodes):
     d = F.diagonal()
     rows = np.repeat(np.arange(nnodes), np.diff(F.indptr))
     off = rows != F.indices
-    st = off & (F.data > THETA * np.sqrt(d[rows] * d[F.indices]))
+    st = off & (F.data > theta * np.sqrt(d[rows] * d[F.indices]))
     G = sp.csr_matrix((F.data[st], (rows[st], F.indices[st])), shape=(nnodes, nnodes))
     G.sort_indices()
     return G
@@ -269,7 +269,16 @@ def build_hierarchy(A0, colour0, B0=None, coarse_max=2048, max_levels=10, stall=
     """SA hierarchy on A0 (in storage order: rows sorted by colour, within each
     block for the whole A_UU; the sweeps select rows by colour), one
     unknown per node on the finest level, near-kernel vectors B0 (default:
-    the constant vector)."""
+    the constant vector).
+
+    Coarsening stops at coarse_max unknowns, at max_levels, or when a level
+    would keep more than `stall` of its unknowns.  Reading: Section 6 fixes
+    the strength threshold (0.01) but not what happens when too few
+    couplings pass it, as on meshes with vertical columns at small eps,
+    where only the vertical couplings are strong and, once the columns are
+    aggregated, no coupling is: such a level is aggregated again with every
+    coupling counted as strong (threshold 0) before coarsening gives up, so
+    that the coarsest level stays small enough for its dense solve."""
     n0 = A0.shape[0]
     if B0 is None:
         B0 = np.ones((n0, 1))
@@ -286,7 +295,12 @@ def build_hierarchy(A0, colour0, B0=None, coarse_max=2048, max_levels=10, stall=
         P0, Bc, cnode = tentative_from_kernel(L.B, L.node, agg)
         nc = P0.shape[1]
         if nc > stall * L.n:
-            break
+            G = node_strength_graph(L.A, L.node, nnodes, 0.0)
+            agg = aggregate_graph(G)
+            P0, Bc, cnode = tentative_from_kernel(L.B, L.node, agg)
+            nc = P0.shape[1]
+            if nc > stall * L.n:
+                break
         P = smoothed_prolongator_from(L.A, P0)
         Ac = structural_product(P.T.tocsr(), L.A, P)
         perm, ccol = colour_level(Ac)

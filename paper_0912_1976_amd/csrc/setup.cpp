@@ -502,7 +502,20 @@ void build_hierarchy(std::vector<Level> &levels, const SetupOptions &opt) {
     std::vector<int32_t> cnode;
     tentative(L, agg, P0, Bc, cnode);
     int64_t nc = P0.ncols;
-    if ((double)nc > 0.8 * (double)L.n()) break;
+    if ((double)nc > 0.8 * (double)L.n()) {
+      // too few couplings pass the threshold (vertical columns at small eps
+      // leave none once the columns are aggregated): aggregate this level
+      // again with every coupling strong before giving up, which keeps the
+      // coarsest level small enough for its dense solve
+      G = node_strength(L.A, L.node, nnodes, 0.0);
+      agg = aggregate_graph(G);
+      P0 = Csr();
+      Bc.clear();
+      cnode.clear();
+      tentative(L, agg, P0, Bc, cnode);
+      nc = P0.ncols;
+      if ((double)nc > 0.8 * (double)L.n()) break;
+    }
     Csr P = spgemm(jacobi_smoother(L.A, opt.prolong_omega), P0);
     Csr Pt = transpose(P);
     Csr Ac = spgemm(Pt, spgemm(L.A, P));

@@ -168,3 +168,31 @@ def test_two_level_with_complete_coarse_space_is_exact():
     g = np.arange(6.0)
     x = amg.vcycle([L0, L1], g)
     assert np.allclose(A @ x, g, atol=1e-12)
+
+
+def test_stalled_level_is_aggregated_with_every_coupling():
+    # a chain whose links are all weak (1e-5 against a unit diagonal) does
+    # not coarsen at the threshold 0.01; the level is then aggregated with
+    # every coupling strong, which for a chain is the aggregation of the
+    # same chain with strong links
+    n = 60
+    weak = sp.diags([-1e-5 * np.ones(n - 1), np.ones(n), -1e-5 * np.ones(n - 1)], [-1, 0, 1], format="csr")
+    assert amg.aggregate(weak).tolist() == list(range(n))
+    levels = amg.build_hierarchy(weak, np.zeros(n, dtype=np.int64), None, coarse_max=10, max_levels=3)
+    assert len(levels) >= 2
+    assert levels[0].agg.tolist() == amg.aggregate(chain(n)).tolist()
+    assert levels[1].n < n // 2
+
+
+def test_vertical_columns_coarsen_below_coarse_max():
+    # aligned columns at eps = 1e-3: only vertical couplings are strong; once
+    # the columns are aggregated the coarsening continues through the
+    # stall rule, and the preconditioned solve still converges
+    m = box_mesh(13, 13, 7, 1e-3, jitter=0.0, seed=1, bathymetry=False)
+    o = solver.setup(m, "N", coarse_max=30)
+    assert o.Abar_levels[-1].n <= 30
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal(o.n)
+    x, it, rel, ok = solver.solve(o, b, 1e-10, "vl_as")
+    xd = spla.spsolve(o.A.tocsc(), b)
+    assert ok and np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)

@@ -20,6 +20,9 @@ CASES = [
     ("N", dict(nx=17, ny=17, nz=9, H=0.01, jitter=0.2, seed=1, bathymetry=False)),
     ("N", dict(nx=21, ny=19, nz=7, H=1e-4, jitter=0.3, seed=5, bathymetry=True)),
     ("R", dict(nx=9, ny=8, nz=5, H=0.01, jitter=0.3, seed=11, bathymetry=True)),
+    # vertical columns: the A_bar coarsening stalls once the columns are
+    # aggregated and continues with every coupling strong
+    ("N", dict(nx=17, ny=17, nz=9, H=1e-3, jitter=0.0, seed=1, bathymetry=False)),
 ]
 ROBIN_ALPHA = 7.5
 
