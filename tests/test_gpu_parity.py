@@ -166,6 +166,21 @@ def test_sspai_extrapolation_matches_oracle(mode, pc):
     assert abs(its[0] - it_o) <= max(3, 0.1 * it_o)
 
 
+def test_vertical_columns_match_oracle():
+    # an extruded box (aligned columns): the A_bar coarsening stalls once the
+    # columns are aggregated and continues with every coupling strong
+    m, s, o = _build(dict(nx=13, ny=13, nz=7, H=1e-3, jitter=0.0, seed=1, bathymetry=False), "N", "vl_as",
+                     coarse_max=30)
+    assert s.info()["abar_rows"][-1] <= 30
+    b_nat = s.rhs(fourier_field(m.xyz, 1e-3, 43))
+    xo, it_o, rel_o, ok = osolver.solve(o, b_nat[o.perm], 1e-11, "vl_as", max_iter=5000)
+    x, its, rels, st = s.solve(b_nat, rtol=1e-11, max_iter=5000)
+    _print("vertical columns iters gpu", its, "oracle", it_o, "relres", rels, rel_o)
+    assert ok and st == 0 and rels[0] <= 1e-11
+    assert _rel(x.cpu().numpy()[o.perm], xo) < 1e-8
+    assert abs(its[0] - it_o) <= max(3, 0.1 * it_o)
+
+
 @pytest.mark.parametrize("pc", ["vl_as", "vl_sor", "vl_add", "jacobi"])
 def test_solution_matches_oracle(pc):
     m, s, o = _build(CFG1, "N", pc)
