@@ -166,6 +166,21 @@ def test_sspai_extrapolation_matches_oracle(mode, pc):
     assert abs(its[0] - it_o) <= max(3, 0.1 * it_o)
 
 
+@pytest.mark.parametrize("nx,ny,nz,H,mode", [(2, 2, 2, 1.0, "N"), (3, 3, 2, 0.1, "N"), (5, 4, 2, 0.01, "N"),
+                                             (4, 4, 3, 0.01, "D"), (3, 2, 2, 0.1, "R")])
+def test_tiny_meshes_match_oracle(nx, ny, nz, H, mode):
+    # one layer of cells, hierarchies that are a single (dense) level, levels
+    # of one or two unknowns
+    m, s, o = _build(dict(nx=nx, ny=ny, nz=nz, H=H, jitter=0.0, seed=1, bathymetry=False), mode, "vl_as",
+                     coarse_max=4)
+    b_nat = s.rhs(fourier_field(m.xyz, H, 44))
+    xo, it_o, rel_o, ok = osolver.solve(o, b_nat[o.perm], 1e-11, "vl_as", max_iter=500)
+    x, its, rels, st = s.solve(b_nat, rtol=1e-11, max_iter=500)
+    _print("tiny", nx, ny, nz, mode, "iters gpu", its, "oracle", it_o)
+    assert ok and st == 0 and rels[0] <= 1e-11
+    assert _rel(x.cpu().numpy()[o.perm], xo) < 1e-8
+
+
 def test_vertical_columns_match_oracle():
     # an extruded box (aligned columns): the A_bar coarsening stalls once the
     # columns are aggregated and continues with every coupling strong
