@@ -1570,7 +1570,7 @@ vemg_status vemg_create(const vemg_options *o, int device, void *hip_stream, vem
     return VEMG_OK;
   });
   if (st != VEMG_OK) {
-    delete h;
+    (void)vemg_destroy(h);  // releases whatever was created before the failure
     return (vemg_status)st;
   }
   *out = h;
