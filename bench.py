@@ -11,8 +11,11 @@ step = one complete solve (setup excluded), inputs resident in HBM.
 Also measured (reported beside the headline in the same JSON line): eight
 right-hand sides per launch, the two mixed-precision forms, the serving
 stream over six resident meshes (continuous batching; saturated and Poisson
-arrivals; mixed precision vs FP64), live kernel timings for the roofline,
-and the CPU oracle on a bounded sample of the headline solve.
+arrivals; mixed precision vs FP64), the free-surface (Robin) top, plain
+smoothed aggregation against the lumping method at three aspect ratios, the
+projected vs SSPAI-refitted extrapolation, the 257 x 257 x 33 and graded
+multiscale configurations, live kernel timings for the roofline, and the
+CPU oracle on a bounded sample of the headline solve.
 """
 from __future__ import annotations
 
