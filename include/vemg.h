@@ -249,7 +249,7 @@ vemg_status vemg_set_precision(vemg_solver s, int precision);
  * name: "perm" (int64 [n], storage -> natural), "colour" (int32 [n]),
  * "Aoff.ptr" (int64), "Aoff.idx" (int32), "Aoff.val", "d", "diag" (double),
  * "E.ptr", "E.idx", "E.val", "S_perm" (int64),
- * "<h>.<level>.<what>" with h in {S, Abar} and what in {A.ptr, A.idx, A.val,
+ * "<h>.<level>.<what>" with h in {S, Abar, SA} and what in {A.ptr, A.idx, A.val,
  * P.ptr, P.idx, P.val, colour, node, agg, Cinv}.  With buf == NULL only
  * *bytes is set; otherwise *bytes must hold the buffer size. */
 vemg_status vemg_export(vemg_solver s, const char *name, void *buf, size_t *bytes);

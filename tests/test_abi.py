@@ -64,3 +64,38 @@ def test_host_only_handle_rejects_compute():
     # rhs is host-side and works
     b = s.rhs(np.ones(m.n))
     assert np.isfinite(b).all()
+
+
+def test_plain_c_consumer(tmp_path):
+    # the header compiles as strict C99 and a C program drives the library
+    # through it; its results match the binding's
+    import shutil
+    import subprocess
+
+    import numpy as np
+
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    libdir = os.path.join(root, "paper_0912_1976_amd")
+    exe = tmp_path / "consumer"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                    "-I", os.path.join(root, "include"), os.path.join(root, "tests", "abi_c", "consumer.c"),
+                    "-L", libdir, "-lvemg", "-Wl,-rpath," + libdir, "-o", str(exe)], check=True)
+    m = box_mesh(9, 8, 5, 0.01, jitter=0.3, seed=11, bathymetry=True)
+    mesh = tmp_path / "mesh.bin"
+    with open(mesh, "wb") as f:
+        np.array([m.n, m.tets.shape[0]], dtype=np.int64).tofile(f)
+        np.ascontiguousarray(m.xyz, dtype=np.float64).tofile(f)
+        np.ascontiguousarray(m.tets, dtype=np.int64).tofile(f)
+        np.ascontiguousarray(m.top, dtype=np.uint8).tofile(f)
+    out = subprocess.run([str(exe), str(mesh)], check=True, capture_output=True, text=True).stdout.split()
+    got = dict(kv.split("=") for kv in out)
+    s = lib_mod.Solver(m.xyz, m.tets, m.top, device=-1, coarse_max=16)
+    info = s.info()
+    perm = s.export("perm", np.int64)
+    assert int(got["n"]) == info["n"] and int(got["n_top"]) == info["n_top"]
+    assert int(got["nnz_offdiag"]) == info["nnz_offdiag"]
+    assert int(got["s_levels"]) == info["s_levels"] and int(got["abar_levels"]) == info["abar_levels"]
+    assert int(got["perm_checksum"]) == int(np.sum(perm * np.arange(1, perm.size + 1)))
+    assert int(got["solve"]) == -7  # VEMG_ERR_STATE: no device
