@@ -206,6 +206,7 @@ struct DLevel {
   std::vector<int64_t> cstart;  // colour ranges, global row indices
   std::vector<int64_t> cstart_top;  // fine level of the whole A_UU: top-block range of each colour
   CsrG P, Pt;                   // prolongation (n x n_next) and restriction
+  Sell Ps;                      // fine levels: the prolongation in SELL-64 (a few entries a row)
   double *Cinv = nullptr;       // coarsest level only
   bool coarsest = false;
   // vectors indexed by global row, [n][kMaxBatch], per precision
@@ -314,7 +315,10 @@ void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, int 
       dl.r32 = h->ar.alloc<float>(cnt);
     }
     if (!dl.coarsest) {
-      dl.P = pack_csrg(h->ar, st, L.P, false);
+      if (dl.fine)
+        dl.Ps = pack_sell(h->ar, st, L.P, false, nullptr, nullptr);
+      else
+        dl.P = pack_csrg(h->ar, st, L.P, false);
       dl.Pt = pack_csrg(h->ar, st, transpose(L.P), false);
     } else {
       dl.Cinv = h->ar.upload(L.Cinv, st);
@@ -350,7 +354,10 @@ void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *
   DLevel &C = H[l + 1];
   launch_csr_rect<T>(st, K, L.Pt, false, r + o, C.g<T>(), done);
   vcycle<T>(st, K, H, l + 1, done);
-  launch_csr_rect<T>(st, K, L.P, true, C.x<T>(), x + o, done);
+  if (L.fine)
+    launch_rect<T>(st, K, L.Ps, true, C.x<T>(), x + o, done);
+  else
+    launch_csr_rect<T>(st, K, L.P, true, C.x<T>(), x + o, done);
   for (int c = nc - 1; c >= 0; --c) gs(c);
 }
 
