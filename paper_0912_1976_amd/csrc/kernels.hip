@@ -530,7 +530,23 @@ __device__ __forceinline__ void sum_partials(const double *__restrict__ p, int64
   double t[kMaxBatch];
 #pragma unroll
   for (int k = 0; k < kMaxBatch; ++k) t[k] = 0.0;
-  for (int64_t j = threadIdx.x; j < np; j += kBlock) {
+  // four of each thread's partials are loaded before any is added, so that a
+  // thread keeps four loads per column in flight; the additions keep the
+  // order j = tid, tid + kBlock, ...
+  int64_t j = threadIdx.x;
+  for (; j + 3 * kBlock < np; j += 4 * kBlock) {
+    double v[4][kMaxBatch];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < kMaxBatch; ++k) v[u][k] = (k < K) ? p[(j + u * kBlock) * K + k] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < kMaxBatch; ++k)
+        if (k < K) t[k] += v[u][k];
+  }
+  for (; j < np; j += kBlock) {
 #pragma unroll
     for (int k = 0; k < kMaxBatch; ++k)
       if (k < K) t[k] += p[j * K + k];
@@ -605,24 +621,53 @@ __global__ __launch_bounds__(kBlock) void k_pcg_set_rho(Scal *s, const double *p
     for (int k = 0; k < s->K; ++k) s->rho[k] = t[k];
 }
 
+// The per-iteration scalar kernels handle column k in thread k, so that the
+// few loads and stores of each column overlap instead of following one
+// another in a single thread.
+__device__ __forceinline__ double column_of(const double (&v)[kMaxBatch], int k) {
+  double out = 0.0;
+#pragma unroll
+  for (int q = 0; q < kMaxBatch; ++q)
+    if (q == k) out = v[q];
+  return out;
+}
+
+// all_done from the columns' flags (thread k < K holds column k's); every
+// thread of the block must call it
+__device__ __forceinline__ void store_all_done(Scal *s, int K, int mine) {
+  __shared__ int flags[kMaxBatch];
+  if ((int)threadIdx.x < K) flags[threadIdx.x] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int all = 1;
+    for (int k = 0; k < K; ++k) all &= flags[k];
+    s->all_done = all;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_pcg_alpha(Scal *s, const double *p, int64_t np) {
   if (s->all_done) return;
+  const int K = s->K;
   double sums[kMaxBatch];
-  sum_partials(p, np, s->K, sums);
-  for (int k = 0; k < s->K; ++k) {
-    const double pq = sums[k];
-    if (threadIdx.x == 0 && !s->done[k]) {
+  sum_partials(p, np, K, sums);
+  const int k = threadIdx.x;
+  int done = 1;
+  if (k < K) {
+    done = s->done[k];
+    if (!done) {
+      const double pq = column_of(sums, k), rho = s->rho[k];
       s->pq[k] = pq;
-      if (!(pq > 0.0) || !isfinite(pq) || !isfinite(s->rho[k])) {
+      if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rho)) {
+        done = 1;
         s->done[k] = 1;
         s->status[k] = -6;
         s->alpha[k] = 0.0;
       } else {
-        s->alpha[k] = s->rho[k] / pq;
+        s->alpha[k] = rho / pq;
       }
     }
   }
-  if (threadIdx.x == 0) update_all_done(s);
+  store_all_done(s, K, done);
 }
 
 template <class T, int K>
@@ -654,39 +699,45 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr(const Scal *s, T *__restrict_
 
 __global__ __launch_bounds__(kBlock) void k_pcg_conv(Scal *s, const double *p, int64_t np) {
   if (s->all_done) return;
+  const int K = s->K;
   double sums[kMaxBatch];
-  sum_partials(p, np, s->K, sums);
-  for (int k = 0; k < s->K; ++k) {
-    const double rr = sums[k];
-    if (threadIdx.x == 0 && !s->done[k]) {
-      int it = s->iters[k] + 1;
+  sum_partials(p, np, K, sums);
+  const int k = threadIdx.x;
+  int done = 1;
+  if (k < K) {
+    done = s->done[k];
+    if (!done) {
+      const double rr = column_of(sums, k);
+      const int it = s->iters[k] + 1;
       s->iters[k] = it;
       s->rr[k] = rr;
-      if (!isfinite(rr)) {
+      int status = 0;
+      if (!isfinite(rr))
+        status = -6;
+      else if (rr <= s->tol2 * s->bnorm2[k])
+        status = 1;
+      else if (it >= s->maxit)
+        status = 2;
+      if (status != 0) {
+        done = 1;
         s->done[k] = 1;
-        s->status[k] = -6;
-      } else if (rr <= s->tol2 * s->bnorm2[k]) {
-        s->done[k] = 1;
-        s->status[k] = 1;
-      } else if (it >= s->maxit) {
-        s->done[k] = 1;
-        s->status[k] = 2;
+        s->status[k] = status;
       }
     }
   }
-  if (threadIdx.x == 0) update_all_done(s);
+  store_all_done(s, K, done);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pcg_beta(Scal *s, const double *p, int64_t np) {
   if (s->all_done) return;
+  const int K = s->K;
   double sums[kMaxBatch];
-  sum_partials(p, np, s->K, sums);
-  for (int k = 0; k < s->K; ++k) {
-    const double rz = sums[k];
-    if (threadIdx.x == 0 && !s->done[k]) {
-      s->beta[k] = rz / s->rho[k];
-      s->rho[k] = rz;
-    }
+  sum_partials(p, np, K, sums);
+  const int k = threadIdx.x;
+  if (k < K && !s->done[k]) {
+    const double rz = column_of(sums, k);
+    s->beta[k] = rz / s->rho[k];
+    s->rho[k] = rz;
   }
 }
 
