@@ -551,22 +551,28 @@ __device__ __forceinline__ void sum_partials(const double *__restrict__ p, int64
     for (int k = 0; k < kMaxBatch; ++k)
       if (k < K) t[k] += p[j * K + k];
   }
-  __shared__ double buf[kMaxBatch][kBlock];
-  __syncthreads();
+  // then a fixed tree: xor shuffles within each wavefront, and the four
+  // wavefront sums added in order (the same result in every thread)
+  __shared__ double buf[kMaxBatch][kSlicesPerBlock];
 #pragma unroll
   for (int k = 0; k < kMaxBatch; ++k)
-    if (k < K) buf[k][threadIdx.x] = t[k];
+    if (k < K) t[k] = wave_sum(t[k]);
   __syncthreads();
-  for (int o = kBlock / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
+  if ((threadIdx.x & (kWave - 1)) == 0) {
 #pragma unroll
-      for (int k = 0; k < kMaxBatch; ++k)
-        if (k < K) buf[k][threadIdx.x] += buf[k][threadIdx.x + o];
-    }
-    __syncthreads();
+    for (int k = 0; k < kMaxBatch; ++k)
+      if (k < K) buf[k][threadIdx.x / kWave] = t[k];
   }
+  __syncthreads();
 #pragma unroll
-  for (int k = 0; k < kMaxBatch; ++k) res[k] = (k < K) ? buf[k][0] : 0.0;
+  for (int k = 0; k < kMaxBatch; ++k) {
+    double r = 0.0;
+    if (k < K) {
+#pragma unroll
+      for (int w = 0; w < kSlicesPerBlock; ++w) r += buf[k][w];
+    }
+    res[k] = r;
+  }
 }
 
 __device__ __forceinline__ void update_all_done(Scal *s) {
