@@ -203,6 +203,7 @@ struct DLevel {
   CsrG Ac;                      // coarse levels: standard form, G lanes per row
   bool fine = false;
   int64_t n = 0, row0 = 0;
+  int64_t n_top = 0;            // fine levels: rows of the top block in the fine matrix
   std::vector<int64_t> cstart;  // colour ranges, global row indices
   std::vector<int64_t> cstart_top;  // fine level of the whole A_UU: top-block range of each colour
   CsrG P, Pt;                   // prolongation (n x n_next) and restriction
@@ -288,6 +289,7 @@ void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, int 
       // fine level: rows of the fine SELL matrix (non-top rows for A_bar,
       // all rows for the whole A_UU), colour ranges in global rows
       dl.fine = true;
+      dl.n_top = h->P.n_top;
       dl.As = h->A;
       dl.row0 = of == kLevelsAbar ? h->P.n_top : 0;
       dl.cstart = h->P.bar_colour_start;
@@ -336,17 +338,29 @@ void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *
     launch_dense<T>(st, K, L.Cinv, L.n, g + o, x + o, done);
     return;
   }
-  launch_fill<T>(st, x + o, L.n * K, T(0), done);
   int nc = (int)L.cstart.size() - 1;
-  auto gs = [&](int c) {
-    if (L.fine && !L.cstart_top.empty())
-      launch_gs<T>(st, K, L.As, L.cstart_top[c], L.cstart_top[c + 1], L.cstart[c], L.cstart[c + 1], g, x, done);
-    else if (L.fine)
-      launch_gs<T>(st, K, L.As, L.cstart[c], L.cstart[c + 1], 0, 0, g, x, done);
-    else
-      launch_csr_gs<T>(st, K, L.Ac, L.cstart[c], L.cstart[c + 1], g, x, done);
+  // forward (zero start: x needs no fill, the colours not swept yet are not
+  // read) and backward sweeps of colour c
+  auto gs = [&](int c, bool first) {
+    if (L.fine) {
+      // A_bar's fine level (no top range) never reads the top columns: they
+      // multiply the smoother vector's top part, which is zero
+      ZeroStart zs;
+      zs.on = first;
+      zs.n_top = L.n_top;
+      zs.top_lim = L.cstart_top.empty() ? 0 : L.cstart_top[c];
+      zs.bar_lim = L.cstart[c];
+      if (!L.cstart_top.empty()) {
+        launch_gs<T>(st, K, L.As, L.cstart_top[c], L.cstart_top[c + 1], L.cstart[c], L.cstart[c + 1], g, x, done,
+                     zs);
+      } else {
+        launch_gs<T>(st, K, L.As, L.cstart[c], L.cstart[c + 1], 0, 0, g, x, done, zs);
+      }
+    } else {
+      launch_csr_gs<T>(st, K, L.Ac, L.cstart[c], L.cstart[c + 1], g, x, done, first ? L.cstart[c] : -1);
+    }
   };
-  for (int c = 0; c < nc; ++c) gs(c);
+  for (int c = 0; c < nc; ++c) gs(c, true);
   if (L.fine)
     launch_spmv<T>(st, K, L.As, 1, L.row0, L.row0 + L.n, x, g, r, nullptr, done);
   else
@@ -358,7 +372,7 @@ void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *
     launch_rect<T>(st, K, L.Ps, true, C.x<T>(), x + o, done);
   else
     launch_csr_rect<T>(st, K, L.P, true, C.x<T>(), x + o, done);
-  for (int c = nc - 1; c >= 0; --c) gs(c);
+  for (int c = nc - 1; c >= 0; --c) gs(c, false);
 }
 
 // One vertical-lumping multigrid cycle on stream st (Section 6, second
@@ -369,10 +383,11 @@ void sor_cycle(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *
   const Problem &P = h->P;
   int64_t n = P.n, m = P.n_top;
   Work<T> &v = work_of<T>(h);
-  launch_fill<T>(st, zz, n * K, T(0), done);
   int nct = (int)P.top_colour_start.size() - 1, ncb = (int)P.bar_colour_start.size() - 1;
   int nc = std::max(nct, ncb);
-  auto sweep = [&](int c) {
+  // the forward sweep starts from zero: zz needs no fill, and colour c reads
+  // only the colours before it (in each block)
+  auto sweep = [&](int c, bool first) {
     int64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
     if (c < nct) {
       a0 = P.top_colour_start[c];
@@ -382,16 +397,21 @@ void sor_cycle(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *
       b0 = P.bar_colour_start[c];
       b1 = P.bar_colour_start[c + 1];
     }
-    launch_gs<T>(st, K, h->A, a0, a1, b0, b1, rr, zz, done);
+    ZeroStart zs;
+    zs.on = first;
+    zs.n_top = m;
+    zs.top_lim = P.top_colour_start[std::min(c, nct)];
+    zs.bar_lim = P.bar_colour_start[std::min(c, ncb)];
+    launch_gs<T>(st, K, h->A, a0, a1, b0, b1, rr, zz, done, zs);
   };
-  for (int c = 0; c < nc; ++c) sweep(c);
+  for (int c = 0; c < nc; ++c) sweep(c, true);
   if (m > 0) {
     launch_spmv<T>(st, K, h->A, 1, 0, n, zz, rr, v.res, nullptr, done);
     launch_csr_rect<T>(st, K, h->Et, false, v.res, h->S[0].g<T>(), done);
     vcycle<T>(st, K, h->S, 0, done);
     launch_rect<T>(st, K, h->E, true, h->S[0].x<T>(), zz, done);
   }
-  for (int c = nc - 1; c >= 0; --c) sweep(c);
+  for (int c = nc - 1; c >= 0; --c) sweep(c, false);
 }
 
 // w = Z Vcyc_Abar(Z^T rr) on stream st (the additive smoother; rows of the top

@@ -96,9 +96,10 @@ constexpr int sell_unroll() {
   return sizeof(T) * K >= 64 ? 1 : sizeof(T) * K >= 32 ? 2 : 4;
 }
 
-template <class T, int K, bool DIFF>
+template <class T, int K, bool DIFF, bool ZS = false>
 __device__ __forceinline__ void sell_row(const Sell &A, int64_t s, int lane, const T *__restrict__ x,
-                                         const Row<T, K> &xr, T (&acc)[K], T &off) {
+                                         const Row<T, K> &xr, T (&acc)[K], T &off,
+                                         const ZeroStart &z = ZeroStart()) {
   const int64_t base = A.sptr[s];
   const int len = (int)((A.sptr[s + 1] - base) >> 6);
   const int32_t *__restrict__ cp = A.col + base + lane;
@@ -111,9 +112,11 @@ __device__ __forceinline__ void sell_row(const Sell &A, int64_t s, int lane, con
   for (int e = 0; e < len; ++e) {
     const int32_t c = cp[(int64_t)e * 64];
     const T v = vp[(int64_t)e * 64];
-    const Row<T, K> xc = ld<T, K>(x, c);
+    if (!ZS || c < (c < z.n_top ? z.top_lim : z.bar_lim)) {
+      const Row<T, K> xc = ld<T, K>(x, c);
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] += DIFF ? v * (xc.v[k] - xr.v[k]) : v * xc.v[k];
+      for (int k = 0; k < K; ++k) acc[k] += DIFF ? v * (xc.v[k] - xr.v[k]) : v * xc.v[k];
+    }
     off += v;
   }
 }
@@ -206,9 +209,9 @@ __device__ __forceinline__ Row<T, K> gs_apply(T d0, T d1, const Row<T, K> &xr, c
 // one wavefront (one slice) per block: a colour holds few rows, so small
 // blocks spread them over every CU; up to two row ranges (the top and the
 // non-top rows of one colour)
-template <class T, int K>
+template <class T, int K, bool ZS>
 __global__ __launch_bounds__(kWave) void k_gs(Sell A, GsDev<T> J, const T *__restrict__ g,
-                                               const int *__restrict__ done) {
+                                               const int *__restrict__ done, ZeroStart z) {
   if (done && *done) return;
   int64_t blk = xcd_block(blockIdx.x, J.nbt);
   int j = 0;
@@ -222,7 +225,13 @@ __global__ __launch_bounds__(kWave) void k_gs(Sell A, GsDev<T> J, const T *__res
   const int64_t s = J.sf[j] + blk;
   const int64_t r = s * 64 + lane;
   if (r < r0 || r >= r1) return;
-  const Row<T, K> xr = ld<T, K>(x, r);
+  Row<T, K> xr;
+  if constexpr (ZS) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) xr.v[k] = T(0);
+  } else {
+    xr = ld<T, K>(x, r);
+  }
   const Row<T, K> gr = ld<T, K>(g, r);
   T d0, d1 = T(0);
   if constexpr (std::is_same<T, double>::value) {
@@ -232,7 +241,7 @@ __global__ __launch_bounds__(kWave) void k_gs(Sell A, GsDev<T> J, const T *__res
     d1 = A.dh32[r];
   }
   T acc[K], off;
-  sell_row<T, K, true>(A, s, lane, x, xr, acc, off);
+  sell_row<T, K, true, ZS>(A, s, lane, x, xr, acc, off, z);
   st<T, K>(x, r, gs_apply<T, K>(d0, d1, xr, gr, acc, off));
 }
 
@@ -296,8 +305,9 @@ __global__ __launch_bounds__(kBlock) void k_prolong_sum(Sell E, int64_t n_top, i
 // ------------------------------------------------------------- CsrG
 // Off-diagonal sum of one row for K columns by its group of G lanes (the
 // result is valid in every lane of the group).
-template <class T, int K, int G>
-__device__ __forceinline__ void group_row(const CsrG &A, int64_t r, int gl, const T *__restrict__ x, T (&acc)[K]) {
+template <class T, int K, int G, bool ZS = false>
+__device__ __forceinline__ void group_row(const CsrG &A, int64_t r, int gl, const T *__restrict__ x, T (&acc)[K],
+                                          int64_t zlim = 0) {
   const int32_t b = A.ptr[r], e = A.ptr[r + 1];
   const T *__restrict__ vals = csr_vals<T>(A);
 #pragma unroll
@@ -305,9 +315,12 @@ __device__ __forceinline__ void group_row(const CsrG &A, int64_t r, int gl, cons
 #pragma unroll 2
   for (int j = b + gl; j < e; j += G) {
     const T v = vals[j];
-    const Row<T, K> xc = ld<T, K>(x, A.col[j]);
+    const int32_t c = A.col[j];
+    if (!ZS || c < zlim) {
+      const Row<T, K> xc = ld<T, K>(x, c);
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] += v * xc.v[k];
+      for (int k = 0; k < K; ++k) acc[k] += v * xc.v[k];
+    }
   }
 #pragma unroll
   for (int o = G / 2; o > 0; o >>= 1) {
@@ -321,8 +334,9 @@ __device__ __forceinline__ void group_row(const CsrG &A, int64_t r, int gl, cons
 // that each XCD works on a contiguous range of rows and the vector values
 // those rows gather stay in that XCD's L2.  MODE 0: y = A x, 1: y = g - A x (square); 2: y = P x, 3: y += P x;
 // 4: one Gauss-Seidel step y_r = (g_r - sum_j a_rj x_j) / a_rr (y = x).
-template <class T, int K, int G, int MODE>
-__device__ __forceinline__ void csr_row_op(const CsrG &A, int64_t r, int gl, const T *x, const T *g, T *y) {
+template <class T, int K, int G, int MODE, bool ZS = false>
+__device__ __forceinline__ void csr_row_op(const CsrG &A, int64_t r, int gl, const T *x, const T *g, T *y,
+                                           int64_t zlim = 0) {
   // the row's own operands are loaded first, so that their latency overlaps
   // the row-pointer -> entries -> gathered values chain of group_row
   Row<T, K> gr, xr, yr;
@@ -337,7 +351,7 @@ __device__ __forceinline__ void csr_row_op(const CsrG &A, int64_t r, int gl, con
       dr = A.s32[r];
   }
   T acc[K];
-  group_row<T, K, G>(A, r, gl, x, acc);  // off-diagonal part only
+  group_row<T, K, G, ZS>(A, r, gl, x, acc, zlim);  // off-diagonal part only
   if (gl != 0) return;
   Row<T, K> out;
   if (MODE == 4) {
@@ -383,14 +397,14 @@ __global__ __launch_bounds__(kWave) void k_csr_spmv(CsrG A, int64_t r0, int64_t 
   csr_row_op<T, K, G, MODE>(A, r, gl, x, g, y);
 }
 
-template <class T, int K, int G>
+template <class T, int K, int G, bool ZS>
 __global__ __launch_bounds__(kWave) void k_csr_gs(CsrG A, int64_t r0, int64_t r1, const T *__restrict__ g,
-                                                   T *__restrict__ x, const int *__restrict__ done) {
+                                                   T *__restrict__ x, const int *__restrict__ done, int64_t zlim) {
   if (done && *done) return;
   const int gl = threadIdx.x & (G - 1);
   const int64_t r = r0 + (xcd_block(blockIdx.x, gridDim.x) * kWave + threadIdx.x) / G;
   if (r >= r1) return;
-  csr_row_op<T, K, G, 4>(A, r, gl, x, g, x);
+  csr_row_op<T, K, G, 4, ZS>(A, r, gl, x, g, x, zlim);
 }
 
 // one wavefront per row of the dense FP64 coarsest inverse
@@ -934,7 +948,7 @@ static inline int64_t slices(int64_t r0, int64_t r1) {
 
 template <class T>
 void launch_gs(hipStream_t stm, int K, const Sell &A, int64_t a0, int64_t a1, int64_t b0, int64_t b1, const T *g,
-               T *x, const int *done) {
+               T *x, const int *done, ZeroStart zs) {
   GsDev<T> J{};
   J.x = x;
   const int64_t ra[2] = {a0, b0}, rb[2] = {a1, b1};
@@ -949,7 +963,12 @@ void launch_gs(hipStream_t stm, int K, const Sell &A, int64_t a0, int64_t a1, in
     ++J.n;
   }
   if (!J.nbt) return;
-  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_gs<T, KK>), grid(J.nbt), dim3(kWave), 0, stm, A, J, g, done))
+  VEMG_K_SWITCH(K, {
+    if (zs.on)
+      hipLaunchKernelGGL((k_gs<T, KK, true>), grid(J.nbt), dim3(kWave), 0, stm, A, J, g, done, zs);
+    else
+      hipLaunchKernelGGL((k_gs<T, KK, false>), grid(J.nbt), dim3(kWave), 0, stm, A, J, g, done, zs);
+  })
 }
 
 template <class T>
@@ -1009,12 +1028,18 @@ void launch_csr_rect(hipStream_t stm, int K, const CsrG &P, bool accumulate, con
 }
 
 template <class T>
-void launch_csr_gs(hipStream_t stm, int K, const CsrG &A, int64_t r0, int64_t r1, const T *g, T *x, const int *done) {
+void launch_csr_gs(hipStream_t stm, int K, const CsrG &A, int64_t r0, int64_t r1, const T *g, T *x, const int *done,
+                   int64_t zlim) {
   int64_t rows = r1 - r0;
   if (rows <= 0) return;
   int64_t nb = (rows * A.G + kWave - 1) / kWave;
-  VEMG_K_SWITCH(K, VEMG_G_SWITCH(A.G, hipLaunchKernelGGL((k_csr_gs<T, KK, GG>), grid(nb), dim3(kWave), 0, stm, A,
-                                                          r0, r1, g, x, done)))
+  VEMG_K_SWITCH(K, VEMG_G_SWITCH(A.G, {
+    if (zlim >= 0)
+      hipLaunchKernelGGL((k_csr_gs<T, KK, GG, true>), grid(nb), dim3(kWave), 0, stm, A, r0, r1, g, x, done, zlim);
+    else
+      hipLaunchKernelGGL((k_csr_gs<T, KK, GG, false>), grid(nb), dim3(kWave), 0, stm, A, r0, r1, g, x, done,
+                         int64_t(0));
+  }))
 }
 
 template <class T>
@@ -1118,13 +1143,14 @@ void launch_pcg_resume(hipStream_t stm, int, Scal *s, unsigned keep) {
   template void launch_spmv<T>(hipStream_t, int, const Sell &, int, int64_t, int64_t, const T *, const T *, T *,      \
                                double *, const int *);                                                               \
   template void launch_gs<T>(hipStream_t, int, const Sell &, int64_t, int64_t, int64_t, int64_t, const T *, T *,       \
-                             const int *);                                                                           \
+                             const int *, ZeroStart);                                                                \
   template void launch_rect<T>(hipStream_t, int, const Sell &, bool, const T *, T *, const int *);                    \
   template void launch_prolong_sum<T>(hipStream_t, int, const Sell &, int64_t, const T *, const T *, const T *, T *,   \
                                       double *, const int *);                                                        \
   template void launch_csr_spmv<T>(hipStream_t, int, const CsrG &, int, int64_t, int64_t, const T *, const T *, T *,   \
                                    const int *);                                                                     \
-  template void launch_csr_gs<T>(hipStream_t, int, const CsrG &, int64_t, int64_t, const T *, T *, const int *);      \
+  template void launch_csr_gs<T>(hipStream_t, int, const CsrG &, int64_t, int64_t, const T *, T *, const int *,       \
+                                 int64_t);                                                                           \
   template void launch_csr_rect<T>(hipStream_t, int, const CsrG &, bool, const T *, T *, const int *);                \
   template void launch_dense<T>(hipStream_t, int, const double *, int64_t, const T *, T *, const int *);              \
   template void launch_fill<T>(hipStream_t, T *, int64_t, T, const int *);                                           \

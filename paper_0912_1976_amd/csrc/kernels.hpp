@@ -79,9 +79,17 @@ void launch_spmv(hipStream_t st, int K, const Sell &A, int mode, int64_t r0, int
                  T *y, double *partial, const int *done);
 // One multicolour Gauss-Seidel step on the rows [a0,a1) and [b0,b1) (rows of
 // one colour): x_i += (g_i - (A x)_i) / a_ii.
+// Zero start (the first sweep from x = 0): of the top block (j < n_top) only
+// the columns j < top_lim are read, of the rest only j < bar_lim; every other
+// value (the colours not swept yet, and the row's own) is taken as zero
+// without being read, so x needs no fill beforehand.
+struct ZeroStart {
+  bool on = false;
+  int64_t n_top = 0, top_lim = 0, bar_lim = 0;
+};
 template <class T>
 void launch_gs(hipStream_t st, int K, const Sell &A, int64_t a0, int64_t a1, int64_t b0, int64_t b1, const T *g,
-               T *x, const int *done);
+               T *x, const int *done, ZeroStart zs = ZeroStart());
 // y = E x (accumulate: y += E x) for a rectangular SELL matrix, rows [0, nrows).
 template <class T>
 void launch_rect(hipStream_t st, int K, const Sell &E, bool accumulate, const T *x, T *y, const int *done);
@@ -95,8 +103,11 @@ void launch_prolong_sum(hipStream_t st, int K, const Sell &E, int64_t n_top, con
 template <class T>
 void launch_csr_spmv(hipStream_t st, int K, const CsrG &A, int mode, int64_t r0, int64_t r1, const T *x,
                      const T *g, T *y, const int *done);
+// zlim >= 0: zero start, only columns j < zlim (the colours swept before) are
+// read and the rest taken as zero
 template <class T>
-void launch_csr_gs(hipStream_t st, int K, const CsrG &A, int64_t r0, int64_t r1, const T *g, T *x, const int *done);
+void launch_csr_gs(hipStream_t st, int K, const CsrG &A, int64_t r0, int64_t r1, const T *g, T *x, const int *done,
+                   int64_t zlim = -1);
 template <class T>
 void launch_csr_rect(hipStream_t st, int K, const CsrG &P, bool accumulate, const T *x, T *y, const int *done);
 // x = Cinv g (dense m x m FP64, row-major), K columns.
