@@ -106,9 +106,9 @@ def kernel_rates(s, info, vemg, K=1, reps=20):
 #   vl_add: both V-cycles without the SOR cycle plus the CG product
 PER_ITERATION = {"vl_as": (4, 3, 4), "vl_sor": (2, 2, 2), "vl_add": (2, 2, 4), "jacobi": (0, 1, 0),
                  "none": (0, 1, 0)}
-KERNEL_NAMES = {"gs": "k_gs<double, 1> (fine multicolour SOR, one colour per launch)",
+KERNEL_NAMES = {"gs": "k_gs<double, 1, false> (fine multicolour SOR, one colour per launch)",
                 "spmv": "k_spmv<double, 1, 0, true> (fine difference-form SpMV fused with p.q)",
-                "cgs": "k_csr_gs<double, 1, 32> (coarse multicolour SOR, one colour per launch)"}
+                "cgs": "k_csr_gs<double, 1, 32, false> (coarse multicolour SOR, one colour per launch)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
 
@@ -164,8 +164,8 @@ def profile_kernels(workload):
 
 
 CALIBRATION_BYTES = 512 << 20
-PMC_KERNELS = {"gs": "k_gs<double, 1>", "spmv": "k_spmv<double, 1, 0, true>", "cgs": "k_csr_gs<double, 1, 32>",
-               "calibration": "MulFunctor"}
+PMC_KERNELS = {"gs": "k_gs<double, 1, false>", "spmv": "k_spmv<double, 1, 0, true>",
+               "cgs": "k_csr_gs<double, 1, 32, false>", "calibration": "MulFunctor"}
 
 
 def _pmc_means(path, counter):
