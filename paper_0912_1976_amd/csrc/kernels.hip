@@ -112,8 +112,22 @@ __device__ __forceinline__ void sell_row(const Sell &A, int64_t s, int lane, con
   for (int e = 0; e < len; ++e) {
     const int32_t c = cp[(int64_t)e * 64];
     const T v = vp[(int64_t)e * 64];
-    if (!ZS || c < (c < z.n_top ? z.top_lim : z.bar_lim)) {
-      const Row<T, K> xc = ld<T, K>(x, c);
+    if constexpr (ZS && K > 2) {
+      // wide rows: the gathers of colours not swept yet are skipped
+      if (c < (c < z.n_top ? z.top_lim : z.bar_lim)) {
+        const Row<T, K> xc = ld<T, K>(x, c);
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += DIFF ? v * (xc.v[k] - xr.v[k]) : v * xc.v[k];
+      }
+    } else {
+      // narrow rows: load every entry (the loads stay pipelined) and zero
+      // the ones not swept yet
+      Row<T, K> xc = ld<T, K>(x, c);
+      if constexpr (ZS) {
+        const bool live = c < (c < z.n_top ? z.top_lim : z.bar_lim);
+#pragma unroll
+        for (int k = 0; k < K; ++k) xc.v[k] = live ? xc.v[k] : T(0);
+      }
 #pragma unroll
       for (int k = 0; k < K; ++k) acc[k] += DIFF ? v * (xc.v[k] - xr.v[k]) : v * xc.v[k];
     }
@@ -316,8 +330,18 @@ __device__ __forceinline__ void group_row(const CsrG &A, int64_t r, int gl, cons
   for (int j = b + gl; j < e; j += G) {
     const T v = vals[j];
     const int32_t c = A.col[j];
-    if (!ZS || c < zlim) {
-      const Row<T, K> xc = ld<T, K>(x, c);
+    if constexpr (ZS && K > 2) {
+      if (c < zlim) {
+        const Row<T, K> xc = ld<T, K>(x, c);
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += v * xc.v[k];
+      }
+    } else {
+      Row<T, K> xc = ld<T, K>(x, c);
+      if constexpr (ZS) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) xc.v[k] = c < zlim ? xc.v[k] : T(0);
+      }
 #pragma unroll
       for (int k = 0; k < K; ++k) acc[k] += v * xc.v[k];
     }
