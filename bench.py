@@ -16,6 +16,11 @@ smoothed aggregation against the lumping method at three aspect ratios, the
 projected vs SSPAI-refitted extrapolation, the 257 x 257 x 33 and graded
 multiscale configurations, live kernel timings for the roofline, and the
 CPU oracle on a bounded sample of the headline solve.
+
+Profiling helpers (no GPU): --pmc-summary and --pmc-traffic read rocprofv3
+counter passes (FETCH_SIZE, WRITE_SIZE) of --profile-kernels runs;
+--trace-timed reads a kernel trace of a bench run and averages the hot
+kernels' dispatches over the live timing after the solves.
 """
 from __future__ import annotations
 
@@ -209,6 +214,39 @@ def pmc_traffic(fetch_dir, write_dir, workload):
             rec["kernels"][key] = {"kernel": KERNEL_NAMES[key], "fetch_kib": fetch[key], "write_kib": write[key],
                                    "hbm_bytes_per_launch": 1024.0 * (fetch[key] / ff + write[key] / wf)}
     print(json.dumps(rec, indent=1))
+
+
+def trace_timed(path):
+    """Mean dispatch duration of each hot kernel over the live timing that
+    follows the solves (its last run of consecutive dispatches, fills between
+    them allowed), from a rocprofv3 kernel-trace CSV: the figure to set beside
+    the per-launch times bench.py measures with HIP events."""
+    import csv
+    import glob
+    files = [path] if path.endswith(".csv") else glob.glob(os.path.join(path, "**", "*kernel_trace.csv"),
+                                                          recursive=True)
+    rows = []
+    for f in files:
+        with open(f, newline="") as fh:
+            rows += [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]) for r in csv.DictReader(fh)]
+    rows.sort()
+    out = {}
+    for key in ("spmv", "gs", "cgs"):
+        pat = PMC_KERNELS[key]
+        run, last = [], []
+        for t0, t1, name in rows:
+            if pat in name:
+                run.append(t1 - t0)
+            elif "k_fill<" not in name:
+                if run:
+                    last = run
+                run = []
+        if run:
+            last = run
+        if last:
+            out[key] = {"kernel": KERNEL_NAMES[key], "dispatches": len(last),
+                        "mean_us": sum(last) / len(last) / 1e3}
+    print(json.dumps(out, indent=1))
 
 
 def pmc_summary(paths):
@@ -517,11 +555,16 @@ def main():
                     help="run only the hot kernels and a copy calibration (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-summary", nargs="+", metavar="DIR_OR_CSV",
                     help="summarise rocprofv3 counter-collection output and exit (no GPU)")
+    ap.add_argument("--trace-timed", metavar="DIR_OR_CSV",
+                    help="mean trace duration of the hot kernels over the live timing after the solves (no GPU)")
     ap.add_argument("--pmc-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="per-launch HBM bytes of the hot kernels from the two PMC passes, as JSON (no GPU)")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args.pmc_summary)
+        return
+    if args.trace_timed:
+        trace_timed(args.trace_timed)
         return
     if args.pmc_traffic:
         pmc_traffic(*args.pmc_traffic, args.workload)

@@ -1,0 +1,95 @@
+"""Host-side logic of bench.py: the one-GPU guard, the PMC traffic arithmetic
+and the trace summary, on small synthetic rocprofv3 CSV files (no GPU)."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def _run(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], capture_output=True, text=True,
+                          cwd=ROOT, timeout=120)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = _run("--gpus", "2")
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def _counter_csv(path, counter, rows):
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, "run_counter_collection.csv"), "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Kernel_Name", "Counter_Name", "Counter_Value"])
+        for name, value in rows:
+            w.writerow([name, counter, value])
+
+
+def test_pmc_traffic_divides_each_counter_by_its_calibration(tmp_path, capsys):
+    kib = bench.CALIBRATION_BYTES / 1024.0
+    cal = "void at::native::vectorized_elementwise_kernel<4, at::native::MulFunctor<double> >"
+    gs = "void vemg::(anonymous namespace)::k_gs<double, 1, false>(vemg::Sell, ...)"
+    gs_zero = "void vemg::(anonymous namespace)::k_gs<double, 1, true>(vemg::Sell, ...)"
+    spmv = "void vemg::(anonymous namespace)::k_spmv<double, 1, 0, true>(vemg::Sell, ...)"
+    # FETCH reads half the true bytes, WRITE all of them; two dispatches per kernel
+    _counter_csv(str(tmp_path / "f"), "FETCH_SIZE",
+                 [(cal, 0.5 * kib), (cal, 0.5 * kib), (gs, 100.0), (gs, 300.0), (gs_zero, 1e6), (spmv, 50.0)])
+    _counter_csv(str(tmp_path / "w"), "WRITE_SIZE",
+                 [(cal, kib), (gs, 10.0), (gs, 30.0), (gs_zero, 1e6), (spmv, 5.0)])
+    bench.pmc_traffic(str(tmp_path / "f"), str(tmp_path / "w"), "thinbox-129x129x33-eps1e-3")
+    rec = json.loads(capsys.readouterr().out)
+    assert rec["source_hash"] == bench._kernel_source_hash()
+    assert rec["calibration"]["fetch_factor"] == pytest.approx(0.5)
+    assert rec["calibration"]["write_factor"] == pytest.approx(1.0)
+    k = rec["kernels"]
+    # the zero-start sweep is not the general form and is not counted
+    assert k["gs"]["fetch_kib"] == pytest.approx(200.0)
+    assert k["gs"]["hbm_bytes_per_launch"] == pytest.approx(1024.0 * (200.0 / 0.5 + 20.0))
+    assert k["spmv"]["hbm_bytes_per_launch"] == pytest.approx(1024.0 * (100.0 + 5.0))
+    assert "cgs" not in k
+
+
+def test_trace_timed_takes_the_last_run_of_each_kernel(tmp_path, capsys):
+    cgs = "void vemg::(anonymous namespace)::k_csr_gs<double, 1, 32, false>(vemg::CsrG, ...)"
+    cgs_zero = "void vemg::(anonymous namespace)::k_csr_gs<double, 1, 32, true>(vemg::CsrG, ...)"
+    fill = "void vemg::(anonymous namespace)::k_fill<double>(double*, long, double, int const*)"
+    other = "vemg::(anonymous namespace)::k_pcg_alpha(...)"
+    rows, t = [], 0
+
+    def add(name, dur):
+        nonlocal t
+        rows.append((name, t, t + dur))
+        t += dur + 1000
+
+    # the solve: sweeps interleaved with other kernels
+    for _ in range(3):
+        add(cgs_zero, 9000)
+        add(cgs, 7000)
+        add(other, 2000)
+    # the live timing: a fill, then back-to-back general sweeps
+    add(fill, 500)
+    for d in (3000, 3200, 3400):
+        add(cgs, d)
+    add(fill, 500)
+    add(cgs, 3400)
+    path = tmp_path / "run_kernel_trace.csv"
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        # rows out of order on purpose: the summary sorts by start time
+        for name, t0, t1 in reversed(rows):
+            w.writerow([name, t0, t1])
+    bench.trace_timed(str(tmp_path))
+    out = json.loads(capsys.readouterr().out)
+    assert set(out) == {"cgs"}
+    assert out["cgs"]["dispatches"] == 4
+    assert out["cgs"]["mean_us"] == pytest.approx(3.25)
