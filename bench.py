@@ -142,10 +142,10 @@ def measured_traffic(kernel_key, workload):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def profile_kernels(workload):
-    """The hot kernels of one PCG iteration, each repeated, plus a plain
-    copy of known size (the calibration of the PMC byte counters): the
-    command profiled by the rocprofv3 --pmc passes."""
+def profile_kernels(workload, K=1):
+    """The hot kernels of one PCG iteration for K right-hand sides, each
+    repeated, plus a plain copy of known size (the calibration of the PMC
+    byte counters): the command profiled by the rocprofv3 --pmc passes."""
     import torch
 
     import paper_0912_1976_amd as vemg
@@ -157,8 +157,8 @@ def profile_kernels(workload):
     s = vemg.Solver(mesh.xyz, mesh.tets, mesh.top, top_bc="pinned", pc="vl_as", device=0)
     info = s.info()
     for name, op in (("fine sweep", vemg.OP_GS_FWD), ("fine spmv", vemg.OP_A), ("coarse sweep", vemg.OP_GS_COARSE)):
-        ms, nl = s.time_op(op, reps=10)
-        print(f"[profile] {name}: {ms:.4f} ms per application, {nl} launches", flush=True)
+        ms, nl = s.time_op(op, reps=10, nrhs=K)
+        print(f"[profile] {name} (K={K}): {ms:.4f} ms per application, {nl} launches", flush=True)
     a = torch.ones(CALIBRATION_BYTES // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
@@ -551,6 +551,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline solve and roofline only")
     ap.add_argument("--serve-requests", type=int, default=96)
     ap.add_argument("--no-configs", action="store_true", help="skip the full-size 257^2 and graded configurations")
+    ap.add_argument("--profile-batch", type=int, default=1, choices=(1, 2, 4, 8),
+                    help="right-hand sides per launch for --profile-kernels")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="run only the hot kernels and a copy calibration (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-summary", nargs="+", metavar="DIR_OR_CSV",
@@ -575,7 +577,7 @@ def main():
         sys.exit(2)
 
     if args.profile_kernels:
-        profile_kernels(args.workload)
+        profile_kernels(args.workload, args.profile_batch)
         return
 
     import numpy as np
