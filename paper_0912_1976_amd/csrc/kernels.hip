@@ -438,8 +438,27 @@ __device__ __forceinline__ void dense_row(const double *__restrict__ C, int64_t 
   double t[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) t[k] = 0.0;
-  for (int64_t j = lane; j < m; j += 64) {
-    const double c = C[i * m + j];
+  // U entries per lane are loaded before they are added (in the same order
+  // as one at a time), so that U loads are in flight instead of one
+  constexpr int U = K >= 4 ? 2 : 8 / K;
+  const double *__restrict__ Ci = C + i * m;
+  int64_t j = lane;
+  for (; j + (U - 1) * 64 < m; j += U * 64) {
+    double c[U];
+    Row<T, K> gj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[u] = Ci[j + u * 64];
+      gj[u] = ld<T, K>(g, j + u * 64);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) t[k] += c[u] * (double)gj[u].v[k];
+    }
+  }
+  for (; j < m; j += 64) {
+    const double c = Ci[j];
     const Row<T, K> gj = ld<T, K>(g, j);
 #pragma unroll
     for (int k = 0; k < K; ++k) t[k] += c * (double)gj.v[k];
@@ -568,18 +587,19 @@ __device__ __forceinline__ void sum_partials(const double *__restrict__ p, int64
   double t[kMaxBatch];
 #pragma unroll
   for (int k = 0; k < kMaxBatch; ++k) t[k] = 0.0;
-  // four of each thread's partials are loaded before any is added, so that a
-  // thread keeps four loads per column in flight; the additions keep the
+  // eight of each thread's partials are loaded before any is added, so that
+  // a thread keeps eight loads per column in flight; the additions keep the
   // order j = tid, tid + kBlock, ...
+  constexpr int U = 8;
   int64_t j = threadIdx.x;
-  for (; j + 3 * kBlock < np; j += 4 * kBlock) {
-    double v[4][kMaxBatch];
+  for (; j + (U - 1) * kBlock < np; j += U * kBlock) {
+    double v[U][kMaxBatch];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int k = 0; k < kMaxBatch; ++k) v[u][k] = (k < K) ? p[(j + u * kBlock) * K + k] : 0.0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int k = 0; k < kMaxBatch; ++k)
         if (k < K) t[k] += v[u][k];
