@@ -113,7 +113,9 @@ PER_ITERATION = {"vl_as": (4, 3, 4), "vl_sor": (2, 2, 2), "vl_add": (2, 2, 4), "
                  "none": (0, 1, 0)}
 KERNEL_NAMES = {"gs": "k_gs<double, 1, false> (fine multicolour SOR, one colour per launch)",
                 "spmv": "k_spmv<double, 1, 0, true> (fine difference-form SpMV fused with p.q)",
-                "cgs": "k_csr_gs<double, 1, 32, false> (coarse multicolour SOR, one colour per launch)"}
+                "cgs": "k_csr_gs<double, 1, 32, false> (coarse multicolour SOR, one colour per launch)",
+                "et": "k_csr_spmv<double, 1, 64, 2> (restriction E~^T, CSR, 64 lanes per surface row)",
+                "e": "k_rect<double, 1, true> (prolongation z += E~ y, SELL, one thread per fine row)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
 
@@ -156,7 +158,8 @@ def profile_kernels(workload, K=1):
                     bathymetry=wl["bathymetry"])
     s = vemg.Solver(mesh.xyz, mesh.tets, mesh.top, top_bc="pinned", pc="vl_as", device=0)
     info = s.info()
-    for name, op in (("fine sweep", vemg.OP_GS_FWD), ("fine spmv", vemg.OP_A), ("coarse sweep", vemg.OP_GS_COARSE)):
+    for name, op in (("fine sweep", vemg.OP_GS_FWD), ("fine spmv", vemg.OP_A), ("coarse sweep", vemg.OP_GS_COARSE),
+                     ("restriction E~^T", vemg.OP_ET), ("prolongation E~", vemg.OP_E)):
         ms, nl = s.time_op(op, reps=10, nrhs=K)
         print(f"[profile] {name} (K={K}): {ms:.4f} ms per application, {nl} launches", flush=True)
     a = torch.ones(CALIBRATION_BYTES // 8, dtype=torch.float64, device="cuda")
@@ -170,7 +173,8 @@ def profile_kernels(workload, K=1):
 
 CALIBRATION_BYTES = 512 << 20
 PMC_KERNELS = {"gs": "k_gs<double, 1, false>", "spmv": "k_spmv<double, 1, 0, true>",
-               "cgs": "k_csr_gs<double, 1, 32, false>", "calibration": "MulFunctor"}
+               "cgs": "k_csr_gs<double, 1, 32, false>", "et": "k_csr_spmv<double, 1, 64, 2>",
+               "e": "k_rect<double, 1, true>", "calibration": "MulFunctor"}
 
 
 def _pmc_means(path, counter):
@@ -209,7 +213,7 @@ def pmc_traffic(fetch_dir, write_dir, workload):
                         f"python3 -u bench.py --profile-kernels --workload {workload}",
                         f"python3 bench.py --pmc-traffic {fetch_dir} {write_dir} --workload {workload}"],
            "kernels": {}}
-    for key in ("gs", "spmv", "cgs"):
+    for key in ("gs", "spmv", "cgs", "et", "e"):
         if key in fetch and key in write:
             rec["kernels"][key] = {"kernel": KERNEL_NAMES[key], "fetch_kib": fetch[key], "write_kib": write[key],
                                    "hbm_bytes_per_launch": 1024.0 * (fetch[key] / ff + write[key] / wf)}

@@ -18,6 +18,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <numeric>
 #include <thread>
 #include <memory>
 #include <string>
@@ -150,7 +151,13 @@ Sell pack_sell(Arena &ar, hipStream_t st, const Csr &A, bool square, const std::
 // CSR (host) -> CsrG (device).  Square matrices keep only off-diagonals
 // (FP64 values with d64 = a_ii; FP32 values a_ij / a_ii with s32 = a_ii).
 // G = smallest power of two >= half the mean row length, clamped to [4, 64].
-CsrG pack_csrg(Arena &ar, hipStream_t st, const Csr &A, bool square, int64_t *stored = nullptr) {
+// With colkey (rectangular operators gathering from the fine level: the
+// spatial rank of column c is (*colkey)[c + coloff]) the rows are stored in
+// the order of their smallest column rank and orow maps them back, so that
+// the rows one XCD works on gather from one region of the fine vector; each
+// row keeps its entries and their order.
+CsrG pack_csrg(Arena &ar, hipStream_t st, const Csr &A, bool square, int64_t *stored = nullptr,
+               const std::vector<int64_t> *colkey = nullptr, int64_t coloff = 0) {
   std::vector<int32_t> ptr(A.nrows + 1, 0), col;
   std::vector<double> val, d(square ? A.nrows : 0, 0.0);
   std::vector<float> val32;
@@ -159,14 +166,24 @@ CsrG pack_csrg(Arena &ar, hipStream_t st, const Csr &A, bool square, int64_t *st
   for (int64_t r = 0; r < A.nrows && square; ++r)
     for (int64_t k = A.ptr[r]; k < A.ptr[r + 1]; ++k)
       if (A.idx[k] == r) d[r] = A.val[k];
-  for (int64_t r = 0; r < A.nrows; ++r) {
+  std::vector<int64_t> rows(A.nrows);
+  std::iota(rows.begin(), rows.end(), 0);
+  const bool permute = colkey != nullptr && !square;
+  if (permute) {
+    std::vector<int64_t> key(A.nrows, INT64_MAX);
+    for (int64_t r = 0; r < A.nrows; ++r)
+      for (int64_t k = A.ptr[r]; k < A.ptr[r + 1]; ++k) key[r] = std::min(key[r], (*colkey)[A.idx[k] + coloff]);
+    std::stable_sort(rows.begin(), rows.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+  }
+  for (int64_t i = 0; i < A.nrows; ++i) {
+    const int64_t r = rows[i];
     for (int64_t k = A.ptr[r]; k < A.ptr[r + 1]; ++k) {
       if (square && A.idx[k] == r) continue;
       col.push_back(A.idx[k]);
       val.push_back(A.val[k]);
       val32.push_back(square ? (float)(A.val[k] / d[r]) : (float)A.val[k]);
     }
-    ptr[r + 1] = (int32_t)col.size();
+    ptr[i + 1] = (int32_t)col.size();
   }
   double mean = A.nrows ? (double)col.size() / (double)A.nrows : 0.0;
   int G = 4;
@@ -179,6 +196,10 @@ CsrG pack_csrg(Arena &ar, hipStream_t st, const Csr &A, bool square, int64_t *st
   M.col = ar.upload(col, st);
   M.val64 = ar.upload(val, st);
   M.val32 = ar.upload(val32, st);
+  if (permute) {
+    std::vector<int32_t> orow(rows.begin(), rows.end());
+    M.orow = ar.upload(orow, st);
+  }
   if (square) {
     std::vector<float> s32(A.nrows);
     for (int64_t r = 0; r < A.nrows; ++r) s32[r] = (float)d[r];
@@ -321,7 +342,9 @@ void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, int 
         dl.Ps = pack_sell(h->ar, st, L.P, false, nullptr, nullptr);
       else
         dl.P = pack_csrg(h->ar, st, L.P, false);
-      dl.Pt = pack_csrg(h->ar, st, transpose(L.P), false);
+      // the fine level's restriction gathers from fine rows row0 + c
+      dl.Pt = dl.fine ? pack_csrg(h->ar, st, transpose(L.P), false, nullptr, &h->P.loc_rank, dl.row0)
+                      : pack_csrg(h->ar, st, transpose(L.P), false);
     } else {
       dl.Cinv = h->ar.upload(L.Cinv, st);
     }
@@ -899,7 +922,7 @@ void upload(Handle *h) {
   h->A = pack_sell(h->ar, st, P.Aoff, true, &P.d, &P.diag, &h->nnz_A);
   if (m > 0) {
     h->E = pack_sell(h->ar, st, P.E, false, nullptr, nullptr, &h->nnz_E);
-    h->Et = pack_csrg(h->ar, st, P.Et, false);
+    h->Et = pack_csrg(h->ar, st, P.Et, false, nullptr, &P.loc_rank, 0);
   }
   size_t cnt = (size_t)n * kMaxBatch;
   auto mk64 = [&](Work<double> &v) {

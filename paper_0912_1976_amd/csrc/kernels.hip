@@ -365,9 +365,14 @@ __device__ __forceinline__ void csr_row_op(const CsrG &A, int64_t r, int gl, con
   // the row-pointer -> entries -> gathered values chain of group_row
   Row<T, K> gr, xr, yr;
   T dr = T(0);
+  // output row of a rectangular operator (its stored rows may be permuted)
+  int64_t ro = r;
+  if constexpr (MODE == 2 || MODE == 3) {
+    if (A.orow) ro = A.orow[r];
+  }
   if (MODE == 1 || MODE == 4) gr = ld<T, K>(g, r);
   if (MODE <= 1) xr = ld<T, K>(x, r);
-  if (MODE == 3) yr = ld<T, K>(y, r);
+  if (MODE == 3) yr = ld<T, K>(y, ro);
   if (MODE <= 1 || MODE == 4) {
     if constexpr (std::is_same<T, double>::value)
       dr = A.d64[r];
@@ -407,7 +412,7 @@ __device__ __forceinline__ void csr_row_op(const CsrG &A, int64_t r, int gl, con
 #pragma unroll
     for (int k = 0; k < K; ++k) out.v[k] += acc[k];
   }
-  st<T, K>(y, r, out);
+  st<T, K>(y, ro, out);
 }
 
 template <class T, int K, int G, int MODE>

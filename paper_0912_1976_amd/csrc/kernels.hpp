@@ -50,6 +50,9 @@ struct CsrG {
   const float *val32 = nullptr;
   const double *d64 = nullptr;
   const float *s32 = nullptr;
+  // rectangular operators only: stored row i is output row orow[i] (the rows
+  // are stored in the spatial order of the columns they gather); null: i
+  const int32_t *orow = nullptr;
   int64_t nrows = 0;
   int G = 4;
 };

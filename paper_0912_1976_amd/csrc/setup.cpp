@@ -802,6 +802,12 @@ void build_problem(Problem &P, const SetupOptions &opt, int64_t n_nodes, const d
     P.perm[s] = U[order[s]];
     P.pos[P.perm[s]] = s;
   }
+  {
+    std::vector<int64_t> rank_u(n);
+    for (int64_t k = 0; k < n; ++k) rank_u[loc[k]] = k;
+    P.loc_rank.resize(n);
+    for (int64_t s = 0; s < n; ++s) P.loc_rank[s] = rank_u[order[s]];
+  }
   P.n_top = 0;
   for (int64_t s = 0; s < n; ++s) P.n_top += P.top[P.perm[s]];
   P.Aoff = permute_sym(Auu, order);

@@ -52,6 +52,7 @@ struct Problem {
   std::vector<uint8_t> top;
   std::vector<int64_t> perm;          // storage position -> natural node
   std::vector<int64_t> pos;           // natural node -> storage position (-1: fixed)
+  std::vector<int64_t> loc_rank;      // storage position -> rank in the spatial (colour-blind) order
   Csr Aoff;                           // off-diagonals of A_UU, storage order
   std::vector<double> d;              // deficit d_i = -sum_{j fixed} a_ij
   std::vector<double> diag;           // a_ii = d_i - sum_j a_ij
