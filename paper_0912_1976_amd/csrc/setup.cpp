@@ -371,29 +371,43 @@ void spd_inverse(std::vector<double> &M, int64_t n) {
       L[i * n + j] = t / ljj;
     }
   }
-  // W = L^{-1} (lower triangular): row i = (e_i - sum_{k<i} L_ik W_k) / L_ii
+  // W = L^{-1} (lower triangular): row i = (e_i - sum_{k<i} L_ik W_k) / L_ii.
+  // Column blocks of W are independent; each thread takes every nt-th block
+  // of 32 columns and updates them in the serial order (k ascending).
   std::vector<double> W(n * n, 0.0);
-  for (int64_t i = 0; i < n; ++i) {
-    double *wi = &W[i * n];
-    wi[i] = 1.0;
-    for (int64_t k = 0; k < i; ++k) {
-      double l = L[i * n + k];
-      const double *wk = &W[k * n];
-      for (int64_t j = 0; j <= k; ++j) wi[j] -= l * wk[j];
+  constexpr int64_t kCols = 32;
+  const int64_t nblk = (n + kCols - 1) / kCols;
+  parallel_threads(n * n * n / 6, [&](int t, int nt) {
+    for (int64_t b = t; b < nblk; b += nt) {
+      const int64_t j0 = b * kCols, j1 = std::min(n, j0 + kCols);
+      for (int64_t i = j0; i < n; ++i) {
+        double *wi = &W[i * n];
+        if (i < j1) wi[i] = 1.0;
+        for (int64_t k = j0; k < i; ++k) {
+          double l = L[i * n + k];
+          const double *wk = &W[k * n];
+          const int64_t je = std::min(j1, k + 1);
+          for (int64_t j = j0; j < je; ++j) wi[j] -= l * wk[j];
+        }
+        double inv = 1.0 / L[i * n + i];
+        const int64_t je = std::min(j1, i + 1);
+        for (int64_t j = j0; j < je; ++j) wi[j] *= inv;
+      }
     }
-    double inv = 1.0 / L[i * n + i];
-    for (int64_t j = 0; j <= i; ++j) wi[j] *= inv;
-  }
-  // A^{-1} = W^T W: accumulate the outer product of every row of W
+  });
+  // A^{-1} = W^T W: M_ij = sum over k >= max(i, j), ascending, of W_ki W_kj.
+  // Rows of M are independent; each thread takes every nt-th row.
   std::fill(M.begin(), M.end(), 0.0);
-  for (int64_t k = 0; k < n; ++k) {
-    const double *wk = &W[k * n];
-    for (int64_t i = 0; i <= k; ++i) {
-      double a = wk[i];
+  parallel_threads(n * n * n / 6, [&](int t, int nt) {
+    for (int64_t i = t; i < n; i += nt) {
       double *mi = &M[i * n];
-      for (int64_t j = 0; j <= k; ++j) mi[j] += a * wk[j];
+      for (int64_t k = i; k < n; ++k) {
+        const double *wk = &W[k * n];
+        double a = wk[i];
+        for (int64_t j = 0; j <= k; ++j) mi[j] += a * wk[j];
+      }
     }
-  }
+  });
 }
 
 // The sparse approximate inverse alternative to the projection (Section 5.4,

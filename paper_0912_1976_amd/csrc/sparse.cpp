@@ -72,48 +72,65 @@ Csr spgemm(const Csr &A, const Csr &B) {
   C.nrows = A.nrows;
   C.ncols = B.ncols;
   C.ptr.assign(C.nrows + 1, 0);
-  std::vector<int64_t> mark(B.ncols, -1);
-  std::vector<double> acc(B.ncols, 0.0);
-  std::vector<int32_t> cols;
-  // pass 1: pattern size
-  for (int64_t i = 0; i < A.nrows; ++i) {
-    int64_t cnt = 0;
-    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
-      int64_t r = A.idx[k];
-      for (int64_t l = B.ptr[r]; l < B.ptr[r + 1]; ++l)
-        if (mark[B.idx[l]] != i) {
-          mark[B.idx[l]] = i;
-          ++cnt;
-        }
+  // rows are shared among threads in contiguous blocks; each row is formed
+  // by one thread exactly as in a serial pass
+  auto block = [&](int t, int nt, int64_t &i0, int64_t &i1) {
+    i0 = A.nrows * t / nt;
+    i1 = A.nrows * (t + 1) / nt;
+  };
+  const int64_t work = A.nnz() + B.nnz();
+  // pass 1: pattern size of every row
+  parallel_threads(work, [&](int t, int nt) {
+    int64_t i0, i1;
+    block(t, nt, i0, i1);
+    std::vector<int64_t> mark(B.ncols, -1);
+    for (int64_t i = i0; i < i1; ++i) {
+      int64_t cnt = 0;
+      for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+        int64_t r = A.idx[k];
+        for (int64_t l = B.ptr[r]; l < B.ptr[r + 1]; ++l)
+          if (mark[B.idx[l]] != i) {
+            mark[B.idx[l]] = i;
+            ++cnt;
+          }
+      }
+      C.ptr[i + 1] = cnt;
     }
-    C.ptr[i + 1] = C.ptr[i] + cnt;
-  }
+  });
+  for (int64_t i = 0; i < C.nrows; ++i) C.ptr[i + 1] += C.ptr[i];
   C.idx.resize(C.ptr.back());
   C.val.resize(C.ptr.back());
-  std::fill(mark.begin(), mark.end(), -1);
-  for (int64_t i = 0; i < A.nrows; ++i) {
-    cols.clear();
-    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
-      int64_t r = A.idx[k];
-      double a = A.val[k];
-      for (int64_t l = B.ptr[r]; l < B.ptr[r + 1]; ++l) {
-        int32_t c = B.idx[l];
-        if (mark[c] != i) {
-          mark[c] = i;
-          acc[c] = 0.0;
-          cols.push_back(c);
+  // pass 2: values, accumulated in the order of A's row and then B's rows
+  parallel_threads(work, [&](int t, int nt) {
+    int64_t i0, i1;
+    block(t, nt, i0, i1);
+    std::vector<int64_t> mark(B.ncols, -1);
+    std::vector<double> acc(B.ncols, 0.0);
+    std::vector<int32_t> cols;
+    for (int64_t i = i0; i < i1; ++i) {
+      cols.clear();
+      for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+        int64_t r = A.idx[k];
+        double a = A.val[k];
+        for (int64_t l = B.ptr[r]; l < B.ptr[r + 1]; ++l) {
+          int32_t c = B.idx[l];
+          if (mark[c] != i) {
+            mark[c] = i;
+            acc[c] = 0.0;
+            cols.push_back(c);
+          }
+          acc[c] += a * B.val[l];
         }
-        acc[c] += a * B.val[l];
+      }
+      std::sort(cols.begin(), cols.end());
+      int64_t p = C.ptr[i];
+      for (int32_t c : cols) {
+        C.idx[p] = c;
+        C.val[p] = acc[c];
+        ++p;
       }
     }
-    std::sort(cols.begin(), cols.end());
-    int64_t p = C.ptr[i];
-    for (int32_t c : cols) {
-      C.idx[p] = c;
-      C.val[p] = acc[c];
-      ++p;
-    }
-  }
+  });
   return C;
 }
 

@@ -3,10 +3,26 @@
 // structural pattern (entries that cancel to zero are stored).
 #pragma once
 
+#include <algorithm>
 #include <cstdint>
+#include <thread>
 #include <vector>
 
 namespace vemg {
+
+// Runs fn(t, nt) on nt host threads (t = 0 on the caller), nt at most 16 and
+// 1 when the work is small.  Every caller splits its work so that each
+// output element is computed by one thread with the serial code's operation
+// order, so the results do not depend on nt.
+template <class F>
+void parallel_threads(int64_t work, F fn) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (work < (int64_t)1 << 16) nt = 1;
+  std::vector<std::thread> pool;
+  for (unsigned t = 1; t < nt; ++t) pool.emplace_back(fn, (int)t, (int)nt);
+  fn(0, (int)nt);
+  for (auto &th : pool) th.join();
+}
 
 struct Csr {
   int64_t nrows = 0, ncols = 0;
