@@ -14,6 +14,7 @@
 #include <queue>
 #include <sstream>
 #include <thread>
+#include <memory>
 #include <tuple>
 
 namespace vemg {
@@ -357,20 +358,31 @@ std::vector<int64_t> stable_colour_sort(const std::vector<int32_t> &col) {
 // A = L L^T, then L^{-1} row by row, then A^{-1} = L^{-T} L^{-1}; every inner
 // loop runs over contiguous memory.
 void spd_inverse(std::vector<double> &M, int64_t n) {
+  // Cholesky by rows: L_ij = (M_ij - sum_{k<j} L_ik L_jk) / L_jj for j < i,
+  // then L_ii = sqrt(M_ii - sum_{k<i} L_ik^2), sums in ascending k.  Threads
+  // take every nt-th row; entry (i, j) waits until row j is complete.
   std::vector<double> L(n * n, 0.0);
-  for (int64_t j = 0; j < n; ++j) {
-    double s = M[j * n + j];
-    for (int64_t k = 0; k < j; ++k) s -= L[j * n + k] * L[j * n + k];
-    if (!(s > 0.0)) fail(-2, "coarsest multigrid level is not positive definite");
-    double ljj = std::sqrt(s);
-    L[j * n + j] = ljj;
-    for (int64_t i = j + 1; i < n; ++i) {
-      double t = M[i * n + j];
-      const double *li = &L[i * n], *lj = &L[j * n];
-      for (int64_t k = 0; k < j; ++k) t -= li[k] * lj[k];
-      L[i * n + j] = t / ljj;
+  std::unique_ptr<std::atomic<int>[]> ready(new std::atomic<int>[n]);
+  for (int64_t i = 0; i < n; ++i) ready[i].store(0, std::memory_order_relaxed);
+  std::atomic<bool> indefinite(false);
+  parallel_threads(n * n * n / 6, [&](int t, int nt) {
+    for (int64_t i = t; i < n; i += nt) {
+      double *li = &L[i * n];
+      for (int64_t j = 0; j < i; ++j) {
+        while (!ready[j].load(std::memory_order_acquire)) std::this_thread::yield();
+        const double *lj = &L[j * n];
+        double v = M[i * n + j];
+        for (int64_t k = 0; k < j; ++k) v -= li[k] * lj[k];
+        li[j] = v / lj[j];
+      }
+      double s = M[i * n + i];
+      for (int64_t k = 0; k < i; ++k) s -= li[k] * li[k];
+      if (!(s > 0.0)) indefinite.store(true);
+      li[i] = std::sqrt(s);
+      ready[i].store(1, std::memory_order_release);
     }
-  }
+  });
+  if (indefinite.load()) fail(-2, "coarsest multigrid level is not positive definite");
   // W = L^{-1} (lower triangular): row i = (e_i - sum_{k<i} L_ik W_k) / L_ii.
   // Column blocks of W are independent; each thread takes every nt-th block
   // of 32 columns and updates them in the serial order (k ascending).
