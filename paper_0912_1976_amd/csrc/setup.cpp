@@ -53,22 +53,51 @@ void tet_gradients(const double *xyz, const int64_t *t, V3 c[4], double &det) {
 // Off-diagonal stiffness on the edge graph, natural numbering.  Each edge
 // value is a left-to-right sum over its elements in ascending element order.
 Csr assemble_offdiag(int64_t n, const double *xyz, int64_t T, const int64_t *tets) {
-  std::vector<std::vector<int32_t>> nb(n);
-  for (int64_t e = 0; e < T; ++e)
-    for (auto &p : kPairs) {
-      int64_t i = tets[4 * e + p[0]], j = tets[4 * e + p[1]];
-      nb[i].push_back((int32_t)j);
-      nb[j].push_back((int32_t)i);
+  // element stiffness entries of the six edges of every element, and the
+  // orientation check, element-parallel
+  std::vector<double> ke(6 * T);
+  std::vector<double> dets(T);
+  parallel_threads(64 * T, [&](int t, int nt) {
+    for (int64_t e = T * t / nt, e1 = T * (t + 1) / nt; e < e1; ++e) {
+      V3 c[4];
+      double det;
+      tet_gradients(xyz, tets + 4 * e, c, det);
+      dets[e] = det;
+      for (int q = 0; q < 6; ++q) {
+        const V3 &ca = c[kPairs[q][0]], &cb = c[kPairs[q][1]];
+        ke[6 * e + q] = ((ca.x * cb.x + ca.y * cb.y) + ca.z * cb.z) / (6.0 * det);
+      }
     }
+  });
+  for (int64_t e = 0; e < T; ++e)
+    if (!(dets[e] > 0.0)) {
+      std::ostringstream os;
+      os << "tetrahedron " << e << " is not positively oriented (6 vol = " << dets[e] << ")";
+      fail(-2, os.str());
+    }
+  // pattern and values by row ranges: thread t owns the rows [r0, r1) and
+  // scans the elements in ascending order, so each edge value is the same
+  // left-to-right sum over its elements as in one serial pass
   Csr A;
   A.nrows = A.ncols = n;
   A.ptr.assign(n + 1, 0);
-  for (int64_t i = 0; i < n; ++i) {
-    auto &v = nb[i];
-    std::sort(v.begin(), v.end());
-    v.erase(std::unique(v.begin(), v.end()), v.end());
-    A.ptr[i + 1] = A.ptr[i] + (int64_t)v.size();
-  }
+  std::vector<std::vector<int32_t>> nb(n);
+  parallel_threads(64 * T, [&](int t, int nt) {
+    const int64_t r0 = n * t / nt, r1 = n * (t + 1) / nt;
+    for (int64_t e = 0; e < T; ++e)
+      for (auto &p : kPairs) {
+        int64_t i = tets[4 * e + p[0]], j = tets[4 * e + p[1]];
+        if (i >= r0 && i < r1) nb[i].push_back((int32_t)j);
+        if (j >= r0 && j < r1) nb[j].push_back((int32_t)i);
+      }
+    for (int64_t i = r0; i < r1; ++i) {
+      auto &v = nb[i];
+      std::sort(v.begin(), v.end());
+      v.erase(std::unique(v.begin(), v.end()), v.end());
+      A.ptr[i + 1] = (int64_t)v.size();
+    }
+  });
+  for (int64_t i = 0; i < n; ++i) A.ptr[i + 1] += A.ptr[i];
   A.idx.resize(A.ptr[n]);
   for (int64_t i = 0; i < n; ++i) std::copy(nb[i].begin(), nb[i].end(), A.idx.begin() + A.ptr[i]);
   nb.clear();
@@ -78,23 +107,15 @@ Csr assemble_offdiag(int64_t n, const double *xyz, int64_t T, const int64_t *tet
     auto b = A.idx.begin() + A.ptr[i], e = A.idx.begin() + A.ptr[i + 1];
     return (int64_t)(std::lower_bound(b, e, j) - A.idx.begin());
   };
-  for (int64_t e = 0; e < T; ++e) {
-    V3 c[4];
-    double det;
-    tet_gradients(xyz, tets + 4 * e, c, det);
-    if (!(det > 0.0)) {
-      std::ostringstream os;
-      os << "tetrahedron " << e << " is not positively oriented (6 vol = " << det << ")";
-      fail(-2, os.str());
-    }
-    for (auto &p : kPairs) {
-      const V3 &ca = c[p[0]], &cb = c[p[1]];
-      double k = ((ca.x * cb.x + ca.y * cb.y) + ca.z * cb.z) / (6.0 * det);
-      int64_t i = tets[4 * e + p[0]], j = tets[4 * e + p[1]];
-      int64_t lo = std::min(i, j), hi = std::max(i, j);
-      A.val[find(lo, (int32_t)hi)] += k;
-    }
-  }
+  parallel_threads(64 * T, [&](int t, int nt) {
+    const int64_t r0 = n * t / nt, r1 = n * (t + 1) / nt;
+    for (int64_t e = 0; e < T; ++e)
+      for (int q = 0; q < 6; ++q) {
+        int64_t i = tets[4 * e + kPairs[q][0]], j = tets[4 * e + kPairs[q][1]];
+        int64_t lo = std::min(i, j), hi = std::max(i, j);
+        if (lo >= r0 && lo < r1) A.val[find(lo, (int32_t)hi)] += ke[6 * e + q];
+      }
+  });
   // mirror the upper triangle (lo < hi) to the lower one
   for (int64_t i = 0; i < n; ++i)
     for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
