@@ -200,38 +200,80 @@ std::vector<int64_t> colour_ranges(const std::vector<int32_t> &col, int64_t a, i
 // ---------------------------------------------------------------- SA pieces
 // Strong node graph: ||A_IJ||_F > theta sqrt(||A_II||_F ||A_JJ||_F), I != J.
 Csr node_strength(const Csr &A, const std::vector<int32_t> &node, int64_t nnodes, double theta) {
-  std::vector<std::vector<std::pair<int32_t, double>>> acc(nnodes);
-  for (int64_t r = 0; r < A.nrows; ++r)
-    for (int64_t k = A.ptr[r]; k < A.ptr[r + 1]; ++k)
-      acc[node[r]].emplace_back(node[A.idx[k]], A.val[k] * A.val[k]);
+  // rows of every node, ascending
+  std::vector<int64_t> nptr(nnodes + 1, 0), nrow(A.nrows);
+  for (int64_t r = 0; r < A.nrows; ++r) ++nptr[node[r] + 1];
+  for (int64_t I = 0; I < nnodes; ++I) nptr[I + 1] += nptr[I];
+  {
+    std::vector<int64_t> fill(nptr.begin(), nptr.end() - 1);
+    for (int64_t r = 0; r < A.nrows; ++r) nrow[fill[node[r]]++] = r;
+  }
+  // ||A_IJ||_F of every node pair: the squares of node I's entries (its rows
+  // ascending, each row's entries in order) summed per J in that order.
+  // Nodes are shared among threads in contiguous ranges.
+  std::vector<double> fd(nnodes, 0.0);
+  std::vector<std::vector<std::pair<int32_t, double>>> rows(nnodes);
+  auto range = [&](int t, int nt, int64_t &I0, int64_t &I1) {
+    I0 = nnodes * t / nt;
+    I1 = nnodes * (t + 1) / nt;
+  };
+  parallel_threads(A.nnz(), [&](int t, int nt) {
+    int64_t I0, I1;
+    range(t, nt, I0, I1);
+    std::vector<std::pair<int32_t, double>> v;
+    for (int64_t I = I0; I < I1; ++I) {
+      v.clear();
+      for (int64_t q = nptr[I]; q < nptr[I + 1]; ++q) {
+        const int64_t r = nrow[q];
+        for (int64_t k = A.ptr[r]; k < A.ptr[r + 1]; ++k) v.emplace_back(node[A.idx[k]], A.val[k] * A.val[k]);
+      }
+      std::stable_sort(v.begin(), v.end(), [](auto &x, auto &y) { return x.first < y.first; });
+      for (size_t k = 0; k < v.size();) {
+        size_t l = k;
+        double s = 0.0;
+        while (l < v.size() && v[l].first == v[k].first) s += v[l++].second;
+        double f = std::sqrt(s);
+        if (v[k].first == I) fd[I] = f;
+        else rows[I].emplace_back(v[k].first, f);
+        k = l;
+      }
+    }
+  });
+  // strong couplings: ||A_IJ||_F > theta sqrt(||A_II||_F ||A_JJ||_F), I != J
   Csr F;
   F.nrows = F.ncols = nnodes;
   F.ptr.assign(nnodes + 1, 0);
-  std::vector<double> fd(nnodes, 0.0);
-  std::vector<std::vector<std::pair<int32_t, double>>> rows(nnodes);
-  for (int64_t I = 0; I < nnodes; ++I) {
-    auto &v = acc[I];
-    std::stable_sort(v.begin(), v.end(), [](auto &x, auto &y) { return x.first < y.first; });
-    for (size_t k = 0; k < v.size();) {
-      size_t l = k;
-      double s = 0.0;
-      while (l < v.size() && v[l].first == v[k].first) s += v[l++].second;
-      double f = std::sqrt(s);
-      if (v[k].first == I) fd[I] = f;
-      else rows[I].emplace_back(v[k].first, f);
-      k = l;
-    }
-    v.clear();
-    v.shrink_to_fit();
-  }
-  for (int64_t I = 0; I < nnodes; ++I) {
-    for (auto &e : rows[I])
-      if (e.second > theta * std::sqrt(fd[I] * fd[e.first])) {
-        F.idx.push_back(e.first);
-        F.val.push_back(e.second);
+  std::vector<std::vector<char>> keep(nnodes);
+  parallel_threads(A.nnz(), [&](int t, int nt) {
+    int64_t I0, I1;
+    range(t, nt, I0, I1);
+    for (int64_t I = I0; I < I1; ++I) {
+      keep[I].resize(rows[I].size());
+      int64_t cnt = 0;
+      for (size_t q = 0; q < rows[I].size(); ++q) {
+        const auto &e = rows[I][q];
+        keep[I][q] = e.second > theta * std::sqrt(fd[I] * fd[e.first]);
+        cnt += keep[I][q];
       }
-    F.ptr[I + 1] = (int64_t)F.idx.size();
-  }
+      F.ptr[I + 1] = cnt;
+    }
+  });
+  for (int64_t I = 0; I < nnodes; ++I) F.ptr[I + 1] += F.ptr[I];
+  F.idx.resize(F.ptr[nnodes]);
+  F.val.resize(F.ptr[nnodes]);
+  parallel_threads(A.nnz(), [&](int t, int nt) {
+    int64_t I0, I1;
+    range(t, nt, I0, I1);
+    for (int64_t I = I0; I < I1; ++I) {
+      int64_t p = F.ptr[I];
+      for (size_t q = 0; q < rows[I].size(); ++q)
+        if (keep[I][q]) {
+          F.idx[p] = rows[I][q].first;
+          F.val[p] = rows[I][q].second;
+          ++p;
+        }
+    }
+  });
   return F;
 }
 
