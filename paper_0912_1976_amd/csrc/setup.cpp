@@ -572,11 +572,7 @@ void sspai_refit(Csr &E, const Csr &A, int64_t m) {
       for (int64_t a = 0; a < q; ++a) E.val[cpos[b + a]] = v[a];
     }
   };
-  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  std::vector<std::thread> pool;
-  for (unsigned t = 1; t < nt; ++t) pool.emplace_back(work);
-  work();
-  for (auto &t : pool) t.join();
+  parallel_threads((int64_t)1 << 20, [&](int, int) { work(); });
   if (bad.load() >= 0) {
     std::ostringstream os;
     os << "extrapolation refit: the system of surface column " << bad.load() << " is not positive definite";

@@ -5,19 +5,25 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <thread>
 #include <vector>
 
 namespace vemg {
 
-// Runs fn(t, nt) on nt host threads (t = 0 on the caller), nt at most 16 and
-// 1 when the work is small.  Every caller splits its work so that each
-// output element is computed by one thread with the serial code's operation
-// order, so the results do not depend on nt.
+// Runs fn(t, nt) on nt host threads (t = 0 on the caller): nt is the
+// environment's VEMG_SETUP_THREADS (1..64) when set, else the hardware
+// concurrency capped at 16, and 1 when the work is small.  Every caller splits
+// its work so that each output element is computed by one thread with the
+// serial code's operation order, so the results do not depend on nt.
 template <class F>
 void parallel_threads(int64_t work, F fn) {
   unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   if (work < (int64_t)1 << 16) nt = 1;
+  if (const char *e = std::getenv("VEMG_SETUP_THREADS")) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v >= 1 && v <= 64) nt = (unsigned)v;
+  }
   std::vector<std::thread> pool;
   for (unsigned t = 1; t < nt; ++t) pool.emplace_back(fn, (int)t, (int)nt);
   fn(0, (int)nt);

@@ -205,3 +205,44 @@ def test_unknown_extrapolation_rejected():
     m = box_mesh(5, 4, 3, 0.1)
     with pytest.raises(KeyError):
         lib.Solver(m.xyz, m.tets, m.top, device=-1, extrapolation="harmonic")
+
+
+# every setup array, for comparing two setups bit for bit
+_ARRAYS = [("perm", np.int64), ("colour", np.int32), ("d", np.float64), ("diag", np.float64),
+           ("Aoff.ptr", np.int64), ("Aoff.idx", np.int32), ("Aoff.val", np.float64),
+           ("E.ptr", np.int64), ("E.idx", np.int32), ("E.val", np.float64), ("S_perm", np.int64)]
+
+
+def _all_arrays(s):
+    out = {name: s.export(name, dt) for name, dt in _ARRAYS}
+    info = s.info()
+    for which, key in (("S", "s_levels"), ("Abar", "abar_levels")):
+        for l in range(info[key]):
+            pre = f"{which}.{l}."
+            names = [("colour", np.int32), ("node", np.int32), ("A.ptr", np.int64), ("A.idx", np.int32),
+                     ("A.val", np.float64)]
+            if l + 1 < info[key]:
+                names += [("agg", np.int32), ("P.ptr", np.int64), ("P.idx", np.int32), ("P.val", np.float64)]
+            else:
+                names += [("Cinv", np.float64)]
+            for n, dt in names:
+                out[pre + n] = s.export(pre + n, dt)
+    return out
+
+
+@pytest.mark.parametrize("extrapolation", ["projection", "sspai"])
+def test_setup_independent_of_host_threads(monkeypatch, extrapolation):
+    """The threaded setup steps compute every element in the serial order, so
+    one thread and seven (uneven splits, threads even for small work) give
+    the same arrays bit for bit."""
+    m = box_mesh(21, 19, 7, 1e-3, jitter=0.3, seed=5, bathymetry=True)
+    got = []
+    for nt in ("1", "7"):
+        monkeypatch.setenv("VEMG_SETUP_THREADS", nt)
+        s = lib.Solver(m.xyz, m.tets, m.top, top_bc="pinned", device=-1, coarse_max=40,
+                       extrapolation=extrapolation)
+        got.append(_all_arrays(s))
+    assert got[0].keys() == got[1].keys()
+    for k in got[0]:
+        assert got[0][k].dtype == got[1][k].dtype
+        assert np.array_equal(got[0][k].view(np.uint8), got[1][k].view(np.uint8)), k
