@@ -146,35 +146,44 @@ std::vector<int32_t> greedy_colouring(const Csr &A, const std::vector<int64_t> &
 
 // Smallest-last vertex order of the off-diagonal pattern: repeatedly remove a
 // vertex of smallest remaining degree (ties to the smallest index), then
-// reverse.  A lazy min-heap of (degree, index); entries whose degree has since
-// dropped, or whose vertex is gone, are skipped when popped.  Row indices are
-// below 2^31 (int32 columns), so a key fits in 64 bits.
+// reverse.  One lazy min-heap of indices per degree: a vertex whose degree
+// drops is pushed again into its new degree's heap, and entries whose degree
+// has since changed, or whose vertex is gone, are skipped when they reach a
+// top.  Every heap below the current minimum degree is empty, so the first
+// valid top from there up is the smallest (degree, index) pair.  Row indices
+// are below 2^31 (int32 columns).
 std::vector<int64_t> smallest_last_order(const Csr &A) {
   const int64_t n = A.nrows;
   std::vector<int64_t> deg(n, 0);
-  for (int64_t i = 0; i < n; ++i)
+  int64_t maxd = 0;
+  for (int64_t i = 0; i < n; ++i) {
     for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) deg[i] += (A.idx[k] != i);
-  // (degree, index) packed into one key, degree in the high half: the key
-  // order is the (degree, index) order
-  auto key = [](int64_t d, int64_t i) { return ((uint64_t)d << 32) | (uint64_t)i; };
-  std::vector<uint64_t> store;
-  store.reserve(2 * (size_t)n);
-  std::priority_queue<uint64_t, std::vector<uint64_t>, std::greater<uint64_t>> heap(std::greater<uint64_t>(),
-                                                                                  std::move(store));
-  for (int64_t i = 0; i < n; ++i) heap.push(key(deg[i], i));
+    maxd = std::max(maxd, deg[i]);
+  }
+  using Heap = std::priority_queue<uint32_t, std::vector<uint32_t>, std::greater<uint32_t>>;
+  std::vector<Heap> bucket(maxd + 1);
+  for (int64_t i = 0; i < n; ++i) bucket[deg[i]].push((uint32_t)i);
   std::vector<char> removed(n, 0);
   std::vector<int64_t> seq;
   seq.reserve(n);
-  while (!heap.empty()) {
-    const uint64_t e = heap.top();
-    heap.pop();
-    const int64_t i = (int64_t)(e & 0xffffffffu), d = (int64_t)(e >> 32);
-    if (removed[i] || d != deg[i]) continue;
+  int64_t dmin = 0;
+  for (int64_t step = 0; step < n; ++step) {
+    int64_t i;
+    while (true) {
+      while (bucket[dmin].empty()) ++dmin;
+      i = bucket[dmin].top();
+      bucket[dmin].pop();
+      if (!removed[i] && deg[i] == dmin) break;
+    }
     removed[i] = 1;
     seq.push_back(i);
     for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
       const int64_t j = A.idx[k];
-      if (j != i && !removed[j]) heap.push(key(--deg[j], j));
+      if (j != i && !removed[j]) {
+        const int64_t d = --deg[j];
+        bucket[d].push((uint32_t)j);
+        dmin = std::min(dmin, d);
+      }
     }
   }
   std::reverse(seq.begin(), seq.end());
