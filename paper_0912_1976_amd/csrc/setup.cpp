@@ -53,20 +53,12 @@ void tet_gradients(const double *xyz, const int64_t *t, V3 c[4], double &det) {
 // Off-diagonal stiffness on the edge graph, natural numbering.  Each edge
 // value is a left-to-right sum over its elements in ascending element order.
 Csr assemble_offdiag(int64_t n, const double *xyz, int64_t T, const int64_t *tets) {
-  // element stiffness entries of the six edges of every element, and the
-  // orientation check, element-parallel
-  std::vector<double> ke(6 * T);
+  // orientation check, element-parallel; the first bad element is reported
   std::vector<double> dets(T);
   parallel_threads(64 * T, [&](int t, int nt) {
     for (int64_t e = T * t / nt, e1 = T * (t + 1) / nt; e < e1; ++e) {
       V3 c[4];
-      double det;
-      tet_gradients(xyz, tets + 4 * e, c, det);
-      dets[e] = det;
-      for (int q = 0; q < 6; ++q) {
-        const V3 &ca = c[kPairs[q][0]], &cb = c[kPairs[q][1]];
-        ke[6 * e + q] = ((ca.x * cb.x + ca.y * cb.y) + ca.z * cb.z) / (6.0 * det);
-      }
+      tet_gradients(xyz, tets + 4 * e, c, dets[e]);
     }
   });
   for (int64_t e = 0; e < T; ++e)
@@ -75,23 +67,29 @@ Csr assemble_offdiag(int64_t n, const double *xyz, int64_t T, const int64_t *tet
       os << "tetrahedron " << e << " is not positively oriented (6 vol = " << dets[e] << ")";
       fail(-2, os.str());
     }
-  // pattern and values by row ranges: thread t owns the rows [r0, r1) and
-  // scans the elements in ascending order, so each edge value is the same
-  // left-to-right sum over its elements as in one serial pass
+  dets = std::vector<double>();
+  // elements of every node, ascending (a stable counting sort)
+  std::vector<int64_t> eptr(n + 1, 0);
+  for (int64_t k = 0; k < 4 * T; ++k) ++eptr[tets[k] + 1];
+  for (int64_t i = 0; i < n; ++i) eptr[i + 1] += eptr[i];
+  std::vector<int64_t> elem(4 * T);
+  {
+    std::vector<int64_t> fill(eptr.begin(), eptr.end() - 1);
+    for (int64_t k = 0; k < 4 * T; ++k) elem[fill[tets[k]]++] = k / 4;
+  }
+  // pattern: the neighbours of node i in its elements, by node ranges
   Csr A;
   A.nrows = A.ncols = n;
   A.ptr.assign(n + 1, 0);
   std::vector<std::vector<int32_t>> nb(n);
   parallel_threads(64 * T, [&](int t, int nt) {
-    const int64_t r0 = n * t / nt, r1 = n * (t + 1) / nt;
-    for (int64_t e = 0; e < T; ++e)
-      for (auto &p : kPairs) {
-        int64_t i = tets[4 * e + p[0]], j = tets[4 * e + p[1]];
-        if (i >= r0 && i < r1) nb[i].push_back((int32_t)j);
-        if (j >= r0 && j < r1) nb[j].push_back((int32_t)i);
-      }
-    for (int64_t i = r0; i < r1; ++i) {
+    for (int64_t i = n * t / nt, i1 = n * (t + 1) / nt; i < i1; ++i) {
       auto &v = nb[i];
+      for (int64_t q = eptr[i]; q < eptr[i + 1]; ++q) {
+        const int64_t *te = tets + 4 * elem[q];
+        for (int a = 0; a < 4; ++a)
+          if (te[a] != i) v.push_back((int32_t)te[a]);
+      }
       std::sort(v.begin(), v.end());
       v.erase(std::unique(v.begin(), v.end()), v.end());
       A.ptr[i + 1] = (int64_t)v.size();
@@ -99,29 +97,44 @@ Csr assemble_offdiag(int64_t n, const double *xyz, int64_t T, const int64_t *tet
   });
   for (int64_t i = 0; i < n; ++i) A.ptr[i + 1] += A.ptr[i];
   A.idx.resize(A.ptr[n]);
-  for (int64_t i = 0; i < n; ++i) std::copy(nb[i].begin(), nb[i].end(), A.idx.begin() + A.ptr[i]);
-  nb.clear();
-  nb.shrink_to_fit();
+  parallel_threads(64 * T, [&](int t, int nt) {
+    for (int64_t i = n * t / nt, i1 = n * (t + 1) / nt; i < i1; ++i) {
+      std::copy(nb[i].begin(), nb[i].end(), A.idx.begin() + A.ptr[i]);
+      nb[i] = std::vector<int32_t>();
+    }
+  });
   A.val.assign(A.idx.size(), 0.0);
   auto find = [&](int64_t i, int32_t j) {
     auto b = A.idx.begin() + A.ptr[i], e = A.idx.begin() + A.ptr[i + 1];
     return (int64_t)(std::lower_bound(b, e, j) - A.idx.begin());
   };
+  // values: the thread owning row lo visits lo's elements in ascending order
+  // and adds every edge (lo, hi), lo < hi, of each, so each edge value is the
+  // left-to-right sum over its elements in ascending element order
   parallel_threads(64 * T, [&](int t, int nt) {
-    const int64_t r0 = n * t / nt, r1 = n * (t + 1) / nt;
-    for (int64_t e = 0; e < T; ++e)
-      for (int q = 0; q < 6; ++q) {
-        int64_t i = tets[4 * e + kPairs[q][0]], j = tets[4 * e + kPairs[q][1]];
-        int64_t lo = std::min(i, j), hi = std::max(i, j);
-        if (lo >= r0 && lo < r1) A.val[find(lo, (int32_t)hi)] += ke[6 * e + q];
+    for (int64_t lo = n * t / nt, l1 = n * (t + 1) / nt; lo < l1; ++lo)
+      for (int64_t q = eptr[lo]; q < eptr[lo + 1]; ++q) {
+        const int64_t *te = tets + 4 * elem[q];
+        V3 c[4];
+        double det;
+        tet_gradients(xyz, te, c, det);
+        for (auto &p : kPairs) {
+          const int64_t i = te[p[0]], j = te[p[1]];
+          if (std::min(i, j) != lo) continue;
+          const V3 &ca = c[p[0]], &cb = c[p[1]];
+          const double k = ((ca.x * cb.x + ca.y * cb.y) + ca.z * cb.z) / (6.0 * det);
+          A.val[find(lo, (int32_t)std::max(i, j))] += k;
+        }
       }
   });
   // mirror the upper triangle (lo < hi) to the lower one
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
-      int64_t j = A.idx[k];
-      if (j < i) A.val[k] = A.val[find(j, (int32_t)i)];
-    }
+  parallel_threads(64 * T, [&](int t, int nt) {
+    for (int64_t i = n * t / nt, i1 = n * (t + 1) / nt; i < i1; ++i)
+      for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+        int64_t j = A.idx[k];
+        if (j < i) A.val[k] = A.val[find(j, (int32_t)i)];
+      }
+  });
   return A;
 }
 
