@@ -970,40 +970,63 @@ void build_problem(Problem &P, const SetupOptions &opt, int64_t n_nodes, const d
     std::vector<std::array<int64_t, 3>> tri = top_triangles(n_tets, tets, P.top);
     if (tri.empty()) fail(-2, "no top-surface triangles (faces with three top nodes)");
     Locator loc2(xyz, tri, xmin, ymin, xmax, ymax);
+    // at most three entries a row, located row-parallel; the first node in
+    // storage order that projects onto no triangle is reported
+    std::vector<int32_t> eidx(3 * n);
+    std::vector<double> eval(3 * n);
+    std::vector<int8_t> ecnt(n, 0);
+    parallel_threads(64 * n, [&](int t, int nt) {
+      for (int64_t s = n * t / nt, s1 = n * (t + 1) / nt; s < s1; ++s) {
+        int64_t i = P.perm[s];
+        if (P.top[i]) {
+          eidx[3 * s] = (int32_t)s;
+          eval[3 * s] = 1.0;
+          ecnt[s] = 1;
+          continue;
+        }
+        double lam[3];
+        int64_t tr = loc2.locate(xyz[3 * i], xyz[3 * i + 1], lam);
+        if (tr < 0) {
+          ecnt[s] = -1;
+          continue;
+        }
+        for (double &l : lam)
+          if (std::fabs(l) <= kTolInside) l = 0.0;
+        double sum = (lam[0] + lam[1]) + lam[2];
+        std::pair<int32_t, double> ent[3];
+        int ne = 0;
+        for (int a = 0; a < 3; ++a) {
+          double w = lam[a] / sum;
+          int64_t v = tri[tr][a];
+          if (w != 0.0 && !fixed[v]) ent[ne++] = {(int32_t)P.pos[v], w};
+        }
+        std::sort(ent, ent + ne);
+        for (int a = 0; a < ne; ++a) {
+          eidx[3 * s + a] = ent[a].first;
+          eval[3 * s + a] = ent[a].second;
+        }
+        ecnt[s] = (int8_t)ne;
+      }
+    });
     Csr E0;
     E0.nrows = n;
     E0.ncols = m;
     E0.ptr.assign(n + 1, 0);
     for (int64_t s = 0; s < n; ++s) {
-      int64_t i = P.perm[s];
-      if (P.top[i]) {
-        E0.idx.push_back((int32_t)s);
-        E0.val.push_back(1.0);
-      } else {
-        double lam[3];
-        int64_t t = loc2.locate(xyz[3 * i], xyz[3 * i + 1], lam);
-        if (t < 0) {
-          std::ostringstream os;
-          os << "node " << i << " does not project onto the top surface";
-          fail(-3, os.str());
-        }
-        for (double &l : lam)
-          if (std::fabs(l) <= kTolInside) l = 0.0;
-        double sum = (lam[0] + lam[1]) + lam[2];
-        std::vector<std::pair<int32_t, double>> ent;
-        for (int a = 0; a < 3; ++a) {
-          double w = lam[a] / sum;
-          int64_t v = tri[t][a];
-          if (w != 0.0 && !fixed[v]) ent.emplace_back((int32_t)P.pos[v], w);
-        }
-        std::sort(ent.begin(), ent.end());
-        for (auto &e : ent) {
-          E0.idx.push_back(e.first);
-          E0.val.push_back(e.second);
-        }
+      if (ecnt[s] < 0) {
+        std::ostringstream os;
+        os << "node " << P.perm[s] << " does not project onto the top surface";
+        fail(-3, os.str());
       }
-      E0.ptr[s + 1] = (int64_t)E0.idx.size();
+      E0.ptr[s + 1] = E0.ptr[s] + ecnt[s];
     }
+    E0.idx.resize(E0.ptr[n]);
+    E0.val.resize(E0.ptr[n]);
+    for (int64_t s = 0; s < n; ++s)
+      for (int a = 0; a < ecnt[s]; ++a) {
+        E0.idx[E0.ptr[s] + a] = eidx[3 * s + a];
+        E0.val[E0.ptr[s] + a] = eval[3 * s + a];
+      }
     if (opt.extrapolation == 1) sspai_refit(E0, A, m);
     Csr E0t = transpose(E0);
     Csr S0 = spgemm(E0t, spgemm(A, E0));
