@@ -246,3 +246,20 @@ def test_setup_independent_of_host_threads(monkeypatch, extrapolation):
     for k in got[0]:
         assert got[0][k].dtype == got[1][k].dtype
         assert np.array_equal(got[0][k].view(np.uint8), got[1][k].view(np.uint8)), k
+
+
+@pytest.mark.parametrize("threads", ["1", "7"])
+def test_projection_error_names_the_node(monkeypatch, threads):
+    """A node below the top whose vertical line misses the top surface is a
+    projection error (status -3) naming that node, on any number of setup
+    threads."""
+    monkeypatch.setenv("VEMG_SETUP_THREADS", threads)
+    m = box_mesh(6, 5, 3, 0.01)
+    xyz = m.xyz.copy()
+    bottom = np.flatnonzero(~m.top.astype(bool))
+    corner = bottom[np.argmin(xyz[bottom, 0] + xyz[bottom, 1])]
+    xyz[corner, :2] -= 0.05
+    with pytest.raises(lib.VemgError) as e:
+        lib.Solver(xyz, m.tets, m.top, device=-1)
+    assert e.value.status == -3
+    assert f"node {corner} " in str(e.value)
