@@ -4,8 +4,10 @@
 #pragma once
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstdlib>
+#include <exception>
 #include <thread>
 #include <vector>
 
@@ -24,10 +26,36 @@ void parallel_threads(int64_t work, F fn) {
     const long v = std::strtol(e, nullptr, 10);
     if (v >= 1 && v <= 64) nt = (unsigned)v;
   }
+  // The threads start together once all exist (some callers' threads wait
+  // on each other's rows); if one cannot be created, those created return at
+  // once and the caller does all the work alone.  An exception in any thread
+  // (an allocation failure, say) is rethrown on the caller's thread once
+  // every thread has finished.
+  std::vector<std::exception_ptr> err(nt);
+  std::atomic<int> gate(0);  // 0: wait, 1: run, 2: abandon
+  auto run = [&](int t) {
+    while (gate.load(std::memory_order_acquire) == 0) std::this_thread::yield();
+    if (gate.load(std::memory_order_acquire) == 2) return;
+    try {
+      fn(t, (int)nt);
+    } catch (...) {
+      err[t] = std::current_exception();
+    }
+  };
   std::vector<std::thread> pool;
-  for (unsigned t = 1; t < nt; ++t) pool.emplace_back(fn, (int)t, (int)nt);
-  fn(0, (int)nt);
+  try {
+    for (unsigned t = 1; t < nt; ++t) pool.emplace_back(run, (int)t);
+  } catch (...) {
+    gate.store(2, std::memory_order_release);
+    for (auto &th : pool) th.join();
+    fn(0, 1);
+    return;
+  }
+  gate.store(1, std::memory_order_release);
+  run(0);
   for (auto &th : pool) th.join();
+  for (auto &e : err)
+    if (e) std::rethrow_exception(e);
 }
 
 struct Csr {
