@@ -99,3 +99,14 @@ def test_plain_c_consumer(tmp_path):
     assert int(got["s_levels"]) == info["s_levels"] and int(got["abar_levels"]) == info["abar_levels"]
     assert int(got["perm_checksum"]) == int(np.sum(perm * np.arange(1, perm.size + 1)))
     assert int(got["solve"]) == -7  # VEMG_ERR_STATE: no device
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without libvemg.so a Solver cannot be made: ImportError, no fallback."""
+    from paper_0912_1976_amd import _lib
+
+    monkeypatch.setattr(_lib, "_LIB", None)
+    monkeypatch.setattr(_lib, "library_path", lambda: os.path.join(os.path.dirname(_lib.__file__), "absent.so"))
+    m = box_mesh(5, 5, 3, 0.01)
+    with pytest.raises(ImportError, match="absent.so"):
+        lib_mod.Solver(m.xyz, m.tets, m.top, device=-1)
