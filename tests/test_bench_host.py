@@ -93,3 +93,21 @@ def test_trace_timed_takes_the_last_run_of_each_kernel(tmp_path, capsys):
     assert set(out) == {"cgs"}
     assert out["cgs"]["dispatches"] == 4
     assert out["cgs"]["mean_us"] == pytest.approx(3.25)
+
+
+def test_traffic_is_reported_only_for_the_profiled_sources(tmp_path, monkeypatch):
+    """The roofline's traffic comes from the committed PMC record only while
+    the kernel sources hash to the recorded value and the workload matches;
+    otherwise it is null."""
+    rec = {"workload": "thinbox-129x129x33-eps1e-3", "source_hash": bench._kernel_source_hash(),
+           "kernels": {"cgs": {"hbm_bytes_per_launch": 1234.0}}}
+    f = tmp_path / "pmc_traffic.json"
+    f.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic("cgs", "thinbox-129x129x33-eps1e-3") == 1234.0
+    assert bench.measured_traffic("gs", "thinbox-129x129x33-eps1e-3") is None
+    assert bench.measured_traffic("cgs", "thinbox-257x257x33-eps1e-4") is None
+    monkeypatch.setattr(bench, "_kernel_source_hash", lambda: "0" * 16)
+    assert bench.measured_traffic("cgs", "thinbox-129x129x33-eps1e-3") is None
+    f.write_text("not json")
+    assert bench.measured_traffic("cgs", "thinbox-129x129x33-eps1e-3") is None
