@@ -24,19 +24,22 @@ Csr transpose(const Csr &A) {
   return T;  // rows visited in ascending order, so columns are sorted
 }
 
+// columns ascending in every row (a row's columns are distinct, so the
+// result does not depend on the sort); rows are shared among threads
 static void sort_rows(Csr &A) {
-  std::vector<std::pair<int32_t, double>> tmp;
-  for (int64_t i = 0; i < A.nrows; ++i) {
-    int64_t a = A.ptr[i], b = A.ptr[i + 1];
-    tmp.clear();
-    for (int64_t k = a; k < b; ++k) tmp.emplace_back(A.idx[k], A.val[k]);
-    std::sort(tmp.begin(), tmp.end(),
-              [](const auto &x, const auto &y) { return x.first < y.first; });
-    for (int64_t k = a; k < b; ++k) {
-      A.idx[k] = tmp[k - a].first;
-      A.val[k] = tmp[k - a].second;
+  parallel_threads(A.nnz(), [&](int t, int nt) {
+    std::vector<std::pair<int32_t, double>> tmp;
+    for (int64_t i = A.nrows * t / nt, i1 = A.nrows * (t + 1) / nt; i < i1; ++i) {
+      int64_t a = A.ptr[i], b = A.ptr[i + 1];
+      tmp.clear();
+      for (int64_t k = a; k < b; ++k) tmp.emplace_back(A.idx[k], A.val[k]);
+      std::sort(tmp.begin(), tmp.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+      for (int64_t k = a; k < b; ++k) {
+        A.idx[k] = tmp[k - a].first;
+        A.val[k] = tmp[k - a].second;
+      }
     }
-  }
+  });
 }
 
 Csr permute_sym(const Csr &A, const std::vector<int64_t> &perm) {
@@ -49,13 +52,15 @@ Csr permute_sym(const Csr &A, const std::vector<int64_t> &perm) {
   for (int64_t i = 0; i < B.nrows; ++i) B.ptr[i + 1] = B.ptr[i] + (A.ptr[perm[i] + 1] - A.ptr[perm[i]]);
   B.idx.resize(A.nnz());
   B.val.resize(A.nnz());
-  for (int64_t i = 0; i < B.nrows; ++i) {
-    int64_t o = perm[i], p = B.ptr[i];
-    for (int64_t k = A.ptr[o]; k < A.ptr[o + 1]; ++k, ++p) {
-      B.idx[p] = (int32_t)inv[A.idx[k]];
-      B.val[p] = A.val[k];
+  parallel_threads(A.nnz(), [&](int t, int nt) {
+    for (int64_t i = B.nrows * t / nt, i1 = B.nrows * (t + 1) / nt; i < i1; ++i) {
+      int64_t o = perm[i], p = B.ptr[i];
+      for (int64_t k = A.ptr[o]; k < A.ptr[o + 1]; ++k, ++p) {
+        B.idx[p] = (int32_t)inv[A.idx[k]];
+        B.val[p] = A.val[k];
+      }
     }
-  }
+  });
   sort_rows(B);
   return B;
 }
