@@ -233,6 +233,20 @@ vemg_status vemg_time_op(vemg_solver s, int op, int nrhs, int reps, double *avg_
 
 vemg_status vemg_get_info(vemg_solver s, vemg_info *info);
 
+/* Device memory needed to solve nrhs right-hand sides on this mesh, for
+ * admission by memory footprint: the bytes the handle holds in HBM from
+ * setup to destroy (fine operator in FP64 and row-scaled FP32, E~ and its
+ * transpose, both smoothed aggregation hierarchies with their coarsest
+ * inverses, the Krylov work space for batches of up to 8 columns) plus the
+ * caller's b and x arrays, 2 * nrhs * n_nodes doubles.  nrhs = 0 gives the
+ * handle alone; its part does not depend on nrhs, since larger requests run
+ * in batches of 8 on the same work space.  Counted at setup from the same
+ * allocation sequence as the upload, so it is exact and is also available
+ * for a host-only handle (device -1) before any device is touched.
+ * Errors: VEMG_ERR_INVALID_ARG (null pointer, nrhs < 0), VEMG_ERR_STATE
+ * (no setup). */
+vemg_status vemg_footprint(vemg_solver s, int nrhs, size_t *bytes);
+
 /* Switches the preconditioner (vemg_pc) of a set-up handle; the setup (E~,
  * both hierarchies, packed operators) serves every preconditioner, so only
  * the captured iteration graphs are dropped.  Waits for the handle's pending
@@ -286,7 +300,10 @@ typedef struct {
   size_t resident_bytes, budget_bytes;
 } vemg_server_stats;
 
-/* hbm_budget: device bytes the resident meshes may use (0 = no limit). */
+/* hbm_budget: device bytes the resident meshes may use (0 = no limit); a
+ * mesh is admitted when its vemg_footprint (nrhs = 0) fits beside the other
+ * resident meshes.  All lanes share two pairs of streams (four hardware
+ * queues in all): lane i runs on pair i mod 2. */
 vemg_status vemg_server_create(int device, size_t hbm_budget, const vemg_options *o, vemg_server *out);
 /* Registers a mesh (host setup now; same arguments as vemg_setup).  Fails
  * with VEMG_ERR_OOM if the mesh alone exceeds the budget. */
@@ -294,8 +311,13 @@ vemg_status vemg_server_add_mesh(vemg_server s, int64_t n_nodes, const double *x
                                  const int64_t *tets, const uint8_t *top_mask, int *mesh_id);
 /* vemg_rhs for a registered mesh (host arrays). */
 vemg_status vemg_server_rhs(vemg_server s, int mesh_id, const double *f_host, double *b_host);
+/* vemg_footprint of a registered mesh: what admission compares against the
+ * budget (nrhs = 0) and what a request of nrhs columns adds for its own b and
+ * x arrays, which the caller allocates. */
+vemg_status vemg_server_footprint(vemg_server s, int mesh_id, int nrhs, size_t *bytes);
 /* Queues nrhs right-hand sides ([nrhs][n_nodes], device, natural order,
- * fully written before the call) and returns at once.  x ([nrhs][n_nodes],
+ * fully written before the call) and returns at once.  Each column stops on
+ * this request's rtol and max_iter, whatever shares its batch.  x ([nrhs][n_nodes],
  * device) is written when the request completes; both buffers must stay
  * valid until then. */
 vemg_status vemg_server_submit(vemg_server s, int mesh_id, int nrhs, const double *b_dev, double *x_dev,

@@ -224,7 +224,8 @@ def add_robin(Aoff, Moff, L, alpha):
 def pin_node(xyz, top):
     """Point condition phi(x_0) = 0 with x_0 on the top surface (eq. point
     condition).  Reading: the top node closest to the origin corner, ties to
-    the smallest index.  Parity unpinned (a choice, not a computation)."""
+    the smallest index.  Pinned against the box's known corner node and a
+    brute-force search (tests/test_oracle_pins.py)."""
     idx = np.nonzero(top)[0]
     d2 = xyz[idx, 0] ** 2 + xyz[idx, 1] ** 2 + xyz[idx, 2] ** 2
     return int(idx[np.argmin(d2)])

@@ -77,6 +77,7 @@ def load_library():
     lib.vemg_solve.argtypes = [P, I32, P, P, D, I32, P, P]
     lib.vemg_apply.argtypes = [P, I32, P, P]
     lib.vemg_get_info.argtypes = [P, C.POINTER(Info)]
+    lib.vemg_footprint.argtypes = [P, I32, C.POINTER(C.c_size_t)]
     lib.vemg_set_preconditioner.argtypes = [P, I32]
     lib.vemg_set_precision.argtypes = [P, I32]
     lib.vemg_time_op.argtypes = [P, I32, I32, I32, C.POINTER(C.c_double), C.POINTER(C.c_int)]
@@ -90,6 +91,7 @@ def load_library():
     lib.vemg_server_create.argtypes = [I32, C.c_size_t, C.POINTER(Options), C.POINTER(P)]
     lib.vemg_server_add_mesh.argtypes = [P, I64, P, I64, P, P, C.POINTER(I32)]
     lib.vemg_server_rhs.argtypes = [P, I32, P, P]
+    lib.vemg_server_footprint.argtypes = [P, I32, I32, C.POINTER(C.c_size_t)]
     lib.vemg_server_submit.argtypes = [P, I32, I32, P, P, D, I32, C.POINTER(U64)]
     lib.vemg_server_poll.argtypes = [P, C.POINTER(U64), I32, C.POINTER(I32)]
     lib.vemg_server_wait.argtypes = [P, U64, D]
@@ -99,12 +101,13 @@ def load_library():
     lib.vemg_server_set_precision.argtypes = [P, I32]
     lib.vemg_server_last_error.argtypes = [P]
     lib.vemg_server_last_error.restype = C.c_char_p
-    for f in ("vemg_server_create", "vemg_server_add_mesh", "vemg_server_rhs", "vemg_server_submit",
+    for f in ("vemg_server_create", "vemg_server_add_mesh", "vemg_server_rhs", "vemg_server_footprint",
+              "vemg_server_submit",
               "vemg_server_poll", "vemg_server_wait", "vemg_server_result", "vemg_server_get_stats",
               "vemg_server_destroy", "vemg_server_set_precision"):
         getattr(lib, f).restype = I32
     for f in ("vemg_create", "vemg_setup", "vemg_rhs", "vemg_matvec", "vemg_solve", "vemg_apply",
-              "vemg_get_info", "vemg_export", "vemg_destroy", "vemg_time_op"):
+              "vemg_get_info", "vemg_footprint", "vemg_export", "vemg_destroy", "vemg_time_op"):
         getattr(lib, f).restype = I32
     _LIB = lib
     return lib
@@ -197,6 +200,13 @@ class Solver:
                       ("p_nnz_abar", inf.abar_levels)):
             out[k] = out[k][:nl]
         return out
+
+    def footprint(self, nrhs=0):
+        """Device bytes for a solve of nrhs right-hand sides (the handle's
+        resident memory plus 2 * nrhs * n_nodes doubles for b and x)."""
+        nb = C.c_size_t(0)
+        self._check(self._lib.vemg_footprint(self._h, nrhs, C.byref(nb)), self._h)
+        return nb.value
 
     def export(self, name, dtype):
         nb = C.c_size_t(0)
@@ -298,6 +308,11 @@ class Server:
         self._check(self._lib.vemg_server_rhs(self._h, mesh_id, f.ctypes.data, b.ctypes.data))
         return b
 
+    def footprint(self, mesh_id, nrhs=0):
+        nb = C.c_size_t(0)
+        self._check(self._lib.vemg_server_footprint(self._h, mesh_id, nrhs, C.byref(nb)))
+        return nb.value
+
     def submit(self, mesh_id, b, rtol=1e-8, max_iter=5000):
         """b: CUDA float64 tensor [nrhs, n_nodes] (written and synchronised)."""
         torch = self._torch
@@ -322,14 +337,17 @@ class Server:
         self._check(self._lib.vemg_server_wait(self._h, rid, timeout))
 
     def result(self, rid):
-        """(x tensor [nrhs, n_nodes], status, iters, relres, latency_ms); releases the request."""
-        b, x = self._live.pop(rid)
+        """(x tensor [nrhs, n_nodes], status, iters, relres, latency_ms); releases the request.
+        Raises (keeping the request's buffers alive) while it is not complete."""
+        b, x = self._live[rid]
         nrhs = b.shape[0]
         st = C.c_int(0)
         its = (C.c_int * nrhs)()
         rel = (C.c_double * nrhs)()
         lat = C.c_double(0.0)
         self._check(self._lib.vemg_server_result(self._h, rid, C.byref(st), its, rel, C.byref(lat)))
+        # the library has reported the request done: its kernels no longer use b or x
+        del self._live[rid]
         return x, st.value, list(its), list(rel), lat.value
 
     def set_precision(self, precision):

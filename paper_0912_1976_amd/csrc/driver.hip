@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -45,23 +46,26 @@ struct DeviceError : std::runtime_error {
                                 std::string(#expr) + ": " + hipGetErrorString(e_));               \
   } while (0)
 
-// device allocations owned by a handle
+// device allocations owned by a handle; with count_only set nothing is
+// allocated or copied, only the bytes are added up (the footprint query)
 struct Arena {
   std::vector<void *> ptrs;
   size_t bytes = 0;
+  bool count_only = false;
   template <class T>
   T *alloc(size_t count) {
     if (count == 0) count = 1;
+    bytes += count * sizeof(T);
+    if (count_only) return nullptr;
     void *p = nullptr;
     HIPCHK(hipMalloc(&p, count * sizeof(T)));
     ptrs.push_back(p);
-    bytes += count * sizeof(T);
     return (T *)p;
   }
   template <class T>
   T *upload(const std::vector<T> &v, hipStream_t st) {
     T *p = alloc<T>(v.size());
-    if (!v.empty()) {
+    if (!v.empty() && !count_only) {
       // the source is a temporary host vector: finish the copy before returning
       HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -264,6 +268,8 @@ struct vemg_solver_s {
   vemg_options opt;
   int device = -1;
   hipStream_t user = nullptr, work = nullptr, work2 = nullptr;  // work2: parallel preconditioner branch
+  bool own_streams = true;  // false: work and work2 belong to a server's stream pool
+  size_t footprint = 0;     // device bytes of the uploaded setup (counted before the upload)
   hipEvent_t ev = nullptr, ev_fork = nullptr, ev_join = nullptr;
   std::string err;
   bool ready = false;
@@ -914,10 +920,14 @@ void solve_ir(Handle *h, int K, double rtol, int max_iter, ColResult *res) {
   launch_round(st, h->v64.xs, h->v64.xl, h->v64.x, n * K);
 }
 
+// Packs the host setup into HBM.  With h->ar.count_only the same sequence
+// of allocations is only counted (no device call), which gives the footprint
+// of a handle before (or without) its upload.
 void upload(Handle *h) {
   hipStream_t st = h->work;
   Problem &P = h->P;
   int64_t n = P.n, m = P.n_top;
+  const bool count = h->ar.count_only;
   h->ar.release();
   h->A = pack_sell(h->ar, st, P.Aoff, true, &P.d, &P.diag, &h->nnz_A);
   if (m > 0) {
@@ -964,17 +974,32 @@ void upload(Handle *h) {
   h->scale_in = h->ar.alloc<double>(kMaxBatch);
   h->scale_out = h->ar.alloc<double>(kMaxBatch);
   h->scal = h->ar.alloc<Scal>(1);
-  // every column starts finished (no right-hand side yet)
-  launch_fill<double>(st, h->part_b, kMaxBatch, 0.0, nullptr);
-  launch_pcg_init(st, kMaxBatch, h->scal, h->part_b, 1, 1.0, 1);
-  // the top block of the smoother vectors stays zero
-  launch_fill<double>(st, h->v64.w, (int64_t)cnt, 0.0, nullptr);
-  launch_fill<float>(st, h->v32.w, (int64_t)cnt, 0.0f, nullptr);
+  if (!count) {
+    // every column starts finished (no right-hand side yet)
+    launch_fill<double>(st, h->part_b, kMaxBatch, 0.0, nullptr);
+    launch_pcg_init(st, kMaxBatch, h->scal, h->part_b, 1, 1.0, 1);
+    // the top block of the smoother vectors stays zero
+    launch_fill<double>(st, h->v64.w, (int64_t)cnt, 0.0, nullptr);
+    launch_fill<float>(st, h->v32.w, (int64_t)cnt, 0.0f, nullptr);
+  }
   if (m > 0) build_levels(h, P.S, h->S, kLevelsS);
   build_levels(h, P.Abar, h->Ab, kLevelsAbar);
   h->SA.clear();
   if (!P.SA.empty()) build_levels(h, P.SA, h->SA, kLevelsSA);
-  HIPCHK(hipStreamSynchronize(st));
+  if (!count) HIPCHK(hipStreamSynchronize(st));
+}
+
+// device bytes that upload() allocates for the current host setup; the
+// handle's device fields are left cleared, so upload() must follow on a
+// device handle
+size_t count_upload_bytes(Handle *h) {
+  Arena saved = std::move(h->ar);
+  h->ar = Arena();
+  h->ar.count_only = true;
+  upload(h);
+  size_t b = h->ar.bytes;
+  h->ar = std::move(saved);
+  return b;
 }
 
 void sync_in(Handle *h) {
@@ -1251,6 +1276,21 @@ int do_export(Handle *h, const std::string &name, void *buf, size_t *bytes) {
   return VEMG_ERR_INVALID_ARG;
 }
 
+// A non-blocking stream with a hardware queue of its own: no implicit
+// ordering with the legacy null stream (so another thread's work cannot join
+// a graph being captured on it; ordering with the caller's stream is
+// explicit, see sync_in), and, being created with a CU mask (every CU, so
+// nothing is restricted), it does not share its queue, so the two
+// preconditioner branches cannot end up serialised behind each other or
+// behind another stream's work.
+hipError_t create_queue_stream(int device, hipStream_t *st) {
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return e;
+  std::vector<uint32_t> mask((prop.multiProcessorCount + 31) / 32, 0xffffffffu);
+  return hipExtStreamCreateWithCUMask(st, (uint32_t)mask.size(), mask.data());
+}
+
 int fail(Handle *h, int code, const std::string &msg) {
   if (h) h->err = msg;
   return code;
@@ -1288,6 +1328,9 @@ double now_s() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+// One solve request.  The submitting thread fills it under the server lock;
+// afterwards the scheduler thread owns iters, rel, status and cols_left
+// until it sets done (under the lock), after which only readers remain.
 struct SReq {
   uint64_t id = 0;
   int mesh = 0, nrhs = 0, max_iter = 0;
@@ -1300,8 +1343,11 @@ struct SReq {
   std::vector<double> rel;
 };
 
+// A column slot of a lane.  It points at its request directly: requests are
+// owned by unique_ptr and never move, so the scheduler reaches them without
+// touching the server's request list.
 struct SSlot {
-  int64_t req = -1;  // index into Server::reqs
+  SReq *req = nullptr;
   int col = 0, restarts = 0;
   double prev = INFINITY;
 };
@@ -1310,29 +1356,38 @@ struct Lane {
   vemg_solver_s *h = nullptr;
   bool resident = false;
   size_t footprint = 0;
-  std::deque<std::pair<int64_t, int>> queue;  // (request, column)
+  std::deque<std::pair<SReq *, int>> queue;  // (request, column), scheduler thread only
   SSlot slot[kMaxBatch];
   bool launched = false;
   uint64_t last_used = 0;
+  Scal *scal_host = nullptr;  // pinned copy of the lane's scalars after its last chunk
+  hipEvent_t scal_ready = nullptr;
   bool busy() const {
     if (!queue.empty()) return true;
     for (auto &s : slot)
-      if (s.req >= 0) return true;
+      if (s.req) return true;
     return false;
   }
 };
+
+// At most kServerStreamPairs pairs of streams serve every lane (lane i uses
+// pair i mod kServerStreamPairs): a pair is the lane's Krylov stream and its
+// second preconditioner branch, each created with a (full) CU mask so that it
+// has a hardware queue of its own.
+constexpr int kServerStreamPairs = 2;
 
 }  // namespace
 }  // namespace vemg
 
 struct vemg_server_s {
   int device = 0;
-  size_t budget = 0, used = 0;
+  size_t budget = 0;
   vemg_options opt;
+  hipStream_t streams[2 * vemg::kServerStreamPairs] = {};
   std::vector<std::unique_ptr<vemg::Lane>> lanes;
-  std::vector<std::unique_ptr<vemg::SReq>> reqs;
-  std::map<uint64_t, int64_t> by_id;
-  std::deque<int64_t> incoming, completed;
+  std::vector<std::unique_ptr<vemg::SReq>> reqs;  // owner; appended under mu
+  std::map<uint64_t, vemg::SReq *> by_id;
+  std::deque<vemg::SReq *> incoming, completed;
   std::mutex mu;
   std::condition_variable cv, cv_done;
   std::thread worker;
@@ -1340,8 +1395,9 @@ struct vemg_server_s {
   uint64_t next_id = 1, tick = 0;
   std::string err;
   double first_submit = -1.0, last_done = -1.0;
-  int64_t chunks = 0, uploads = 0, evictions = 0, cols_done = 0;
-  double occupancy_sum = 0.0;
+  // written by the scheduler thread, read by vemg_server_get_stats
+  std::atomic<size_t> used{0};
+  std::atomic<int64_t> chunks{0}, uploads{0}, evictions{0}, cols_done{0}, active_slots{0};
   int64_t reqs_base = 0;  // requests before the last statistics reset
 };
 
@@ -1369,42 +1425,40 @@ bool lane_admit(Server *sv, Lane &L) {
     lane_release(sv, *victim);
   }
   upload(L.h);
-  L.footprint = L.h->ar.bytes;
+  if (L.h->ar.bytes != L.footprint)
+    throw DeviceError(VEMG_ERR_DEVICE, "device allocations differ from the counted footprint");
   L.resident = true;
   sv->used += L.footprint;
   sv->uploads++;
   return true;
 }
 
-double lane_tol(Server *sv, Lane &L) {
-  double t = 1.0;
-  for (auto &sl : L.slot)
-    if (sl.req >= 0) t = std::min(t, sv->reqs[sl.req]->rtol);
-  return t;
-}
-
-int lane_maxit(Server *sv, Lane &L) {
-  int m = 1;
-  for (auto &sl : L.slot)
-    if (sl.req >= 0) m = std::max(m, sv->reqs[sl.req]->max_iter);
-  return std::min(m, 1 << 20);
+// each slot stops on its own request's tolerance and iteration cap
+SlotStop lane_stop(const Lane &L) {
+  SlotStop st;
+  for (int k = 0; k < kMaxBatch; ++k) {
+    const SReq *q = L.slot[k].req;
+    st.tol[k] = q ? q->rtol : 1.0;
+    st.maxit[k] = q ? q->max_iter : 1;
+  }
+  return st;
 }
 
 // (re)start the slot columns in mask: join (x = 0, r = b) or restart (r = res)
-void lane_start(Server *sv, Lane &L, unsigned mask, bool restart) {
+void lane_start(Lane &L, unsigned mask, bool restart) {
   Handle *h = L.h;
   hipStream_t st = h->work;
   int64_t n = h->P.n, N = h->P.n_nodes;
   if (!restart)
     for (int k = 0; k < kMaxBatch; ++k)
       if ((mask >> k) & 1u) {
-        SReq &q = *sv->reqs[L.slot[k].req];
+        const SReq &q = *L.slot[k].req;
         launch_gather(st, kMaxBatch, k, q.b + (int64_t)L.slot[k].col * N, h->perm, h->b, n);
       }
   launch_slot_vectors(st, mask, restart, h->b, h->v64.res, h->v64.xs, h->v64.xl, h->v64.x, h->v64.r, n);
   launch_dot<double>(st, kMaxBatch, h->b, h->b, n, h->part_b, nullptr);
-  launch_slot_scalars(st, mask, restart, h->scal, h->part_b, vec_blocks(n), lane_tol(sv, L), lane_maxit(sv, L),
-                      h->scale_in, h->scale_out);
+  launch_slot_scalars(st, mask, restart, h->scal, h->part_b, vec_blocks(n), lane_stop(L), h->scale_in,
+                      h->scale_out);
   int64_t np = 0;
   if (h->opt.precision != VEMG_FP64)
     np = precond_mixed(h, kMaxBatch, h->v64.r, h->v64.z, nullptr);
@@ -1418,7 +1472,7 @@ void finish_request(Server *sv, SReq &q) {
   std::lock_guard<std::mutex> lk(sv->mu);
   q.done = true;
   q.t_done = now_s();
-  sv->completed.push_back(sv->by_id[q.id]);
+  sv->completed.push_back(&q);
   sv->last_done = q.t_done;
   sv->cv_done.notify_all();
 }
@@ -1428,10 +1482,11 @@ void finish_request(Server *sv, SReq &q) {
 void lane_collect(Server *sv, Lane &L) {
   Handle *h = L.h;
   hipStream_t st = h->work;
-  Scal hs = read_scal(h);
+  HIPCHK(hipEventSynchronize(L.scal_ready));
+  const Scal hs = *L.scal_host;
   unsigned fin = 0;
   for (int k = 0; k < kMaxBatch; ++k)
-    if (L.slot[k].req >= 0 && hs.done[k]) fin |= 1u << k;
+    if (L.slot[k].req && hs.done[k]) fin |= 1u << k;
   if (!fin) return;
   launch_fold(st, kMaxBatch, fin, h->v64.xs, h->v64.xl, h->v64.x, h->P.n);
   double rr[kMaxBatch];
@@ -1443,7 +1498,7 @@ void lane_collect(Server *sv, Lane &L) {
   for (int k = 0; k < kMaxBatch; ++k) {
     if (!((fin >> k) & 1u)) continue;
     SSlot &sl = L.slot[k];
-    SReq &q = *sv->reqs[sl.req];
+    SReq &q = *sl.req;
     double bb = hs.bnorm2[k];
     double rel;
     int status;
@@ -1475,7 +1530,7 @@ void lane_collect(Server *sv, Lane &L) {
     sl = SSlot();
     sv->cols_done++;
   }
-  if (restart) lane_start(sv, L, restart, true);
+  if (restart) lane_start(L, restart, true);
   HIPCHK(hipStreamSynchronize(st));
   for (SReq *q : finished) finish_request(sv, *q);
 }
@@ -1483,6 +1538,7 @@ void lane_collect(Server *sv, Lane &L) {
 void server_loop(Server *sv) {
   (void)hipSetDevice(sv->device);
   while (true) {
+    int precision;
     {
       std::unique_lock<std::mutex> lk(sv->mu);
       auto has_work = [&]() {
@@ -1494,11 +1550,11 @@ void server_loop(Server *sv) {
       sv->cv.wait(lk, [&]() { return sv->stop || has_work(); });
       if (sv->stop && !has_work()) break;
       while (!sv->incoming.empty()) {
-        int64_t ri = sv->incoming.front();
+        SReq *q = sv->incoming.front();
         sv->incoming.pop_front();
-        SReq &q = *sv->reqs[ri];
-        for (int c = 0; c < q.nrhs; ++c) sv->lanes[q.mesh]->queue.emplace_back(ri, c);
+        for (int c = 0; c < q->nrhs; ++c) sv->lanes[q->mesh]->queue.emplace_back(q, c);
       }
+      precision = sv->opt.precision;
     }
     try {
       // admission, joins and launches: every lane's chunk is queued before
@@ -1509,24 +1565,29 @@ void server_loop(Server *sv) {
         if (!L.busy()) continue;
         if (!lane_admit(sv, L)) continue;
         L.last_used = ++sv->tick;
+        // a precision switch waits for every request to finish, so a lane
+        // that takes it is idle
+        L.h->opt.precision = precision;
         unsigned mask = 0;
         for (int k = 0; k < kMaxBatch && !L.queue.empty(); ++k)
-          if (L.slot[k].req < 0) {
+          if (!L.slot[k].req) {
             L.slot[k] = SSlot();
             L.slot[k].req = L.queue.front().first;
             L.slot[k].col = L.queue.front().second;
             L.queue.pop_front();
             mask |= 1u << k;
           }
-        if (mask) lane_start(sv, L, mask, false);
+        if (mask) lane_start(L, mask, false);
         int active = 0;
-        for (auto &sl : L.slot) active += sl.req >= 0;
+        for (auto &sl : L.slot) active += sl.req != nullptr;
         if (!active) continue;
         int kind = L.h->opt.precision != VEMG_FP64 ? kGraphMixedPC : kGraphFP64;
         for (int it = 0; it < L.h->opt.poll_every; ++it) run_iteration<double>(L.h, kMaxBatch, kind);
+        HIPCHK(hipMemcpyAsync(L.scal_host, L.h->scal, sizeof(Scal), hipMemcpyDeviceToHost, L.h->work));
+        HIPCHK(hipEventRecord(L.scal_ready, L.h->work));
         L.launched = true;
         sv->chunks++;
-        sv->occupancy_sum += active / (double)kMaxBatch;
+        sv->active_slots += active;
       }
       for (auto &Lp : sv->lanes)
         if (Lp->launched) lane_collect(sv, *Lp);
@@ -1540,7 +1601,7 @@ void server_loop(Server *sv) {
           q->done = true;
           q->status = VEMG_ERR_DEVICE;
           q->t_done = now_s();
-          sv->completed.push_back(sv->by_id[q->id]);
+          sv->completed.push_back(q.get());
         }
       for (auto &L : sv->lanes) {
         L->queue.clear();
@@ -1551,6 +1612,63 @@ void server_loop(Server *sv) {
       break;
     }
   }
+}
+
+}  // namespace
+}  // namespace vemg
+
+namespace vemg {
+namespace {
+
+bool valid_options(const vemg_options &opt) {
+  return !(opt.top_bc < 0 || opt.top_bc > 2 ||
+           (opt.top_bc == VEMG_TOP_ROBIN && !(opt.robin_alpha > 0.0 && std::isfinite(opt.robin_alpha))) ||
+           opt.pc < 0 || opt.pc > 5 || opt.max_levels < 1 || opt.max_levels > 16 || opt.coarse_max < 1 ||
+           opt.coarse_max > 8192 || !(opt.theta >= 0.0) || opt.poll_every < 1 || opt.precision < 0 ||
+           opt.precision > 2 || !(opt.inner_rtol > 0.0 && opt.inner_rtol < 1.0) || opt.max_outer < 1 ||
+           opt.extrapolation < 0 || opt.extrapolation > 1);
+}
+
+// A handle on `device`.  pool == nullptr: the handle creates its own two work
+// streams; otherwise it runs on pool[0] (Krylov part, first branch) and
+// pool[1] (second branch), which stay the caller's.
+vemg_status create_handle(const vemg_options *o, int device, hipStream_t user, const hipStream_t *pool,
+                          vemg_solver *out) {
+  if (!out) return VEMG_ERR_INVALID_ARG;
+  *out = nullptr;
+  vemg_options opt;
+  if (o)
+    opt = *o;
+  else
+    vemg_default_options(&opt);
+  if (!valid_options(opt)) return VEMG_ERR_INVALID_ARG;
+  auto *h = new (std::nothrow) vemg_solver_s();
+  if (!h) return VEMG_ERR_OOM;
+  h->opt = opt;
+  h->device = device;
+  h->user = user;
+  int st = guarded(h, [&]() -> int {
+    if (device >= 0) {
+      if (pool) {
+        h->own_streams = false;
+        h->work = pool[0];
+        h->work2 = pool[1];
+      } else {
+        HIPCHK(create_queue_stream(device, &h->work));
+        HIPCHK(create_queue_stream(device, &h->work2));
+      }
+      HIPCHK(hipEventCreateWithFlags(&h->ev, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    }
+    return VEMG_OK;
+  });
+  if (st != VEMG_OK) {
+    (void)vemg_destroy(h);  // releases whatever was created before the failure
+    return (vemg_status)st;
+  }
+  *out = h;
+  return VEMG_OK;
 }
 
 }  // namespace
@@ -1580,51 +1698,7 @@ void vemg_default_options(vemg_options *o) {
 }
 
 vemg_status vemg_create(const vemg_options *o, int device, void *hip_stream, vemg_solver *out) {
-  if (!out) return VEMG_ERR_INVALID_ARG;
-  *out = nullptr;
-  vemg_options opt;
-  if (o)
-    opt = *o;
-  else
-    vemg_default_options(&opt);
-  if (opt.top_bc < 0 || opt.top_bc > 2 ||
-      (opt.top_bc == VEMG_TOP_ROBIN && !(opt.robin_alpha > 0.0 && std::isfinite(opt.robin_alpha))) ||
-      opt.pc < 0 || opt.pc > 5 || opt.max_levels < 1 || opt.max_levels > 16 ||
-      opt.coarse_max < 1 || opt.coarse_max > 8192 || !(opt.theta >= 0.0) || opt.poll_every < 1 ||
-      opt.precision < 0 || opt.precision > 2 || !(opt.inner_rtol > 0.0 && opt.inner_rtol < 1.0) || opt.max_outer < 1 ||
-      opt.extrapolation < 0 || opt.extrapolation > 1)
-    return VEMG_ERR_INVALID_ARG;
-  auto *h = new (std::nothrow) vemg_solver_s();
-  if (!h) return VEMG_ERR_OOM;
-  h->opt = opt;
-  h->device = device;
-  h->user = (hipStream_t)hip_stream;
-  int st = guarded(h, [&]() -> int {
-    if (device >= 0) {
-      // non-blocking streams: no implicit ordering with the legacy null
-      // stream, so another thread's work cannot join a graph being captured
-      // here (ordering with the caller's stream is explicit, see sync_in)
-      // Both work streams get dedicated hardware queues: a stream created with
-      // a CU mask (here every CU, so nothing is restricted) does not share its
-      // queue, so the two preconditioner branches cannot end up serialised
-      // behind each other or behind another stream's work.
-      hipDeviceProp_t prop;
-      HIPCHK(hipGetDeviceProperties(&prop, device));
-      std::vector<uint32_t> mask((prop.multiProcessorCount + 31) / 32, 0xffffffffu);
-      HIPCHK(hipExtStreamCreateWithCUMask(&h->work, (uint32_t)mask.size(), mask.data()));
-      HIPCHK(hipExtStreamCreateWithCUMask(&h->work2, (uint32_t)mask.size(), mask.data()));
-      HIPCHK(hipEventCreateWithFlags(&h->ev, hipEventDisableTiming));
-      HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-      HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
-    }
-    return VEMG_OK;
-  });
-  if (st != VEMG_OK) {
-    (void)vemg_destroy(h);  // releases whatever was created before the failure
-    return (vemg_status)st;
-  }
-  *out = h;
-  return VEMG_OK;
+  return vemg::create_handle(o, device, (hipStream_t)hip_stream, nullptr, out);
 }
 
 vemg_status vemg_setup(vemg_solver s, int64_t n_nodes, const double *xyz, int64_t n_tets, const int64_t *tets,
@@ -1647,7 +1721,12 @@ vemg_status vemg_setup(vemg_solver s, int64_t n_nodes, const double *xyz, int64_
     so.coarse_max = s->opt.coarse_max;
     s->P = vemg::Problem();
     vemg::build_problem(s->P, so, n_nodes, xyz, n_tets, tets, top_mask);
-    if (s->device >= 0) vemg::upload(s);
+    s->footprint = vemg::count_upload_bytes(s);
+    if (s->device >= 0) {
+      vemg::upload(s);
+      if (s->ar.bytes != s->footprint)
+        throw vemg::DeviceError(VEMG_ERR_DEVICE, "device allocations differ from the counted footprint");
+    }
     s->ready = true;
     s->err.clear();
     return VEMG_OK;
@@ -1751,6 +1830,13 @@ vemg_status vemg_get_info(vemg_solver s, vemg_info *info) {
   return VEMG_OK;
 }
 
+vemg_status vemg_footprint(vemg_solver s, int nrhs, size_t *bytes) {
+  if (!s || !bytes || nrhs < 0) return VEMG_ERR_INVALID_ARG;
+  if (!s->ready) return VEMG_ERR_STATE;
+  *bytes = s->footprint + (size_t)2 * (size_t)nrhs * (size_t)s->P.n_nodes * sizeof(double);
+  return VEMG_OK;
+}
+
 vemg_status vemg_export(vemg_solver s, const char *name, void *buf, size_t *bytes) {
   if (!s || !name || !bytes) return VEMG_ERR_INVALID_ARG;
   if (!s->ready) return VEMG_ERR_STATE;
@@ -1768,8 +1854,8 @@ vemg_status vemg_destroy(vemg_solver s) {
     if (s->ev) (void)hipEventDestroy(s->ev);
     if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
     if (s->ev_join) (void)hipEventDestroy(s->ev_join);
-    if (s->work) (void)hipStreamDestroy(s->work);
-    if (s->work2) (void)hipStreamDestroy(s->work2);
+    if (s->own_streams && s->work) (void)hipStreamDestroy(s->work);
+    if (s->own_streams && s->work2) (void)hipStreamDestroy(s->work2);
   }
   delete s;
   return VEMG_OK;
@@ -1797,15 +1883,25 @@ const char *vemg_last_error(vemg_solver s) { return s ? s->err.c_str() : ""; }
 vemg_status vemg_server_create(int device, size_t hbm_budget, const vemg_options *o, vemg_server *out) {
   if (!out || device < 0) return VEMG_ERR_INVALID_ARG;
   *out = nullptr;
+  vemg_options opt;
+  if (o)
+    opt = *o;
+  else
+    vemg_default_options(&opt);
+  if (!vemg::valid_options(opt)) return VEMG_ERR_INVALID_ARG;
   auto *sv = new (std::nothrow) vemg_server_s();
   if (!sv) return VEMG_ERR_OOM;
-  if (o)
-    sv->opt = *o;
-  else
-    vemg_default_options(&sv->opt);
+  sv->opt = opt;
   if (sv->opt.precision == VEMG_MIXED_IR) sv->opt.precision = VEMG_MIXED_PC;
   sv->device = device;
   sv->budget = hbm_budget;
+  hipError_t e = hipSetDevice(device);
+  for (int i = 0; e == hipSuccess && i < 2 * vemg::kServerStreamPairs; ++i)
+    e = vemg::create_queue_stream(device, &sv->streams[i]);
+  if (e != hipSuccess) {
+    (void)vemg_server_destroy(sv);
+    return e == hipErrorOutOfMemory ? VEMG_ERR_OOM : VEMG_ERR_DEVICE;
+  }
   *out = sv;
   return VEMG_OK;
 }
@@ -1818,59 +1914,75 @@ vemg_status vemg_server_add_mesh(vemg_server sv, int64_t n_nodes, const double *
     sv->err = "meshes must be added before the first submit";
     return VEMG_ERR_STATE;
   }
+  const int lane = (int)sv->lanes.size();
+  const hipStream_t *pair = &sv->streams[2 * (lane % vemg::kServerStreamPairs)];
   vemg_solver h = nullptr;
-  vemg_status st = vemg_create(&sv->opt, sv->device, nullptr, &h);
+  vemg_status st = vemg::create_handle(&sv->opt, sv->device, nullptr, pair, &h);
   if (st != VEMG_OK) return st;
-  st = vemg_setup(h, n_nodes, xyz, n_tets, tets, top_mask);
-  if (st != VEMG_OK) {
-    sv->err = h->err;
-    vemg_destroy(h);
-    return st;
-  }
-  // capture both iteration graphs now, while no other thread uses the device
+  // a mesh that alone exceeds the budget is refused before its upload
+  auto L = std::make_unique<vemg::Lane>();
+  L->h = h;
   int gst = guarded(h, [&]() -> int {
+    h->device = -1;  // host setup only: the footprint is counted, nothing uploaded yet
+    vemg_status s2 = vemg_setup(h, n_nodes, xyz, n_tets, tets, top_mask);
+    h->device = sv->device;
+    if (s2 != VEMG_OK) return s2;
+    HIPCHK(hipSetDevice(sv->device));
+    L->footprint = h->footprint;
+    if (sv->budget && L->footprint > sv->budget) {
+      h->err = "mesh needs more device memory than the budget";
+      return VEMG_ERR_OOM;
+    }
+    HIPCHK(hipHostMalloc((void **)&L->scal_host, sizeof(vemg::Scal), hipHostMallocDefault));
+    HIPCHK(hipEventCreateWithFlags(&L->scal_ready, hipEventDisableTiming));
+    if (sv->budget && sv->used + L->footprint > sv->budget) return VEMG_OK;  // uploaded when needed
+    vemg::upload(h);
+    if (h->ar.bytes != L->footprint)
+      throw vemg::DeviceError(VEMG_ERR_DEVICE, "device allocations differ from the counted footprint");
+    // capture both iteration graphs now, while no other thread uses the device
     if (h->opt.use_graphs) {
       vemg::iteration_graphs<double>(h, vemg::kMaxBatch, vemg::kGraphFP64);
       vemg::iteration_graphs<double>(h, vemg::kMaxBatch, vemg::kGraphMixedPC);
       HIPCHK(hipStreamSynchronize(h->work));
     }
-    h->allow_capture = false;
+    L->resident = true;
+    sv->used += L->footprint;
+    sv->uploads++;
     return VEMG_OK;
   });
+  h->allow_capture = false;
   if (gst != VEMG_OK) {
     sv->err = h->err;
+    if (L->scal_host) (void)hipHostFree(L->scal_host);
+    if (L->scal_ready) (void)hipEventDestroy(L->scal_ready);
     vemg_destroy(h);
     return (vemg_status)gst;
   }
-  auto L = std::make_unique<vemg::Lane>();
-  L->h = h;
-  L->footprint = h->ar.bytes;
-  L->resident = true;
-  sv->used += L->footprint;
-  sv->uploads++;
-  if (sv->budget && L->footprint > sv->budget) {
-    sv->err = "mesh needs more device memory than the budget";
-    vemg_destroy(h);
-    sv->used -= L->footprint;
-    return VEMG_ERR_OOM;
-  }
-  if (sv->budget && sv->used > sv->budget) {
-    // keep the host setup; the scheduler uploads the mesh when it is needed
-    int r = guarded(h, [&]() -> int {
-      vemg::lane_release(sv, *L);
-      sv->evictions--;
-      return VEMG_OK;
-    });
-    if (r != VEMG_OK) return (vemg_status)r;
-  }
-  *mesh_id = (int)sv->lanes.size();
+  *mesh_id = lane;
   sv->lanes.push_back(std::move(L));
   return VEMG_OK;
 }
 
 vemg_status vemg_server_rhs(vemg_server sv, int mesh_id, const double *f_host, double *b_host) {
-  if (!sv || mesh_id < 0 || mesh_id >= (int)sv->lanes.size()) return VEMG_ERR_INVALID_ARG;
-  return vemg_rhs(sv->lanes[mesh_id]->h, f_host, b_host);
+  if (!sv) return VEMG_ERR_INVALID_ARG;
+  vemg_solver h;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (mesh_id < 0 || mesh_id >= (int)sv->lanes.size()) return VEMG_ERR_INVALID_ARG;
+    h = sv->lanes[mesh_id]->h;
+  }
+  return vemg_rhs(h, f_host, b_host);  // host arithmetic on the immutable host setup
+}
+
+vemg_status vemg_server_footprint(vemg_server sv, int mesh_id, int nrhs, size_t *bytes) {
+  if (!sv) return VEMG_ERR_INVALID_ARG;
+  vemg_solver h;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (mesh_id < 0 || mesh_id >= (int)sv->lanes.size()) return VEMG_ERR_INVALID_ARG;
+    h = sv->lanes[mesh_id]->h;
+  }
+  return vemg_footprint(h, nrhs, bytes);  // reads the footprint fixed at setup
 }
 
 vemg_status vemg_server_submit(vemg_server sv, int mesh_id, int nrhs, const double *b_dev, double *x_dev, double rtol,
@@ -1890,15 +2002,15 @@ vemg_status vemg_server_submit(vemg_server sv, int mesh_id, int nrhs, const doub
   q->b = b_dev;
   q->x = x_dev;
   q->rtol = rtol;
-  q->max_iter = max_iter;
+  q->max_iter = std::min(max_iter, 1 << 20);
   q->t_submit = vemg::now_s();
   q->cols_left = nrhs;
   q->iters.assign(nrhs, 0);
   q->rel.assign(nrhs, 0.0);
   if (sv->first_submit < 0) sv->first_submit = q->t_submit;
   if (req_id) *req_id = q->id;
-  sv->by_id[q->id] = (int64_t)sv->reqs.size();
-  sv->incoming.push_back((int64_t)sv->reqs.size());
+  sv->by_id[q->id] = q.get();
+  sv->incoming.push_back(q.get());
   sv->reqs.push_back(std::move(q));
   sv->cv.notify_all();
   return VEMG_OK;
@@ -1909,7 +2021,7 @@ vemg_status vemg_server_poll(vemg_server sv, uint64_t *done_ids, int cap, int *n
   std::lock_guard<std::mutex> lk(sv->mu);
   int k = 0;
   while (k < cap && !sv->completed.empty()) {
-    done_ids[k++] = sv->reqs[sv->completed.front()]->id;
+    done_ids[k++] = sv->completed.front()->id;
     sv->completed.pop_front();
   }
   *n_done = k;
@@ -1921,7 +2033,7 @@ vemg_status vemg_server_wait(vemg_server sv, uint64_t req_id, double timeout_s) 
   std::unique_lock<std::mutex> lk(sv->mu);
   auto it = sv->by_id.find(req_id);
   if (it == sv->by_id.end()) return VEMG_ERR_INVALID_ARG;
-  vemg::SReq *q = sv->reqs[it->second].get();
+  vemg::SReq *q = it->second;
   auto pred = [&]() { return q->done; };
   if (timeout_s > 0) {
     if (!sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) return VEMG_ERR_STATE;
@@ -1937,7 +2049,7 @@ vemg_status vemg_server_result(vemg_server sv, uint64_t req_id, int *status, int
   std::lock_guard<std::mutex> lk(sv->mu);
   auto it = sv->by_id.find(req_id);
   if (it == sv->by_id.end()) return VEMG_ERR_INVALID_ARG;
-  vemg::SReq &q = *sv->reqs[it->second];
+  const vemg::SReq &q = *it->second;
   if (!q.done) return VEMG_ERR_STATE;
   if (status) *status = q.status;
   for (int c = 0; c < q.nrhs; ++c) {
@@ -1978,10 +2090,11 @@ vemg_status vemg_server_get_stats(vemg_server sv, vemg_server_stats *st) {
   }
   if (sv->last_done > sv->first_submit && sv->first_submit >= 0) {
     st->busy_s = sv->last_done - sv->first_submit;
-    st->solves_per_s = (double)sv->cols_done / st->busy_s;
+    st->solves_per_s = (double)st->columns_done / st->busy_s;
   }
-  st->mean_slot_occupancy = sv->chunks ? sv->occupancy_sum / (double)sv->chunks : 0.0;
-  st->chunks = sv->chunks;
+  const int64_t chunks = sv->chunks;
+  st->mean_slot_occupancy = chunks ? (double)sv->active_slots / (double)(chunks * vemg::kMaxBatch) : 0.0;
+  st->chunks = chunks;
   st->uploads = sv->uploads;
   st->evictions = sv->evictions;
   st->resident_bytes = sv->used;
@@ -1993,16 +2106,15 @@ vemg_status vemg_server_set_precision(vemg_server sv, int precision) {
   if (!sv || precision < 0 || precision > 2) return VEMG_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> lk(sv->mu);
   if (!sv->incoming.empty()) return VEMG_ERR_STATE;
-  for (auto &L : sv->lanes)
-    if (L->busy()) return VEMG_ERR_STATE;
   for (auto &q : sv->reqs)
     if (!q->done) return VEMG_ERR_STATE;
-  int p = precision == VEMG_MIXED_IR ? VEMG_MIXED_PC : precision;
-  sv->opt.precision = p;
-  for (auto &L : sv->lanes) L->h->opt.precision = p;
+  // every request is done: the scheduler holds no slot and applies the new
+  // precision to a lane before its next chunk
+  sv->opt.precision = precision == VEMG_MIXED_IR ? VEMG_MIXED_PC : precision;
   sv->first_submit = sv->last_done = -1.0;
-  sv->chunks = sv->cols_done = 0;
-  sv->occupancy_sum = 0.0;
+  sv->chunks = 0;
+  sv->cols_done = 0;
+  sv->active_slots = 0;
   for (auto &q : sv->reqs) q->t_done = q->t_submit = 0.0;
   sv->reqs_base = (int64_t)sv->reqs.size();
   return VEMG_OK;
@@ -2016,7 +2128,14 @@ vemg_status vemg_server_destroy(vemg_server sv) {
     sv->cv.notify_all();
   }
   if (sv->worker.joinable()) sv->worker.join();
-  for (auto &L : sv->lanes) vemg_destroy(L->h);
+  (void)hipSetDevice(sv->device);
+  for (auto &L : sv->lanes) {
+    vemg_destroy(L->h);
+    if (L->scal_host) (void)hipHostFree(L->scal_host);
+    if (L->scal_ready) (void)hipEventDestroy(L->scal_ready);
+  }
+  for (hipStream_t st : sv->streams)
+    if (st) (void)hipStreamDestroy(st);
   delete sv;
   return VEMG_OK;
 }

@@ -677,8 +677,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Scal *s, const double *pb, 
   }
   if (threadIdx.x == 0) {
     s->K = K;
-    s->tol2 = tol * tol;
-    s->maxit = maxit;
+    for (int k = 0; k < kMaxBatch; ++k) {
+      s->tol2[k] = tol * tol;
+      s->maxit[k] = maxit;
+    }
     update_all_done(s);
   }
 }
@@ -783,9 +785,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_conv(Scal *s, const double *p, i
       int status = 0;
       if (!isfinite(rr))
         status = -6;
-      else if (rr <= s->tol2 * s->bnorm2[k])
+      else if (rr <= s->tol2[k] * s->bnorm2[k])
         status = 1;
-      else if (it >= s->maxit)
+      else if (it >= s->maxit[k])
         status = 2;
       if (status != 0) {
         done = 1;
@@ -852,7 +854,7 @@ __global__ void k_slot_vectors(unsigned mask, int restart, const double *__restr
 }
 
 __global__ __launch_bounds__(kBlock) void k_slot_scalars(unsigned mask, int restart, Scal *s, const double *pb,
-                                                         int64_t npb, double tol, int maxit, double *scale_in,
+                                                         int64_t npb, SlotStop stop, double *scale_in,
                                                          double *scale_out) {
   double sums[kMaxBatch];
   sum_partials(pb, npb, kMaxBatch, sums);
@@ -863,6 +865,8 @@ __global__ __launch_bounds__(kBlock) void k_slot_scalars(unsigned mask, int rest
       if (!restart) {
         s->bnorm2[k] = t;
         s->iters[k] = 0;
+        s->tol2[k] = stop.tol[k] * stop.tol[k];
+        s->maxit[k] = stop.maxit[k];
         double nb = sqrt(t);
         bool ok = t > 0.0 && isfinite(t);
         scale_in[k] = ok ? 1.0 / nb : 0.0;
@@ -883,8 +887,6 @@ __global__ __launch_bounds__(kBlock) void k_slot_scalars(unsigned mask, int rest
   }
   if (threadIdx.x == 0) {
     s->K = kMaxBatch;
-    s->tol2 = tol * tol;
-    s->maxit = maxit;
     update_all_done(s);
   }
 }
@@ -914,8 +916,8 @@ void launch_slot_vectors(hipStream_t stm, unsigned mask, bool restart, const dou
                      hi, lo, x, r, n);
 }
 void launch_slot_scalars(hipStream_t stm, unsigned mask, bool restart, Scal *s, const double *pb, int64_t npb,
-                         double tol, int maxit, double *scale_in, double *scale_out) {
-  hipLaunchKernelGGL(k_slot_scalars, dim3(1), dim3(kBlock), 0, stm, mask, (int)restart, s, pb, npb, tol, maxit,
+                         const SlotStop &stop, double *scale_in, double *scale_out) {
+  hipLaunchKernelGGL(k_slot_scalars, dim3(1), dim3(kBlock), 0, stm, mask, (int)restart, s, pb, npb, stop,
                      scale_in, scale_out);
 }
 void launch_slot_rho(hipStream_t stm, unsigned mask, Scal *s, const double *p, int64_t np) {

@@ -61,10 +61,18 @@ struct CsrG {
 struct Scal {
   double rho[kMaxBatch], alpha[kMaxBatch], beta[kMaxBatch], bnorm2[kMaxBatch], rr[kMaxBatch],
       pq[kMaxBatch];
-  double tol2;
+  double tol2[kMaxBatch];  // squared relative tolerance of each column
   int done[kMaxBatch], iters[kMaxBatch], status[kMaxBatch];  // status: 0 running, 1 converged,
                                                             // 2 max_iter, -6 breakdown
-  int all_done, maxit, K;
+  int maxit[kMaxBatch];  // iteration cap of each column
+  int all_done, K;
+};
+
+// Stopping parameters of the slots that (re)start in a continuous batch:
+// each column converges on its own request's tolerance and iteration cap.
+struct SlotStop {
+  double tol[kMaxBatch];
+  int maxit[kMaxBatch];
 };
 
 inline int64_t sell_blocks(int64_t r0, int64_t r1) {
@@ -176,7 +184,7 @@ void launch_slot_vectors(hipStream_t st, unsigned mask, bool restart, const doub
 // (1 for a zero right-hand side), status_k = 0, and the FP32 scaling of the
 // preconditioner input scale_in_k = 1/||b_k||, scale_out_k = ||b_k||
 void launch_slot_scalars(hipStream_t st, unsigned mask, bool restart, Scal *s, const double *pb, int64_t npb,
-                         double tol, int maxit, double *scale_in, double *scale_out);
+                         const SlotStop &stop, double *scale_in, double *scale_out);
 // rho_k from the partials of r.z, for the columns in mask
 void launch_slot_rho(hipStream_t st, unsigned mask, Scal *s, const double *p, int64_t np);
 // p_k = z_k for the columns in mask

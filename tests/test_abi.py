@@ -99,6 +99,49 @@ def test_plain_c_consumer(tmp_path):
     assert int(got["s_levels"]) == info["s_levels"] and int(got["abar_levels"]) == info["abar_levels"]
     assert int(got["perm_checksum"]) == int(np.sum(perm * np.arange(1, perm.size + 1)))
     assert int(got["solve"]) == -7  # VEMG_ERR_STATE: no device
+    # footprint of a host-only handle: counted without a device; b and x of
+    # three columns add 2 * 3 * n_nodes doubles
+    fp0, fp3 = int(got["footprint0"]), int(got["footprint3"])
+    assert fp0 > 0 and int(got["device_bytes"]) == 0
+    assert fp3 - fp0 == 2 * 3 * m.n * 8
+    assert s.footprint(0) == fp0
+
+
+def build_consumer(tmp_path):
+    import shutil
+    import subprocess
+
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    libdir = os.path.join(root, "paper_0912_1976_amd")
+    exe = tmp_path / "consumer"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                    "-I", os.path.join(root, "include"), os.path.join(root, "tests", "abi_c", "consumer.c"),
+                    "-L", libdir, "-lvemg", "-Wl,-rpath," + libdir, "-o", str(exe)], check=True)
+    return exe
+
+
+def write_mesh(path, m):
+    with open(path, "wb") as f:
+        np.array([m.n, m.tets.shape[0]], dtype=np.int64).tofile(f)
+        np.ascontiguousarray(m.xyz, dtype=np.float64).tofile(f)
+        np.ascontiguousarray(m.tets, dtype=np.int64).tofile(f)
+        np.ascontiguousarray(m.top, dtype=np.uint8).tofile(f)
+
+
+def test_footprint_arguments():
+    m = box_mesh(6, 5, 4, 0.01, jitter=0.2, seed=3)
+    s = lib_mod.Solver(m.xyz, m.tets, m.top, device=-1)
+    lib = s._lib
+    nb = C.c_size_t(0)
+    assert lib.vemg_footprint(s._h, -1, C.byref(nb)) == -1
+    assert lib.vemg_footprint(s._h, 0, None) == -1
+    assert lib.vemg_footprint(None, 0, C.byref(nb)) == -1
+    # a larger problem holds more
+    big = box_mesh(12, 11, 6, 0.01, jitter=0.2, seed=3)
+    sb = lib_mod.Solver(big.xyz, big.tets, big.top, device=-1)
+    assert sb.footprint(0) > s.footprint(0) > 0
 
 
 def test_missing_library_fails_loudly(monkeypatch):
