@@ -1,21 +1,27 @@
 """Benchmark of the vertical-extrapolation multigrid PCG on one MI355X.
 
-Headline workload: thin box 129 x 129 x 33 vertices (549,152 free unknowns),
-aspect ratio 1e-3, bathymetric floor z = -H(1 + 0.3 sin 2 pi x sin 2 pi y),
-+-0.3 h seeded horizontal jitter of every interior vertex on every layer,
-6 P1 tetrahedra per cell, point condition on the top (Neumann elsewhere),
-right-hand side b = M f for a seeded 16-mode smooth random field, relative
-residual tolerance 1e-8, vertical lumping + additive smoother, FP64.  One
-step = one complete solve (setup excluded), inputs resident in HBM.
+Headline workload (one step = one solve of a batch of right-hand sides,
+setup excluded, inputs resident in HBM): the thin box of 257 x 257 x 33
+vertices (2,179,616 free unknowns), aspect ratio 1e-4, bathymetric floor
+z = -H(1 + 0.3 sin 2 pi x sin 2 pi y), +-0.3 h seeded horizontal jitter of
+every interior vertex on every layer, 6 P1 tetrahedra per cell, point
+condition on the top (Neumann elsewhere), eight right-hand sides b = M f of
+seeded 16-mode smooth random fields solved together (one SpMM-style batch),
+relative residual 1e-8 for every column, vertical lumping + additive
+smoother, FP64.  value = unknowns x iterations summed over the columns, per
+second.
 
-Also measured (reported beside the headline in the same JSON line): eight
-right-hand sides per launch, the two mixed-precision forms, the serving
-stream over six resident meshes (continuous batching; saturated and Poisson
-arrivals; mixed precision vs FP64), the free-surface (Robin) top, plain
-smoothed aggregation against the lumping method at three aspect ratios, the
-projected vs SSPAI-refitted extrapolation, the 257 x 257 x 33 and graded
-multiscale configurations, live kernel timings for the roofline, and the
-CPU oracle on a bounded sample of the headline solve.
+Beside it in the same JSON line: the mixed-precision forms on the same batch
+with every column's error against the FP64 oracle (sampled fixture), the
+dominant kernel's roofline and the whole iteration's algorithmic bytes
+against its time, the other configurations (17 x 17 x 9 at 1e-10 and the
+129 x 129 x 33 box, each with the point condition and the Dirichlet top;
+the 4.0M-unknown graded multiscale mesh; the 512-request serving stream over
+six resident meshes, mixed precision against FP64), and the CPU oracle
+timed on a bounded sample of the headline workload in a child process on
+one host core (it runs while the GPU is measured).  --paper-comparisons adds
+the comparisons of Section 6 (smoothed aggregation against the lumping
+method, VL + SOR), the free-surface top and the SSPAI extrapolation.
 
 Profiling helpers (no GPU): --pmc-summary and --pmc-traffic read rocprofv3
 counter passes (FETCH_SIZE, WRITE_SIZE) of --profile-kernels runs;
@@ -34,10 +40,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
-    "thinbox-129x129x33-eps1e-3": dict(nx=129, nz=33, H=1e-3, jitter=0.3, seed=2, bathymetry=True, rhs_seed=100),
-    "thinbox-257x257x33-eps1e-4": dict(nx=257, nz=33, H=1e-4, jitter=0.3, seed=4, bathymetry=True, rhs_seed=200),
-    "thinbox-17x17x9-eps1e-2": dict(nx=17, nz=9, H=1e-2, jitter=0.2, seed=1, bathymetry=False, rhs_seed=100),
+    "thinbox-257x257x33-eps1e-4": dict(kind="box", nx=257, nz=33, H=1e-4, jitter=0.3, seed=4, bathymetry=True,
+                                       rhs_seed=200, nrhs=8, rtol=1e-8),
+    "thinbox-129x129x33-eps1e-3": dict(kind="box", nx=129, nz=33, H=1e-3, jitter=0.3, seed=2, bathymetry=True,
+                                       rhs_seed=100, nrhs=1, rtol=1e-8),
+    "thinbox-17x17x9-eps1e-2": dict(kind="box", nx=17, nz=9, H=1e-2, jitter=0.2, seed=1, bathymetry=False,
+                                    rhs_seed=100, nrhs=1, rtol=1e-10),
+    "graded-hmin1/960-eps1e-3": dict(kind="graded", h_min=1 / 960, H=1e-3, jitter=0.25, seed=3, nrhs=1,
+                                     rtol=1e-8),
 }
+HEADLINE = "thinbox-257x257x33-eps1e-4"
 # serving meshes: (n, layers, H), seeds 5..10 -> 10,625 ... 2,179,617 nodes
 SERVE_MESHES = [(25, 17, 1e-2), (49, 21, 4e-3), (97, 21, 1.6e-3), (129, 33, 6.3e-4), (177, 33, 2.5e-4),
                 (257, 33, 1e-4)]
@@ -51,51 +63,124 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def spmv_bytes(info, K=1, elt=8, val=8):
-    """Algorithmic bytes of one difference-form SpMV over all rows: every
-    stored off-diagonal (value + 4-byte column), per row the deficit (or the
-    two FP32 row factors) and, per column of the batch, x_i, y_i and one
-    gathered x_j."""
-    return info["nnz_offdiag"] * (val + 4) + info["n"] * (8 + 3 * elt * K)
+def build_mesh(wl):
+    from inputs import box_mesh, graded_mesh
+    if wl["kind"] == "graded":
+        return graded_mesh(wl["h_min"], wl["H"], jitter=wl["jitter"], seed=wl["seed"])
+    return box_mesh(wl["nx"], wl["nx"], wl["nz"], wl["H"], jitter=wl["jitter"], seed=wl["seed"],
+                    bathymetry=wl["bathymetry"])
 
 
-def gs_sweep_bytes(info, K=1, elt=8, val=8):
-    """One forward multicolour sweep: every off-diagonal once, per row the
-    row factors and, per column, g_i, the read and write of x_i and one
-    gathered x_j."""
-    return info["nnz_offdiag"] * (val + 4) + info["n"] * (8 + 4 * elt * K)
+# ---------------------------------------------------------------------------
+# Algorithmic bytes: what each kernel must move at least, every stored array
+# (without padding) and every vector read or written once per pass, from the
+# sizes of the built arrays (vemg_info).  T = bytes per vector value, V = per
+# matrix value, K = columns of the batch; column indices and row pointers are
+# 4 bytes.  Fine rows carry one 8-byte row datum (the deficit in FP64, the two
+# FP32 row factors in mixed precision).
+# ---------------------------------------------------------------------------
+
+def spmv_bytes(info, K=1, elt=8, val=8, residual=False, rows=None, nnz=None):
+    """Difference-form SpMV y = A x (or y = g - A x): the off-diagonals and
+    the row datum, x read and y written (and g read)."""
+    n = info["n"] if rows is None else rows
+    nnz = info["nnz_offdiag"] if nnz is None else nnz
+    return nnz * (val + 4) + n * 8 + (3 if residual else 2) * n * elt * K
+
+
+def gs_sweep_bytes(info, K=1, elt=8, val=8, rows=None, nnz=None):
+    """One multicolour sweep (all colours): the off-diagonals and row datum,
+    g read, x read and written once."""
+    n = info["n"] if rows is None else rows
+    nnz = info["nnz_offdiag"] if nnz is None else nnz
+    return nnz * (val + 4) + n * 8 + 3 * n * elt * K
+
+
+def csr_level_bytes(rows, off, K, elt, val):
+    """Coarse square level (CSR, diagonal apart): one sweep, and one residual."""
+    sweep = off * (val + 4) + rows * (4 + 8) + 3 * rows * elt * K
+    return sweep, sweep
+
+
+def transfer_bytes(p_nnz, rows, rows_c, K, elt, val):
+    """Restriction (CSR of P^T: rows_c rows) and prolongation added into the
+    fine vector (P: rows rows)."""
+    restrict = p_nnz * (val + 4) + rows_c * 4 + rows * elt * K + rows_c * elt * K
+    prolong = p_nnz * (val + 4) + rows * 4 + rows_c * elt * K + 2 * rows * elt * K
+    return restrict, prolong
 
 
 def coarse_gs_bytes(info, level=1, K=1, elt=8, val=8):
-    """One forward multicolour sweep on a coarse A_bar level (CSR, standard
-    form without the diagonal): every off-diagonal once (value + column), per
-    row the row pointer, the diagonal and, per column, g_i, the read and
-    write of x_i and one gathered x_j."""
-    off = info["abar_nnz"][level] - info["abar_rows"][level]
-    return off * (val + 4) + info["abar_rows"][level] * (4 + 8 + 4 * elt * K)
+    """One forward sweep on A_bar level `level` (all its colours)."""
+    return csr_level_bytes(info["abar_rows"][level], info["abar_nnz"][level], K, elt, val)[0]
 
 
 def restrict_bytes(info, K=1, elt=8, val=8):
-    """The restriction g = E~^T r (CSR of E~^T): every stored entry (value +
-    column), r read once, per surface row the row pointer and the output."""
-    return info["e_nnz"] * (val + 4) + info["n"] * elt * K + info["n_top"] * (4 + elt * K)
+    """g = E~^T r (CSR of E~^T, rows in spatial order with a map back)."""
+    m = info["n_top"]
+    return info["e_nnz"] * (val + 4) + m * (4 + 4) + info["n"] * elt * K + m * elt * K
 
 
 def prolong_bytes(info, K=1, elt=8, val=8):
-    """The prolongation z += E~ y: every stored entry (value + column), z read
-    and written once, y read once."""
-    return info["e_nnz"] * (val + 4) + 2 * info["n"] * elt * K + info["n_top"] * elt * K
+    """z += E~ y: the entries, y read, z read and written."""
+    return info["e_nnz"] * (val + 4) + info["n_top"] * elt * K + 2 * info["n"] * elt * K
 
 
-def kernel_rates(s, info, vemg, K=1, reps=20):
+def vcycle_bytes(rows, off, pnnz, K, elt, val, fine_rows=None, fine_nnz=None):
+    """One V(1,1)-cycle: per level two sweeps, the residual, the restriction
+    and the prolongation; the coarsest level's dense inverse.  The finest
+    level of A_bar is the fine SELL operator's non-top rows."""
+    total = 0
+    L = len(rows)
+    for l in range(L):
+        m = rows[l]
+        if l == L - 1:
+            total += m * m * 8 + 2 * m * elt * K
+            break
+        if l == 0 and fine_rows is not None:
+            sw = gs_sweep_bytes(None, K, elt, val, rows=fine_rows, nnz=fine_nnz)
+            res = spmv_bytes(None, K, elt, val, residual=True, rows=fine_rows, nnz=fine_nnz)
+        else:
+            sw, res = csr_level_bytes(m, off[l], K, elt, val)
+        r, p = transfer_bytes(pnnz[l], m, rows[l + 1], K, elt, val)
+        total += 2 * sw + res + r + p
+    return total
+
+
+def iteration_bytes(info, K=1, pc="vl_as", precision="fp64"):
+    """Algorithmic bytes of one PCG iteration (preconditioner included) for a
+    batch of K columns, from the built arrays' sizes.  Mixed precision: the
+    preconditioner in FP32 (values and vectors), the Krylov part in FP64, plus
+    the demotion of r and promotion of z."""
+    n = info["n"]
+    pe, pv = (4, 4) if precision != "fp64" else (8, 8)
+    krylov = spmv_bytes(info, K) + 6 * n * 8 * K + 3 * n * 8 * K   # q = A p with p.q; x, r update; p = z + beta p
+    sor = (2 * gs_sweep_bytes(info, K, pe, pv) + spmv_bytes(info, K, pe, pv, residual=True)
+           + restrict_bytes(info, K, pe, pv) + prolong_bytes(info, K, pe, pv)) if info["n_top"] else 0
+    s_cycle = vcycle_bytes(info["s_rows"], info["s_nnz"], info["p_nnz_s"], K, pe, pv) if info["n_top"] else 0
+    nbar = info["n"] - info["n_top"]
+    a_cycle = vcycle_bytes(info["abar_rows"], info["abar_nnz"], info["p_nnz_abar"], K, pe, pv,
+                           fine_rows=nbar, fine_nnz=info["abar_nnz"][0])
+    join = 4 * n * pe * K + n * 8 * K  # z += w over the non-top rows with r.z; (mixed) r read for the dot
+    mixed = (n * 8 * K + n * 4 * K) * 2 if precision != "fp64" else 0
+    if pc == "vl_sor":
+        return krylov + sor + s_cycle + n * pe * K * 2 + mixed
+    if pc == "vl_add":
+        return (krylov + restrict_bytes(info, K, pe, pv) + s_cycle + a_cycle + prolong_bytes(info, K, pe, pv)
+                + join + mixed)
+    return krylov + sor + s_cycle + a_cycle + join + mixed
+
+
+def kernel_rates(s, info, vemg, K=1, reps=20, precision="fp64"):
     """Live per-application times of the hot operators of one iteration
     (HIP events on the library's stream) and their algorithmic rates."""
+    pe, pv = (4, 4) if precision == "mixed_ir" else (8, 8)
     out = {}
-    for name, op, nbytes in (("spmv", vemg.OP_A, spmv_bytes(info, K)),
-                             ("fine_sweep", vemg.OP_GS_FWD, gs_sweep_bytes(info, K)),
-                             ("coarse_sweep", vemg.OP_GS_COARSE, coarse_gs_bytes(info, K=K)),
-                             ("restrict_Et", vemg.OP_ET, restrict_bytes(info, K)),
-                             ("prolong_E", vemg.OP_E, prolong_bytes(info, K))):
+    for name, op, nbytes in (("spmv", vemg.OP_A, spmv_bytes(info, K, pe, pv)),
+                             ("fine_sweep", vemg.OP_GS_FWD, gs_sweep_bytes(info, K, pe, pv)),
+                             ("coarse_sweep", vemg.OP_GS_COARSE, coarse_gs_bytes(info, 1, K, pe, pv)),
+                             ("restrict_Et", vemg.OP_ET, restrict_bytes(info, K, pe, pv)),
+                             ("prolong_E", vemg.OP_E, prolong_bytes(info, K, pe, pv))):
         try:
             ms, nl = s.time_op(op, reps=reps, nrhs=K)
         except vemg.VemgError:
@@ -105,21 +190,35 @@ def kernel_rates(s, info, vemg, K=1, reps=20):
     return out
 
 
-# Fine-level sweeps, fine SpMVs and coarse (first coarse level of A_bar and
-# the surface operator) sweeps per PCG iteration, by preconditioner:
-#   vl_as:  SOR cycle (2 fine sweeps, 1 residual SpMV, 2 sweeps on S) and the
-#           A_bar V-cycle (2 fine sweeps over the non-top rows, 1 residual
-#           SpMV, 2 sweeps on A_bar level 1), plus the CG product
+# Fine-level sweeps, fine SpMVs and sweeps on A_bar's first coarse level per
+# PCG iteration, by preconditioner (the surface levels are not timed apart):
+#   vl_as:  SOR cycle (2 fine sweeps, 1 residual SpMV) and the A_bar V-cycle
+#           (2 fine sweeps over the non-top rows, 1 residual SpMV, 2 sweeps on
+#           A_bar level 1), plus the CG product
 #   vl_sor: the SOR cycle alone plus the CG product
-#   vl_add: both V-cycles without the SOR cycle plus the CG product
-PER_ITERATION = {"vl_as": (4, 3, 4), "vl_sor": (2, 2, 2), "vl_add": (2, 2, 4), "jacobi": (0, 1, 0),
+#   vl_add: the A_bar V-cycle plus the CG product
+PER_ITERATION = {"vl_as": (4, 3, 2), "vl_sor": (2, 2, 0), "vl_add": (2, 2, 2), "jacobi": (0, 1, 0),
                  "none": (0, 1, 0)}
-KERNEL_NAMES = {"gs": "k_gs<double, 1, false> (fine multicolour SOR, one colour per launch)",
-                "spmv": "k_spmv<double, 1, 0, true> (fine difference-form SpMV fused with p.q)",
-                "cgs": "k_csr_gs<double, 1, 32, false> (coarse multicolour SOR, one colour per launch)",
-                "et": "k_csr_spmv<double, 1, 64, 2> (restriction E~^T, CSR, 64 lanes per surface row)",
-                "e": "k_rect<double, 1, true> (prolongation z += E~ y, SELL, one thread per fine row)"}
+KERNEL_NAMES = {
+    "gs": "k_gs<double, {K}, false> (fine multicolour SOR, one colour per launch)",
+    "spmv": "k_spmv<double, {K}, 0, true> (fine difference-form SpMV fused with p.q)",
+    "cgs": "k_csr_gs<double, {K}, 32, false> (coarse multicolour SOR, one colour per launch)",
+    "et": "k_csr_spmv<double, {K}, 64, 2> (restriction E~^T, CSR, 64 lanes per surface row)",
+    "e": "k_rect<double, {K}, true> (prolongation z += E~ y, SELL, one thread per fine row)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+
+
+def dominant_kernel(rates, pc, K):
+    """The hot kernel with the largest share of one iteration's time: its
+    algorithmic bytes and average duration per launch (the roofline entry)."""
+    n_gs, n_spmv, n_cgs = PER_ITERATION[pc]
+    share = {"gs": n_gs * rates["fine_sweep"]["ms"], "spmv": n_spmv * rates["spmv"]["ms"],
+             "cgs": n_cgs * rates.get("coarse_sweep", {"ms": 0.0})["ms"]}
+    key = max(share, key=share.get)
+    r = rates[{"gs": "fine_sweep", "spmv": "spmv", "cgs": "coarse_sweep"}[key]]
+    return key, {"kernel": KERNEL_NAMES[key].format(K=K), "bytes_per_launch": r["bytes"] / r["launches"],
+                 "ms_per_launch": r["ms"] / r["launches"], "launches_per_application": r["launches"],
+                 "ms_per_iteration_estimate": share}
 
 
 def _kernel_source_hash():
@@ -131,17 +230,18 @@ def _kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_key, workload):
+def measured_traffic(kernel_key, workload, K):
     """HBM bytes per launch of a kernel from the committed rocprofv3 PMC
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel's reading),
-    or None when there is none for this kernel and workload or the kernel
-    sources changed since the counters were taken."""
+    or None when there is none for this kernel, workload and batch width, or
+    the kernel sources changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("source_hash") != _kernel_source_hash() or rec.get("workload") != workload:
+    if (rec.get("source_hash") != _kernel_source_hash() or rec.get("workload") != workload
+            or rec.get("K", 1) != K):
         return None
     k = rec.get("kernels", {}).get(kernel_key)
     return None if k is None else k.get("hbm_bytes_per_launch")
@@ -154,11 +254,8 @@ def profile_kernels(workload, K=1):
     import torch
 
     import paper_0912_1976_amd as vemg
-    from inputs import box_mesh
 
-    wl = WORKLOADS[workload]
-    mesh = box_mesh(wl["nx"], wl["nx"], wl["nz"], wl["H"], jitter=wl["jitter"], seed=wl["seed"],
-                    bathymetry=wl["bathymetry"])
+    mesh = build_mesh(WORKLOADS[workload])
     s = vemg.Solver(mesh.xyz, mesh.tets, mesh.top, top_bc="pinned", pc="vl_as", device=0)
     info = s.info()
     for name, op in (("fine sweep", vemg.OP_GS_FWD), ("fine spmv", vemg.OP_A), ("coarse sweep", vemg.OP_GS_COARSE),
@@ -175,12 +272,17 @@ def profile_kernels(workload, K=1):
 
 
 CALIBRATION_BYTES = 512 << 20
-PMC_KERNELS = {"gs": "k_gs<double, 1, false>", "spmv": "k_spmv<double, 1, 0, true>",
-               "cgs": "k_csr_gs<double, 1, 32, false>", "et": "k_csr_spmv<double, 1, 64, 2>",
-               "e": "k_rect<double, 1, true>", "calibration": "MulFunctor"}
 
 
-def _pmc_means(path, counter):
+def pmc_kernels(K):
+    """Kernel-name patterns of the hot kernels with K columns (and of the
+    calibration copy) in rocprofv3 output."""
+    return {"gs": f"k_gs<double, {K}, false>", "spmv": f"k_spmv<double, {K}, 0, true>",
+            "cgs": f"k_csr_gs<double, {K}, 32, false>", "et": f"k_csr_spmv<double, {K}, 64, 2>",
+            "e": f"k_rect<double, {K}, true>", "calibration": "MulFunctor"}
+
+
+def _pmc_means(path, counter, K):
     import csv
     import glob
     files = [path] if path.endswith(".csv") else glob.glob(os.path.join(path, "**", "*counter_collection.csv"),
@@ -191,7 +293,7 @@ def _pmc_means(path, counter):
             for row in csv.DictReader(fh):
                 if row["Counter_Name"] != counter:
                     continue
-                for key, pat in PMC_KERNELS.items():
+                for key, pat in pmc_kernels(K).items():
                     if pat in row["Kernel_Name"]:
                         t = out.setdefault(key, [0.0, 0])
                         t[0] += float(row["Counter_Value"])
@@ -199,31 +301,32 @@ def _pmc_means(path, counter):
     return {k: v[0] / v[1] for k, v in out.items()}
 
 
-def pmc_traffic(fetch_dir, write_dir, workload):
+def pmc_traffic(fetch_dir, write_dir, workload, K):
     """HBM-side bytes per launch of the hot kernels from the two PMC passes:
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each divided by what the
     same counter reads for the calibration product (CALIBRATION_BYTES read
     and written once) relative to its true size."""
-    fetch = _pmc_means(fetch_dir, "FETCH_SIZE")
-    write = _pmc_means(write_dir, "WRITE_SIZE")
+    fetch = _pmc_means(fetch_dir, "FETCH_SIZE", K)
+    write = _pmc_means(write_dir, "WRITE_SIZE", K)
     kib = CALIBRATION_BYTES / 1024.0
     ff, wf = fetch["calibration"] / kib, write["calibration"] / kib
-    rec = {"workload": workload, "source_hash": _kernel_source_hash(),
+    cmd = f"python3 -u bench.py --profile-kernels --workload {workload} --profile-batch {K}"
+    rec = {"workload": workload, "K": K, "source_hash": _kernel_source_hash(),
            "calibration": {"bytes": CALIBRATION_BYTES, "fetch_factor": ff, "write_factor": wf},
-           "commands": [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o run -- "
-                        f"python3 -u bench.py --profile-kernels --workload {workload}",
-                        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {write_dir} -o run -- "
-                        f"python3 -u bench.py --profile-kernels --workload {workload}",
-                        f"python3 bench.py --pmc-traffic {fetch_dir} {write_dir} --workload {workload}"],
+           "commands": [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o run -- {cmd}",
+                        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {write_dir} -o run -- {cmd}",
+                        f"python3 bench.py --pmc-traffic {fetch_dir} {write_dir} --workload {workload} "
+                        f"--profile-batch {K}"],
            "kernels": {}}
     for key in ("gs", "spmv", "cgs", "et", "e"):
         if key in fetch and key in write:
-            rec["kernels"][key] = {"kernel": KERNEL_NAMES[key], "fetch_kib": fetch[key], "write_kib": write[key],
+            rec["kernels"][key] = {"kernel": KERNEL_NAMES[key].format(K=K), "fetch_kib": fetch[key],
+                                   "write_kib": write[key],
                                    "hbm_bytes_per_launch": 1024.0 * (fetch[key] / ff + write[key] / wf)}
     print(json.dumps(rec, indent=1))
 
 
-def trace_timed(path):
+def trace_timed(path, K):
     """Mean dispatch duration of each hot kernel over the live timing that
     follows the solves (its last run of consecutive dispatches, fills between
     them allowed), from a rocprofv3 kernel-trace CSV: the figure to set beside
@@ -238,8 +341,9 @@ def trace_timed(path):
             rows += [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]) for r in csv.DictReader(fh)]
     rows.sort()
     out = {}
+    pats = pmc_kernels(K)
     for key in ("spmv", "gs", "cgs"):
-        pat = PMC_KERNELS[key]
+        pat = pats[key]
         run, last = [], []
         for t0, t1, name in rows:
             if pat in name:
@@ -251,7 +355,7 @@ def trace_timed(path):
         if run:
             last = run
         if last:
-            out[key] = {"kernel": KERNEL_NAMES[key], "dispatches": len(last),
+            out[key] = {"kernel": KERNEL_NAMES[key].format(K=K), "dispatches": len(last),
                         "mean_us": sum(last) / len(last) / 1e3}
     print(json.dumps(out, indent=1))
 
@@ -297,28 +401,93 @@ def timed_solves(s, b, steps, warmup, rtol):
     return x, times, iters, rels, sts
 
 
-def cpu_baseline(mesh, wl, iters):
-    """The oracle as it stands, single-threaded, timed over `iters` PCG
-    iterations of the headline solve (its setup untimed)."""
-    import numpy as np  # noqa: F401
+def _cpu_baseline_child(workload, iters, core, queue):
+    """Child process: the oracle as it stands on one host core, its setup
+    untimed, then `iters` PCG iterations (VL + additive smoother) on column 0
+    of the workload timed."""
+    try:
+        os.sched_setaffinity(0, {core})
+    except (AttributeError, OSError):
+        pass
     from threadpoolctl import threadpool_limits
 
-    from inputs import fourier_field
+    from inputs import fourier_field, manufactured_u
     from oracle import pcg, precond, solver as osolver
 
+    wl = WORKLOADS[workload]
     with threadpool_limits(limits=1):
+        mesh = build_mesh(wl)
         t0 = time.perf_counter()
         o = osolver.setup(mesh, "N")
         t_setup = time.perf_counter() - t0
-        b = osolver.rhs_from_field(o, fourier_field(mesh.xyz, wl["H"], wl["rhs_seed"]))
+        if wl["kind"] == "graded":
+            b = osolver.rhs_from_solution(o, manufactured_u(mesh.xyz, wl["H"]))
+        else:
+            b = osolver.rhs_from_field(o, fourier_field(mesh.xyz, wl["H"], wl["rhs_seed"]))
         M = precond.make(o, "vl_as")
         t0 = time.perf_counter()
         _, it, _, _ = pcg.pcg(lambda v: osolver.apply_A(o, v), M, b, 0.0, max_iter=iters)
         t = time.perf_counter() - t0
-    return {"value": o.n * it / t, "unit": "DOF*iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{it} PCG iterations (VL + additive smoother) of the headline solve, oracle setup "
-                      f"{t_setup:.1f} s untimed",
-            "seconds": round(t, 3), "cpu": _cpu_model(), "host_cpus": os.cpu_count()}
+    queue.put({"value": o.n * it / t, "unit": "DOF*iters/s", "cores": 1, "kind": "oracle",
+               "sample": f"{it} PCG iterations (VL + additive smoother) of column 0 of the {workload} "
+                         f"workload (full mesh, {o.n} unknowns), oracle setup {t_setup:.1f} s untimed, "
+                         f"run in a child process pinned to host core {core} while the GPU was measured",
+               "seconds": round(t, 3), "setup_s": round(t_setup, 1), "cpu": _cpu_model(),
+               "host_cpus": os.cpu_count()})
+
+
+def start_cpu_baseline(workload, iters):
+    """Starts the oracle's timed sample in a child process on one host core
+    (the last one this process may use) and returns (process, queue)."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    q = ctx.Queue()
+    try:
+        core = max(os.sched_getaffinity(0))
+    except AttributeError:
+        core = 0
+    p = ctx.Process(target=_cpu_baseline_child, args=(workload, iters, core, q), daemon=True)
+    p.start()
+    return p, q
+
+
+def finish_cpu_baseline(handle, timeout):
+    p, q = handle
+    try:
+        out = q.get(timeout=timeout)
+    except Exception:
+        out = None
+    p.join(5)
+    if p.is_alive():
+        p.terminate()
+    return out
+
+
+def oracle_fixture(workload, mode="N"):
+    """The oracle's sampled FP64 solution of a workload (tests/golden), or
+    None: {column: (sample node array, values, norm2)}."""
+    import numpy as np
+    tag = workload.replace("/", "_")
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_samples_{tag}_{mode}.txt")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    nodes = np.asarray(rec["sample_nodes"], dtype=np.int64)
+    return {int(c): (nodes, np.array([float.fromhex(v) for v in col["values"]]), col["norm2"], col["iterations"])
+            for c, col in rec["columns"].items()}
+
+
+def error_vs_oracle(x_nat, fixture, col):
+    """Relative error of a solution against the oracle's on the fixture's
+    sample nodes: ||x - x_o||_S / ||x_o||_S (None without a fixture)."""
+    import numpy as np
+    if fixture is None or col not in fixture:
+        return None
+    nodes, vals, _, _ = fixture[col]
+    xs = x_nat[nodes]
+    return float(np.linalg.norm(xs - vals) / np.linalg.norm(vals))
 
 
 def _cpu_model():
@@ -332,11 +501,14 @@ def _cpu_model():
     return "unknown"
 
 
-def serving(nreq, seed, rtol, dev):
+def serving(nreq, seed, rtol, dev, calib=64):
     """Stream of solve requests over six resident meshes: each request picks a
-    mesh uniformly and 1..8 right-hand sides (seeded).  Run saturated (all
-    submitted at once) and with Poisson arrivals at 0.8x the saturated
-    request rate, in mixed precision and in FP64."""
+    mesh uniformly and 1..8 right-hand sides (seeded).  Per precision (mixed
+    first, the configuration's solver, then FP64 on the same plan): the first
+    `calib` requests submitted at once measure the saturated request rate,
+    then all `nreq` requests arrive as a Poisson stream at 0.8 times that
+    rate.  Every request is checked for status and relative residual, and
+    each column's mixed result against its FP64 result."""
     import numpy as np
     import torch
 
@@ -359,103 +531,118 @@ def serving(nreq, seed, rtol, dev):
     plan = [(int(rng.integers(0, len(meshes))), int(rng.integers(1, 9))) for _ in range(nreq)]
     cols = [rng.permutation(8)[:k] for _, k in plan]
 
-    def run(rate):
+    def run(count, rate, keep):
         rids = []
-        gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, nreq) if rate else np.zeros(nreq)
-        t_start = time.perf_counter()
-        t_next = t_start
-        for (mi, k), c, gap in zip(plan, cols, gaps):
+        gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, count) if rate else np.zeros(count)
+        t_next = time.perf_counter()
+        for (mi, k), c, gap in zip(plan[:count], cols[:count], gaps):
             t_next += gap
             d = t_next - time.perf_counter()
             if d > 0:
                 time.sleep(d)
             rids.append(srv.submit(meshes[mi], pools[mi][torch.as_tensor(c, device=dev)], rtol=rtol))
-        worst, floor = 0, 0
+        worst, floor, relmax, xs = 0, 0, 0.0, []
         for rid in rids:
-            srv.wait(rid, timeout=600.0)
+            srv.wait(rid, timeout=900.0)
             x, st, its, rel, lat = srv.result(rid)
             worst = min(worst, st) if st < 0 else max(worst, st)
             floor += int(st == 2)
+            relmax = max(relmax, max(rel))
+            if keep:
+                xs.append(x)
         s = srv.stats()
-        return {"requests": nreq, "columns": int(s["columns_done"]), "solves_per_s": s["solves_per_s"],
-                "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"], "mean_ms": s["mean_ms"], "max_ms": s["max_ms"],
-                "busy_s": s["busy_s"], "slot_occupancy": s["mean_slot_occupancy"], "worst_status": worst,
-                "requests_at_floor": floor, "arrival_rate_per_s": rate}
+        out = {"requests": count, "columns": int(s["columns_done"]), "solves_per_s": s["solves_per_s"],
+               "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"], "mean_ms": s["mean_ms"], "max_ms": s["max_ms"],
+               "busy_s": s["busy_s"], "slot_occupancy": s["mean_slot_occupancy"], "worst_status": worst,
+               "requests_at_floor": floor, "max_relres": relmax, "arrival_rate_per_s": rate}
+        return out, xs
 
-    out = {"meshes_nodes": sizes, "setup_s": t_setup, "rtol": rtol}
+    out = {"meshes_nodes": sizes, "setup_s": t_setup, "rtol": rtol, "requests": nreq,
+           "stream_pairs": 2}
+    results = {}
     for prec in ("mixed_pc", "fp64"):
         srv.set_precision(prec)
-        sat = run(0.0)
-        log(f"serving {prec} saturated: {sat['solves_per_s']:.1f} solves/s p50 {sat['p50_ms']:.1f} ms")
+        sat, _ = run(min(calib, nreq), 0.0, False)
         rate = 0.8 * sat["requests"] / sat["busy_s"]
+        log(f"serving {prec} saturated ({sat['requests']} requests): {sat['solves_per_s']:.1f} solves/s")
         srv.set_precision(prec)
-        poi = run(rate)
-        log(f"serving {prec} poisson {rate:.1f}/s: p50 {poi['p50_ms']:.1f} ms p99 {poi['p99_ms']:.1f} ms")
-        out[prec] = {"saturated": sat, "poisson": poi}
+        poi, xs = run(nreq, rate, True)
+        results[prec] = xs
+        log(f"serving {prec} poisson {rate:.2f}/s, {nreq} requests: {poi['solves_per_s']:.1f} solves/s, "
+            f"p50 {poi['p50_ms']:.1f} ms p99 {poi['p99_ms']:.1f} ms")
+        out[prec] = {"saturated_calibration": sat, "poisson": poi}
+    diffs = [float(torch.linalg.norm(a[k] - b[k]) / torch.linalg.norm(b[k]))
+             for a, b in zip(results["mixed_pc"], results["fp64"]) for k in range(a.shape[0])]
+    out["max_rel_diff_mixed_vs_fp64"] = max(diffs)
     srv.close()
     return out
 
 
-def config_runs(dev, rtol):
-    """The two other single-GPU configurations at full size.
-    * 257 x 257 x 33 thin box, eps 1e-4 (2.18M unknowns), eight seeded smooth
-      right-hand sides per solve: FP64, FP32 inner PCG inside FP64 iterative
-      refinement, and FP32 preconditioner in FP64 CG; solves/s and the error
-      of every column against the FP64 solution.
-    * Centre-refined multiscale thin box (h_min 1/900, 16-64 layers, eps 1e-3,
-      about 3.5M unknowns), b = A x* for the manufactured x*: VL + additive
-      smoother against VL + SOR (the paper's Mesh B comparison), iterations,
-      time to tolerance and the relative max-norm error against x*."""
+def timed_config(s, B, steps, warmup, rtol, info, fixture=None):
+    """Median time to tolerance of one solve of the batch B, with iterations,
+    statuses, relative residuals and errors against the oracle's fixture."""
+    import numpy as np
+    x, t, it, rel, st = timed_solves(s, B, steps, warmup, rtol)
+    med = float(np.median(t))
+    X = x.cpu().numpy().reshape(-1, x.shape[-1])
+    out = {"time_to_tol_ms": 1e3 * med, "iterations": it[0], "max_relres": max(rel[0]), "status": st[0],
+           "dof_iters_per_s": info["n"] * sum(it[0]) / med, "solves_per_s": X.shape[0] / med}
+    if fixture is not None:
+        errs = [error_vs_oracle(X[k], fixture, k) for k in range(X.shape[0])]
+        out["rel_err_vs_oracle_sampled"] = [e for e in errs]
+    return x, out
+
+
+def config_runs(dev, steps):
+    """The other configurations at full size, each with the point condition
+    (mode N) and the Dirichlet top (mode D):
+    * 17 x 17 x 9 box, eps 1e-2, tolerance 1e-10;
+    * 129 x 129 x 33 bathymetric box, eps 1e-3, tolerance 1e-8;
+    * centre-refined multiscale box (h_min 1/960, 16-64 layers, eps 1e-3,
+      3,974,225 nodes), b = A x* for the manufactured x* (the paper's error
+      protocol): VL + additive smoother and VL + SOR (the paper's Mesh B
+      comparison), iterations, time to tolerance and the error against x*."""
     import numpy as np
     import torch
 
     import paper_0912_1976_amd as vemg
-    from inputs import box_mesh, fourier_field, graded_mesh, manufactured_u
+    from inputs import fourier_field, manufactured_u
 
     out = {}
-    t0 = time.perf_counter()
-    m = box_mesh(257, 257, 33, 1e-4, jitter=0.3, seed=4, bathymetry=True)
-    s = vemg.Solver(m.xyz, m.tets, m.top, top_bc="pinned", pc="vl_as", device=0)
-    B = torch.as_tensor(np.stack([s.rhs(fourier_field(m.xyz, 1e-4, 200 + k)) for k in range(8)]), device=dev)
-    rec = {"workload": "thinbox-257x257x33-eps1e-4", "n_dof": s.info()["n"], "rhs_per_solve": 8,
-           "setup_s": time.perf_counter() - t0}
-    rec["kernels"] = {"K1": kernel_rates(s, s.info(), vemg, 1), "K8": kernel_rates(s, s.info(), vemg, 8, reps=10)}
-    x64 = None
-    for prec in ("fp64", "mixed_ir", "mixed_pc"):
-        s.set_precision(prec)
-        x, t, it, rel, st = timed_solves(s, B, 2, 1, rtol)
-        r = {"ms_per_batch": 1e3 * float(np.median(t)), "solves_per_s": 8 / float(np.median(t)),
-             "iterations": it[0], "max_relres": max(rel[0]), "status": st[0]}
-        if x64 is None:
-            x64 = x
-        else:
-            r["max_rel_err_vs_fp64"] = max(float(torch.linalg.norm(x[k] - x64[k]) / torch.linalg.norm(x64[k]))
-                                           for k in range(8))
-        rec[prec] = r
-        log(f"config 4 {prec}: {r['solves_per_s']:.1f} solves/s, iterations {max(r['iterations'])}")
-    s.close()
-    out["thinbox_257_eps1e-4_batch8"] = rec
-
-    t0 = time.perf_counter()
-    m = graded_mesh(1 / 900, 1e-3, jitter=0.25, seed=3)
-    s = vemg.Solver(m.xyz, m.tets, m.top, top_bc="pinned", pc="vl_as", device=0)
-    info = s.info()
-    rec = {"workload": "graded-hmin1/900-eps1e-3", "n_dof": info["n"], "setup_s": time.perf_counter() - t0}
-    xs = manufactured_u(m.xyz, 1e-3)
-    b = s.matvec(xs)
-    free = np.zeros(m.n, bool)
-    free[s.export("perm", np.int64)] = True
-    for pc in ("vl_as", "vl_sor"):
-        s.set_preconditioner(pc)
-        x, t, it, rel, st = timed_solves(s, b, 2, 1, rtol)
-        xh = x.cpu().numpy()
-        err = float(np.max(np.abs(xh[free] - xs[free])) / np.max(np.abs(xs[free])))
-        rec[pc] = {"time_to_tol_ms": 1e3 * float(np.median(t)), "iterations": it[0][0], "relres": rel[0][0],
-                   "status": st[0], "dof_iters_per_s": info["n"] * it[0][0] / float(np.median(t)),
-                   "max_rel_err_vs_manufactured": err}
-        log(f"config 3 {pc}: {rec[pc]['iterations']} iterations, {rec[pc]['time_to_tol_ms']:.1f} ms")
-    s.close()
-    out["graded_multiscale"] = rec
+    for name in ("thinbox-17x17x9-eps1e-2", "thinbox-129x129x33-eps1e-3", "graded-hmin1/960-eps1e-3"):
+        wl = WORKLOADS[name]
+        t0 = time.perf_counter()
+        mesh = build_mesh(wl)
+        t_mesh = time.perf_counter() - t0
+        rec = {"mesh_nodes": mesh.n, "mesh_s": t_mesh, "rtol": wl["rtol"]}
+        for mode in ("N", "D"):
+            t0 = time.perf_counter()
+            s = vemg.Solver(mesh.xyz, mesh.tets, mesh.top, top_bc=mode, pc="vl_as", device=0)
+            info = s.info()
+            r = {"n_dof": info["n"], "setup_s": time.perf_counter() - t0}
+            if wl["kind"] == "graded":
+                xs = manufactured_u(mesh.xyz, wl["H"])
+                b = s.matvec(xs)
+                free = np.zeros(mesh.n, bool)
+                free[s.export("perm", np.int64)] = True
+                for pc in ("vl_as", "vl_sor"):
+                    s.set_preconditioner(pc)
+                    x, rr = timed_config(s, b, 2, 1, wl["rtol"], info)
+                    xh = x.cpu().numpy()
+                    rr["max_rel_err_vs_manufactured"] = float(np.max(np.abs(xh[free] - xs[free]))
+                                                              / np.max(np.abs(xs[free])))
+                    rr["rel_l2_err_vs_manufactured"] = float(np.linalg.norm(xh[free] - xs[free])
+                                                             / np.linalg.norm(xs[free]))
+                    r[pc] = rr
+                    log(f"{name} {mode} {pc}: {rr['iterations']} iterations, {rr['time_to_tol_ms']:.1f} ms")
+            else:
+                b = torch.as_tensor(s.rhs(fourier_field(mesh.xyz, wl["H"], wl["rhs_seed"])), device=dev)
+                x, rr = timed_config(s, b, steps, 2, wl["rtol"], info, oracle_fixture(name, mode))
+                r.update(rr)
+                log(f"{name} {mode}: {rr['iterations']} iterations, {rr['time_to_tol_ms']:.2f} ms")
+            s.close()
+            rec[mode] = r
+        out[name] = rec
     return out
 
 
@@ -548,20 +735,21 @@ def robin_runs(mesh, wl, dev, rtol):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="thinbox-129x129x33-eps1e-3", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=HEADLINE, choices=sorted(WORKLOADS))
     ap.add_argument("--pc", default="vl_as", choices=sorted(PER_ITERATION))
-    ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline solve and roofline only")
-    ap.add_argument("--serve-requests", type=int, default=96,
-                    help="requests per serving stream (four streams: mixed and FP64, saturated and Poisson); "
-                         "the full serving configuration is 512, about seven minutes more than the default")
-    ap.add_argument("--no-configs", action="store_true", help="skip the full-size 257^2 and graded configurations")
-    ap.add_argument("--profile-batch", type=int, default=1, choices=(1, 2, 4, 8),
-                    help="right-hand sides per launch for --profile-kernels")
+    ap.add_argument("--serve-requests", type=int, default=512,
+                    help="requests of the serving stream (the serving configuration's 512 by default)")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other full-size configurations")
+    ap.add_argument("--paper-comparisons", action="store_true",
+                    help="also run Section 6's comparisons (SA, VL + SOR), the Robin top and SSPAI")
+    ap.add_argument("--profile-batch", type=int, default=8, choices=(1, 2, 4, 8),
+                    help="right-hand sides per launch for --profile-kernels / --pmc-traffic / --trace-timed")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="run only the hot kernels and a copy calibration (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-summary", nargs="+", metavar="DIR_OR_CSV",
@@ -575,10 +763,10 @@ def main():
         pmc_summary(args.pmc_summary)
         return
     if args.trace_timed:
-        trace_timed(args.trace_timed)
+        trace_timed(args.trace_timed, args.profile_batch)
         return
     if args.pmc_traffic:
-        pmc_traffic(*args.pmc_traffic, args.workload)
+        pmc_traffic(*args.pmc_traffic, args.workload, args.profile_batch)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -589,85 +777,96 @@ def main():
         profile_kernels(args.workload, args.profile_batch)
         return
 
+    wl = WORKLOADS[args.workload]
+    # the oracle's timed sample runs on one host core while the GPU is measured
+    cpu_job = None if args.no_cpu_baseline else start_cpu_baseline(args.workload, args.cpu_iters)
+
     import numpy as np
     import torch
 
     import paper_0912_1976_amd as vemg
-    from inputs import box_mesh, fourier_field
+    from inputs import fourier_field, manufactured_u
 
-    wl = WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
     log(f"workload {args.workload}: building mesh")
-    mesh = box_mesh(wl["nx"], wl["nx"], wl["nz"], wl["H"], jitter=wl["jitter"], seed=wl["seed"],
-                    bathymetry=wl["bathymetry"])
+    mesh = build_mesh(wl)
     t0 = time.perf_counter()
     s = vemg.Solver(mesh.xyz, mesh.tets, mesh.top, top_bc="pinned", pc=args.pc, device=0)
     t_setup = time.perf_counter() - t0
     info = s.info()
-    n = info["n"]
-    b1 = torch.as_tensor(s.rhs(fourier_field(mesh.xyz, wl["H"], wl["rhs_seed"])), device=dev)
-    log(f"setup {t_setup:.2f} s, n={n}; timing {args.steps} FP64 solves")
-    x64, times, iters, rels, sts = timed_solves(s, b1, args.steps, args.warmup, args.rtol)
+    n, K = info["n"], wl["nrhs"]
+    if wl["kind"] == "graded":
+        B = s.matvec(manufactured_u(mesh.xyz, wl["H"]))
+    else:
+        B = torch.as_tensor(np.stack([s.rhs(fourier_field(mesh.xyz, wl["H"], wl["rhs_seed"] + k))
+                                      for k in range(K)]), device=dev)
+        if K == 1:
+            B = B[0]
+    rtol = wl["rtol"]
+    log(f"setup {t_setup:.2f} s, n={n}; timing {args.steps} FP64 solves of {K} right-hand side(s)")
+    x64, times, iters, rels, sts = timed_solves(s, B, args.steps, args.warmup, rtol)
     total = sum(times)
-    its = iters[0][0]
-    value = n * sum(i[0] for i in iters) / total
-    log(f"FP64: {its} iterations, {1e3 * total / args.steps:.2f} ms/solve, relres {rels[0][0]:.2e}")
+    col_iters = sum(sum(i) for i in iters)
+    value = n * col_iters / total
+    max_it = max(iters[0])
+    log(f"FP64: iterations {iters[0]}, {1e3 * total / args.steps:.2f} ms/solve, relres {max(rels[0]):.2e}")
+    fixture = oracle_fixture(args.workload)
+    X64 = x64.cpu().numpy().reshape(K, -1)
+    err64 = [error_vs_oracle(X64[k], fixture, k) for k in range(K)]
 
-    # live per-kernel timing (HIP events on the library's stream)
-    ms_spmv, _ = s.time_op(vemg.OP_A, reps=50)
-    ms_gs, nl_gs = s.time_op(vemg.OP_GS_FWD, reps=20)
-    try:
-        ms_cgs, nl_cgs = s.time_op(vemg.OP_GS_COARSE, reps=20)
-    except vemg.VemgError:  # A_bar has no coarse level above the coarsest
-        ms_cgs, nl_cgs = 0.0, 1
-    n_gs, n_spmv, n_cgs = PER_ITERATION[args.pc]
-    share = {"gs": n_gs * ms_gs, "spmv": n_spmv * ms_spmv, "cgs": n_cgs * ms_cgs}
-    dom_key = max(share, key=share.get)
-    dom = {"gs": (gs_sweep_bytes(info) / nl_gs, ms_gs / nl_gs),
-           "spmv": (spmv_bytes(info), ms_spmv),
-           "cgs": (coarse_gs_bytes(info) / nl_cgs, ms_cgs / nl_cgs)}[dom_key]
-    achieved = dom[0] / (dom[1] * 1e-3) / 1e9
-    traffic = measured_traffic(dom_key, args.workload)
+    # live per-kernel timing (HIP events on the library's stream) and the roofline
+    rates = kernel_rates(s, info, vemg, K, reps=20)
+    dom_key, dom = dominant_kernel(rates, args.pc, K)
+    achieved = dom["bytes_per_launch"] / (dom["ms_per_launch"] * 1e-3) / 1e9
+    traffic = measured_traffic(dom_key, args.workload, K)
+    it_bytes = iteration_bytes(info, K, args.pc)
+    ms_iter = 1e3 * float(np.median(times)) / max_it
+    whole = {"bytes_per_iteration": it_bytes, "ms_per_iteration": ms_iter,
+             "GBs": it_bytes / (ms_iter * 1e-3) / 1e9,
+             "frac": it_bytes / (ms_iter * 1e-3) / 1e9 / HBM_PEAK_GBS,
+             "note": "algorithmic bytes of one PCG iteration from the built arrays' sizes over the solve's "
+                     "time per iteration (the slowest column's count)"}
+    log(f"dominant kernel {dom['kernel']}: {achieved:.0f} GB/s; whole iteration {whole['GBs']:.0f} GB/s")
 
-    extras = {}
+    extras = {"kernels": rates, "whole_iteration": whole, "fp64_rel_err_vs_oracle_sampled": err64}
     if not args.no_extras:
-        B8 = torch.as_tensor(np.stack([s.rhs(fourier_field(mesh.xyz, wl["H"], wl["rhs_seed"] + k))
-                                       for k in range(8)]), device=dev)
-        xb, tb, ib, rb, _ = timed_solves(s, B8, 3, 1, args.rtol)
-        extras["fp64_batch8"] = {"solves_per_s": 8 * 3 / sum(tb), "ms_per_batch": 1e3 * sum(tb) / 3,
-                                 "iterations": ib[0], "max_relres": max(rb[0])}
-        extras["kernels_batch8"] = kernel_rates(s, info, vemg, 8, reps=10)
-        extras["transfers"] = {k: v for k, v in kernel_rates(s, info, vemg, 1).items()
-                               if k in ("restrict_Et", "prolong_E")}
-        log(f"FP64 x8: {extras['fp64_batch8']['solves_per_s']:.1f} solves/s")
-        for prec in ("mixed_ir", "mixed_pc"):
-            sm = vemg.Solver(mesh.xyz, mesh.tets, mesh.top, top_bc="pinned", pc=args.pc, device=0, precision=prec)
-            xm, tm, im, rm, stm = timed_solves(sm, b1, max(3, args.steps // 2), 1, args.rtol)
-            err = float(torch.linalg.norm(xm - x64) / torch.linalg.norm(x64))
-            xmb, tmb, imb, rmb, _ = timed_solves(sm, B8, 3, 1, args.rtol)
-            errb = float(torch.linalg.norm(xmb - xb) / torch.linalg.norm(xb))
-            rec = {"time_to_tol_ms": 1e3 * float(np.median(tm)), "iterations": im[0][0], "relres": rm[0][0],
-                   "status": stm[0], "rel_err_vs_fp64": err, "batch8_solves_per_s": 8 * 3 / sum(tmb),
-                   "batch8_rel_err_vs_fp64": errb}
-            if prec == "mixed_ir":
-                ms32, _ = sm.time_op(vemg.OP_A, reps=50)
-                rec["spmv32_ms"] = ms32
-                rec["spmv32_GBs"] = spmv_bytes(info, 1, 4, 4) / (ms32 * 1e-3) / 1e9
+        # mixed precision on the same handle and batch
+        for prec in ("mixed_pc", "mixed_ir"):
+            s.set_precision(prec)
+            xm, tm, im, rm, stm = timed_solves(s, B, max(2, args.steps // 2), 1, rtol)
+            Xm = xm.cpu().numpy().reshape(K, -1)
+            med = float(np.median(tm))
+            rec = {"ms_per_solve": 1e3 * med, "solves_per_s": K / med, "iterations": im[0],
+                   "max_relres": max(rm[0]), "status": stm[0],
+                   "dof_iters_per_s": n * sum(im[0]) / med,
+                   "rel_err_vs_oracle_sampled": [error_vs_oracle(Xm[k], fixture, k) for k in range(K)],
+                   "max_rel_err_vs_fp64": max(float(np.linalg.norm(Xm[k] - X64[k]) / np.linalg.norm(X64[k]))
+                                              for k in range(K)),
+                   "iteration_bytes": iteration_bytes(info, K, args.pc, prec)}
             extras[prec] = rec
-            log(f"{prec}: {rec['time_to_tol_ms']:.1f} ms, iters {rec['iterations']}, err {err:.1e}")
-            sm.close()
-        log("serving stream")
-        extras["serving"] = serving(args.serve_requests, 11, args.rtol, dev)
-        extras["robin_top"] = robin_runs(mesh, wl, dev, args.rtol)
-        extras["sa_baseline"] = sa_baseline_runs(dev, args.rtol)
-        extras["sspai_extrapolation"] = sspai_runs(dev, args.rtol)
+            log(f"{prec}: {rec['solves_per_s']:.2f} solves/s, iterations {im[0]}")
+        s.set_precision("fp64")
+        if K > 1:
+            x1, t1, i1, r1, st1 = timed_solves(s, B[0], max(2, args.steps // 2), 1, rtol)
+            extras["fp64_one_rhs"] = {"time_to_tol_ms": 1e3 * float(np.median(t1)), "iterations": i1[0][0],
+                                      "dof_iters_per_s": n * i1[0][0] / float(np.median(t1))}
+            extras["kernels_one_rhs"] = kernel_rates(s, info, vemg, 1, reps=20)
+        s.close()
         if not args.no_configs:
-            extras["configs"] = config_runs(dev, args.rtol)
+            extras["configs"] = config_runs(dev, max(3, args.steps))
+        if not args.no_serving:
+            log("serving stream")
+            extras["serving"] = serving(args.serve_requests, 11, 1e-8, dev)
+        if args.paper_comparisons:
+            extras["sa_baseline"] = sa_baseline_runs(dev, 1e-8)
+            m2 = build_mesh(WORKLOADS["thinbox-129x129x33-eps1e-3"])
+            extras["robin_top"] = robin_runs(m2, WORKLOADS["thinbox-129x129x33-eps1e-3"], dev, 1e-8)
+            extras["sspai_extrapolation"] = sspai_runs(dev, 1e-8)
 
     cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle)")
-        cpu = cpu_baseline(mesh, wl, args.cpu_iters)
+    if cpu_job is not None:
+        log("waiting for the cpu baseline (oracle)")
+        cpu = finish_cpu_baseline(cpu_job, timeout=600)
 
     line = {
         "metric": "DOF-iters/s, time to 1e-8 rel residual; solves/s + p50/p99 (mixed vs FP64)",
@@ -682,22 +881,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n_dof": n, "rtol": args.rtol, "precond": args.pc,
-                   "top": "point condition (Neumann elsewhere)", "precision": "fp64", "rhs_per_solve": 1},
-        "iterations": its,
+        "config": {"workload": args.workload, "n_dof": n, "rhs_per_step": K, "rtol": rtol, "precond": args.pc,
+                   "top": "point condition (Neumann elsewhere)", "precision": "fp64",
+                   "value_definition": "unknowns x iterations summed over the batch's columns per second"},
+        "iterations": iters[0],
         "time_to_tol_ms": 1e3 * float(np.median(times)),
-        "solves_per_s": args.steps / total,
-        "relres": max(r[0] for r in rels),
+        "solves_per_s": K * args.steps / total,
+        "relres": max(max(r) for r in rels),
         "setup_s": t_setup,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": KERNEL_NAMES[dom_key],
-                     "bytes_per_launch": dom[0], "ms_per_launch": dom[1]},
-        "kernels": {"spmv_ms": ms_spmv, "spmv_GBs": spmv_bytes(info) / (ms_spmv * 1e-3) / 1e9,
-                    "gs_sweep_ms": ms_gs, "gs_sweep_GBs": gs_sweep_bytes(info) / (ms_gs * 1e-3) / 1e9,
-                    "gs_launches": nl_gs, "coarse_sweep_ms": ms_cgs,
-                    "coarse_sweep_GBs": coarse_gs_bytes(info) / (ms_cgs * 1e-3) / 1e9 if ms_cgs else None,
-                    "coarse_launches": nl_cgs,
-                    "ms_per_iteration_estimate": share},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, **dom},
         "extras": extras,
         "cpu_baseline": cpu,
     }

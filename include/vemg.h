@@ -91,10 +91,15 @@ typedef enum {
 
 /* Precision of the solve.
  *   VEMG_FP64        everything in FP64.
- *   VEMG_MIXED_IR    FP64 iterative refinement: outer residual r = b - A x in
- *                    FP64; inner PCG (SpMV, transfers, smoothers, vectors) in
- *                    FP32 with per-row scaled operators, its inner products
- *                    accumulated in FP64, coarsest solves in FP64; x += d in FP64.
+ *   VEMG_MIXED_IR    FP64 iterative refinement around an FP32 PCG that keeps
+ *                    its Krylov space: the inner PCG (SpMV, transfers,
+ *                    smoothers, vectors) runs in FP32 with per-row scaled
+ *                    operators on A d = b / ||b||, its inner products
+ *                    accumulated in FP64 and its coarsest solves in FP64;
+ *                    every poll_every iterations its correction is added to
+ *                    the FP64 solution and its residual replaced by the true
+ *                    FP64 residual b - A x (reliable update), without
+ *                    restarting the search directions.
  *   VEMG_MIXED_PC    FP64 CG (SpMV, vectors, inner products) whose
  *                    preconditioner (transfers, smoothers, V-cycles) runs in FP32. */
 typedef enum { VEMG_FP64 = 0, VEMG_MIXED_IR = 1, VEMG_MIXED_PC = 2 } vemg_precision;
@@ -127,8 +132,8 @@ typedef struct {
   int max_restarts;    /* restarts from the true residual, 5 */
   int use_graphs;      /* capture one PCG iteration in a hipGraph, 1 */
   int precision;       /* vemg_precision, VEMG_FP64 */
-  double inner_rtol;   /* VEMG_MIXED_IR: relative tolerance of each inner FP32 solve, 1e-4 */
-  int max_outer;       /* VEMG_MIXED_IR: refinement steps, 30 */
+  double inner_rtol;   /* in (0, 1); not used by the solver (kept for the layout), 1e-4 */
+  int max_outer;       /* >= 1; not used by the solver (kept for the layout), 30 */
   double robin_alpha;  /* VEMG_TOP_ROBIN: alpha > 0 (ignored otherwise), 0 */
   int extrapolation;   /* vemg_extrapolation, VEMG_EXTRAP_PROJECTION */
 } vemg_options;

@@ -231,6 +231,7 @@ struct DLevel {
   int64_t n_top = 0;            // fine levels: rows of the top block in the fine matrix
   std::vector<int64_t> cstart;  // colour ranges, global row indices
   std::vector<int64_t> cstart_top;  // fine level of the whole A_UU: top-block range of each colour
+  const int32_t *order = nullptr;   // fine levels: slice visit order of the residual product
   CsrG P, Pt;                   // prolongation (n x n_next) and restriction
   Sell Ps;                      // fine levels: the prolongation in SELL-64 (a few entries a row)
   double *Cinv = nullptr;       // coarsest level only
@@ -252,7 +253,9 @@ struct DLevel {
   }
 };
 
-enum GraphKind { kGraphFP64 = 0, kGraphFP32 = 1, kGraphMixedPC = 2 };
+// kGraphFP32Reliable: an FP32 iteration followed by the reliable update of
+// the mixed-precision solve (the last iteration of every chunk)
+enum GraphKind { kGraphFP64 = 0, kGraphFP32 = 1, kGraphMixedPC = 2, kGraphFP32Reliable = 3 };
 
 // the captured graphs of one PCG iteration: a single graph, or four segments
 struct IterGraphs {
@@ -284,6 +287,9 @@ struct vemg_solver_s {
   double *b = nullptr, *diag = nullptr, *scale_in = nullptr, *scale_out = nullptr, *dscal = nullptr;
   double *part_pq = nullptr, *part_rr = nullptr, *part_rz = nullptr, *part_b = nullptr, *part_t = nullptr;
   int64_t *perm = nullptr;
+  // slice visit orders (spatial, across colours) of the products over all
+  // rows and over the non-top rows
+  int32_t *order_all = nullptr, *order_bar = nullptr;
   vemg::Scal *scal = nullptr;
   int64_t nnz_A = 0, nnz_E = 0;
   std::map<int, vemg::IterGraphs> graphs;  // key: kind * 16 + K
@@ -319,6 +325,7 @@ void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, int 
       dl.n_top = h->P.n_top;
       dl.As = h->A;
       dl.row0 = of == kLevelsAbar ? h->P.n_top : 0;
+      dl.order = of == kLevelsAbar ? h->order_bar : h->order_all;
       dl.cstart = h->P.bar_colour_start;
       if (of == kLevelsSA) {
         const int nc = std::max((int)h->P.top_colour_start.size(), (int)h->P.bar_colour_start.size()) - 1;
@@ -391,7 +398,7 @@ void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *
   };
   for (int c = 0; c < nc; ++c) gs(c, true);
   if (L.fine)
-    launch_spmv<T>(st, K, L.As, 1, L.row0, L.row0 + L.n, x, g, r, nullptr, done);
+    launch_spmv<T>(st, K, L.As, 1, L.row0, L.row0 + L.n, x, g, r, nullptr, done, L.order);
   else
     launch_csr_spmv<T>(st, K, L.Ac, 1, 0, L.n, x, g, r, done);
   DLevel &C = H[l + 1];
@@ -435,7 +442,7 @@ void sor_cycle(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *
   };
   for (int c = 0; c < nc; ++c) sweep(c, true);
   if (m > 0) {
-    launch_spmv<T>(st, K, h->A, 1, 0, n, zz, rr, v.res, nullptr, done);
+    launch_spmv<T>(st, K, h->A, 1, 0, n, zz, rr, v.res, nullptr, done, h->order_all);
     launch_csr_rect<T>(st, K, h->Et, false, v.res, h->S[0].g<T>(), done);
     vcycle<T>(st, K, h->S, 0, done);
     launch_rect<T>(st, K, h->E, true, h->S[0].x<T>(), zz, done);
@@ -568,6 +575,23 @@ int64_t precond_mixed(Handle *h, int K, const double *rr, double *zz, const int 
 // so that the two branches overlap on the device.
 enum Segment { kSegPre = 0, kSegBranch = 1, kSegMain = 2, kSegPost = 3 };
 
+// Reliable update of the mixed-precision solve (FP32 PCG on A d = b / ||b||):
+// the FP32 correction accumulated since the last update is scaled by ||b||,
+// folded into the FP64 solution hi + lo without rounding error and cleared;
+// the true residual b - A (hi + lo) is evaluated in extended precision
+// (v64.res) and, scaled by 1 / ||b||, replaces the FP32 recurrence residual.
+// The search directions are kept.  The kernels run whatever the columns'
+// state, so that a chunk always ends with every correction folded.
+void reliable_update(Handle *h, int K) {
+  hipStream_t st = h->work;
+  const int64_t n = h->P.n;
+  launch_promote(st, K, h->v32.x, h->scale_out, h->v64.x, n, false, nullptr);
+  launch_fold(st, K, (1u << K) - 1u, h->v64.xs, h->v64.xl, h->v64.x, n);
+  launch_fill<float>(st, h->v32.x, n * K, 0.0f, nullptr);
+  launch_residual_ext(st, K, h->A, h->b, h->v64.xs, h->v64.xl, h->v64.res);
+  launch_demote(st, K, h->v64.res, h->scale_in, h->v32.r, n, nullptr);
+}
+
 template <class T>
 void pcg_segment(Handle *h, int K, int kind, int seg) {
   hipStream_t st = h->work;
@@ -577,12 +601,14 @@ void pcg_segment(Handle *h, int K, int kind, int seg) {
   const bool mixed = kind == kGraphMixedPC;
   switch (seg) {
     case kSegPre:
-      launch_spmv<T>(st, K, h->A, 0, 0, n, v.p, (const T *)nullptr, v.q, h->part_pq, done);
+      launch_spmv<T>(st, K, h->A, 0, 0, n, v.p, (const T *)nullptr, v.q, h->part_pq, done, h->order_all);
       launch_pcg_alpha(st, K, h->scal, h->part_pq, sell_blocks(0, n));
       launch_pcg_xr<T>(st, K, h->scal, v.x, v.r, v.p, v.q, n, h->part_rr);
       launch_pcg_conv(st, K, h->scal, h->part_rr, vec_blocks(n));
       if constexpr (std::is_same<T, double>::value)
         if (mixed) launch_demote(st, K, v.r, h->scale_in, h->v32.tmp, n, done);
+      if constexpr (std::is_same<T, float>::value)
+        if (kind == kGraphFP32Reliable) reliable_update(h, K);
       break;
     case kSegBranch:
       if (mixed)
@@ -634,10 +660,12 @@ void pcg_iteration(Handle *h, int K, int kind) {
     pcg_segment<T>(h, K, kind, kSegPost);
     return;
   }
-  launch_spmv<T>(st, K, h->A, 0, 0, n, v.p, (const T *)nullptr, v.q, h->part_pq, done);
+  launch_spmv<T>(st, K, h->A, 0, 0, n, v.p, (const T *)nullptr, v.q, h->part_pq, done, h->order_all);
   launch_pcg_alpha(st, K, h->scal, h->part_pq, sell_blocks(0, n));
   launch_pcg_xr<T>(st, K, h->scal, v.x, v.r, v.p, v.q, n, h->part_rr);
   launch_pcg_conv(st, K, h->scal, h->part_rr, vec_blocks(n));
+  if constexpr (std::is_same<T, float>::value)
+    if (kind == kGraphFP32Reliable) reliable_update(h, K);
   int64_t np = 0;
   if (kind == kGraphMixedPC) {
     if constexpr (std::is_same<T, double>::value) np = precond_mixed(h, K, v.r, v.z, done);
@@ -840,82 +868,102 @@ void solve_cg(Handle *h, int K, double rtol, int max_iter, ColResult *res) {
   launch_round(st, v.xs, v.xl, v.x, n * K);
 }
 
-// FP64 iterative refinement with FP32 inner PCG; h->b holds K columns.
+// Iterates a mixed-precision solve until every column has stopped: chunks of
+// poll_every FP32 iterations, the last of each chunk with the reliable update.
+Scal iterate_reliable(Handle *h, int K) {
+  const int poll = std::max(1, h->opt.poll_every);
+  while (true) {
+    for (int k = 0; k + 1 < poll; ++k) run_iteration<float>(h, K, kGraphFP32);
+    run_iteration<float>(h, K, kGraphFP32Reliable);
+    Scal hs = read_scal(h);
+    if (hs.all_done) return hs;
+  }
+}
+
+// Mixed precision (VEMG_MIXED_IR): FP64 iterative refinement whose inner FP32
+// PCG keeps its Krylov space.  The inner PCG (SpMV, transfers, smoothers and
+// vectors in FP32 with per-row scaled operators, inner products accumulated
+// in FP64, coarsest solves in FP64) runs on A d = b / ||b||; every poll_every
+// iterations a reliable update folds its correction into the FP64 solution
+// hi + lo and replaces its residual with the true FP64 residual (evaluated in
+// extended precision), without restarting the search directions.  A column
+// whose recurrence residual meets rtol is confirmed on that true residual
+// and, if it is not met, restarted from it (at most max_restarts times, while
+// each restart at least halves it).  h->b holds K columns.
 void solve_ir(Handle *h, int K, double rtol, int max_iter, ColResult *res) {
   hipStream_t st = h->work;
   int64_t n = h->P.n;
-  double bb[kMaxBatch];
+  Work<float> &v = h->v32;
+  double bb[kMaxBatch], sin[kMaxBatch], sout[kMaxBatch];
   rhs_norms(h, K, bb);
+  for (int k = 0; k < K; ++k) {
+    const double nb = std::sqrt(bb[k]);
+    const bool ok = nb > 0.0 && std::isfinite(nb);
+    sin[k] = ok ? 1.0 / nb : 0.0;
+    sout[k] = ok ? nb : 0.0;
+  }
+  upload_scales(h, K, sin, sout);
   launch_fill<double>(st, h->v64.x, n * K, 0.0, nullptr);
   launch_fill<double>(st, h->v64.xs, n * K, 0.0, nullptr);
   launch_fill<double>(st, h->v64.xl, n * K, 0.0, nullptr);
+  launch_fill<float>(st, v.x, n * K, 0.0f, nullptr);
+  launch_demote(st, K, h->b, h->scale_in, v.r, n, nullptr);
+  // bnorm2 of the scaled system (about 1); a zero b stops its column at once,
+  // a non-finite one (scaled to NaN) as a breakdown
+  launch_dot<float>(st, K, v.r, v.r, n, h->part_b, nullptr);
+  launch_pcg_init(st, K, h->scal, h->part_b, vec_blocks(n), rtol, max_iter);
   double prev[kMaxBatch];
   bool fin[kMaxBatch];
+  int restarts = 0;
   for (int k = 0; k < K; ++k) {
     prev[k] = INFINITY;
     fin[k] = false;
     res[k] = ColResult();
   }
-  for (int outer = 0;; ++outer) {
-    double rr[kMaxBatch];
-    true_residual(h, K, rr);  // v64.res = b - A (xs + xl)
-    double sin[kMaxBatch], sout[kMaxBatch];
-    bool any = false;
-    for (int k = 0; k < K; ++k) {
-      sin[k] = sout[k] = 0.0;
-      ColResult &c = res[k];
-      if (fin[k]) continue;
-      if (bb[k] == 0.0) {
-        c.rel = 0.0;
-        c.status = VEMG_OK;
-        fin[k] = true;
-        continue;
-      }
-      if (!std::isfinite(bb[k]) || !std::isfinite(rr[k])) {
-        c.rel = NAN;
-        c.status = VEMG_ERR_BREAKDOWN;
-        fin[k] = true;
-        continue;
-      }
-      c.rel = std::sqrt(rr[k] / bb[k]);
-      if (c.rel <= rtol) {
-        c.status = VEMG_OK;
-        fin[k] = true;
-      } else if (c.iters >= max_iter) {
-        c.status = VEMG_WARN_MAXITER;
-        fin[k] = true;
-      } else if (outer >= h->opt.max_outer || (outer >= 2 && c.rel > 0.5 * prev[k])) {
-        c.status = VEMG_WARN_FLOOR;
-        fin[k] = true;
-      } else {
-        double nr = std::sqrt(rr[k]);
-        sin[k] = 1.0 / nr;
-        sout[k] = nr;
-        prev[k] = c.rel;
-        any = true;
-      }
-    }
-    if (!any) break;
-    upload_scales(h, K, sin, sout);
-    // inner FP32 solve of A d = r / ||r|| (finished columns get a zero rhs)
-    Work<float> &v = h->v32;
-    launch_demote(st, K, h->v64.res, h->scale_in, v.r, n, nullptr);
-    launch_fill<float>(st, v.x, n * K, 0.0f, nullptr);
-    launch_dot<float>(st, K, v.r, v.r, n, h->part_b, nullptr);
-    int inner_max = max_iter;
-    for (int k = 0; k < K; ++k)
-      if (!fin[k]) inner_max = std::min(inner_max, std::max(1, max_iter - res[k].iters));
-    launch_pcg_init(st, K, h->scal, h->part_b, vec_blocks(n), h->opt.inner_rtol, inner_max);
+  while (true) {
     int64_t np = 0;
     precond<float>(h, K, v.r, v.z, h->part_rz, &np, nullptr);
     launch_pcg_set_rho(st, K, h->scal, h->part_rz, np);
     launch_copy<float>(st, v.z, v.p, n * K, nullptr);
-    Scal hs = iterate<float>(h, K, kGraphFP32);
-    for (int k = 0; k < K; ++k)
-      if (!fin[k]) res[k].iters += hs.iters[k];
-    // the FP64 correction d = ||r|| d32, folded into the extended solution
-    launch_promote(st, K, v.x, h->scale_out, h->v64.x, n, false, nullptr);
-    launch_fold(st, K, (1u << K) - 1u, h->v64.xs, h->v64.xl, h->v64.x, n);
+    Scal hs = iterate_reliable(h, K);
+    // the last iteration folded every correction and left b - A (hi + lo) in v64.res
+    launch_dot<double>(st, K, h->v64.res, h->v64.res, n, h->part_t, nullptr);
+    launch_reduce(st, K, h->part_t, vec_blocks(n), h->dscal);
+    double rr[kMaxBatch];
+    HIPCHK(hipMemcpyAsync(rr, h->dscal, K * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    unsigned keep = 0;
+    bool any = false;
+    for (int k = 0; k < K; ++k) {
+      ColResult &c = res[k];
+      c.iters = hs.iters[k];
+      if (fin[k]) {
+        keep |= 1u << k;
+        continue;
+      }
+      if (bb[k] == 0.0) {
+        c.rel = 0.0;
+        c.status = VEMG_OK;
+      } else if (hs.status[k] == -6 || !std::isfinite(bb[k]) || !std::isfinite(rr[k])) {
+        c.rel = NAN;
+        c.status = VEMG_ERR_BREAKDOWN;
+      } else {
+        c.rel = std::sqrt(rr[k] / bb[k]);
+        if (c.rel <= rtol) c.status = VEMG_OK;
+        else if (hs.iters[k] >= max_iter) c.status = VEMG_WARN_MAXITER;
+        else if (restarts >= h->opt.max_restarts || c.rel > 0.5 * prev[k]) c.status = VEMG_WARN_FLOOR;
+        else {
+          prev[k] = c.rel;
+          any = true;
+          continue;  // restart this column from its true residual (already in v32.r)
+        }
+      }
+      fin[k] = true;
+      keep |= 1u << k;
+    }
+    if (!any) break;
+    ++restarts;
+    launch_pcg_resume(st, K, h->scal, keep);
   }
   launch_round(st, h->v64.xs, h->v64.xl, h->v64.x, n * K);
 }
@@ -964,6 +1012,22 @@ void upload(Handle *h) {
   h->b = h->ar.alloc<double>(cnt);
   h->diag = h->ar.upload(P.diag, st);
   h->perm = h->ar.upload(P.perm, st);
+  // The products over all rows visit their slices in spatial order across
+  // the colours (a slice's key: the spatial rank of its first row in the
+  // range), so that the contiguous part of the visit order one XCD takes is
+  // one region of every colour, and a row's neighbours, which lie in the
+  // other colours, are gathered through the same XCD's L2.
+  auto slice_order = [&](int64_t r0, int64_t r1) {
+    const int64_t s0 = r0 / kWave, s1 = (r1 + kWave - 1) / kWave;
+    std::vector<int32_t> ord(std::max<int64_t>(s1 - s0, 0));
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+      return P.loc_rank[std::max((s0 + a) * kWave, r0)] < P.loc_rank[std::max((s0 + b) * kWave, r0)];
+    });
+    return h->ar.upload(ord, st);
+  };
+  h->order_all = slice_order(0, n);
+  h->order_bar = slice_order(m, n);
   int64_t npmax = (std::max(sell_blocks(0, n), vec_blocks(n)) + 8) * kMaxBatch;
   h->part_pq = h->ar.alloc<double>(npmax);
   h->part_rr = h->ar.alloc<double>(npmax);
@@ -1056,7 +1120,7 @@ void apply_op(Handle *h, int op, const T *in, T *out) {
   Work<T> &v = work_of<T>(h);
   switch (op) {
     case VEMG_OP_A:
-      launch_spmv<T>(st, 1, h->A, 0, 0, n, in, (const T *)nullptr, out, nullptr, nullptr);
+      launch_spmv<T>(st, 1, h->A, 0, 0, n, in, (const T *)nullptr, out, nullptr, nullptr, h->order_all);
       break;
     case VEMG_OP_PRECOND: {
       launch_copy<T>(st, in, v.tmp, n, nullptr);
@@ -1137,7 +1201,7 @@ void time_once(Handle *h, int op, int K) {
   int64_t n = P.n;
   Work<T> &v = work_of<T>(h);
   if (op == VEMG_OP_A) {
-    launch_spmv<T>(st, K, h->A, 0, 0, n, v.p, (const T *)nullptr, v.q, h->part_pq, nullptr);
+    launch_spmv<T>(st, K, h->A, 0, 0, n, v.p, (const T *)nullptr, v.q, h->part_pq, nullptr, h->order_all);
     return;
   }
   if (op == VEMG_OP_ET) {
@@ -1750,7 +1814,7 @@ vemg_status vemg_matvec(vemg_solver s, const double *x_dev, double *y_dev) {
     int64_t n = s->P.n;
     vemg::sync_in(s);
     vemg::launch_gather(st, 1, 0, x_dev, s->perm, s->v64.tmp, n);
-    vemg::launch_spmv<double>(st, 1, s->A, 0, 0, n, s->v64.tmp, nullptr, s->v64.res, nullptr, nullptr);
+    vemg::launch_spmv<double>(st, 1, s->A, 0, 0, n, s->v64.tmp, nullptr, s->v64.res, nullptr, nullptr, s->order_all);
     vemg::launch_fill<double>(st, y_dev, s->P.n_nodes, 0.0, nullptr);
     vemg::launch_scatter(st, 1, 0, s->v64.res, s->perm, y_dev, n);
     HIPCHK(hipGetLastError());

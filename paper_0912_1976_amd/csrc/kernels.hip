@@ -87,27 +87,40 @@ __device__ __forceinline__ const float *csr_vals<float>(const CsrG &A) {
   return A.val32;
 }
 
-// Off-diagonal terms of one SELL row for K columns: acc = sum_j v_j (x_j - x_r)
-// (DIFF) or sum_j v_j x_j, and off = sum_j v_j.
-// entries of a row kept in flight per lane: fewer as the gathered rows of K
-// values grow, so that the registers they take still allow several waves
+// Lanes that share one row of a K-column batch in the fine kernels: each
+// lane holds CPL = K / LPR consecutive columns, 16 bytes at most, so that a
+// gathered row is one 16-byte load per lane and the LPR lanes of a row read
+// it contiguously.  Narrow rows keep one lane per row.  Spreading a wide row
+// over lanes keeps the registers per lane small and several gathers in
+// flight per lane, where a 64-byte row per lane allowed one.
 template <class T, int K>
-constexpr int sell_unroll() {
-  return sizeof(T) * K >= 64 ? 1 : sizeof(T) * K >= 32 ? 2 : 4;
+constexpr int row_lanes() {
+  return sizeof(T) * K <= 16 ? 1 : (int)(sizeof(T) * K / 16);
 }
 
-template <class T, int K, bool DIFF, bool ZS = false>
-__device__ __forceinline__ void sell_row(const Sell &A, int64_t s, int lane, const T *__restrict__ x,
-                                         const Row<T, K> &xr, T (&acc)[K], T &off,
+// entries of a row kept in flight per lane
+template <class T, int C>
+constexpr int sell_unroll() {
+  return sizeof(T) * C >= 64 ? 1 : sizeof(T) * C >= 32 ? 2 : 4;
+}
+
+// Off-diagonal terms of one SELL row (position t of slice s) for the C
+// columns [q C, q C + C) of a K-column batch: acc = sum_j v_j (x_j - x_r)
+// (DIFF) or sum_j v_j x_j, and off = sum_j v_j.  Every column is summed over
+// the row's entries in storage order, whatever C is.
+template <class T, int K, int C, bool DIFF, bool ZS = false>
+__device__ __forceinline__ void sell_row(const Sell &A, int64_t s, int t, int q, const T *__restrict__ x,
+                                         const Row<T, C> &xr, T (&acc)[C], T &off,
                                          const ZeroStart &z = ZeroStart()) {
   const int64_t base = A.sptr[s];
   const int len = (int)((A.sptr[s + 1] - base) >> 6);
-  const int32_t *__restrict__ cp = A.col + base + lane;
-  const T *__restrict__ vp = sell_vals<T>(A) + base + lane;
+  const int32_t *__restrict__ cp = A.col + base + t;
+  const T *__restrict__ vp = sell_vals<T>(A) + base + t;
+  const T *__restrict__ xq = x + q * C;
 #pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = T(0);
+  for (int k = 0; k < C; ++k) acc[k] = T(0);
   off = T(0);
-  constexpr int U = sell_unroll<T, K>();
+  constexpr int U = sell_unroll<T, C>();
 #pragma unroll U
   for (int e = 0; e < len; ++e) {
     const int32_t c = cp[(int64_t)e * 64];
@@ -115,35 +128,84 @@ __device__ __forceinline__ void sell_row(const Sell &A, int64_t s, int lane, con
     if constexpr (ZS && K > 2) {
       // wide rows: the gathers of colours not swept yet are skipped
       if (c < (c < z.n_top ? z.top_lim : z.bar_lim)) {
-        const Row<T, K> xc = ld<T, K>(x, c);
+        const Row<T, C> xc = *reinterpret_cast<const Row<T, C> *>(xq + (int64_t)c * K);
 #pragma unroll
-        for (int k = 0; k < K; ++k) acc[k] += DIFF ? v * (xc.v[k] - xr.v[k]) : v * xc.v[k];
+        for (int k = 0; k < C; ++k) acc[k] += DIFF ? v * (xc.v[k] - xr.v[k]) : v * xc.v[k];
       }
     } else {
       // narrow rows: load every entry (the loads stay pipelined) and zero
       // the ones not swept yet
-      Row<T, K> xc = ld<T, K>(x, c);
+      Row<T, C> xc = *reinterpret_cast<const Row<T, C> *>(xq + (int64_t)c * K);
       if constexpr (ZS) {
         const bool live = c < (c < z.n_top ? z.top_lim : z.bar_lim);
 #pragma unroll
-        for (int k = 0; k < K; ++k) xc.v[k] = live ? xc.v[k] : T(0);
+        for (int k = 0; k < C; ++k) xc.v[k] = live ? xc.v[k] : T(0);
       }
 #pragma unroll
-      for (int k = 0; k < K; ++k) acc[k] += DIFF ? v * (xc.v[k] - xr.v[k]) : v * xc.v[k];
+      for (int k = 0; k < C; ++k) acc[k] += DIFF ? v * (xc.v[k] - xr.v[k]) : v * xc.v[k];
     }
     off += v;
   }
 }
 
+// columns [q C, q C + C) of row r
+template <class T, int K, int C>
+__device__ __forceinline__ Row<T, C> ldp(const T *__restrict__ p, int64_t r, int q) {
+  return *reinterpret_cast<const Row<T, C> *>(p + r * K + q * C);
+}
+template <class T, int K, int C>
+__device__ __forceinline__ void stp(T *__restrict__ p, int64_t r, int q, const Row<T, C> &v) {
+  *reinterpret_cast<Row<T, C> *>(p + r * K + q * C) = v;
+}
+
+// Block sums of per-row products when a row's K columns are spread over LPR
+// lanes (blocks of kBlock * LPR threads covering kBlock rows): the products
+// are first laid out one row per thread of the block's first kBlock threads,
+// which then reduce exactly as block_sum_store does, so every column's sum
+// has the same rounding as with one lane per row.  Every thread of the block
+// must call it.
+template <int K, int LPR>
+__device__ __forceinline__ void block_sum_rows(const double (&v)[K / LPR], double *out) {
+  constexpr int C = K / LPR;
+  if constexpr (LPR == 1) {
+    block_sum_store<K>(v, out);
+  } else {
+    __shared__ double buf[kBlock][K];
+    const int rloc = threadIdx.x / LPR, q = threadIdx.x % LPR;
+#pragma unroll
+    for (int j = 0; j < C; ++j) buf[rloc][q * C + j] = v[j];
+    __syncthreads();
+    __shared__ double red[kSlicesPerBlock][kMaxBatch];
+    if (threadIdx.x < kBlock) {  // whole wavefronts: wavefront w holds the rows of slice w
+      const int w = threadIdx.x >> 6;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double t = wave_sum(buf[threadIdx.x][k]);
+        if ((threadIdx.x & 63) == 0) red[w][k] = t;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kSlicesPerBlock; ++w) t += red[w][k];
+        out[k] = t;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------- fine matrix
-// (A x)_r in difference form (MODE 0), or g_r - (A x)_r (MODE 1)
-// (A x)_r in difference form (MODE 0), or g_r - (A x)_r (MODE 1); the row's
-// own operands are loaded before its entries
-template <class T, int K, int MODE>
-__device__ __forceinline__ Row<T, K> fine_row(const Sell &A, int64_t s, int lane, int64_t r, const T *__restrict__ x,
-                                              const Row<T, K> &xr, const T *__restrict__ g) {
-  Row<T, K> gr;
-  if (MODE == 1) gr = ld<T, K>(g, r);
+// (A x)_r in difference form (MODE 0), or g_r - (A x)_r (MODE 1), columns
+// [q C, q C + C); the row's own operands are loaded before its entries
+template <class T, int K, int C, int MODE>
+__device__ __forceinline__ Row<T, C> fine_row(const Sell &A, int64_t s, int t, int q, int64_t r,
+                                              const T *__restrict__ x, const Row<T, C> &xr,
+                                              const T *__restrict__ g) {
+  Row<T, C> gr;
+  if (MODE == 1) gr = ldp<T, K, C>(g, r, q);
   T d0, d1 = T(0);
   if constexpr (std::is_same<T, double>::value) {
     d0 = A.d64[r];
@@ -151,46 +213,53 @@ __device__ __forceinline__ Row<T, K> fine_row(const Sell &A, int64_t s, int lane
     d0 = A.s32[r];
     d1 = A.dh32[r];
   }
-  T acc[K], off;
-  sell_row<T, K, true>(A, s, lane, x, xr, acc, off);
-  Row<T, K> out;
+  T acc[C], off;
+  sell_row<T, K, C, true>(A, s, t, q, x, xr, acc, off);
+  Row<T, C> out;
   if constexpr (std::is_same<T, double>::value) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) out.v[k] = acc[k] + d0 * xr.v[k];
+    for (int k = 0; k < C; ++k) out.v[k] = acc[k] + d0 * xr.v[k];
   } else {
 #pragma unroll
-    for (int k = 0; k < K; ++k) out.v[k] = d0 * (acc[k] + d1 * xr.v[k]);
+    for (int k = 0; k < C; ++k) out.v[k] = d0 * (acc[k] + d1 * xr.v[k]);
   }
   if (MODE == 1) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) out.v[k] = gr.v[k] - out.v[k];
+    for (int k = 0; k < C; ++k) out.v[k] = gr.v[k] - out.v[k];
   }
   return out;
 }
 
+// Blocks of kBlock rows (four slices), row_lanes<T, K>() lanes per row.
+// order (may be null): the i-th slice of the range visited is s_first +
+// order[i], a permutation of the range's slices; the blocks of one XCD take a
+// contiguous part of it.
 template <class T, int K, int MODE, bool DOT>
-__global__ __launch_bounds__(kBlock) void k_spmv(Sell A, int64_t r0, int64_t r1, int64_t s_first, int64_t nb,
-                                                 const T *__restrict__ x, const T *__restrict__ g,
-                                                 T *__restrict__ y, double *__restrict__ partial,
-                                                 const int *__restrict__ done) {
+__global__ __launch_bounds__((kBlock * row_lanes<T, K>())) void k_spmv(
+    Sell A, int64_t r0, int64_t r1, int64_t s_first, int64_t ns, int64_t nb, const int32_t *__restrict__ order,
+    const T *__restrict__ x, const T *__restrict__ g, T *__restrict__ y, double *__restrict__ partial,
+    const int *__restrict__ done) {
+  constexpr int LPR = row_lanes<T, K>(), C = K / LPR;
   if (done && *done) return;
   const int64_t blk = xcd_block(blockIdx.x, nb);
-  const int lane = threadIdx.x & 63;
-  const int64_t s = s_first + blk * kSlicesPerBlock + (threadIdx.x >> 6);
-  const int64_t r = s * 64 + lane;
-  double prod[K];
+  const int rloc = threadIdx.x / LPR, q = threadIdx.x % LPR;
+  const int t = rloc & 63;
+  const int64_t i = blk * kSlicesPerBlock + (rloc >> 6);
+  const int64_t s = s_first + (order && i < ns ? (int64_t)order[i] : i);
+  const int64_t r = s * 64 + t;
+  double prod[C];
 #pragma unroll
-  for (int k = 0; k < K; ++k) prod[k] = 0.0;
-  if (r >= r0 && r < r1) {
-    const Row<T, K> xr = ld<T, K>(x, r);
-    const Row<T, K> out = fine_row<T, K, MODE>(A, s, lane, r, x, xr, g);
-    st<T, K>(y, r, out);
+  for (int k = 0; k < C; ++k) prod[k] = 0.0;
+  if (i < ns && r >= r0 && r < r1) {
+    const Row<T, C> xr = ldp<T, K, C>(x, r, q);
+    const Row<T, C> out = fine_row<T, K, C, MODE>(A, s, t, q, r, x, xr, g);
+    stp<T, K, C>(y, r, q, out);
     if (DOT) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) prod[k] = (double)xr.v[k] * (double)out.v[k];
+      for (int k = 0; k < C; ++k) prod[k] = (double)xr.v[k] * (double)out.v[k];
     }
   }
-  if (DOT) block_sum_store<K>(prod, partial + blk * K);
+  if (DOT) block_sum_rows<K, LPR>(prod, partial + blk * K);
 }
 
 // device form of the row ranges of one multicolour step
@@ -204,28 +273,29 @@ struct GsDev {
 
 // one Gauss-Seidel step of row r: x_r + (g_r - (A x)_r) / a_rr, with the
 // row's diagonal data d0, d1 loaded by the caller
-template <class T, int K>
-__device__ __forceinline__ Row<T, K> gs_apply(T d0, T d1, const Row<T, K> &xr, const Row<T, K> &gr,
-                                              const T (&acc)[K], T off) {
-  Row<T, K> out;
+template <class T, int C>
+__device__ __forceinline__ Row<T, C> gs_apply(T d0, T d1, const Row<T, C> &xr, const Row<T, C> &gr,
+                                              const T (&acc)[C], T off) {
+  Row<T, C> out;
   if constexpr (std::is_same<T, double>::value) {
     const double dr = d0, diag = dr - off;
 #pragma unroll
-    for (int k = 0; k < K; ++k) out.v[k] = xr.v[k] + (gr.v[k] - (acc[k] + dr * xr.v[k])) / diag;
+    for (int k = 0; k < C; ++k) out.v[k] = xr.v[k] + (gr.v[k] - (acc[k] + dr * xr.v[k])) / diag;
   } else {
     const float inv_s = 1.0f / d0, dh = d1, diag = dh - off;
 #pragma unroll
-    for (int k = 0; k < K; ++k) out.v[k] = xr.v[k] + (gr.v[k] * inv_s - (acc[k] + dh * xr.v[k])) / diag;
+    for (int k = 0; k < C; ++k) out.v[k] = xr.v[k] + (gr.v[k] * inv_s - (acc[k] + dh * xr.v[k])) / diag;
   }
   return out;
 }
 
-// one wavefront (one slice) per block: a colour holds few rows, so small
-// blocks spread them over every CU; up to two row ranges (the top and the
-// non-top rows of one colour)
+// one slice per block (a colour holds few rows, so small blocks spread them
+// over every CU), row_lanes<T, K>() lanes per row; up to two row ranges (the
+// top and the non-top rows of one colour)
 template <class T, int K, bool ZS>
-__global__ __launch_bounds__(kWave) void k_gs(Sell A, GsDev<T> J, const T *__restrict__ g,
-                                               const int *__restrict__ done, ZeroStart z) {
+__global__ __launch_bounds__((kWave * row_lanes<T, K>())) void k_gs(Sell A, GsDev<T> J, const T *__restrict__ g,
+                                                                   const int *__restrict__ done, ZeroStart z) {
+  constexpr int LPR = row_lanes<T, K>(), C = K / LPR;
   if (done && *done) return;
   int64_t blk = xcd_block(blockIdx.x, J.nbt);
   int j = 0;
@@ -235,18 +305,18 @@ __global__ __launch_bounds__(kWave) void k_gs(Sell A, GsDev<T> J, const T *__res
   }
   const int64_t r0 = J.r0[j], r1 = J.r1[j];
   T *x = J.x;
-  const int lane = threadIdx.x & 63;
+  const int t = threadIdx.x / LPR, q = threadIdx.x % LPR;
   const int64_t s = J.sf[j] + blk;
-  const int64_t r = s * 64 + lane;
+  const int64_t r = s * 64 + t;
   if (r < r0 || r >= r1) return;
-  Row<T, K> xr;
+  Row<T, C> xr;
   if constexpr (ZS) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) xr.v[k] = T(0);
+    for (int k = 0; k < C; ++k) xr.v[k] = T(0);
   } else {
-    xr = ld<T, K>(x, r);
+    xr = ldp<T, K, C>(x, r, q);
   }
-  const Row<T, K> gr = ld<T, K>(g, r);
+  const Row<T, C> gr = ldp<T, K, C>(g, r, q);
   T d0, d1 = T(0);
   if constexpr (std::is_same<T, double>::value) {
     d0 = A.d64[r];
@@ -254,9 +324,9 @@ __global__ __launch_bounds__(kWave) void k_gs(Sell A, GsDev<T> J, const T *__res
     d0 = A.s32[r];
     d1 = A.dh32[r];
   }
-  T acc[K], off;
-  sell_row<T, K, true, ZS>(A, s, lane, x, xr, acc, off, z);
-  st<T, K>(x, r, gs_apply<T, K>(d0, d1, xr, gr, acc, off));
+  T acc[C], off;
+  sell_row<T, K, C, true, ZS>(A, s, t, q, x, xr, acc, off, z);
+  stp<T, K, C>(x, r, q, gs_apply<T, C>(d0, d1, xr, gr, acc, off));
 }
 
 template <class T, int K, bool ACC>
@@ -272,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_rect(Sell E, int64_t nb, const T *__
 #pragma unroll
   for (int k = 0; k < K; ++k) zero.v[k] = T(0);
   T acc[K], off;
-  sell_row<T, K, false>(E, s, lane, x, zero, acc, off);
+  sell_row<T, K, K, false>(E, s, lane, 0, x, zero, acc, off);
   Row<T, K> out;
   if (ACC) out = ld<T, K>(y, r);
 #pragma unroll
@@ -298,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_sum(Sell E, int64_t n_top, i
 #pragma unroll
     for (int k = 0; k < K; ++k) zero.v[k] = T(0);
     T acc[K], off;
-    sell_row<T, K, false>(E, s, lane, ys, zero, acc, off);
+    sell_row<T, K, K, false>(E, s, lane, 0, ys, zero, acc, off);
     Row<T, K> out;
     if (r >= n_top) {
       const Row<T, K> wr = ld<T, K>(w, r);
@@ -974,20 +1044,21 @@ void launch_slot_copy(hipStream_t stm, unsigned mask, const double *z, double *p
 
 template <class T>
 void launch_spmv(hipStream_t stm, int K, const Sell &A, int mode, int64_t r0, int64_t r1, const T *x, const T *g,
-                 T *y, double *partial, const int *done) {
+                 T *y, double *partial, const int *done, const int32_t *order) {
   int64_t nb = sell_blocks(r0, r1);
   if (!nb) return;
-  int64_t sf = r0 / kWave;
+  int64_t sf = r0 / kWave, ns = (r1 + kWave - 1) / kWave - sf;
   VEMG_K_SWITCH(K, {
+    const dim3 blk(kBlock * row_lanes<T, KK>());
     if (mode == 0) {
       if (partial)
-        hipLaunchKernelGGL((k_spmv<T, KK, 0, true>), grid(nb), dim3(kBlock), 0, stm, A, r0, r1, sf, nb, x, g, y,
+        hipLaunchKernelGGL((k_spmv<T, KK, 0, true>), grid(nb), blk, 0, stm, A, r0, r1, sf, ns, nb, order, x, g, y,
                            partial, done);
       else
-        hipLaunchKernelGGL((k_spmv<T, KK, 0, false>), grid(nb), dim3(kBlock), 0, stm, A, r0, r1, sf, nb, x, g, y,
+        hipLaunchKernelGGL((k_spmv<T, KK, 0, false>), grid(nb), blk, 0, stm, A, r0, r1, sf, ns, nb, order, x, g, y,
                            partial, done);
     } else {
-      hipLaunchKernelGGL((k_spmv<T, KK, 1, false>), grid(nb), dim3(kBlock), 0, stm, A, r0, r1, sf, nb, x, g, y,
+      hipLaunchKernelGGL((k_spmv<T, KK, 1, false>), grid(nb), blk, 0, stm, A, r0, r1, sf, ns, nb, order, x, g, y,
                          partial, done);
     }
   })
@@ -1015,10 +1086,11 @@ void launch_gs(hipStream_t stm, int K, const Sell &A, int64_t a0, int64_t a1, in
   }
   if (!J.nbt) return;
   VEMG_K_SWITCH(K, {
+    const dim3 blk(kWave * row_lanes<T, KK>());
     if (zs.on)
-      hipLaunchKernelGGL((k_gs<T, KK, true>), grid(J.nbt), dim3(kWave), 0, stm, A, J, g, done, zs);
+      hipLaunchKernelGGL((k_gs<T, KK, true>), grid(J.nbt), blk, 0, stm, A, J, g, done, zs);
     else
-      hipLaunchKernelGGL((k_gs<T, KK, false>), grid(J.nbt), dim3(kWave), 0, stm, A, J, g, done, zs);
+      hipLaunchKernelGGL((k_gs<T, KK, false>), grid(J.nbt), blk, 0, stm, A, J, g, done, zs);
   })
 }
 
@@ -1192,7 +1264,7 @@ void launch_pcg_resume(hipStream_t stm, int, Scal *s, unsigned keep) {
 
 #define VEMG_INSTANTIATE(T)                                                                                          \
   template void launch_spmv<T>(hipStream_t, int, const Sell &, int, int64_t, int64_t, const T *, const T *, T *,      \
-                               double *, const int *);                                                               \
+                               double *, const int *, const int32_t *);                                              \
   template void launch_gs<T>(hipStream_t, int, const Sell &, int64_t, int64_t, int64_t, int64_t, const T *, T *,       \
                              const int *, ZeroStart);                                                                \
   template void launch_rect<T>(hipStream_t, int, const Sell &, bool, const T *, T *, const int *);                    \
