@@ -180,6 +180,18 @@ vemg_status vemg_rhs(vemg_solver s, const double *f_host, double *b_host);
  * order; y is 0 at fixed nodes. */
 vemg_status vemg_matvec(vemg_solver s, const double *x_dev, double *y_dev);
 
+/* vemg_matvec for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels, with the two storage-order work vectors taken from a
+ * static buffer of the library (32 MiB, held on every GPU the library runs on
+ * until the process ends) instead of the handle, so the call itself
+ * allocates nothing.  Limit: n (free unknowns, vemg_info.n) <= 2^21 =
+ * 2,097,152; larger handles get VEMG_ERR_INVALID_ARG with the sizes in
+ * vemg_last_error.  Every call on one GPU shares that GPU's buffer: calls
+ * that overlap on one GPU (from several threads or handles) race.  Result
+ * and errors otherwise as vemg_matvec. */
+vemg_status vemg_matvec_noalloc(vemg_solver s, const double *x_dev, double *y_dev);
+
 /* Solves A x = b for nrhs right-hand sides stored one after another
  * ([nrhs][n_nodes], device).  Right-hand sides are solved in batches of up
  * to 8 that share every matrix read (SpMM-style launches); each column

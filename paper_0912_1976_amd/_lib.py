@@ -74,6 +74,7 @@ def load_library():
     lib.vemg_setup.argtypes = [P, I64, P, I64, P, P]
     lib.vemg_rhs.argtypes = [P, P, P]
     lib.vemg_matvec.argtypes = [P, P, P]
+    lib.vemg_matvec_noalloc.argtypes = [P, P, P]
     lib.vemg_solve.argtypes = [P, I32, P, P, D, I32, P, P]
     lib.vemg_apply.argtypes = [P, I32, P, P]
     lib.vemg_get_info.argtypes = [P, C.POINTER(Info)]
@@ -106,7 +107,7 @@ def load_library():
               "vemg_server_poll", "vemg_server_wait", "vemg_server_result", "vemg_server_get_stats",
               "vemg_server_destroy", "vemg_server_set_precision"):
         getattr(lib, f).restype = I32
-    for f in ("vemg_create", "vemg_setup", "vemg_rhs", "vemg_matvec", "vemg_solve", "vemg_apply",
+    for f in ("vemg_create", "vemg_setup", "vemg_rhs", "vemg_matvec", "vemg_matvec_noalloc", "vemg_solve", "vemg_apply",
               "vemg_get_info", "vemg_footprint", "vemg_export", "vemg_destroy", "vemg_time_op"):
         getattr(lib, f).restype = I32
     _LIB = lib

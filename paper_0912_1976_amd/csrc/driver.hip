@@ -1383,6 +1383,36 @@ int guarded(Handle *h, F &&f) {
 }  // namespace vemg
 
 
+// ============================================================== static buffer
+// Device memory for vemg_matvec_noalloc, which allocates nothing: a
+// file-scope array that every GPU the library runs on holds until the process
+// ends.  In host code its name is only a stand-in; the device address on each
+// GPU comes from hipGetSymbolAddress, looked up once per device.
+namespace vemg {
+
+constexpr int64_t kScratchRows = int64_t(1) << 21;  // unknowns: two vectors of this length, 32 MiB
+
+namespace {
+
+__device__ __align__(256) double scratch[2 * kScratchRows];
+
+std::mutex scratch_mu;
+std::map<int, double *> scratch_addr;  // device ordinal -> address of scratch on that device
+
+// address of the static buffer on `device` (the current device)
+double *scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  auto it = scratch_addr.find(device);
+  if (it != scratch_addr.end()) return it->second;
+  void *p = nullptr;
+  HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  scratch_addr[device] = (double *)p;
+  return (double *)p;
+}
+
+}  // namespace
+}  // namespace vemg
+
 // ============================================================== serving
 namespace vemg {
 namespace {
@@ -1817,6 +1847,29 @@ vemg_status vemg_matvec(vemg_solver s, const double *x_dev, double *y_dev) {
     vemg::launch_spmv<double>(st, 1, s->A, 0, 0, n, s->v64.tmp, nullptr, s->v64.res, nullptr, nullptr, s->order_all);
     vemg::launch_fill<double>(st, y_dev, s->P.n_nodes, 0.0, nullptr);
     vemg::launch_scatter(st, 1, 0, s->v64.res, s->perm, y_dev, n);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return VEMG_OK;
+  });
+}
+
+vemg_status vemg_matvec_noalloc(vemg_solver s, const double *x_dev, double *y_dev) {
+  if (!s || !x_dev || !y_dev) return VEMG_ERR_INVALID_ARG;
+  if (!s->ready || s->device < 0) return VEMG_ERR_STATE;
+  if (s->P.n > vemg::kScratchRows) {
+    s->err = "vemg_matvec_noalloc: " + std::to_string(s->P.n) + " unknowns exceed the static buffer's " +
+             std::to_string(vemg::kScratchRows);
+    return VEMG_ERR_INVALID_ARG;
+  }
+  return (vemg_status)guarded(s, [&]() -> int {
+    double *buf = vemg::scratch_of(s->device);  // [0, n): x in storage order; [n, 2n): A x
+    hipStream_t st = s->work;
+    int64_t n = s->P.n;
+    vemg::sync_in(s);
+    vemg::launch_gather(st, 1, 0, x_dev, s->perm, buf, n);
+    vemg::launch_spmv<double>(st, 1, s->A, 0, 0, n, buf, nullptr, buf + n, nullptr, nullptr, s->order_all);
+    vemg::launch_fill<double>(st, y_dev, s->P.n_nodes, 0.0, nullptr);
+    vemg::launch_scatter(st, 1, 0, buf + n, s->perm, y_dev, n);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     return VEMG_OK;
