@@ -127,7 +127,8 @@ typedef struct {
   double theta;        /* strength threshold, 0.01 (Section 6) */
   double prolong_omega;/* prolongator smoothing, 2/3 (Section 6) */
   int max_levels;      /* per hierarchy, 10 */
-  int64_t coarse_max;  /* unknowns on the coarsest level (solved exactly), 2048 */
+  int64_t coarse_max;  /* unknowns on the coarsest level (solved exactly through an explicit
+                          FP64 inverse), 8192 (at most 8192) */
   int poll_every;      /* PCG iterations per host poll of the convergence flag, 8 */
   int max_restarts;    /* restarts from the true residual, 5 */
   int use_graphs;      /* capture one PCG iteration in a hipGraph, 1 */

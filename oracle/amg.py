@@ -265,7 +265,7 @@ def smoothed_prolongator_from(A, P0):
     return structural_product(on_pattern(pat, S), P0)
 
 
-def build_hierarchy(A0, colour0, B0=None, coarse_max=2048, max_levels=10, stall=0.8):
+def build_hierarchy(A0, colour0, B0=None, coarse_max=8192, max_levels=10, stall=0.8):
     """SA hierarchy on A0 (in storage order: rows sorted by colour, within each
     block for the whole A_UU; the sweeps select rows by colour), one
     unknown per node on the finest level, near-kernel vectors B0 (default:

@@ -39,7 +39,7 @@ class OracleSetup:
     mass: sp.csr_matrix       # full consistent mass matrix, natural order
     xyz: np.ndarray
     top: np.ndarray
-    coarse_max: int = 2048    # hierarchy parameters (also for the SA baseline)
+    coarse_max: int = 8192    # hierarchy parameters (also for the SA baseline)
     max_levels: int = 10
     extrapolation: str = "projection"
 
@@ -48,7 +48,7 @@ class OracleSetup:
         return self.perm.size
 
 
-def setup(mesh, mode="N", coarse_max=2048, max_levels=10, alpha=0.0, extrapolation="projection"):
+def setup(mesh, mode="N", coarse_max=8192, max_levels=10, alpha=0.0, extrapolation="projection"):
     """Assembly (Section 3), E~ (Section 5.4) and both SA hierarchies (Section 6).
     mode 'N' (point condition), 'D' (Dirichlet top) or 'R' (Robin top with
     coefficient alpha > 0, the free-surface condition of Section 2).

@@ -125,7 +125,7 @@ class Solver:
     """
 
     def __init__(self, xyz, tets, top, *, top_bc="pinned", pc="vl_as", device=0, pin_node=-1,
-                 use_graphs=True, poll_every=8, coarse_max=2048, max_levels=10, max_restarts=5,
+                 use_graphs=True, poll_every=8, coarse_max=8192, max_levels=10, max_restarts=5,
                  precision="fp64", inner_rtol=1e-4, max_outer=30, robin_alpha=0.0,
                  extrapolation="projection"):
         self._lib = load_library()
@@ -266,7 +266,7 @@ class Server:
     request is collected with result()."""
 
     def __init__(self, *, device=0, hbm_budget=0, top_bc="pinned", pc="vl_as", precision="mixed_pc",
-                 poll_every=8, coarse_max=2048, max_restarts=5, robin_alpha=0.0, extrapolation="projection"):
+                 poll_every=8, coarse_max=8192, max_restarts=5, robin_alpha=0.0, extrapolation="projection"):
         import torch
         self._torch = torch
         self._lib = load_library()

@@ -1780,7 +1780,7 @@ void vemg_default_options(vemg_options *o) {
   o->theta = 0.01;
   o->prolong_omega = 2.0 / 3.0;
   o->max_levels = 10;
-  o->coarse_max = 2048;
+  o->coarse_max = 8192;
   o->poll_every = 8;
   o->max_restarts = 5;
   o->use_graphs = 1;

@@ -506,51 +506,54 @@ __global__ __launch_bounds__(kWave) void k_csr_gs(CsrG A, int64_t r0, int64_t r1
   csr_row_op<T, K, G, 4, ZS>(A, r, gl, x, g, x, zlim);
 }
 
-// one wavefront per row of the dense FP64 coarsest inverse
-template <class T, int K>
-__device__ __forceinline__ void dense_row(const double *__restrict__ C, int64_t m, int64_t i, int lane,
-                                          const T *__restrict__ g, T *__restrict__ x) {
-  double t[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) t[k] = 0.0;
-  // U entries per lane are loaded before they are added (in the same order
-  // as one at a time), so that U loads are in flight instead of one
-  constexpr int U = K >= 4 ? 2 : 8 / K;
-  const double *__restrict__ Ci = C + i * m;
-  int64_t j = lane;
-  for (; j + (U - 1) * 64 < m; j += U * 64) {
-    double c[U];
-    Row<T, K> gj[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      c[u] = Ci[j + u * 64];
-      gj[u] = ld<T, K>(g, j + u * 64);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) t[k] += c[u] * (double)gj[u].v[k];
-    }
-  }
-  for (; j < m; j += 64) {
-    const double c = Ci[j];
-    const Row<T, K> gj = ld<T, K>(g, j);
-#pragma unroll
-    for (int k = 0; k < K; ++k) t[k] += c * (double)gj.v[k];
-  }
-  Row<T, K> out;
-#pragma unroll
-  for (int k = 0; k < K; ++k) out.v[k] = (T)wave_sum(t[k]);
-  if (lane == 0) st<T, K>(x, i, out);
-}
+// Dense FP64 coarsest inverse applied to K columns, x = Cinv g.  A block
+// takes kDenseRows rows (kDenseRows / 4 per wavefront) and walks the columns
+// in tiles whose g values are staged in LDS once for all its rows, so that g
+// is read from L2 once per block instead of once per row; the inverse is
+// streamed once.  Lane l of a wavefront adds the columns j = l, l + 64, ...
+// of its rows in ascending order, then the wavefront sums its lanes, so the
+// rounding does not depend on the tiling.
+constexpr int kDenseRows = 16;
+constexpr int kDenseTile = 256;
 
 template <class T, int K>
 __global__ __launch_bounds__(kBlock) void k_dense(const double *__restrict__ C, int64_t m, const T *__restrict__ g,
                                                   T *__restrict__ x, const int *__restrict__ done) {
   if (done && *done) return;
-  const int64_t i = (int64_t)blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
-  if (i >= m) return;
-  dense_row<T, K>(C, m, i, threadIdx.x & 63, g, x);
+  constexpr int RW = kDenseRows / kSlicesPerBlock;  // rows per wavefront
+  __shared__ Row<T, K> gt[kDenseTile];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i0 = (int64_t)blockIdx.x * kDenseRows + w * RW;
+  double t[RW][K];
+#pragma unroll
+  for (int r = 0; r < RW; ++r)
+#pragma unroll
+    for (int k = 0; k < K; ++k) t[r][k] = 0.0;
+  for (int64_t j0 = 0; j0 < m; j0 += kDenseTile) {
+    const int nt = (int)((m - j0) < kDenseTile ? (m - j0) : kDenseTile);
+    __syncthreads();
+    for (int j = threadIdx.x; j < nt; j += kBlock) gt[j] = ld<T, K>(g, j0 + j);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      if (i0 + r >= m) break;  // uniform over the wavefront
+      const double *__restrict__ Ci = C + (i0 + r) * m + j0;
+#pragma unroll 4
+      for (int j = lane; j < nt; j += 64) {
+        const double c = Ci[j];
+        const Row<T, K> gj = gt[j];
+#pragma unroll
+        for (int k = 0; k < K; ++k) t[r][k] += c * (double)gj.v[k];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    Row<T, K> out;
+#pragma unroll
+    for (int k = 0; k < K; ++k) out.v[k] = (T)wave_sum(t[r][k]);
+    if (lane == 0 && i0 + r < m) st<T, K>(x, i0 + r, out);
+  }
 }
 
 // ------------------------------------------------------------- vectors
@@ -1168,7 +1171,7 @@ void launch_csr_gs(hipStream_t stm, int K, const CsrG &A, int64_t r0, int64_t r1
 template <class T>
 void launch_dense(hipStream_t stm, int K, const double *Cinv, int64_t m, const T *g, T *x, const int *done) {
   if (m <= 0) return;
-  int64_t nb = (m + kSlicesPerBlock - 1) / kSlicesPerBlock;
+  int64_t nb = (m + kDenseRows - 1) / kDenseRows;
   VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_dense<T, KK>), grid(nb), dim3(kBlock), 0, stm, Cinv, m, g, x, done))
 }
 

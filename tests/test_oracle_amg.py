@@ -124,7 +124,7 @@ def test_kuhn_box_needs_exactly_four_colours():
     # the minimum; the Kuhn split admits four ((i + j + k) mod 4 differs along
     # every edge), and the smallest-last greedy colouring finds that minimum
     m = box_mesh(9, 8, 6, 1e-3, jitter=0.3, seed=4, bathymetry=True)
-    s = solver.setup(m, "N")
+    s = solver.setup(m, "N", coarse_max=256)
     assert ordering.is_valid_colouring(s.A, s.colour)
     assert int(s.colour.max()) + 1 == 4
 

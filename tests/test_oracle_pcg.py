@@ -91,7 +91,7 @@ def test_vertical_lumping_iterations_flat_in_aspect_ratio(jitter):
     its = {pc: [] for pc in ("vl_as", "vl_sor", "vl_add", "sa")}
     for H in (1e-2, 1e-3, 1e-4):
         m = box_mesh(17, 17, 9, H, jitter=jitter, seed=1, bathymetry=True)
-        s = solver.setup(m, "N")
+        s = solver.setup(m, "N", coarse_max=256)
         b = solver.rhs_from_field(s, fourier_field(m.xyz, H, 9))
         for pc in its:
             _, it, _, ok = solver.solve(s, b, 1e-8, pc, max_iter=20000)
@@ -110,7 +110,7 @@ def test_additive_smoother_pays_off_on_multiscale_mesh():
     # a V-cycle over all scales of A_bar, cuts the iteration count sharply.
     from inputs import graded_mesh
     m = graded_mesh(1 / 40, 1e-3, jitter=0.25, seed=3)
-    s = solver.setup(m, "N")
+    s = solver.setup(m, "N", coarse_max=256)
     b = solver.rhs_from_field(s, fourier_field(m.xyz, 1e-3, 100))
     its = {}
     for pc in ("vl_as", "vl_sor"):
@@ -177,7 +177,7 @@ def test_extended_refinement_goes_below_the_fp64_floor():
     # residual the same preconditioned iteration reaches far lower.
     from oracle import fem
     m = box_mesh(17, 17, 9, 1e-4, jitter=0.3, seed=1, bathymetry=True)
-    s = solver.setup(m, "N")
+    s = solver.setup(m, "N", coarse_max=256)
     b = solver.rhs_from_field(s, fourier_field(m.xyz, 1e-4, 9))
     M = precond.make(s, "vl_as")
     A = lambda v: solver.apply_A(s, v)
