@@ -171,6 +171,13 @@ def iteration_bytes(info, K=1, pc="vl_as", precision="fp64"):
     return krylov + sor + s_cycle + a_cycle + join + mixed
 
 
+def coarsest_bytes(info, K=1, elt=8):
+    """The surface hierarchy's coarsest dense inverse times a vector: the FP64
+    inverse streamed once, g read and x written."""
+    m = info["s_rows"][info["s_levels"] - 1] if info["s_levels"] else 0
+    return m * m * 8 + 2 * m * elt * K
+
+
 def kernel_rates(s, info, vemg, K=1, reps=20, precision="fp64"):
     """Live per-application times of the hot operators of one iteration
     (HIP events on the library's stream) and their algorithmic rates."""
@@ -179,6 +186,7 @@ def kernel_rates(s, info, vemg, K=1, reps=20, precision="fp64"):
     for name, op, nbytes in (("spmv", vemg.OP_A, spmv_bytes(info, K, pe, pv)),
                              ("fine_sweep", vemg.OP_GS_FWD, gs_sweep_bytes(info, K, pe, pv)),
                              ("coarse_sweep", vemg.OP_GS_COARSE, coarse_gs_bytes(info, 1, K, pe, pv)),
+                             ("coarsest_dense", vemg.OP_COARSEST, coarsest_bytes(info, K, pe)),
                              ("restrict_Et", vemg.OP_ET, restrict_bytes(info, K, pe, pv)),
                              ("prolong_E", vemg.OP_E, prolong_bytes(info, K, pe, pv))):
         try:
@@ -202,7 +210,7 @@ PER_ITERATION = {"vl_as": (4, 3, 2), "vl_sor": (2, 2, 0), "vl_add": (2, 2, 2), "
 KERNEL_NAMES = {
     "gs": "k_gs<double, {K}, false> (fine multicolour SOR, one colour per launch)",
     "spmv": "k_spmv<double, {K}, 0, true> (fine difference-form SpMV fused with p.q)",
-    "cgs": "k_csr_gs<double, {K}, 32, false> (coarse multicolour SOR, one colour per launch)",
+    "cgs": "k_patch_gs<double, {K}, false, false> (coarse block multicolour SOR, one patch colour per launch)",
     "et": "k_csr_spmv<double, {K}, 64, 2> (restriction E~^T, CSR, 64 lanes per surface row)",
     "e": "k_rect<double, {K}, true> (prolongation z += E~ y, SELL, one thread per fine row)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
@@ -278,7 +286,7 @@ def pmc_kernels(K):
     """Kernel-name patterns of the hot kernels with K columns (and of the
     calibration copy) in rocprofv3 output."""
     return {"gs": f"k_gs<double, {K}, false>", "spmv": f"k_spmv<double, {K}, 0, true>",
-            "cgs": f"k_csr_gs<double, {K}, 32, false>", "et": f"k_csr_spmv<double, {K}, 64, 2>",
+            "cgs": f"k_patch_gs<double, {K}, false, false>", "et": f"k_csr_spmv<double, {K}, 64, 2>",
             "e": f"k_rect<double, {K}, true>", "calibration": "MulFunctor"}
 
 

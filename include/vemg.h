@@ -233,14 +233,17 @@ typedef enum {
   VEMG_OP_VCYCLE_S = 4,
   VEMG_OP_VCYCLE_ABAR = 5,
   VEMG_OP_GS_FWD = 6,
-  VEMG_OP_GS_COARSE = 7  /* vemg_time_op only: one forward sweep on the first coarse level of A_bar */
+  VEMG_OP_GS_COARSE = 7, /* vemg_time_op only: one forward sweep on the first coarse level of A_bar */
+  VEMG_OP_COARSEST = 8   /* vemg_time_op only: the coarsest surface level's dense inverse times a vector */
 } vemg_op;
 vemg_status vemg_apply(vemg_solver s, int op, const double *in_dev, double *out_dev);
 
 /* Benchmark support: average device time in milliseconds of one
  * application of VEMG_OP_A (one SpMV launch), VEMG_OP_GS_FWD (one forward
  * multicolour sweep over all rows, one launch per colour),
- * VEMG_OP_GS_COARSE (the same on A_bar's first coarse level), VEMG_OP_ET
+ * VEMG_OP_GS_COARSE (the same on A_bar's first coarse level, one launch per
+ * patch colour), VEMG_OP_COARSEST (the explicit inverse of the surface
+ * hierarchy's coarsest level times a vector, one launch), VEMG_OP_ET
  * (the restriction E~^T, one launch) or VEMG_OP_E (the prolongation E~
  * added into an n-vector, as the SOR cycle applies it, one launch) to nrhs (1..8)
  * columns, in the handle's inner precision (FP32 for VEMG_MIXED_IR, FP64
@@ -282,8 +285,11 @@ vemg_status vemg_set_precision(vemg_solver s, int precision);
  * "Aoff.ptr" (int64), "Aoff.idx" (int32), "Aoff.val", "d", "diag" (double),
  * "E.ptr", "E.idx", "E.val", "S_perm" (int64),
  * "<h>.<level>.<what>" with h in {S, Abar, SA} and what in {A.ptr, A.idx, A.val,
- * P.ptr, P.idx, P.val, colour, node, agg, Cinv}.  With buf == NULL only
- * *bytes is set; otherwise *bytes must hold the buffer size. */
+ * P.ptr, P.idx, P.val, colour, node, agg, Cinv, rank (int64)}; levels in the
+ * block multicolour order of the coarse SOR sweeps (all but the fine levels
+ * of Abar and SA) also export patch, pcolour, lcolour (int32 per row) and
+ * pc_start, patch_row, seg_ptr, seg_row (int64 ranges).  With buf == NULL
+ * only *bytes is set; otherwise *bytes must hold the buffer size. */
 vemg_status vemg_export(vemg_solver s, const char *name, void *buf, size_t *bytes);
 
 vemg_status vemg_destroy(vemg_solver s);

@@ -29,9 +29,13 @@ Readings where the paper is silent (all stated in the design notes):
   P = (I - omega D^{-1} A) P^, D = diag(A), so P keeps A's near-kernel;
 * the sparsity pattern of every product is structural (entries that cancel
   to zero are kept);
-* SOR sweeps are multicolour: each level is stored colour by colour (greedy
-  colouring in the level's creation order, then a stable sort by colour);
-  forward = colours ascending, backward = colours descending;
+* SOR sweeps are multicolour.  The coarse levels are stored in the block
+  multicolour (patch) order of ordering.patch_order: patches of unknowns
+  consecutive in the spatial order, patch colour, patch, local colour; the
+  sweep takes the composite colours (patch colour, local colour) ascending
+  (forward) or descending (backward).  The spatial order of a coarse level
+  ranks its aggregates by their first member in the finer level's spatial
+  order (the unknowns of one aggregate in creation order);
 * coarsening stops at <= coarse_max unknowns, when a level would keep more
   than 0.8 of its unknowns, or at max_levels; the coarsest level is solved
   exactly (dense Cholesky).
@@ -125,10 +129,14 @@ def tentative_prolongator(agg):
 
 @dataclass
 class Level:
-    A: sp.csr_matrix                 # standard form, storage (colour-sorted) order
-    colour: np.ndarray               # colour of each row (non-decreasing)
+    A: sp.csr_matrix                 # standard form, storage order
+    colour: np.ndarray               # sweep colour of each row (composite on patch-ordered levels)
     node: np.ndarray                 # aggregation node of each row (dof)
     B: np.ndarray                    # near-kernel vectors restricted to this level [n, k]
+    rank: np.ndarray | None = None   # position of each row in the level's spatial order
+    patch: np.ndarray | None = None  # patch-ordered levels: patch, patch colour, local colour
+    pcolour: np.ndarray | None = None
+    lcolour: np.ndarray | None = None
     P: sp.csr_matrix | None = None   # prolongator to this level from the next
     chol: tuple | None = None        # Cholesky factor on the coarsest level
     agg: np.ndarray | None = None    # aggregate of each node
@@ -139,12 +147,27 @@ class Level:
         return self.A.shape[0]
 
 
-def colour_level(A):
-    """Greedy colouring in smallest-last order, then stable sort by colour.
-    Returns (permutation new->old, colours in new order)."""
-    col = ordering.colouring(A)
-    perm = np.argsort(col, kind="stable")
-    return perm, col[perm]
+def patch_level(A, rank):
+    """Block multicolour (patch) order of a level whose unknowns have the
+    spatial ranks `rank` (ordering.patch_order).  Returns (permutation
+    new->old, dict of the per-row arrays in the new order: colour (the
+    composite sweep colour), patch, pcolour, lcolour, rank)."""
+    perm, patch, pcol, lcol = ordering.patch_order(A, rank)
+    return perm, dict(colour=ordering.composite_colour(pcol, lcol), patch=patch, pcolour=pcol,
+                      lcolour=lcol, rank=np.asarray(rank)[perm])
+
+
+def coarse_rank(L, agg, cnode):
+    """Spatial rank of the coarse unknowns (creation order): aggregates are
+    ranked by their member of smallest rank in the finer level L, and the
+    unknowns of one aggregate follow their creation order."""
+    nagg = int(agg.max()) + 1
+    first = np.full(nagg, np.iinfo(np.int64).max, dtype=np.int64)
+    np.minimum.at(first, agg[L.node], np.asarray(L.rank, dtype=np.int64))
+    order = np.lexsort((np.arange(cnode.size), first[cnode]))
+    rank = np.empty(cnode.size, dtype=np.int64)
+    rank[order] = np.arange(cnode.size)
+    return rank
 
 
 def permute(A, perm):
@@ -265,11 +288,14 @@ def smoothed_prolongator_from(A, P0):
     return structural_product(on_pattern(pat, S), P0)
 
 
-def build_hierarchy(A0, colour0, B0=None, coarse_max=8192, max_levels=10, stall=0.8):
-    """SA hierarchy on A0 (in storage order: rows sorted by colour, within each
-    block for the whole A_UU; the sweeps select rows by colour), one
-    unknown per node on the finest level, near-kernel vectors B0 (default:
-    the constant vector).
+def build_hierarchy(A0, colour0, B0=None, coarse_max=8192, max_levels=10, stall=0.8, rank0=None, first=None):
+    """SA hierarchy on A0 (in storage order, with the sweep colour colour0 of
+    every row; the sweeps select rows by colour), one unknown per node on
+    the finest level, near-kernel vectors B0 (default: the constant vector),
+    spatial rank rank0 of every row (default: the storage order).  first:
+    optional dict of the first level's patch arrays (patch, pcolour,
+    lcolour) when it is patch-ordered itself.  Every coarser level is stored
+    in its patch order (patch_level).
 
     Coarsening stops at coarse_max unknowns, at max_levels, or when a level
     would keep more than `stall` of its unknowns.  Reading: Section 6 fixes
@@ -283,7 +309,8 @@ def build_hierarchy(A0, colour0, B0=None, coarse_max=8192, max_levels=10, stall=
     if B0 is None:
         B0 = np.ones((n0, 1))
     levels = [Level(A=A0.tocsr(), colour=np.asarray(colour0), node=np.arange(n0),
-                    B=np.asarray(B0, dtype=np.float64))]
+                    B=np.asarray(B0, dtype=np.float64),
+                    rank=np.arange(n0) if rank0 is None else np.asarray(rank0), **(first or {}))]
     nnodes = n0
     while True:
         L = levels[-1]
@@ -303,12 +330,12 @@ def build_hierarchy(A0, colour0, B0=None, coarse_max=8192, max_levels=10, stall=
                 break
         P = smoothed_prolongator_from(L.A, P0)
         Ac = structural_product(P.T.tocsr(), L.A, P)
-        perm, ccol = colour_level(Ac)
+        perm, arrs = patch_level(Ac, coarse_rank(L, agg, cnode))
         L.P = P[:, perm].tocsr()
         L.P.sort_indices()
         L.agg = agg
         nnodes = int(agg.max()) + 1
-        levels.append(Level(A=permute(Ac, perm), colour=ccol, node=cnode[perm], B=Bc[perm]))
+        levels.append(Level(A=permute(Ac, perm), node=cnode[perm], B=Bc[perm], **arrs))
     last = levels[-1]
     last.chol = sla.cho_factor(last.A.toarray(), lower=True)
     return levels
@@ -327,8 +354,8 @@ def gs_sweep(A, diag, colour, g, x, forward=True):
     the rows of one colour share no entries, so updating them together is
     the sequential sweep taken in colour order."""
     x = x.copy()
-    ncol = int(colour.max()) + 1 if colour.size else 0
-    seq = range(ncol) if forward else range(ncol - 1, -1, -1)
+    cols = np.unique(colour).tolist()
+    seq = cols if forward else cols[::-1]
     for c in seq:
         rows = np.nonzero(colour == c)[0]
         if rows.size == 0:

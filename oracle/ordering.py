@@ -11,7 +11,9 @@ which keeps the number of colour classes (sequential sweep stages) small:
 four on a Kuhn-split box, whose tetrahedra are 4-cliques.  These are
 readings of the paper (it does not fix an order); they are pinned by the
 validity tests (permutation, valid colouring, the smallest-last property)
-and, for the GPU library, by bit-exact comparison.
+and, for the GPU library, by bit-exact comparison.  The coarse multigrid
+levels are swept in a block multicolour order (patches of unknowns, see
+patch_order below).
 
 Locality key of a free node (x, y, z):
   T = max(1, round(sqrt(m_top / 64)))   tiles per side, m_top = #top nodes
@@ -26,6 +28,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
+import scipy.sparse as sp
 
 
 def locality_order(xyz, top, free):
@@ -132,3 +135,94 @@ def is_valid_colouring(A, colour):
     A = A.tocoo()
     off = A.row != A.col
     return bool(np.all(colour[A.row[off]] != colour[A.col[off]]))
+
+
+# ---------------------------------------------------------------------------
+# Patch ordering of the coarse multigrid levels
+# ---------------------------------------------------------------------------
+# Reading (the paper fixes no SOR order): the sweeps of the coarse levels
+# visit their unknowns in a block multicolour order.  The unknowns, taken in
+# their spatial order (a rank per unknown), are cut into consecutive patches
+# of at most PATCH_ROWS unknowns whose rows hold at most PATCH_ENTRIES
+# off-diagonal entries together (a patch always takes at least one unknown).
+# Two patches are neighbours when an entry of the level's matrix couples
+# them.  The patches are coloured (greedy in smallest-last order on the patch
+# graph), and the unknowns of every patch are coloured on the patch's own
+# couplings (greedy in smallest-last order, unknowns in rank order).  The
+# sweep order is: patch colour, then patch, then local colour, then rank.
+# Unknowns of equal (patch colour, local colour) are never coupled (within a
+# patch by the local colouring, across patches by the patch colouring), so a
+# sweep in this order is the multicolour sweep over the composite colours
+# (patch colour, local colour) in lexicographic order, and that is a plain
+# sequential forward (or, reversed, backward) SOR sweep.
+PATCH_ROWS = 64
+PATCH_ENTRIES = 4096
+
+
+def _pattern_csr(A):
+    """Off-diagonal structural pattern of a square matrix (CSR, sorted)."""
+    A = A.tocoo()
+    off = A.row != A.col
+    n = A.shape[0]
+    P = sp.csr_matrix((np.ones(int(off.sum())), (A.row[off], A.col[off])), shape=(n, n))
+    P.sum_duplicates()
+    P.sort_indices()
+    return P
+
+
+def patches_of(A, rank, rows_max=PATCH_ROWS, entries_max=PATCH_ENTRIES):
+    """Patch of every unknown (patches numbered in rank order): the unknowns
+    in rank order are appended to the current patch until it holds rows_max
+    unknowns or the next unknown's off-diagonal count would take the patch's
+    total above entries_max; then a new patch starts."""
+    A = _pattern_csr(A)
+    n = A.shape[0]
+    length = np.diff(A.indptr)
+    patch = np.empty(n, dtype=np.int64)
+    p, rows, ents = -1, 0, 0
+    for i in np.argsort(rank, kind="stable").tolist():
+        L = int(length[i])
+        if p < 0 or rows == rows_max or ents + L > entries_max:
+            p, rows, ents = p + 1, 0, 0
+        patch[i] = p
+        rows += 1
+        ents += L
+    return patch
+
+
+def patch_graph(A, patch):
+    """Patch adjacency: patches p != q are neighbours when some entry a_ij has
+    i in p and j in q.  CSR pattern over the patches."""
+    A = _pattern_csr(A).tocoo()
+    npatch = int(patch.max()) + 1 if patch.size else 0
+    pi, pj = patch[A.row], patch[A.col]
+    cross = pi != pj
+    G = sp.csr_matrix((np.ones(int(cross.sum())), (pi[cross], pj[cross])), shape=(npatch, npatch))
+    G.sum_duplicates()
+    G.sort_indices()
+    return G
+
+
+def patch_order(A, rank, rows_max=PATCH_ROWS, entries_max=PATCH_ENTRIES):
+    """The block multicolour order described above.  Returns (perm, patch,
+    pcolour, lcolour): perm[new] = old, and the patch, patch colour and local
+    colour of every unknown in the new order."""
+    A = _pattern_csr(A)
+    n = A.shape[0]
+    rank = np.asarray(rank)
+    patch = patches_of(A, rank, rows_max, entries_max)
+    pcol = colouring(patch_graph(A, patch)) if n else np.zeros(0, dtype=np.int64)
+    lcol = np.zeros(n, dtype=np.int64)
+    by_patch = np.lexsort((rank, patch))          # rows of each patch in rank order
+    starts = np.searchsorted(patch[by_patch], np.arange(int(patch.max()) + 2 if n else 1))
+    for p in range(starts.size - 1):
+        rows = by_patch[starts[p]:starts[p + 1]]
+        lcol[rows] = colouring(A[rows][:, rows].tocsr())
+    perm = np.lexsort((rank, lcol, patch, pcol[patch]))
+    return perm, patch[perm], pcol[patch][perm], lcol[perm]
+
+
+def composite_colour(pcolour, lcolour, rows_max=PATCH_ROWS):
+    """One integer per (patch colour, local colour) pair, in the pairs'
+    lexicographic order (a local colour is below the patch's row count)."""
+    return np.asarray(pcolour) * rows_max + np.asarray(lcolour)

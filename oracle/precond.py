@@ -78,7 +78,7 @@ def sa_levels(s, coarse_max=None, max_levels=None):
     node order for its baseline; this is the order of the lumping method."""
     if getattr(s, "_sa_levels", None) is None:
         s._sa_levels = amg.build_hierarchy(s.A, s.colour, None, coarse_max or s.coarse_max,
-                                           max_levels or s.max_levels)
+                                           max_levels or s.max_levels, rank0=s.rank)
     return s._sa_levels
 
 

@@ -7,8 +7,9 @@ eq. phi_decomposition), each block in locality order, then stably sorted by
 the colour of A_UU (greedy in smallest-last order, see ordering.py).  The
 non-top block is the matrix A_bar of eq. equation_decomposition; its colouring
 is the restriction of the colouring of A_UU.  The surface operator
-S = E~^T A E~ (indexed in the top block's storage order) is coloured the same
-way and stored colour by colour as well; E~'s columns follow that order.
+S = E~^T A E~ (indexed in the top block's storage order) is stored in the
+block multicolour (patch) order of the coarse levels, its spatial order being
+the locality order of the top nodes; E~'s columns follow that order.
 """
 from __future__ import annotations
 
@@ -32,6 +33,7 @@ class OracleSetup:
     A: sp.csr_matrix          # standard form A_UU, storage order
     diag: np.ndarray
     colour: np.ndarray        # colour of every storage row (sorted within each block)
+    rank: np.ndarray          # position of every storage row in the locality order
     E: sp.csr_matrix | None   # n x m', columns in S storage order
     S_perm: np.ndarray | None  # S storage position -> top-block position
     S_levels: list | None
@@ -87,6 +89,9 @@ def setup(mesh, mode="N", coarse_max=8192, max_levels=10, alpha=0.0, extrapolati
     colour = colour_u[order_u]
     n_top = int(np.count_nonzero(top[perm]))
     n = perm.size
+    loc_pos = np.full(n_nodes, -1, dtype=np.int64)
+    loc_pos[loc] = np.arange(loc.size)
+    rank = loc_pos[perm]      # the top block ranks first (block 0 of the locality key)
 
     # surface branch: E~, S = E~^T A E~ and its hierarchy (mode N only)
     E = None
@@ -97,7 +102,7 @@ def setup(mesh, mode="N", coarse_max=8192, max_levels=10, alpha=0.0, extrapolati
         if extrapolation == "sspai":
             E0 = extrap.sspai_refit(E0, A, n_top)
         S0 = amg.structural_product(E0.T.tocsr(), A, E0)
-        S_perm, S_col = amg.colour_level(S0)
+        S_perm, S_arr = amg.patch_level(S0, rank[:n_top])
         E = E0[:, S_perm].tocsr()
         E.sort_indices()
         # near-kernel of the vertically lumped operator: the constant and the
@@ -105,15 +110,18 @@ def setup(mesh, mode="N", coarse_max=8192, max_levels=10, alpha=0.0, extrapolati
         # of x, y has no vertical gradient, so it lies in ker A_0, Section 4)
         top_nodes = perm[:n_top][S_perm]
         B0 = np.column_stack([np.ones(n_top), xyz[top_nodes, 0], xyz[top_nodes, 1]])
-        S_levels = amg.build_hierarchy(amg.permute(S0, S_perm), S_col, B0, coarse_max, max_levels)
+        S_levels = amg.build_hierarchy(amg.permute(S0, S_perm), S_arr["colour"], B0, coarse_max, max_levels,
+                                       rank0=S_arr["rank"],
+                                       first={k: S_arr[k] for k in ("patch", "pcolour", "lcolour")})
 
     # interior branch: A_bar = non-top block
     Abar = A[n_top:, n_top:].tocsr()
     Abar.sort_indices()
-    Abar_levels = amg.build_hierarchy(Abar, colour[n_top:], None, coarse_max, max_levels)
+    Abar_levels = amg.build_hierarchy(Abar, colour[n_top:], None, coarse_max, max_levels,
+                                      rank0=rank[n_top:] - n_top)
 
     return OracleSetup(mode=mode, n_nodes=n_nodes, pin=pin, perm=perm, n_top=n_top,
-                       Aoff=Aoff, d=d, A=A, diag=diag, colour=colour, E=E, S_perm=S_perm,
+                       Aoff=Aoff, d=d, A=A, diag=diag, colour=colour, rank=rank, E=E, S_perm=S_perm,
                        S_levels=S_levels, Abar_levels=Abar_levels,
                        mass=fem.assemble_mass(xyz, tets), xyz=xyz, top=top, coarse_max=coarse_max,
                        max_levels=max_levels, extrapolation=extrapolation)

@@ -7,5 +7,5 @@ that passes PyTorch device tensors as raw pointers.
 """
 from ._lib import (  # noqa: F401
     Solver, Server, VemgError, load_library, library_path, OP_A, OP_PRECOND, OP_ET, OP_E,
-    OP_VCYCLE_S, OP_VCYCLE_ABAR, OP_GS_FWD, OP_GS_COARSE, STATUS,
+    OP_VCYCLE_S, OP_VCYCLE_ABAR, OP_GS_FWD, OP_GS_COARSE, OP_COARSEST, STATUS,
 )

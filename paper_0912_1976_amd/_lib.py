@@ -16,7 +16,7 @@ _LIB = None
 
 STATUS = {0: "ok", 1: "max_iter", 2: "floor", -1: "invalid_arg", -2: "mesh", -3: "projection",
           -4: "oom", -5: "device", -6: "breakdown", -7: "state"}
-OP_A, OP_PRECOND, OP_ET, OP_E, OP_VCYCLE_S, OP_VCYCLE_ABAR, OP_GS_FWD, OP_GS_COARSE = range(8)
+OP_A, OP_PRECOND, OP_ET, OP_E, OP_VCYCLE_S, OP_VCYCLE_ABAR, OP_GS_FWD, OP_GS_COARSE, OP_COARSEST = range(9)
 _PC = {"vl_as": 0, "vl_sor": 1, "jacobi": 2, "none": 3, "vl_add": 4, "sa": 5}
 _TOP = {"pinned": 0, "N": 0, "dirichlet": 1, "D": 1, "robin": 2, "R": 2}
 _PREC = {"fp64": 0, "mixed": 1, "mixed_ir": 1, "mixed_pc": 2}

@@ -226,6 +226,8 @@ struct Work {
 struct DLevel {
   Sell As;                      // fine A_bar level: rows [row0, row0 + n) of the fine SELL matrix
   CsrG Ac;                      // coarse levels: standard form, G lanes per row
+  PatchSweep ps;                // coarse levels: the patches of the sweeps
+  std::vector<int64_t> pc_start, pc_row;  // patch colour c: stored patches [pc_start[c], pc_start[c+1]), first row
   bool fine = false;
   int64_t n = 0, row0 = 0;
   int64_t n_top = 0;            // fine levels: rows of the top block in the fine matrix
@@ -234,7 +236,8 @@ struct DLevel {
   const int32_t *order = nullptr;   // fine levels: slice visit order of the residual product
   CsrG P, Pt;                   // prolongation (n x n_next) and restriction
   Sell Ps;                      // fine levels: the prolongation in SELL-64 (a few entries a row)
-  double *Cinv = nullptr;       // coarsest level only
+  double *Cinv = nullptr;       // coarsest level only: its explicit inverse
+  double *dpart = nullptr;      // and the dense product's partial sums (dense_chunks(n) x n x kMaxBatch)
   bool coarsest = false;
   // vectors indexed by global row, [n][kMaxBatch], per precision
   double *x64 = nullptr, *g64 = nullptr, *r64 = nullptr;
@@ -308,6 +311,69 @@ Work<T> &work_of(Handle *h) {
   if constexpr (std::is_same<T, double>::value) return h->v64; else return h->v32;
 }
 
+// The patch arrays of a coarse level for its sweeps: row ranges of the stored
+// patches and, per patch, F = (D_p + L_p)^{-1} of its diagonal block in stored
+// order (forward substitution on the host in FP64) packed by rows, F^T packed
+// by rows for the backward sweep, and both times D_p rounded to FP32 for the
+// row-scaled FP32 operator.
+void pack_patches(Arena &ar, hipStream_t st, const Level &L, DLevel &dl) {
+  static_assert(kPatchRows == kPatchLdsRows, "the patch size of the order and of the sweep kernel differ");
+  const int64_t n = L.n(), np = (int64_t)L.patch_list.size();
+  if (n > INT32_MAX) throw DeviceError(hipErrorInvalidValue, "coarse level above 2^31 rows");
+  std::vector<int32_t> prow(L.patch_row.begin(), L.patch_row.end());
+  std::vector<int64_t> toff(np + 1, 0);
+  for (int64_t p = 0; p < np; ++p) {
+    const int64_t m = L.patch_row[p + 1] - L.patch_row[p];
+    if (m > kPatchLdsRows) throw DeviceError(hipErrorInvalidValue, "a patch exceeds the sweep kernel's rows");
+    toff[p + 1] = toff[p] + m * (m + 1) / 2;
+  }
+  std::vector<double> tf(toff[np]), tb(toff[np]);
+  std::vector<float> tf32(toff[np]), tb32(toff[np]);
+  if (!ar.count_only) {
+    std::vector<double> M, F;
+    for (int64_t p = 0; p < np; ++p) {
+      const int64_t ps = L.patch_row[p], m = L.patch_row[p + 1] - ps;
+      M.assign(m * m, 0.0);
+      F.assign(m * m, 0.0);
+      for (int64_t r = 0; r < m; ++r)
+        for (int64_t k = L.A.ptr[ps + r]; k < L.A.ptr[ps + r + 1]; ++k) {
+          const int64_t c = L.A.idx[k] - ps;
+          if (c >= 0 && c <= r) M[r * m + c] = L.A.val[k];
+        }
+      // columns of F = (D + L)^{-1}: forward substitution on unit vectors
+      for (int64_t c = 0; c < m; ++c) {
+        F[c * m + c] = 1.0 / M[c * m + c];
+        for (int64_t r = c + 1; r < m; ++r) {
+          double t = 0.0;
+          for (int64_t k = c; k < r; ++k) t += M[r * m + k] * F[k * m + c];
+          F[r * m + c] = -t / M[r * m + r];
+        }
+      }
+      double *fwd = tf.data() + toff[p], *bwd = tb.data() + toff[p];
+      float *fwd32 = tf32.data() + toff[p], *bwd32 = tb32.data() + toff[p];
+      for (int64_t r = 0, o = 0; r < m; ++r)
+        for (int64_t c = 0; c <= r; ++c, ++o) {
+          fwd[o] = F[r * m + c];
+          fwd32[o] = (float)(F[r * m + c] * M[c * m + c]);
+        }
+      for (int64_t r = 0, o = 0; r < m; ++r)
+        for (int64_t c = r; c < m; ++c, ++o) {
+          bwd[o] = F[c * m + r];
+          bwd32[o] = (float)(F[c * m + r] * M[c * m + c]);
+        }
+    }
+  }
+  dl.ps.prow = ar.upload(prow, st);
+  dl.ps.toff = ar.upload(toff, st);
+  dl.ps.tf64 = ar.upload(tf, st);
+  dl.ps.tb64 = ar.upload(tb, st);
+  dl.ps.tf32 = ar.upload(tf32, st);
+  dl.ps.tb32 = ar.upload(tb32, st);
+  dl.pc_start = L.pc_start;
+  dl.pc_row.resize(L.pc_start.size());
+  for (size_t c = 0; c < L.pc_start.size(); ++c) dl.pc_row[c] = L.patch_row[L.pc_start[c]];
+}
+
 enum LevelsOf { kLevelsS = 0, kLevelsAbar = 1, kLevelsSA = 2 };
 
 void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, int of) {
@@ -341,7 +407,7 @@ void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, int 
       dl.r32 = h->v32.resA;
     } else {
       dl.Ac = pack_csrg(h->ar, st, L.A, true);
-      dl.cstart = L.colour_start;
+      pack_patches(h->ar, st, L, dl);
       size_t cnt = (size_t)dl.n * kMaxBatch;
       dl.x64 = h->ar.alloc<double>(cnt);
       dl.g64 = h->ar.alloc<double>(cnt);
@@ -360,6 +426,7 @@ void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, int 
                       : pack_csrg(h->ar, st, transpose(L.P), false);
     } else {
       dl.Cinv = h->ar.upload(L.Cinv, st);
+      dl.dpart = h->ar.alloc<double>((size_t)dense_chunks(dl.n) * dl.n * kMaxBatch);
     }
     D.push_back(dl);
   }
@@ -371,12 +438,12 @@ void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *
   T *x = L.x<T>(), *g = L.g<T>(), *r = L.r<T>();
   const int64_t o = L.row0 * K;
   if (L.coarsest) {
-    launch_dense<T>(st, K, L.Cinv, L.n, g + o, x + o, done);
+    launch_dense<T>(st, K, L.Cinv, L.n, g + o, x + o, L.dpart, done);
     return;
   }
-  int nc = (int)L.cstart.size() - 1;
+  const int nc = (int)(L.fine ? L.cstart.size() : L.pc_start.size()) - 1;
   // forward (zero start: x needs no fill, the colours not swept yet are not
-  // read) and backward sweeps of colour c
+  // read) and backward sweeps of colour c (coarse levels: patch colour c)
   auto gs = [&](int c, bool first) {
     if (L.fine) {
       // A_bar's fine level (no top range) never reads the top columns: they
@@ -393,7 +460,8 @@ void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *
         launch_gs<T>(st, K, L.As, L.cstart[c], L.cstart[c + 1], 0, 0, g, x, done, zs);
       }
     } else {
-      launch_csr_gs<T>(st, K, L.Ac, L.cstart[c], L.cstart[c + 1], g, x, done, first ? L.cstart[c] : -1);
+      launch_patch_gs<T>(st, K, L.Ac, L.ps, L.pc_start[c], L.pc_start[c + 1] - L.pc_start[c], g, x, done,
+                         first ? L.pc_row[c] : -1, !first);
     }
   };
   for (int c = 0; c < nc; ++c) gs(c, true);
@@ -1212,10 +1280,16 @@ void time_once(Handle *h, int op, int K) {
     launch_rect<T>(st, K, h->E, true, h->S[0].x<T>(), v.z, nullptr);
     return;
   }
+  if (op == VEMG_OP_COARSEST) {
+    DLevel &L = h->S.back();
+    launch_dense<T>(st, K, L.Cinv, L.n, L.g<T>(), L.x<T>(), L.dpart, nullptr);
+    return;
+  }
   if (op == VEMG_OP_GS_COARSE) {
     DLevel &L = h->Ab[1];
-    for (size_t c = 0; c + 1 < L.cstart.size(); ++c)
-      launch_csr_gs<T>(st, K, L.Ac, L.cstart[c], L.cstart[c + 1], L.g<T>(), L.x<T>(), nullptr);
+    for (size_t c = 0; c + 1 < L.pc_start.size(); ++c)
+      launch_patch_gs<T>(st, K, L.Ac, L.ps, L.pc_start[c], L.pc_start[c + 1] - L.pc_start[c], L.g<T>(), L.x<T>(),
+                         nullptr, -1, false);
     return;
   }
   int nct = (int)P.top_colour_start.size() - 1, ncb = (int)P.bar_colour_start.size() - 1;
@@ -1237,14 +1311,16 @@ int do_time(Handle *h, int op, int K, int reps, double *avg_ms, int *launches) {
   hipStream_t st = h->work;
   const Problem &P = h->P;
   int64_t n = P.n;
-  if (op != VEMG_OP_A && op != VEMG_OP_GS_FWD && op != VEMG_OP_GS_COARSE && op != VEMG_OP_ET && op != VEMG_OP_E)
+  if (op != VEMG_OP_A && op != VEMG_OP_GS_FWD && op != VEMG_OP_GS_COARSE && op != VEMG_OP_ET && op != VEMG_OP_E &&
+      op != VEMG_OP_COARSEST)
     return VEMG_ERR_INVALID_ARG;
+  if (op == VEMG_OP_COARSEST && (P.n_top == 0 || h->S.empty())) return VEMG_ERR_STATE;
   if (op == VEMG_OP_GS_COARSE && (h->Ab.size() < 2 || h->Ab[1].coarsest)) return VEMG_ERR_STATE;
   if ((op == VEMG_OP_ET || op == VEMG_OP_E) && (P.n_top == 0 || h->S.empty())) return VEMG_ERR_STATE;
   if (K != 1 && K != 2 && K != 4 && K != 8) return VEMG_ERR_INVALID_ARG;
   int nc = std::max((int)P.top_colour_start.size() - 1, (int)P.bar_colour_start.size() - 1);
   if (op == VEMG_OP_GS_COARSE) {
-    nc = (int)h->Ab[1].cstart.size() - 1;
+    nc = (int)h->Ab[1].pc_start.size() - 1;
     DLevel &L = h->Ab[1];
     if (h->opt.precision == VEMG_MIXED_IR) {
       launch_fill<float>(st, L.g32, L.n * K, 1.0f, nullptr);
@@ -1286,7 +1362,14 @@ int do_time(Handle *h, int op, int K, int reps, double *avg_ms, int *launches) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *avg_ms = (double)ms / reps;
-  if (launches) *launches = (op == VEMG_OP_A || op == VEMG_OP_ET || op == VEMG_OP_E) ? 1 : nc;
+  if (op == VEMG_OP_COARSEST) {
+    DLevel &L = h->S.back();
+    if (h->opt.precision == VEMG_MIXED_IR)
+      launch_fill<float>(st, L.g32, L.n * K, 1.0f, nullptr);
+    else
+      launch_fill<double>(st, L.g64, L.n * K, 1.0, nullptr);
+  }
+  if (launches) *launches = (op == VEMG_OP_A || op == VEMG_OP_ET || op == VEMG_OP_E || op == VEMG_OP_COARSEST) ? 1 : nc;
   return VEMG_OK;
 }
 
@@ -1333,6 +1416,14 @@ int do_export(Handle *h, const std::string &name, void *buf, size_t *bytes) {
     if (what.rfind("A.", 0) == 0) return export_csr(L.A, what.substr(2), buf, bytes);
     if (what.rfind("P.", 0) == 0) return export_csr(L.P, what.substr(2), buf, bytes);
     if (what == "colour") return export_vec(L.colour, buf, bytes);
+    if (what == "rank") return export_vec(L.rank, buf, bytes);
+    if (what == "patch") return export_vec(L.patch, buf, bytes);
+    if (what == "pcolour") return export_vec(L.pcolour, buf, bytes);
+    if (what == "lcolour") return export_vec(L.lcolour, buf, bytes);
+    if (what == "pc_start") return export_vec(L.pc_start, buf, bytes);
+    if (what == "patch_row") return export_vec(L.patch_row, buf, bytes);
+    if (what == "seg_ptr") return export_vec(L.seg_ptr, buf, bytes);
+    if (what == "seg_row") return export_vec(L.seg_row, buf, bytes);
     if (what == "node") return export_vec(L.node, buf, bytes);
     if (what == "agg") return export_vec(L.agg, buf, bytes);
     if (what == "Cinv") return export_vec(L.Cinv, buf, bytes);

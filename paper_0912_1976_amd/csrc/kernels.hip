@@ -389,9 +389,8 @@ __global__ __launch_bounds__(kBlock) void k_prolong_sum(Sell E, int64_t n_top, i
 // ------------------------------------------------------------- CsrG
 // Off-diagonal sum of one row for K columns by its group of G lanes (the
 // result is valid in every lane of the group).
-template <class T, int K, int G, bool ZS = false>
-__device__ __forceinline__ void group_row(const CsrG &A, int64_t r, int gl, const T *__restrict__ x, T (&acc)[K],
-                                          int64_t zlim = 0) {
+template <class T, int K, int G>
+__device__ __forceinline__ void group_row(const CsrG &A, int64_t r, int gl, const T *__restrict__ x, T (&acc)[K]) {
   const int32_t b = A.ptr[r], e = A.ptr[r + 1];
   const T *__restrict__ vals = csr_vals<T>(A);
 #pragma unroll
@@ -399,22 +398,9 @@ __device__ __forceinline__ void group_row(const CsrG &A, int64_t r, int gl, cons
 #pragma unroll 2
   for (int j = b + gl; j < e; j += G) {
     const T v = vals[j];
-    const int32_t c = A.col[j];
-    if constexpr (ZS && K > 2) {
-      if (c < zlim) {
-        const Row<T, K> xc = ld<T, K>(x, c);
+    const Row<T, K> xc = ld<T, K>(x, A.col[j]);
 #pragma unroll
-        for (int k = 0; k < K; ++k) acc[k] += v * xc.v[k];
-      }
-    } else {
-      Row<T, K> xc = ld<T, K>(x, c);
-      if constexpr (ZS) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) xc.v[k] = c < zlim ? xc.v[k] : T(0);
-      }
-#pragma unroll
-      for (int k = 0; k < K; ++k) acc[k] += v * xc.v[k];
-    }
+    for (int k = 0; k < K; ++k) acc[k] += v * xc.v[k];
   }
 #pragma unroll
   for (int o = G / 2; o > 0; o >>= 1) {
@@ -426,11 +412,9 @@ __device__ __forceinline__ void group_row(const CsrG &A, int64_t r, int gl, cons
 // Row r of a CsrG operation, by its group of G lanes (lane 0 of the group
 // writes).  The kernels below renumber their blocks like the fine ones, so
 // that each XCD works on a contiguous range of rows and the vector values
-// those rows gather stay in that XCD's L2.  MODE 0: y = A x, 1: y = g - A x (square); 2: y = P x, 3: y += P x;
-// 4: one Gauss-Seidel step y_r = (g_r - sum_j a_rj x_j) / a_rr (y = x).
-template <class T, int K, int G, int MODE, bool ZS = false>
-__device__ __forceinline__ void csr_row_op(const CsrG &A, int64_t r, int gl, const T *x, const T *g, T *y,
-                                           int64_t zlim = 0) {
+// those rows gather stay in that XCD's L2.  MODE 0: y = A x, 1: y = g - A x (square); 2: y = P x, 3: y += P x.
+template <class T, int K, int G, int MODE>
+__device__ __forceinline__ void csr_row_op(const CsrG &A, int64_t r, int gl, const T *x, const T *g, T *y) {
   // the row's own operands are loaded first, so that their latency overlaps
   // the row-pointer -> entries -> gathered values chain of group_row
   Row<T, K> gr, xr, yr;
@@ -440,29 +424,20 @@ __device__ __forceinline__ void csr_row_op(const CsrG &A, int64_t r, int gl, con
   if constexpr (MODE == 2 || MODE == 3) {
     if (A.orow) ro = A.orow[r];
   }
-  if (MODE == 1 || MODE == 4) gr = ld<T, K>(g, r);
+  if (MODE == 1) gr = ld<T, K>(g, r);
   if (MODE <= 1) xr = ld<T, K>(x, r);
   if (MODE == 3) yr = ld<T, K>(y, ro);
-  if (MODE <= 1 || MODE == 4) {
+  if (MODE <= 1) {
     if constexpr (std::is_same<T, double>::value)
       dr = A.d64[r];
     else
       dr = A.s32[r];
   }
   T acc[K];
-  group_row<T, K, G, ZS>(A, r, gl, x, acc, zlim);  // off-diagonal part only
+  group_row<T, K, G>(A, r, gl, x, acc);  // off-diagonal part only
   if (gl != 0) return;
   Row<T, K> out;
-  if (MODE == 4) {
-    if constexpr (std::is_same<T, double>::value) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) out.v[k] = (gr.v[k] - acc[k]) / dr;
-    } else {
-      const float inv_s = 1.0f / dr;
-#pragma unroll
-      for (int k = 0; k < K; ++k) out.v[k] = gr.v[k] * inv_s - acc[k];
-    }
-  } else if (MODE <= 1) {
+  if (MODE <= 1) {
     if constexpr (std::is_same<T, double>::value) {
 #pragma unroll
       for (int k = 0; k < K; ++k) out.v[k] = acc[k] + dr * xr.v[k];
@@ -496,64 +471,193 @@ __global__ __launch_bounds__(kWave) void k_csr_spmv(CsrG A, int64_t r0, int64_t 
   csr_row_op<T, K, G, MODE>(A, r, gl, x, g, y);
 }
 
-template <class T, int K, int G, bool ZS>
-__global__ __launch_bounds__(kWave) void k_csr_gs(CsrG A, int64_t r0, int64_t r1, const T *__restrict__ g,
-                                                   T *__restrict__ x, const int *__restrict__ done, int64_t zlim) {
-  if (done && *done) return;
-  const int gl = threadIdx.x & (G - 1);
-  const int64_t r = r0 + (xcd_block(blockIdx.x, gridDim.x) * kWave + threadIdx.x) / G;
-  if (r >= r1) return;
-  csr_row_op<T, K, G, 4, ZS>(A, r, gl, x, g, x, zlim);
+// Patch sweep: one block per patch, kPatchGroup lanes per unknown (enough
+// lanes that a row's couplings take one or two loads per lane).  First every
+// unknown of the patch sums the couplings whose values the sweep takes as
+// they stand -- other patches (with a zero start only the patch colours swept
+// before) and, without a zero start, its own patch's later unknowns (earlier
+// ones backward) -- into h = g - sum (FP32: g / a_ii - sum over row-scaled
+// values); then every unknown takes its row of the patch's triangular factor
+// times h.  One block barrier; no sequential stages inside the patch.
+constexpr int kPatchGroup = 16;
+constexpr int kPatchThreads = kPatchGroup * kPatchLdsRows;
+
+template <class T>
+__device__ __forceinline__ const T *patch_factor(const PatchSweep &S, bool bwd);
+template <>
+__device__ __forceinline__ const double *patch_factor<double>(const PatchSweep &S, bool bwd) {
+  return bwd ? S.tb64 : S.tf64;
+}
+template <>
+__device__ __forceinline__ const float *patch_factor<float>(const PatchSweep &S, bool bwd) {
+  return bwd ? S.tb32 : S.tf32;
 }
 
-// Dense FP64 coarsest inverse applied to K columns, x = Cinv g.  A block
-// takes kDenseRows rows (kDenseRows / 4 per wavefront) and walks the columns
-// in tiles whose g values are staged in LDS once for all its rows, so that g
-// is read from L2 once per block instead of once per row; the inverse is
-// streamed once.  Lane l of a wavefront adds the columns j = l, l + 64, ...
-// of its rows in ascending order, then the wavefront sums its lanes, so the
-// rounding does not depend on the tiling.
-constexpr int kDenseRows = 16;
-constexpr int kDenseTile = 256;
-
 template <class T, int K>
-__global__ __launch_bounds__(kBlock) void k_dense(const double *__restrict__ C, int64_t m, const T *__restrict__ g,
-                                                  T *__restrict__ x, const int *__restrict__ done) {
+__device__ __forceinline__ void group_sum(T (&acc)[K]) {
+#pragma unroll
+  for (int o = kPatchGroup / 2; o > 0; o >>= 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += __shfl_xor(acc[k], o, kPatchGroup);
+  }
+}
+
+template <class T, int K, bool ZS, bool BWD>
+__global__ __launch_bounds__(kPatchThreads) void k_patch_gs(CsrG A, PatchSweep S, int64_t p0, int64_t np,
+                                                            const T *__restrict__ g, T *__restrict__ x,
+                                                            const int *__restrict__ done, int64_t zlim) {
+  constexpr int G = kPatchGroup;
+  __shared__ Row<T, K> hs[kPatchLdsRows];
   if (done && *done) return;
-  constexpr int RW = kDenseRows / kSlicesPerBlock;  // rows per wavefront
-  __shared__ Row<T, K> gt[kDenseTile];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t i0 = (int64_t)blockIdx.x * kDenseRows + w * RW;
-  double t[RW][K];
+  const int64_t p = p0 + xcd_block(blockIdx.x, np);
+  const int32_t ps = S.prow[p], pe = S.prow[p + 1];
+  const int q = threadIdx.x / G, gl = threadIdx.x % G;
+  const int32_t i = ps + q;
+  const bool own = i < pe;
+  const T *__restrict__ vals = csr_vals<T>(A);
+  // the row's part of the patch factor does not depend on the sums: load it
+  // first, beside the row's own operands (kPatchLdsRows / G entries a lane at most)
+  constexpr int FR = kPatchLdsRows / G;
+  const int m = pe - ps;
+  T fr[FR];
+  {
+    const T *__restrict__ f = patch_factor<T>(S, BWD) + S.toff[p];
+    // forward row q: columns 0..q packed from q (q + 1) / 2; backward: columns q..m-1 from q m - q (q - 1) / 2
+    const T *__restrict__ row = BWD ? f + q * m - q * (q - 1) / 2 - q : f + q * (q + 1) / 2;
 #pragma unroll
-  for (int r = 0; r < RW; ++r)
+    for (int t = 0; t < FR; ++t) {
+      const int j = gl + t * G;
+      fr[t] = (own && (BWD ? (j >= q && j < m) : j <= q)) ? row[j] : T(0);
+    }
+  }
+  if (own) {
+    const Row<T, K> gr = ld<T, K>(g, i);
+    T dr = T(1);
+    if constexpr (!std::is_same<T, double>::value) dr = A.s32[i];
+    const int32_t b = A.ptr[i], e = A.ptr[i + 1];
+    T acc[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) t[r][k] = 0.0;
-  for (int64_t j0 = 0; j0 < m; j0 += kDenseTile) {
-    const int nt = (int)((m - j0) < kDenseTile ? (m - j0) : kDenseTile);
-    __syncthreads();
-    for (int j = threadIdx.x; j < nt; j += kBlock) gt[j] = ld<T, K>(g, j0 + j);
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < RW; ++r) {
-      if (i0 + r >= m) break;  // uniform over the wavefront
-      const double *__restrict__ Ci = C + (i0 + r) * m + j0;
+    for (int k = 0; k < K; ++k) acc[k] = T(0);
 #pragma unroll 4
-      for (int j = lane; j < nt; j += 64) {
-        const double c = Ci[j];
-        const Row<T, K> gj = gt[j];
+    for (int32_t j = b + gl; j < e; j += G) {
+      const int32_t c = A.col[j];
+      const T v = vals[j];
+      const bool inside = c >= ps && c < pe;
+      const bool take = inside ? (!ZS && (BWD ? c < i : c > i)) : (!ZS || c < zlim);
+      if (take) {
+        const Row<T, K> xc = ld<T, K>(x, c);
 #pragma unroll
-        for (int k = 0; k < K; ++k) t[r][k] += c * (double)gj.v[k];
+        for (int k = 0; k < K; ++k) acc[k] += v * xc.v[k];
       }
+    }
+    group_sum<T, K>(acc);
+    if (gl == 0) {
+      Row<T, K> h;
+      if constexpr (std::is_same<T, double>::value) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) h.v[k] = gr.v[k] - acc[k];
+      } else {
+        const float inv_s = 1.0f / dr;
+#pragma unroll
+        for (int k = 0; k < K; ++k) h.v[k] = gr.v[k] * inv_s - acc[k];
+      }
+      hs[q] = h;
+    }
+  }
+  __syncthreads();
+  if (!own) return;
+  T acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = T(0);
+#pragma unroll
+  for (int t = 0; t < FR; ++t) {
+    const int j = gl + t * G;
+    if (BWD ? (j >= q && j < m) : j <= q) {
+      const Row<T, K> hj = hs[j];
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc[k] += fr[t] * hj.v[k];
+    }
+  }
+  group_sum<T, K>(acc);
+  if (gl == 0) {
+    Row<T, K> out;
+#pragma unroll
+    for (int k = 0; k < K; ++k) out.v[k] = acc[k];
+    st<T, K>(x, i, out);
+  }
+}
+
+// Dense FP64 coarsest inverse applied to K columns, x = C g.  C is symmetric,
+// so it is read by columns (C_ji = C_ij): the 64 lanes of a wavefront take 64
+// consecutive outputs i and read 64 consecutive entries of row j of C
+// together, and g_j is the same for the whole wavefront; C is streamed once,
+// with several rows in flight per lane.  The columns j are cut into chunks of
+// kDenseChunk (dense_chunks of them); a block of four wavefronts takes 64
+// outputs over one chunk, each wavefront a quarter of it, sums the quarters
+// in LDS in wavefront order and writes the chunk's partial sums, which
+// k_dense_sum adds in chunk order (a single chunk is written directly).  No
+// summation order depends on K.
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void k_dense_part(const double *__restrict__ C, int64_t m,
+                                                       const T *__restrict__ g, double *__restrict__ part,
+                                                       T *__restrict__ x, const int *__restrict__ done) {
+  if (done && *done) return;
+  __shared__ double red[kSlicesPerBlock][K][kWave];
+  __shared__ Row<T, K> gt[kDenseChunk];  // the chunk's g, read by every lane of a wavefront at once
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * kWave + lane;
+  const int64_t c = blockIdx.y;
+  const int64_t jc = c * kDenseChunk;
+  const int nj = (int)(m - jc < kDenseChunk ? m - jc : kDenseChunk);
+  for (int j = threadIdx.x; j < nj; j += kBlock) gt[j] = ld<T, K>(g, jc + j);
+  __syncthreads();
+  constexpr int Q = kDenseChunk / kSlicesPerBlock;
+  const int j0 = w * Q;
+  const int j1 = j0 + Q < nj ? j0 + Q : nj;
+  double t[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) t[k] = 0.0;
+  if (i < m) {
+    const double *__restrict__ Ci = C + jc * m + i;
+#pragma unroll 8
+    for (int j = j0; j < j1; ++j) {
+      const double cji = Ci[(int64_t)j * m];
+      const Row<T, K> gj = gt[j];
+#pragma unroll
+      for (int k = 0; k < K; ++k) t[k] += cji * (double)gj.v[k];
     }
   }
 #pragma unroll
-  for (int r = 0; r < RW; ++r) {
+  for (int k = 0; k < K; ++k) red[w][k][lane] = t[k];
+  __syncthreads();
+  if (w != 0 || i >= m) return;
+  Row<double, K> s;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double v = red[0][k][lane];
+#pragma unroll
+    for (int q = 1; q < kSlicesPerBlock; ++q) v += red[q][k][lane];
+    s.v[k] = v;
+  }
+  if (gridDim.y == 1) {
     Row<T, K> out;
 #pragma unroll
-    for (int k = 0; k < K; ++k) out.v[k] = (T)wave_sum(t[r][k]);
-    if (lane == 0 && i0 + r < m) st<T, K>(x, i0 + r, out);
+    for (int k = 0; k < K; ++k) out.v[k] = (T)s.v[k];
+    st<T, K>(x, i, out);
+  } else {
+    st<double, K>(part + c * m * K, i, s);
   }
+}
+
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void k_dense_sum(const double *__restrict__ part, int64_t m, int64_t nc,
+                                                      T *__restrict__ x, const int *__restrict__ done) {
+  if (done && *done) return;
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;  // output t = i K + k
+  if (t >= m * K) return;
+  double s = part[t];
+  for (int64_t c = 1; c < nc; ++c) s += part[c * m * K + t];
+  x[t] = (T)s;
 }
 
 // ------------------------------------------------------------- vectors
@@ -1154,25 +1258,34 @@ void launch_csr_rect(hipStream_t stm, int K, const CsrG &P, bool accumulate, con
 }
 
 template <class T>
-void launch_csr_gs(hipStream_t stm, int K, const CsrG &A, int64_t r0, int64_t r1, const T *g, T *x, const int *done,
-                   int64_t zlim) {
-  int64_t rows = r1 - r0;
-  if (rows <= 0) return;
-  int64_t nb = (rows * A.G + kWave - 1) / kWave;
-  VEMG_K_SWITCH(K, VEMG_G_SWITCH(A.G, {
+void launch_patch_gs(hipStream_t stm, int K, const CsrG &A, const PatchSweep &S, int64_t p0, int64_t np, const T *g,
+                     T *x, const int *done, int64_t zlim, bool backward) {
+  if (np <= 0) return;
+  VEMG_K_SWITCH(K, {
     if (zlim >= 0)
-      hipLaunchKernelGGL((k_csr_gs<T, KK, GG, true>), grid(nb), dim3(kWave), 0, stm, A, r0, r1, g, x, done, zlim);
+      hipLaunchKernelGGL((k_patch_gs<T, KK, true, false>), grid(np), dim3(kPatchThreads), 0, stm, A, S, p0, np, g, x,
+                         done, zlim);
+    else if (backward)
+      hipLaunchKernelGGL((k_patch_gs<T, KK, false, true>), grid(np), dim3(kPatchThreads), 0, stm, A, S, p0, np, g, x,
+                         done, int64_t(0));
     else
-      hipLaunchKernelGGL((k_csr_gs<T, KK, GG, false>), grid(nb), dim3(kWave), 0, stm, A, r0, r1, g, x, done,
-                         int64_t(0));
-  }))
+      hipLaunchKernelGGL((k_patch_gs<T, KK, false, false>), grid(np), dim3(kPatchThreads), 0, stm, A, S, p0, np, g, x,
+                         done, int64_t(0));
+  })
 }
 
 template <class T>
-void launch_dense(hipStream_t stm, int K, const double *Cinv, int64_t m, const T *g, T *x, const int *done) {
+void launch_dense(hipStream_t stm, int K, const double *Cinv, int64_t m, const T *g, T *x, double *part,
+                  const int *done) {
   if (m <= 0) return;
-  int64_t nb = (m + kDenseRows - 1) / kDenseRows;
-  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_dense<T, KK>), grid(nb), dim3(kBlock), 0, stm, Cinv, m, g, x, done))
+  const int64_t nc = dense_chunks(m);
+  const dim3 gr((unsigned)((m + kWave - 1) / kWave), (unsigned)nc);
+  VEMG_K_SWITCH(K, {
+    hipLaunchKernelGGL((k_dense_part<T, KK>), gr, dim3(kBlock), 0, stm, Cinv, m, g, part, x, done);
+    if (nc > 1)
+      hipLaunchKernelGGL((k_dense_sum<T, KK>), grid((m * KK + kBlock - 1) / kBlock), dim3(kBlock), 0, stm, part, m,
+                         nc, x, done);
+  })
 }
 
 template <class T>
@@ -1275,10 +1388,10 @@ void launch_pcg_resume(hipStream_t stm, int, Scal *s, unsigned keep) {
                                       double *, const int *);                                                        \
   template void launch_csr_spmv<T>(hipStream_t, int, const CsrG &, int, int64_t, int64_t, const T *, const T *, T *,   \
                                    const int *);                                                                     \
-  template void launch_csr_gs<T>(hipStream_t, int, const CsrG &, int64_t, int64_t, const T *, T *, const int *,       \
-                                 int64_t);                                                                           \
+  template void launch_patch_gs<T>(hipStream_t, int, const CsrG &, const PatchSweep &, int64_t, int64_t, const T *,  \
+                                   T *, const int *, int64_t, bool);                                                 \
   template void launch_csr_rect<T>(hipStream_t, int, const CsrG &, bool, const T *, T *, const int *);                \
-  template void launch_dense<T>(hipStream_t, int, const double *, int64_t, const T *, T *, const int *);              \
+  template void launch_dense<T>(hipStream_t, int, const double *, int64_t, const T *, T *, double *, const int *);    \
   template void launch_fill<T>(hipStream_t, T *, int64_t, T, const int *);                                           \
   template void launch_copy<T>(hipStream_t, const T *, T *, int64_t, const int *);                                   \
   template void launch_dot<T>(hipStream_t, int, const T *, const T *, int64_t, double *, const int *);                \

@@ -116,16 +116,43 @@ void launch_prolong_sum(hipStream_t st, int K, const Sell &E, int64_t n_top, con
 template <class T>
 void launch_csr_spmv(hipStream_t st, int K, const CsrG &A, int mode, int64_t r0, int64_t r1, const T *x,
                      const T *g, T *y, const int *done);
-// zlim >= 0: zero start, only columns j < zlim (the colours swept before) are
-// read and the rest taken as zero
+// Block multicolour (patch) order of a coarse level: its unknowns are stored
+// patch by patch (patch colour, patch, local colour), a patch holding at most
+// kPatchLdsRows unknowns.  Unknowns of patches of one colour are never
+// coupled, so a forward sweep is, patch colour by patch colour, one exact
+// triangular solve per patch: with h_p = g_p - A_pq x_q over the couplings
+// to other patches (and to the patch's own later unknowns, with their old
+// values), the patch's new values are (D_p + L_p)^{-1} h_p, L_p the strictly
+// lower part of the patch's block in stored order -- the sequential SOR
+// sweep in that order.  Backward: (D_p + U_p)^{-1} = ((D_p + L_p)^{-1})^T.
+constexpr int kPatchLdsRows = 64;
+struct PatchSweep {
+  const int32_t *prow = nullptr;  // stored patch i: rows [prow[i], prow[i+1])
+  const int64_t *toff = nullptr;  // its factors start at toff[i] (m (m + 1) / 2 entries each)
+  // FP64: F = (D_p + L_p)^{-1} packed by rows (row r: columns 0..r) and F^T
+  // packed by rows (row r: columns r..m-1); FP32 (row-scaled operator):
+  // F D_p and F^T D_p, rounded
+  const double *tf64 = nullptr, *tb64 = nullptr;
+  const float *tf32 = nullptr, *tb32 = nullptr;
+};
+// One Gauss-Seidel sweep over the patches [p0, p0 + np) of one patch colour,
+// one block per patch (the patch colours launched in turn, ascending for a
+// forward sweep and descending for backward).  zlim >= 0: zero start
+// (forward from x = 0): of the other patches only the rows j < zlim (the
+// patch colours swept before) are read and the rest taken as zero, so x
+// needs no fill.
 template <class T>
-void launch_csr_gs(hipStream_t st, int K, const CsrG &A, int64_t r0, int64_t r1, const T *g, T *x, const int *done,
-                   int64_t zlim = -1);
+void launch_patch_gs(hipStream_t st, int K, const CsrG &A, const PatchSweep &S, int64_t p0, int64_t np, const T *g,
+                     T *x, const int *done, int64_t zlim, bool backward);
 template <class T>
 void launch_csr_rect(hipStream_t st, int K, const CsrG &P, bool accumulate, const T *x, T *y, const int *done);
-// x = Cinv g (dense m x m FP64, row-major), K columns.
+// x = Cinv g (dense m x m FP64, symmetric, row-major), K columns; part:
+// dense_chunks(m) * m * K doubles of scratch for the column chunks' partial sums.
+constexpr int kDenseChunk = 512;
+inline int64_t dense_chunks(int64_t m) { return (m + kDenseChunk - 1) / kDenseChunk; }
 template <class T>
-void launch_dense(hipStream_t st, int K, const double *Cinv, int64_t m, const T *g, T *x, const int *done);
+void launch_dense(hipStream_t st, int K, const double *Cinv, int64_t m, const T *g, T *x, double *part,
+                  const int *done);
 
 // ---- vectors ([n][K]) ----------------------------------------------------
 template <class T>

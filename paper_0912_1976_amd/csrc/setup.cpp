@@ -219,6 +219,168 @@ std::vector<int64_t> colour_ranges(const std::vector<int32_t> &col, int64_t a, i
   return st;
 }
 
+// ---------------------------------------------------------------- patch order
+// Block multicolour order of the coarse levels.  The unknowns, in their
+// spatial order (rank), are cut into consecutive patches of at most
+// kPatchRows unknowns holding at most kPatchEntries off-diagonal entries
+// together (at least one unknown each); the patch graph (patches coupled by
+// an entry) is coloured greedily in smallest-last order, and so is every
+// patch's own coupling graph, its unknowns indexed in rank order.  The
+// storage order sorts by (patch colour, patch, local colour, rank).  Unknowns
+// of equal (patch colour, local colour) are never coupled, so a sweep that
+// takes the patch colours in turn, and inside every patch its local colours
+// in turn, is the sequential SOR sweep in the stored order.
+struct PatchOrder {
+  std::vector<int64_t> perm;                // new -> old
+  std::vector<int32_t> patch, pcol, lcol;  // per unknown, in the new order
+};
+
+PatchOrder patch_order(const Csr &A, const std::vector<int64_t> &rank) {
+  const int64_t n = A.nrows;
+  PatchOrder out;
+  std::vector<int64_t> ro(n);  // unknowns in rank order
+  for (int64_t i = 0; i < n; ++i) ro[rank[i]] = i;
+  std::vector<int32_t> patch(n);
+  std::vector<int64_t> pstart;  // first position (in ro) of every patch
+  {
+    int64_t rows = 0, ents = 0;
+    for (int64_t t = 0; t < n; ++t) {
+      const int64_t i = ro[t];
+      int64_t len = 0;
+      for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) len += (A.idx[k] != i);
+      if (pstart.empty() || rows == kPatchRows || ents + len > kPatchEntries) {
+        pstart.push_back(t);
+        rows = 0;
+        ents = 0;
+      }
+      patch[i] = (int32_t)pstart.size() - 1;
+      ++rows;
+      ents += len;
+    }
+  }
+  const int64_t np = (int64_t)pstart.size();
+  pstart.push_back(n);
+  // patch graph
+  Csr G;
+  G.nrows = G.ncols = np;
+  G.ptr.assign(np + 1, 0);
+  std::vector<int32_t> nb;
+  for (int64_t p = 0; p < np; ++p) {
+    nb.clear();
+    for (int64_t t = pstart[p]; t < pstart[p + 1]; ++t) {
+      const int64_t i = ro[t];
+      for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+        const int32_t q = patch[A.idx[k]];
+        if (q != p) nb.push_back(q);
+      }
+    }
+    std::sort(nb.begin(), nb.end());
+    nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+    G.idx.insert(G.idx.end(), nb.begin(), nb.end());
+    G.ptr[p + 1] = (int64_t)G.idx.size();
+  }
+  G.val.assign(G.idx.size(), 1.0);
+  std::vector<int32_t> pcol = sweep_colouring(G);
+  // local colourings, unknowns of a patch indexed in rank order
+  std::vector<int32_t> lcol(n);
+  std::vector<int64_t> local(n, -1);
+  for (int64_t p = 0; p < np; ++p) {
+    const int64_t a = pstart[p], m = pstart[p + 1] - a;
+    for (int64_t t = 0; t < m; ++t) local[ro[a + t]] = t;
+    Csr L;
+    L.nrows = L.ncols = m;
+    L.ptr.assign(m + 1, 0);
+    for (int64_t t = 0; t < m; ++t) {
+      const int64_t i = ro[a + t];
+      const size_t k0 = L.idx.size();
+      for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+        const int64_t j = A.idx[k];
+        if (j != i && patch[j] == p) L.idx.push_back((int32_t)local[j]);
+      }
+      std::sort(L.idx.begin() + k0, L.idx.end());
+      L.ptr[t + 1] = (int64_t)L.idx.size();
+    }
+    L.val.assign(L.idx.size(), 1.0);
+    std::vector<int32_t> c = sweep_colouring(L);
+    for (int64_t t = 0; t < m; ++t) lcol[ro[a + t]] = c[t];
+  }
+  out.perm.resize(n);
+  std::iota(out.perm.begin(), out.perm.end(), 0);
+  std::sort(out.perm.begin(), out.perm.end(), [&](int64_t a, int64_t b) {
+    return std::make_tuple(pcol[patch[a]], patch[a], lcol[a], rank[a]) <
+           std::make_tuple(pcol[patch[b]], patch[b], lcol[b], rank[b]);
+  });
+  out.patch.resize(n);
+  out.pcol.resize(n);
+  out.lcol.resize(n);
+  for (int64_t t = 0; t < n; ++t) {
+    const int64_t i = out.perm[t];
+    out.patch[t] = patch[i];
+    out.pcol[t] = pcol[patch[i]];
+    out.lcol[t] = lcol[i];
+  }
+  return out;
+}
+
+// Stores a level's patch arrays (new order), its composite sweep colour and
+// spatial rank, and the ranges its sweeps launch over.
+void set_patches(Level &L, const PatchOrder &po, const std::vector<int64_t> &rank_old) {
+  const int64_t n = (int64_t)po.perm.size();
+  L.patch = po.patch;
+  L.pcolour = po.pcol;
+  L.lcolour = po.lcol;
+  L.colour.resize(n);
+  L.rank.resize(n);
+  for (int64_t t = 0; t < n; ++t) {
+    L.colour[t] = po.pcol[t] * (int32_t)kPatchRows + po.lcol[t];
+    L.rank[t] = rank_old[po.perm[t]];
+  }
+  // patches are contiguous in the new order, numbered in rank order: list
+  // them in storage order, with their row ranges and local colour segments
+  L.patch_list.clear();
+  L.patch_row.clear();
+  L.seg_ptr.clear();
+  L.seg_row.clear();
+  L.pc_start.clear();
+  for (int64_t t = 0; t < n; ++t) {
+    const bool new_patch = t == 0 || po.patch[t] != po.patch[t - 1];
+    if (new_patch) {
+      if (L.pc_start.empty() || po.pcol[t] != po.pcol[L.patch_row.back()])
+        for (int32_t c = (int32_t)L.pc_start.size(); c <= po.pcol[t]; ++c)
+          L.pc_start.push_back((int64_t)L.patch_list.size());
+      L.patch_list.push_back(po.patch[t]);
+      L.patch_row.push_back(t);
+      L.seg_ptr.push_back((int64_t)L.seg_row.size());
+    }
+    if (new_patch || po.lcol[t] != po.lcol[t - 1]) L.seg_row.push_back(t);
+  }
+  L.pc_start.push_back((int64_t)L.patch_list.size());
+  L.patch_row.push_back(n);
+  L.seg_ptr.push_back((int64_t)L.seg_row.size());
+  L.seg_row.push_back(n);
+}
+
+// Spatial rank of the coarse unknowns (creation order): aggregates ranked by
+// their member of smallest rank in the finer level, the unknowns of one
+// aggregate in creation order.
+std::vector<int64_t> coarse_rank(const Level &L, const std::vector<int32_t> &agg,
+                                 const std::vector<int32_t> &cnode) {
+  int32_t na = 0;
+  for (auto a : agg) na = std::max(na, a + 1);
+  std::vector<int64_t> first(na, INT64_MAX);
+  for (int64_t i = 0; i < L.n(); ++i) {
+    const int32_t a = agg[L.node[i]];
+    first[a] = std::min(first[a], L.rank[i]);
+  }
+  const int64_t nc = (int64_t)cnode.size();
+  std::vector<int64_t> ord(nc);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return first[cnode[a]] < first[cnode[b]]; });
+  std::vector<int64_t> rank(nc);
+  for (int64_t t = 0; t < nc; ++t) rank[ord[t]] = t;
+  return rank;
+}
+
 // ---------------------------------------------------------------- SA pieces
 // Strong node graph: ||A_IJ||_F > theta sqrt(||A_II||_F ||A_JJ||_F), I != J.
 Csr node_strength(const Csr &A, const std::vector<int32_t> &node, int64_t nnodes, double theta) {
@@ -438,13 +600,6 @@ Csr jacobi_smoother(const Csr &A, double omega) {
   return S;
 }
 
-std::vector<int64_t> stable_colour_sort(const std::vector<int32_t> &col) {
-  std::vector<int64_t> p(col.size());
-  std::iota(p.begin(), p.end(), 0);
-  std::stable_sort(p.begin(), p.end(), [&](int64_t a, int64_t b) { return col[a] < col[b]; });
-  return p;
-}
-
 // Dense inverse of a small SPD matrix (row-major, in place): Cholesky
 // A = L L^T, then L^{-1} row by row, then A^{-1} = L^{-T} L^{-1}; every inner
 // loop runs over contiguous memory.
@@ -606,7 +761,7 @@ void build_hierarchy(std::vector<Level> &levels, const SetupOptions &opt) {
   int64_t nnodes = levels[0].n();
   while (true) {
     Level &L = levels.back();
-    L.colour_start = colour_ranges(L.colour, 0, L.n());
+    if (L.patch.empty()) L.colour_start = colour_ranges(L.colour, 0, L.n());
     if (L.n() <= opt.coarse_max || (int)levels.size() >= opt.max_levels) break;
     Csr G = node_strength(L.A, L.node, nnodes, opt.theta);
     std::vector<int32_t> agg = aggregate_graph(G);
@@ -632,8 +787,9 @@ void build_hierarchy(std::vector<Level> &levels, const SetupOptions &opt) {
     Csr P = spgemm(jacobi_smoother(L.A, opt.prolong_omega), P0);
     Csr Pt = transpose(P);
     Csr Ac = spgemm(Pt, spgemm(L.A, P));
-    std::vector<int32_t> ccol = sweep_colouring(Ac);
-    std::vector<int64_t> cperm = stable_colour_sort(ccol);
+    const std::vector<int64_t> crank = coarse_rank(L, agg, cnode);
+    const PatchOrder po = patch_order(Ac, crank);
+    const std::vector<int64_t> &cperm = po.perm;
     std::vector<int64_t> cinv(nc);
     for (int64_t i = 0; i < nc; ++i) cinv[cperm[i]] = i;
     L.P = permute_cols(P, cinv);
@@ -642,12 +798,11 @@ void build_hierarchy(std::vector<Level> &levels, const SetupOptions &opt) {
     for (auto a : agg) nnodes = std::max<int64_t>(nnodes, a + 1);
     Level C;
     C.A = permute_sym(Ac, cperm);
-    C.colour.resize(nc);
+    set_patches(C, po, crank);
     C.node.resize(nc);
     C.k = L.k;
     C.B.resize(nc * L.k);
     for (int64_t i = 0; i < nc; ++i) {
-      C.colour[i] = ccol[cperm[i]];
       C.node[i] = cnode[cperm[i]];
       for (int c = 0; c < L.k; ++c) C.B[i * L.k + c] = Bc[cperm[i] * L.k + c];
     }
@@ -1030,20 +1185,20 @@ void build_problem(Problem &P, const SetupOptions &opt, int64_t n_nodes, const d
     if (opt.extrapolation == 1) sspai_refit(E0, A, m);
     Csr E0t = transpose(E0);
     Csr S0 = spgemm(E0t, spgemm(A, E0));
-    std::vector<int32_t> scol = sweep_colouring(S0);
-    P.S_perm = stable_colour_sort(scol);
+    const std::vector<int64_t> srank(P.loc_rank.begin(), P.loc_rank.begin() + m);  // the top block ranks first
+    const PatchOrder spo = patch_order(S0, srank);
+    P.S_perm = spo.perm;
     std::vector<int64_t> sinv(m);
     for (int64_t i = 0; i < m; ++i) sinv[P.S_perm[i]] = i;
     P.E = permute_cols(E0, sinv);
     P.Et = transpose(P.E);
     Level L0;
     L0.A = permute_sym(S0, P.S_perm);
-    L0.colour.resize(m);
+    set_patches(L0, spo, srank);
     L0.node.resize(m);
     L0.k = 3;
     L0.B.resize(3 * m);
     for (int64_t i = 0; i < m; ++i) {
-      L0.colour[i] = scol[P.S_perm[i]];
       L0.node[i] = (int32_t)i;
       int64_t nd = P.perm[P.S_perm[i]];
       L0.B[3 * i] = 1.0;
@@ -1070,6 +1225,8 @@ void build_problem(Problem &P, const SetupOptions &opt, int64_t n_nodes, const d
     B0.A.ptr[s - m + 1] = (int64_t)B0.A.idx.size();
   }
   B0.colour.assign(P.colour.begin() + m, P.colour.end());
+  B0.rank.resize(nb);
+  for (int64_t i = 0; i < nb; ++i) B0.rank[i] = P.loc_rank[m + i] - m;
   B0.node.resize(nb);
   std::iota(B0.node.begin(), B0.node.end(), 0);
   B0.k = 1;
@@ -1085,6 +1242,7 @@ void build_problem(Problem &P, const SetupOptions &opt, int64_t n_nodes, const d
     Level F;
     F.A = A;
     F.colour = P.colour;
+    F.rank = P.loc_rank;
     F.node.resize(n);
     std::iota(F.node.begin(), F.node.end(), 0);
     F.k = 1;

@@ -18,10 +18,24 @@ struct SetupError : std::runtime_error {
   SetupError(int c, const std::string &m) : std::runtime_error(m), code(c) {}
 };
 
+// Patches of the block multicolour order of the coarse levels: at most
+// kPatchRows unknowns and kPatchEntries off-diagonal entries each (the sweep
+// kernel takes one patch per block, an unknown per group of lanes).
+constexpr int64_t kPatchRows = 64;
+constexpr int64_t kPatchEntries = 4096;
+
 struct Level {
-  Csr A;                              // standard form, storage (colour-sorted) order
-  std::vector<int32_t> colour;        // per row, non-decreasing
-  std::vector<int64_t> colour_start;  // ncolours + 1
+  Csr A;                              // standard form, storage order
+  std::vector<int32_t> colour;        // sweep colour per row (composite on patch-ordered levels)
+  std::vector<int64_t> colour_start;  // fine levels: ncolours + 1 (rows sorted by colour)
+  std::vector<int64_t> rank;          // position of each row in the level's spatial order
+  // patch-ordered levels (every coarse level and the surface level):
+  std::vector<int32_t> patch, pcolour, lcolour;  // per row
+  std::vector<int64_t> pc_start;    // patch colour c: entries [pc_start[c], pc_start[c+1]) of patch_list
+  std::vector<int32_t> patch_list;  // patches in storage order
+  std::vector<int64_t> patch_row;   // row range of the i-th stored patch: [patch_row[i], patch_row[i+1])
+  std::vector<int64_t> seg_ptr;     // its local colour segments: seg_row[seg_ptr[i] .. seg_ptr[i+1]]
+  std::vector<int64_t> seg_row;     // segment starts (+ n at the end)
   std::vector<int32_t> node;          // aggregation node of each row
   std::vector<double> B;              // near-kernel vectors, row-major [n][k]
   int k = 1;

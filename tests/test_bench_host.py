@@ -60,8 +60,8 @@ def test_pmc_traffic_divides_each_counter_by_its_calibration(tmp_path, capsys):
 
 
 def test_trace_timed_takes_the_last_run_of_each_kernel(tmp_path, capsys):
-    cgs = "void vemg::(anonymous namespace)::k_csr_gs<double, 1, 32, false>(vemg::CsrG, ...)"
-    cgs_zero = "void vemg::(anonymous namespace)::k_csr_gs<double, 1, 32, true>(vemg::CsrG, ...)"
+    cgs = "void vemg::(anonymous namespace)::k_patch_gs<double, 1, false, false>(vemg::CsrG, ...)"
+    cgs_zero = "void vemg::(anonymous namespace)::k_patch_gs<double, 1, true, false>(vemg::CsrG, ...)"
     fill = "void vemg::(anonymous namespace)::k_fill<double>(double*, long, double, int const*)"
     other = "vemg::(anonymous namespace)::k_pcg_alpha(...)"
     rows, t = [], 0

@@ -136,7 +136,15 @@ def test_sa_baseline_matches_oracle(mode):
     _print("sa iters gpu", its, "oracle", it_o)
     assert ok and st == 0
     assert _rel(x.cpu().numpy()[o.perm], xo) < 1e-8
-    assert abs(its[0] - it_o) <= max(3, 0.1 * it_o)
+    # iteration counts at 1e-8: at 1e-11 the count depends on how many
+    # restarts the rounding of several hundred iterations leaves necessary
+    # (the oracle's own count there moves between 351 and 380 under relative
+    # perturbations of b of 1e-15, one restart more costs about 80)
+    _, it_o8, _, ok8 = osolver.solve(o, b_nat[o.perm], 1e-8, "sa", max_iter=5000)
+    _, its8, _, st8 = s.solve(b_nat, rtol=1e-8, max_iter=5000)
+    _print("sa iters at 1e-8 gpu", its8, "oracle", it_o8)
+    assert ok8 and st8 == 0
+    assert abs(its8[0] - it_o8) <= max(3, 0.1 * it_o8)
 
 
 @pytest.mark.parametrize("pc", ["vl_as", "vl_sor"])

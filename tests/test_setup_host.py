@@ -23,6 +23,8 @@ CASES = [
     # vertical columns: the A_bar coarsening stalls once the columns are
     # aggregated and continues with every coupling strong
     ("N", dict(nx=17, ny=17, nz=9, H=1e-3, jitter=0.0, seed=1, bathymetry=False)),
+    # several patches on the surface level and the first coarse levels
+    ("N", dict(nx=33, ny=33, nz=9, H=1e-2, jitter=0.3, seed=2, bathymetry=True)),
 ]
 ROBIN_ALPHA = 7.5
 
@@ -101,6 +103,12 @@ def test_hierarchies(pair, which):
         pre = f"{which}.{l}."
         assert np.array_equal(s.export(pre + "colour", np.int32), L.colour)
         assert np.array_equal(s.export(pre + "node", np.int32), L.node)
+        assert np.array_equal(s.export(pre + "rank", np.int64), L.rank)
+        if L.patch is not None:
+            # block multicolour order: patches and both colourings bit for bit
+            assert np.array_equal(s.export(pre + "patch", np.int32), L.patch)
+            assert np.array_equal(s.export(pre + "pcolour", np.int32), L.pcolour)
+            assert np.array_equal(s.export(pre + "lcolour", np.int32), L.lcolour)
         A = _csr(s, pre + "A")
         _same_pattern(A, L.A)
         _close(A[2], L.A.data)
@@ -219,8 +227,10 @@ def _all_arrays(s):
     for which, key in (("S", "s_levels"), ("Abar", "abar_levels")):
         for l in range(info[key]):
             pre = f"{which}.{l}."
-            names = [("colour", np.int32), ("node", np.int32), ("A.ptr", np.int64), ("A.idx", np.int32),
-                     ("A.val", np.float64)]
+            names = [("colour", np.int32), ("node", np.int32), ("rank", np.int64), ("A.ptr", np.int64),
+                     ("A.idx", np.int32), ("A.val", np.float64)]
+            if which == "S" or l > 0:
+                names += [("patch", np.int32), ("pcolour", np.int32), ("lcolour", np.int32)]
             if l + 1 < info[key]:
                 names += [("agg", np.int32), ("P.ptr", np.int64), ("P.idx", np.int32), ("P.val", np.float64)]
             else:
@@ -263,3 +273,39 @@ def test_projection_error_names_the_node(monkeypatch, threads):
         lib.Solver(xyz, m.tets, m.top, device=-1)
     assert e.value.status == -3
     assert f"node {corner} " in str(e.value)
+
+
+def test_patch_ranges_drive_the_sequential_sweep():
+    # the ranges the sweep kernel launches over (patch colours -> stored
+    # patches -> local colour segments), walked on the host exactly as the
+    # launches and the kernel's barriers take them, give the oracle's sweep
+    from oracle import amg
+    m = box_mesh(33, 33, 9, 1e-2, jitter=0.3, seed=2, bathymetry=True)
+    s = lib.Solver(m.xyz, m.tets, m.top, top_bc="N", device=-1, coarse_max=40)
+    o = osolver.setup(m, "N", coarse_max=40)
+    for which, levels, first in (("S", o.S_levels, 0), ("Abar", o.Abar_levels, 1)):
+        for l in range(first, len(levels) - 1):
+            L = levels[l]
+            pre = f"{which}.{l}."
+            pc_start = s.export(pre + "pc_start", np.int64)
+            prow = s.export(pre + "patch_row", np.int64)
+            sptr = s.export(pre + "seg_ptr", np.int64)
+            seg = s.export(pre + "seg_row", np.int64)
+            n = L.n
+            assert prow[0] == 0 and prow[-1] == n and seg[-1] == n and pc_start[-1] == prow.size - 1
+            A = L.A.tocsr()
+            g = np.random.default_rng(l).standard_normal(n)
+            for forward in (True, False):
+                x = np.zeros(n)
+                colours = range(pc_start.size - 1) if forward else range(pc_start.size - 2, -1, -1)
+                for c in colours:
+                    # the patches of one colour are independent: one after the other here
+                    for p in range(pc_start[c], pc_start[c + 1]):
+                        segs = list(range(sptr[p], sptr[p + 1]))
+                        assert seg[segs[0]] == prow[p] and seg[sptr[p + 1]] == prow[p + 1]
+                        for k in (segs if forward else segs[::-1]):
+                            rows = np.arange(seg[k], seg[k + 1])
+                            assert np.unique(L.pcolour[rows]).size == 1 and np.unique(L.lcolour[rows]).size == 1
+                            x[rows] = x[rows] + (g[rows] - A[rows] @ x) / L.diag[rows]
+                ref = amg.gs_sweep(A, L.diag, L.colour, g, np.zeros(n), forward=forward)
+                assert np.max(np.abs(x - ref)) <= 1e-13 * np.max(np.abs(ref))
