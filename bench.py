@@ -212,7 +212,8 @@ KERNEL_NAMES = {
     "spmv": "k_spmv<double, {K}, 0, true> (fine difference-form SpMV fused with p.q)",
     "cgs": "k_patch_gs<double, {K}, false, false> (coarse block multicolour SOR, one patch colour per launch)",
     "et": "k_csr_spmv<double, {K}, 64, 2> (restriction E~^T, CSR, 64 lanes per surface row)",
-    "e": "k_rect<double, {K}, true> (prolongation z += E~ y, SELL, one thread per fine row)"}
+    "e": "k_rect<double, {K}, true> (prolongation z += E~ y, SELL, one thread per fine row)",
+    "dense": "k_dense_part<double, {K}> (the surface coarsest level's explicit inverse streamed by columns)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
 
@@ -267,7 +268,8 @@ def profile_kernels(workload, K=1):
     s = vemg.Solver(mesh.xyz, mesh.tets, mesh.top, top_bc="pinned", pc="vl_as", device=0)
     info = s.info()
     for name, op in (("fine sweep", vemg.OP_GS_FWD), ("fine spmv", vemg.OP_A), ("coarse sweep", vemg.OP_GS_COARSE),
-                     ("restriction E~^T", vemg.OP_ET), ("prolongation E~", vemg.OP_E)):
+                     ("coarsest dense product", vemg.OP_COARSEST), ("restriction E~^T", vemg.OP_ET),
+                     ("prolongation E~", vemg.OP_E)):
         ms, nl = s.time_op(op, reps=10, nrhs=K)
         print(f"[profile] {name} (K={K}): {ms:.4f} ms per application, {nl} launches", flush=True)
     a = torch.ones(CALIBRATION_BYTES // 8, dtype=torch.float64, device="cuda")
@@ -287,7 +289,7 @@ def pmc_kernels(K):
     calibration copy) in rocprofv3 output."""
     return {"gs": f"k_gs<double, {K}, false>", "spmv": f"k_spmv<double, {K}, 0, true>",
             "cgs": f"k_patch_gs<double, {K}, false, false>", "et": f"k_csr_spmv<double, {K}, 64, 2>",
-            "e": f"k_rect<double, {K}, true>", "calibration": "MulFunctor"}
+            "e": f"k_rect<double, {K}, true>", "dense": f"k_dense_part<double, {K}>", "calibration": "MulFunctor"}
 
 
 def _pmc_means(path, counter, K):
@@ -326,7 +328,7 @@ def pmc_traffic(fetch_dir, write_dir, workload, K):
                         f"python3 bench.py --pmc-traffic {fetch_dir} {write_dir} --workload {workload} "
                         f"--profile-batch {K}"],
            "kernels": {}}
-    for key in ("gs", "spmv", "cgs", "et", "e"):
+    for key in ("gs", "spmv", "cgs", "et", "e", "dense"):
         if key in fetch and key in write:
             rec["kernels"][key] = {"kernel": KERNEL_NAMES[key].format(K=K), "fetch_kib": fetch[key],
                                    "write_kib": write[key],
