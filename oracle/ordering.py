@@ -155,7 +155,7 @@ def is_valid_colouring(A, colour):
 # sweep in this order is the multicolour sweep over the composite colours
 # (patch colour, local colour) in lexicographic order, and that is a plain
 # sequential forward (or, reversed, backward) SOR sweep.
-PATCH_ROWS = 64
+PATCH_ROWS = 128
 PATCH_ENTRIES = 4096
 
 

@@ -471,15 +471,15 @@ __global__ __launch_bounds__(kWave) void k_csr_spmv(CsrG A, int64_t r0, int64_t 
   csr_row_op<T, K, G, MODE>(A, r, gl, x, g, y);
 }
 
-// Patch sweep: one block per patch, kPatchGroup lanes per unknown (enough
-// lanes that a row's couplings take one or two loads per lane).  First every
+// Patch sweep: one block per patch, kPatchGroup lanes per unknown (a coarse
+// row's few dozen couplings take a handful of loads per lane).  First every
 // unknown of the patch sums the couplings whose values the sweep takes as
 // they stand -- other patches (with a zero start only the patch colours swept
 // before) and, without a zero start, its own patch's later unknowns (earlier
 // ones backward) -- into h = g - sum (FP32: g / a_ii - sum over row-scaled
 // values); then every unknown takes its row of the patch's triangular factor
 // times h.  One block barrier; no sequential stages inside the patch.
-constexpr int kPatchGroup = 16;
+constexpr int kPatchGroup = 8;
 constexpr int kPatchThreads = kPatchGroup * kPatchLdsRows;
 
 template <class T>

@@ -125,7 +125,7 @@ void launch_csr_spmv(hipStream_t st, int K, const CsrG &A, int mode, int64_t r0,
 // values), the patch's new values are (D_p + L_p)^{-1} h_p, L_p the strictly
 // lower part of the patch's block in stored order -- the sequential SOR
 // sweep in that order.  Backward: (D_p + U_p)^{-1} = ((D_p + L_p)^{-1})^T.
-constexpr int kPatchLdsRows = 64;
+constexpr int kPatchLdsRows = 128;
 struct PatchSweep {
   const int32_t *prow = nullptr;  // stored patch i: rows [prow[i], prow[i+1])
   const int64_t *toff = nullptr;  // its factors start at toff[i] (m (m + 1) / 2 entries each)

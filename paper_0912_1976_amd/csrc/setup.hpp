@@ -21,7 +21,7 @@ struct SetupError : std::runtime_error {
 // Patches of the block multicolour order of the coarse levels: at most
 // kPatchRows unknowns and kPatchEntries off-diagonal entries each (the sweep
 // kernel takes one patch per block, an unknown per group of lanes).
-constexpr int64_t kPatchRows = 64;
+constexpr int64_t kPatchRows = 128;
 constexpr int64_t kPatchEntries = 4096;
 
 struct Level {
