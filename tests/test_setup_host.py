@@ -309,3 +309,39 @@ def test_patch_ranges_drive_the_sequential_sweep():
                             x[rows] = x[rows] + (g[rows] - A[rows] @ x) / L.diag[rows]
                 ref = amg.gs_sweep(A, L.diag, L.colour, g, np.zeros(n), forward=forward)
                 assert np.max(np.abs(x - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_patch_factor_sweep_is_the_sequential_sweep():
+    # the sweep kernel's arithmetic on the host: per patch colour, per patch,
+    # h = g - (couplings to other patches and, without a zero start, to the
+    # patch's own later unknowns at their old values), then the patch's new
+    # values (D_p + L_p)^{-1} h (backward: the transpose, earlier unknowns
+    # old); equal to the oracle's sequential sweep up to rounding
+    import scipy.linalg as sla
+    from oracle import amg
+    m = box_mesh(33, 33, 9, 1e-2, jitter=0.3, seed=2, bathymetry=True)
+    s = lib.Solver(m.xyz, m.tets, m.top, top_bc="N", device=-1, coarse_max=40)
+    o = osolver.setup(m, "N", coarse_max=40)
+    L = o.S_levels[0]
+    pc_start = s.export("S.0.pc_start", np.int64)
+    prow = s.export("S.0.patch_row", np.int64)
+    A = L.A.tocsr()
+    D = A.toarray()
+    n = L.n
+    g = np.random.default_rng(5).standard_normal(n)
+    x0 = np.random.default_rng(6).standard_normal(n)
+    for forward, start in ((True, np.zeros(n)), (True, x0), (False, x0)):
+        x = start.copy()
+        colours = range(pc_start.size - 1) if forward else range(pc_start.size - 2, -1, -1)
+        for c in colours:
+            new = {}
+            for p in range(pc_start[c], pc_start[c + 1]):
+                a, b = prow[p], prow[p + 1]
+                B = D[a:b, a:b]
+                tri = np.tril(B) if forward else np.triu(B)
+                h = g[a:b] - D[a:b, :a] @ x[:a] - D[a:b, b:] @ x[b:] - (B - tri) @ x[a:b]
+                new[p] = sla.solve_triangular(tri, h, lower=forward)
+            for p, v in new.items():          # the patches of one colour are independent
+                x[prow[p]:prow[p + 1]] = v
+        ref = amg.gs_sweep(A, L.diag, L.colour, g, start, forward=forward)
+        assert np.max(np.abs(x - ref)) <= 1e-11 * np.max(np.abs(ref))
