@@ -411,44 +411,61 @@ def timed_solves(s, b, steps, warmup, rtol):
     return x, times, iters, rels, sts
 
 
-def _cpu_baseline_child(workload, iters, core, queue):
-    """Child process: the oracle as it stands on one host core, its setup
-    untimed, then `iters` PCG iterations (VL + additive smoother) on column 0
-    of the workload timed."""
+def _oracle_sample(workload, iters, core, tol=0.0):
+    """The oracle as it stands on one host core, its setup untimed, then
+    PCG (VL + additive smoother) on column 0 of the workload timed: `iters`
+    iterations, or fewer when the relative residual reaches `tol` first."""
+    from inputs import fourier_field, manufactured_u
+    from oracle import pcg, precond, solver as osolver
+
+    wl = WORKLOADS[workload]
+    mesh = build_mesh(wl)
+    t0 = time.perf_counter()
+    o = osolver.setup(mesh, "N")
+    t_setup = time.perf_counter() - t0
+    if wl["kind"] == "graded":
+        b = osolver.rhs_from_solution(o, manufactured_u(mesh.xyz, wl["H"]))
+    else:
+        b = osolver.rhs_from_field(o, fourier_field(mesh.xyz, wl["H"], wl["rhs_seed"]))
+    M = precond.make(o, "vl_as")
+    t0 = time.perf_counter()
+    _, it, hist, _ = pcg.pcg(lambda v: osolver.apply_A(o, v), M, b, tol, max_iter=iters)
+    t = time.perf_counter() - t0
+    what = f"{it} PCG iterations" if tol == 0.0 else f"the whole solve ({it} PCG iterations to {hist[-1]:.1e})"
+    return {"value": o.n * it / t, "unit": "DOF*iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{what} (VL + additive smoother) of column 0 of the {workload} "
+                      f"workload (full mesh, {o.n} unknowns), oracle setup {t_setup:.1f} s untimed, "
+                      f"run in a child process pinned to host core {core} while the GPU was measured",
+            "seconds": round(t, 3), "setup_s": round(t_setup, 1), "cpu": _cpu_model(),
+            "host_cpus": os.cpu_count()}
+
+
+# the other configurations whose oracle is timed too, with the relative
+# residual that ends the sample early (0: the fixed iteration count); the
+# graded mesh's oracle setup alone takes minutes, the serving stream is a mix
+# of the box meshes
+CPU_BASELINE_CONFIGS = {"thinbox-17x17x9-eps1e-2": 1e-8, "thinbox-129x129x33-eps1e-3": 0.0}
+
+
+def _cpu_baseline_child(workloads, iters, core, queue):
+    """Child process: the oracle samples of the workloads in turn, each put on
+    the queue as (workload, result) when done."""
     try:
         os.sched_setaffinity(0, {core})
     except (AttributeError, OSError):
         pass
     from threadpoolctl import threadpool_limits
 
-    from inputs import fourier_field, manufactured_u
-    from oracle import pcg, precond, solver as osolver
-
-    wl = WORKLOADS[workload]
     with threadpool_limits(limits=1):
-        mesh = build_mesh(wl)
-        t0 = time.perf_counter()
-        o = osolver.setup(mesh, "N")
-        t_setup = time.perf_counter() - t0
-        if wl["kind"] == "graded":
-            b = osolver.rhs_from_solution(o, manufactured_u(mesh.xyz, wl["H"]))
-        else:
-            b = osolver.rhs_from_field(o, fourier_field(mesh.xyz, wl["H"], wl["rhs_seed"]))
-        M = precond.make(o, "vl_as")
-        t0 = time.perf_counter()
-        _, it, _, _ = pcg.pcg(lambda v: osolver.apply_A(o, v), M, b, 0.0, max_iter=iters)
-        t = time.perf_counter() - t0
-    queue.put({"value": o.n * it / t, "unit": "DOF*iters/s", "cores": 1, "kind": "oracle",
-               "sample": f"{it} PCG iterations (VL + additive smoother) of column 0 of the {workload} "
-                         f"workload (full mesh, {o.n} unknowns), oracle setup {t_setup:.1f} s untimed, "
-                         f"run in a child process pinned to host core {core} while the GPU was measured",
-               "seconds": round(t, 3), "setup_s": round(t_setup, 1), "cpu": _cpu_model(),
-               "host_cpus": os.cpu_count()})
+        for w in workloads:
+            tol = CPU_BASELINE_CONFIGS.get(w, 0.0)
+            queue.put((w, _oracle_sample(w, 1000 if tol > 0.0 else iters, core, tol)))
 
 
-def start_cpu_baseline(workload, iters):
-    """Starts the oracle's timed sample in a child process on one host core
-    (the last one this process may use) and returns (process, queue)."""
+def start_cpu_baseline(workloads, iters):
+    """Starts the oracle's timed samples of the workloads (the headline first)
+    in a child process on one host core (the last one this process may use)
+    and returns (process, queue)."""
     import multiprocessing as mp
     ctx = mp.get_context("spawn")
     q = ctx.Queue()
@@ -456,17 +473,26 @@ def start_cpu_baseline(workload, iters):
         core = max(os.sched_getaffinity(0))
     except AttributeError:
         core = 0
-    p = ctx.Process(target=_cpu_baseline_child, args=(workload, iters, core, q), daemon=True)
+    p = ctx.Process(target=_cpu_baseline_child, args=(list(workloads), iters, core, q), daemon=True)
     p.start()
     return p, q
 
 
-def finish_cpu_baseline(handle, timeout):
+def finish_cpu_baseline(handle, count, timeout):
+    """{workload: result} of the first `count` samples that finish within
+    `timeout` seconds in all; the child is then stopped."""
+    import queue as _queue
     p, q = handle
-    try:
-        out = q.get(timeout=timeout)
-    except Exception:
-        out = None
+    out = {}
+    deadline = time.perf_counter() + timeout
+    while len(out) < count and time.perf_counter() < deadline:
+        try:
+            w, r = q.get(timeout=2.0)
+        except _queue.Empty:
+            if not p.is_alive() and q.empty():
+                break  # the child ended (or failed) without another result
+            continue
+        out[w] = r
     p.join(5)
     if p.is_alive():
         p.terminate()
@@ -789,7 +815,10 @@ def main():
 
     wl = WORKLOADS[args.workload]
     # the oracle's timed sample runs on one host core while the GPU is measured
-    cpu_job = None if args.no_cpu_baseline else start_cpu_baseline(args.workload, args.cpu_iters)
+    cpu_workloads = [args.workload] + [w for w in CPU_BASELINE_CONFIGS if w != args.workload]
+    if args.no_extras or args.no_configs:
+        cpu_workloads = cpu_workloads[:1]
+    cpu_job = None if args.no_cpu_baseline else start_cpu_baseline(cpu_workloads, args.cpu_iters)
 
     import numpy as np
     import torch
@@ -876,7 +905,11 @@ def main():
     cpu = None
     if cpu_job is not None:
         log("waiting for the cpu baseline (oracle)")
-        cpu = finish_cpu_baseline(cpu_job, timeout=600)
+        samples = finish_cpu_baseline(cpu_job, len(cpu_workloads), timeout=600)
+        cpu = samples.get(args.workload)
+        others = {w: r for w, r in samples.items() if w != args.workload}
+        if others:
+            extras["cpu_baseline_configs"] = others
 
     line = {
         "metric": "DOF-iters/s, time to 1e-8 rel residual; solves/s + p50/p99 (mixed vs FP64)",

@@ -1,5 +1,6 @@
-"""Host-side logic of bench.py: the one-GPU guard, the PMC traffic arithmetic
-and the trace summary, on small synthetic rocprofv3 CSV files (no GPU)."""
+"""Host-side logic of bench.py: the one-GPU guard, the PMC traffic arithmetic,
+the trace summary on small synthetic rocprofv3 CSV files, and the oracle
+baseline child on the smallest box (no GPU)."""
 import csv
 import json
 import os
@@ -149,3 +150,15 @@ def test_iteration_bytes_add_up_the_preconditioner_branches():
     # batches and FP32 preconditioners scale the vector traffic, not the matrices
     assert bench.iteration_bytes(info, 8, "vl_as") > full
     assert bench.iteration_bytes(info, 1, "vl_as", "mixed_pc") < full + 4 * 100 * 12
+
+
+def test_cpu_baseline_child_reports_each_config():
+    """The oracle's samples run in a child process on one core and come back
+    per workload; the small box is timed over its whole solve."""
+    h = bench.start_cpu_baseline(["thinbox-17x17x9-eps1e-2"], 5)
+    out = bench.finish_cpu_baseline(h, 1, 120)
+    r = out["thinbox-17x17x9-eps1e-2"]
+    assert r["kind"] == "oracle" and r["cores"] == 1 and r["unit"] == "DOF*iters/s"
+    assert r["value"] > 0.0
+    assert "whole solve" in r["sample"]
+    assert not h[0].is_alive()
