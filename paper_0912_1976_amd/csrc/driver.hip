@@ -465,9 +465,19 @@ void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *
     }
   };
   for (int c = 0; c < nc; ++c) gs(c, true);
-  if (L.fine)
-    launch_spmv<T>(st, K, L.As, 1, L.row0, L.row0 + L.n, x, g, r, nullptr, done, L.order);
-  else
+  if (L.fine) {
+    // the rows of the last colour have a zero residual after the forward sweep
+    ZeroRows zr;
+    if (nc > 0) {
+      if (!L.cstart_top.empty()) {
+        zr.a0 = L.cstart_top[nc - 1];
+        zr.a1 = L.cstart_top[nc];
+      }
+      zr.b0 = L.cstart[nc - 1];
+      zr.b1 = L.cstart[nc];
+    }
+    launch_spmv<T>(st, K, L.As, 1, L.row0, L.row0 + L.n, x, g, r, nullptr, done, L.order, zr);
+  } else
     launch_csr_spmv<T>(st, K, L.Ac, 1, 0, L.n, x, g, r, done);
   DLevel &C = H[l + 1];
   launch_csr_rect<T>(st, K, L.Pt, false, r + o, C.g<T>(), done);
@@ -510,7 +520,19 @@ void sor_cycle(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *
   };
   for (int c = 0; c < nc; ++c) sweep(c, true);
   if (m > 0) {
-    launch_spmv<T>(st, K, h->A, 1, 0, n, zz, rr, v.res, nullptr, done, h->order_all);
+    // the rows swept by the last launch have a zero residual
+    ZeroRows zr;
+    if (nc > 0) {
+      if (nc - 1 < nct) {
+        zr.a0 = P.top_colour_start[nc - 1];
+        zr.a1 = P.top_colour_start[nc];
+      }
+      if (nc - 1 < ncb) {
+        zr.b0 = P.bar_colour_start[nc - 1];
+        zr.b1 = P.bar_colour_start[nc];
+      }
+    }
+    launch_spmv<T>(st, K, h->A, 1, 0, n, zz, rr, v.res, nullptr, done, h->order_all, zr);
     launch_csr_rect<T>(st, K, h->Et, false, v.res, h->S[0].g<T>(), done);
     vcycle<T>(st, K, h->S, 0, done);
     launch_rect<T>(st, K, h->E, true, h->S[0].x<T>(), zz, done);

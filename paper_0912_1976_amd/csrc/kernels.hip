@@ -238,8 +238,9 @@ template <class T, int K, int MODE, bool DOT>
 __global__ __launch_bounds__((kBlock * row_lanes<T, K>())) void k_spmv(
     Sell A, int64_t r0, int64_t r1, int64_t s_first, int64_t ns, int64_t nb, const int32_t *__restrict__ order,
     const T *__restrict__ x, const T *__restrict__ g, T *__restrict__ y, double *__restrict__ partial,
-    const int *__restrict__ done) {
+    const int *__restrict__ done, ZeroRows zr) {
   constexpr int LPR = row_lanes<T, K>(), C = K / LPR;
+  static_assert(!(MODE == 1 && DOT), "the residual form has no block reduction");
   if (done && *done) return;
   const int64_t blk = xcd_block(blockIdx.x, nb);
   const int rloc = threadIdx.x / LPR, q = threadIdx.x % LPR;
@@ -251,6 +252,13 @@ __global__ __launch_bounds__((kBlock * row_lanes<T, K>())) void k_spmv(
 #pragma unroll
   for (int k = 0; k < C; ++k) prod[k] = 0.0;
   if (i < ns && r >= r0 && r < r1) {
+    if (MODE == 1 && ((r >= zr.a0 && r < zr.a1) || (r >= zr.b0 && r < zr.b1))) {
+      Row<T, C> zero;
+#pragma unroll
+      for (int k = 0; k < C; ++k) zero.v[k] = T(0);
+      stp<T, K, C>(y, r, q, zero);
+      return;  // MODE 1 has no block reduction, so the lane may leave
+    }
     const Row<T, C> xr = ldp<T, K, C>(x, r, q);
     const Row<T, C> out = fine_row<T, K, C, MODE>(A, s, t, q, r, x, xr, g);
     stp<T, K, C>(y, r, q, out);
@@ -1151,7 +1159,7 @@ void launch_slot_copy(hipStream_t stm, unsigned mask, const double *z, double *p
 
 template <class T>
 void launch_spmv(hipStream_t stm, int K, const Sell &A, int mode, int64_t r0, int64_t r1, const T *x, const T *g,
-                 T *y, double *partial, const int *done, const int32_t *order) {
+                 T *y, double *partial, const int *done, const int32_t *order, ZeroRows zr) {
   int64_t nb = sell_blocks(r0, r1);
   if (!nb) return;
   int64_t sf = r0 / kWave, ns = (r1 + kWave - 1) / kWave - sf;
@@ -1160,13 +1168,13 @@ void launch_spmv(hipStream_t stm, int K, const Sell &A, int mode, int64_t r0, in
     if (mode == 0) {
       if (partial)
         hipLaunchKernelGGL((k_spmv<T, KK, 0, true>), grid(nb), blk, 0, stm, A, r0, r1, sf, ns, nb, order, x, g, y,
-                           partial, done);
+                           partial, done, zr);
       else
         hipLaunchKernelGGL((k_spmv<T, KK, 0, false>), grid(nb), blk, 0, stm, A, r0, r1, sf, ns, nb, order, x, g, y,
-                           partial, done);
+                           partial, done, zr);
     } else {
       hipLaunchKernelGGL((k_spmv<T, KK, 1, false>), grid(nb), blk, 0, stm, A, r0, r1, sf, ns, nb, order, x, g, y,
-                         partial, done);
+                         partial, done, zr);
     }
   })
 }
@@ -1380,7 +1388,7 @@ void launch_pcg_resume(hipStream_t stm, int, Scal *s, unsigned keep) {
 
 #define VEMG_INSTANTIATE(T)                                                                                          \
   template void launch_spmv<T>(hipStream_t, int, const Sell &, int, int64_t, int64_t, const T *, const T *, T *,      \
-                               double *, const int *, const int32_t *);                                              \
+                               double *, const int *, const int32_t *, ZeroRows);                                    \
   template void launch_gs<T>(hipStream_t, int, const Sell &, int64_t, int64_t, int64_t, int64_t, const T *, T *,       \
                              const int *, ZeroStart);                                                                \
   template void launch_rect<T>(hipStream_t, int, const Sell &, bool, const T *, T *, const int *);                    \

@@ -83,13 +83,20 @@ inline int64_t sell_blocks(int64_t r0, int64_t r1) {
 inline int64_t vec_blocks(int64_t n) { return (n + kBlock - 1) / kBlock; }
 
 // ---- fine matrix (SELL, difference form) ---------------------------------
+// Rows [a0, a1) and [b0, b1) whose residual is zero in exact arithmetic: the
+// rows of the last colour of a forward multicolour Gauss-Seidel sweep with
+// relaxation 1, whose neighbours all lie in colours swept before them.
+struct ZeroRows {
+  int64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+};
 // y = A x (mode 0) or y = g - A x (mode 1) on rows [r0, r1).  With partial,
 // partial[block * K + k] = sum over the block's rows of x_ik y_ik.  order
 // (optional): the range's slices in visit order (offsets from slice r0 / 64),
-// so that the blocks of one XCD take one spatial region of every colour.
+// so that the blocks of one XCD take one spatial region of every colour.  In
+// mode 1 the rows of zr get y = 0 without reading their entries.
 template <class T>
 void launch_spmv(hipStream_t st, int K, const Sell &A, int mode, int64_t r0, int64_t r1, const T *x, const T *g,
-                 T *y, double *partial, const int *done, const int32_t *order = nullptr);
+                 T *y, double *partial, const int *done, const int32_t *order = nullptr, ZeroRows zr = ZeroRows());
 // One multicolour Gauss-Seidel step on the rows [a0,a1) and [b0,b1) (rows of
 // one colour): x_i += (g_i - (A x)_i) / a_ii.
 // Zero start (the first sweep from x = 0): of the top block (j < n_top) only

@@ -144,6 +144,25 @@ def test_multicolour_gs_equals_sequential_gs():
     assert np.max(np.abs(y - ref)) < 1e-12 * np.max(np.abs(ref))
 
 
+def test_last_colour_residual_vanishes_after_forward_sweep():
+    # with relaxation 1 the rows of the last colour are solved exactly from
+    # neighbours that no later colour changes: their residual g - A x is zero
+    # up to rounding (the library writes it as zero); the other colours' is not
+    m, s = _hier()
+    for A, diag, colour in ((s.A, s.diag, s.colour), (s.Abar_levels[0].A, s.Abar_levels[0].diag,
+                                                      s.Abar_levels[0].colour)):
+        n = A.shape[0]
+        g = np.random.default_rng(2).standard_normal(n)
+        for x0 in (np.zeros(n), np.random.default_rng(3).standard_normal(n)):
+            x = amg.gs_sweep(A, diag, colour, g, x0, forward=True)
+            r = g - A @ x
+            scale = np.abs(g) + abs(A) @ np.abs(x)
+            last = colour == colour.max()
+            assert last.any() and (~last).any()
+            assert np.max(np.abs(r[last]) / scale[last]) < 1e-13
+            assert np.max(np.abs(r[~last]) / scale[~last]) > 1e-3
+
+
 @pytest.mark.parametrize("which", ["S", "Abar"])
 def test_vcycle_is_symmetric_positive_definite(which):
     m, s = _hier()
