@@ -823,6 +823,84 @@ __device__ __forceinline__ void sum_partials(const double *__restrict__ p, int64
   }
 }
 
+// Lanes that load one partial row of K columns, 16 bytes each (one lane of 8
+// bytes for K = 1), and the block size of the kernels that use
+// sum_partials_wide.
+template <int K>
+constexpr int partial_lanes() {
+  return K >= 2 ? K / 2 : 1;
+}
+template <int K>
+constexpr int wide_block() {
+  return kBlock * partial_lanes<K>();
+}
+
+// sum_partials for a K known at compile time, by a block of wide_block<K>()
+// threads: the lanes of row group v (partial_lanes<K>() consecutive threads)
+// load rows v, v + kBlock, ... whole, one 16-byte piece each, so that a
+// wavefront reads consecutive rows and keeps several times the loads in
+// flight.  Each lane adds its columns over those rows in that order, which
+// is thread v's order in sum_partials, and the first kBlock threads then
+// take thread v's place in its tree: the result equals sum_partials' bit for
+// bit.  Every thread of the block must call it.
+template <int K>
+__device__ __forceinline__ void sum_partials_wide(const double *__restrict__ p, int64_t np,
+                                                  double (&res)[kMaxBatch]) {
+  constexpr int LP = partial_lanes<K>(), CW = K / LP;
+  const int v = threadIdx.x / LP, c = threadIdx.x % LP;
+  double t[CW];
+#pragma unroll
+  for (int k = 0; k < CW; ++k) t[k] = 0.0;
+  auto load = [&](int64_t j, double(&w)[CW]) {
+    if constexpr (CW == 2) {
+      const double2 q = *reinterpret_cast<const double2 *>(p + j * K + c * 2);
+      w[0] = q.x;
+      w[1] = q.y;
+    } else {
+      w[0] = p[j * K + c];
+    }
+  };
+  constexpr int U = 8;
+  int64_t j = v;
+  for (; j + (U - 1) * kBlock < np; j += U * kBlock) {
+    double w[U][CW];
+#pragma unroll
+    for (int u = 0; u < U; ++u) load(j + u * kBlock, w[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < CW; ++k) t[k] += w[u][k];
+  }
+  for (; j < np; j += kBlock) {
+    double w[CW];
+    load(j, w);
+#pragma unroll
+    for (int k = 0; k < CW; ++k) t[k] += w[k];
+  }
+  __shared__ double col[K][kBlock];
+#pragma unroll
+  for (int k = 0; k < CW; ++k) col[c * CW + k][v] = t[k];
+  __syncthreads();
+  __shared__ double buf[K][kSlicesPerBlock];
+  if (threadIdx.x < kBlock) {  // whole wavefronts
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double w = wave_sum(col[k][threadIdx.x]);
+      if ((threadIdx.x & (kWave - 1)) == 0) buf[k][threadIdx.x / kWave] = w;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kMaxBatch; ++k) {
+    double r = 0.0;
+    if (k < K) {
+#pragma unroll
+      for (int w = 0; w < kSlicesPerBlock; ++w) r += buf[k][w];
+    }
+    res[k] = r;
+  }
+}
+
 __device__ __forceinline__ void update_all_done(Scal *s) {
   int all = 1;
   for (int k = 0; k < s->K; ++k) all &= s->done[k];
@@ -901,11 +979,11 @@ __device__ __forceinline__ void store_all_done(Scal *s, int K, int mine) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_pcg_alpha(Scal *s, const double *p, int64_t np) {
+template <int K>
+__global__ __launch_bounds__(wide_block<K>()) void k_pcg_alpha(Scal *s, const double *p, int64_t np) {
   if (s->all_done) return;
-  const int K = s->K;
   double sums[kMaxBatch];
-  sum_partials(p, np, K, sums);
+  sum_partials_wide<K>(p, np, sums);
   const int k = threadIdx.x;
   int done = 1;
   if (k < K) {
@@ -953,11 +1031,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr(const Scal *s, T *__restrict_
   block_sum_store<K>(t, partial + (int64_t)blockIdx.x * K);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pcg_conv(Scal *s, const double *p, int64_t np) {
+template <int K>
+__global__ __launch_bounds__(wide_block<K>()) void k_pcg_conv(Scal *s, const double *p, int64_t np) {
   if (s->all_done) return;
-  const int K = s->K;
   double sums[kMaxBatch];
-  sum_partials(p, np, K, sums);
+  sum_partials_wide<K>(p, np, sums);
   const int k = threadIdx.x;
   int done = 1;
   if (k < K) {
@@ -984,11 +1062,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_conv(Scal *s, const double *p, i
   store_all_done(s, K, done);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pcg_beta(Scal *s, const double *p, int64_t np) {
+template <int K>
+__global__ __launch_bounds__(wide_block<K>()) void k_pcg_beta(Scal *s, const double *p, int64_t np) {
   if (s->all_done) return;
-  const int K = s->K;
   double sums[kMaxBatch];
-  sum_partials(p, np, K, sums);
+  sum_partials_wide<K>(p, np, sums);
   const int k = threadIdx.x;
   if (k < K && !s->done[k]) {
     const double rz = column_of(sums, k);
@@ -1361,19 +1439,20 @@ void launch_pcg_init(hipStream_t stm, int K, Scal *s, const double *pb, int64_t 
 void launch_pcg_set_rho(hipStream_t stm, int, Scal *s, const double *p, int64_t np) {
   hipLaunchKernelGGL(k_pcg_set_rho, dim3(1), dim3(kBlock), 0, stm, s, p, np);
 }
-void launch_pcg_alpha(hipStream_t stm, int, Scal *s, const double *p, int64_t np) {
-  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(kBlock), 0, stm, s, p, np);
+// the per-iteration scalar kernels take K (= s->K) at compile time
+void launch_pcg_alpha(hipStream_t stm, int K, Scal *s, const double *p, int64_t np) {
+  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_pcg_alpha<KK>), dim3(1), dim3(wide_block<KK>()), 0, stm, s, p, np))
 }
 template <class T>
 void launch_pcg_xr(hipStream_t stm, int K, Scal *s, T *x, T *r, const T *p, const T *q, int64_t n, double *partial) {
   VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_pcg_xr<T, KK>), grid(vec_blocks(n)), dim3(kBlock), 0, stm, s, x, r, p, q, n,
                                       partial))
 }
-void launch_pcg_conv(hipStream_t stm, int, Scal *s, const double *p, int64_t np) {
-  hipLaunchKernelGGL(k_pcg_conv, dim3(1), dim3(kBlock), 0, stm, s, p, np);
+void launch_pcg_conv(hipStream_t stm, int K, Scal *s, const double *p, int64_t np) {
+  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_pcg_conv<KK>), dim3(1), dim3(wide_block<KK>()), 0, stm, s, p, np))
 }
-void launch_pcg_beta(hipStream_t stm, int, Scal *s, const double *p, int64_t np) {
-  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(kBlock), 0, stm, s, p, np);
+void launch_pcg_beta(hipStream_t stm, int K, Scal *s, const double *p, int64_t np) {
+  VEMG_K_SWITCH(K, hipLaunchKernelGGL((k_pcg_beta<KK>), dim3(1), dim3(wide_block<KK>()), 0, stm, s, p, np))
 }
 template <class T>
 void launch_pcg_p(hipStream_t stm, int K, Scal *s, T *pvec, const T *z, int64_t n) {
