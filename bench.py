@@ -19,7 +19,9 @@ against its time, the other configurations (17 x 17 x 9 at 1e-10 and the
 the 4.0M-unknown graded multiscale mesh; the 512-request serving stream over
 six resident meshes, mixed precision against FP64), and the CPU oracle
 timed on a bounded sample of the headline workload in a child process on
-one host core (it runs while the GPU is measured).  --paper-comparisons adds
+one host core (it runs while the GPU is measured), then on the 17x17x9 box
+(a whole solve) and a sample of the 129x129x33 box, reported per
+configuration beside the headline's.  --paper-comparisons adds
 the comparisons of Section 6 (smoothed aggregation against the lumping
 method, VL + SOR), the free-surface top and the SSPAI extrapolation.
 
