@@ -262,8 +262,8 @@ enum GraphKind { kGraphFP64 = 0, kGraphFP32 = 1, kGraphMixedPC = 2, kGraphFP32Re
 
 // the captured graphs of one PCG iteration: a single graph, or four segments
 struct IterGraphs {
-  hipGraph_t graph[4] = {};
-  hipGraphExec_t exec[4] = {};
+  hipGraph_t graph[5] = {};
+  hipGraphExec_t exec[5] = {};
   int parts = 0;
 };
 
@@ -293,6 +293,17 @@ struct vemg_solver_s {
   // slice visit orders (spatial, across colours) of the products over all
   // rows and over the non-top rows
   int32_t *order_all = nullptr, *order_bar = nullptr;
+  // VL + additive smoother: the smoother's fine forward sweep and residual
+  // take the SOR cycle's for every non-top row they share; the rows that
+  // differ, per colour for the sweep (reuse_gs[reuse_gs_start[c] ..
+  // reuse_gs_start[c+1]), and for the residual (reuse_res, n_reuse_res)
+  bool reuse = false;
+  // the top block of the additive smoother's x (rows [0, n_top) of v64.w and
+  // v32.w) is zero in the layout of every batch width up to w_clean
+  int w_clean = vemg::kMaxBatch;
+  int32_t *reuse_gs = nullptr, *reuse_res = nullptr;
+  std::vector<int64_t> reuse_gs_start;
+  int64_t n_reuse_res = 0;
   vemg::Scal *scal = nullptr;
   int64_t nnz_A = 0, nnz_E = 0;
   std::map<int, vemg::IterGraphs> graphs;  // key: kind * 16 + K
@@ -432,8 +443,19 @@ void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, int 
   }
 }
 
+// The rows of a fine level whose forward sweep and residual differ from the
+// SOR cycle's, which has already stored its values for every other row (the
+// additive smoother beside the SOR cycle).
+struct Reuse {
+  const int32_t *gs = nullptr;           // dirty rows, colour by colour
+  const std::vector<int64_t> *gs_start = nullptr;
+  const int32_t *res = nullptr;          // rows whose residual is recomputed
+  int64_t nres = 0;
+};
+
 template <class T>
-void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *done) {
+void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *done,
+            const Reuse *reuse = nullptr) {
   DLevel &L = H[l];
   T *x = L.x<T>(), *g = L.g<T>(), *r = L.r<T>();
   const int64_t o = L.row0 * K;
@@ -464,19 +486,35 @@ void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *
                          first ? L.pc_row[c] : -1, !first);
     }
   };
-  for (int c = 0; c < nc; ++c) gs(c, true);
-  if (L.fine) {
-    // the rows of the last colour have a zero residual after the forward sweep
-    ZeroRows zr;
-    if (nc > 0) {
-      if (!L.cstart_top.empty()) {
-        zr.a0 = L.cstart_top[nc - 1];
-        zr.a1 = L.cstart_top[nc];
-      }
-      zr.b0 = L.cstart[nc - 1];
-      zr.b1 = L.cstart[nc];
+  // the rows of the last colour have a zero residual after the forward sweep
+  ZeroRows zr;
+  if (L.fine && nc > 0) {
+    if (!L.cstart_top.empty()) {
+      zr.a0 = L.cstart_top[nc - 1];
+      zr.a1 = L.cstart_top[nc];
     }
-    launch_spmv<T>(st, K, L.As, 1, L.row0, L.row0 + L.n, x, g, r, nullptr, done, L.order, zr);
+    zr.b0 = L.cstart[nc - 1];
+    zr.b1 = L.cstart[nc];
+  }
+  if (reuse && L.fine && L.cstart_top.empty()) {
+    // x and r hold the SOR cycle's values; sweep and recompute only the rows
+    // where the two differ, with the same arithmetic
+    for (int c = 0; c < nc; ++c) {
+      ZeroStart zs;
+      zs.on = true;
+      zs.n_top = L.n_top;
+      zs.top_lim = 0;
+      zs.bar_lim = L.cstart[c];
+      const int64_t a = (*reuse->gs_start)[c], b = (*reuse->gs_start)[c + 1];
+      launch_gs_rows<T>(st, K, L.As, reuse->gs + a, b - a, g, x, done, zs);
+    }
+    launch_spmv_rows<T>(st, K, L.As, reuse->res, reuse->nres, x, g, r, done, zr);
+  } else {
+    for (int c = 0; c < nc; ++c) gs(c, true);
+  }
+  if (L.fine) {
+    if (!(reuse && L.cstart_top.empty()))
+      launch_spmv<T>(st, K, L.As, 1, L.row0, L.row0 + L.n, x, g, r, nullptr, done, L.order, zr);
   } else
     launch_csr_spmv<T>(st, K, L.Ac, 1, 0, L.n, x, g, r, done);
   DLevel &C = H[l + 1];
@@ -492,13 +530,18 @@ void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *
 // One vertical-lumping multigrid cycle on stream st (Section 6, second
 // preconditioner): forward multicolour SOR on A from zero, E~ coarse
 // correction through one V-cycle on the surface operator, backward SOR.
+// part: 0 the whole cycle, 1 the forward sweep and the residual (with
+// share, their non-top rows are also stored to the additive smoother's fine
+// vectors), 2 the rest
 template <class T>
-void sor_cycle(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *done) {
+void sor_cycle(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *done, int part = 0,
+               bool share = false) {
   const Problem &P = h->P;
   int64_t n = P.n, m = P.n_top;
   Work<T> &v = work_of<T>(h);
   int nct = (int)P.top_colour_start.size() - 1, ncb = (int)P.bar_colour_start.size() - 1;
   int nc = std::max(nct, ncb);
+  T *x2 = share ? v.w : nullptr, *r2 = share ? v.resA : nullptr;
   // the forward sweep starts from zero: zz needs no fill, and colour c reads
   // only the colours before it (in each block)
   auto sweep = [&](int c, bool first) {
@@ -516,23 +559,28 @@ void sor_cycle(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *
     zs.n_top = m;
     zs.top_lim = P.top_colour_start[std::min(c, nct)];
     zs.bar_lim = P.bar_colour_start[std::min(c, ncb)];
-    launch_gs<T>(st, K, h->A, a0, a1, b0, b1, rr, zz, done, zs);
+    launch_gs<T>(st, K, h->A, a0, a1, b0, b1, rr, zz, done, zs, first ? x2 : nullptr, m);
   };
-  for (int c = 0; c < nc; ++c) sweep(c, true);
-  if (m > 0) {
-    // the rows swept by the last launch have a zero residual
-    ZeroRows zr;
-    if (nc > 0) {
-      if (nc - 1 < nct) {
-        zr.a0 = P.top_colour_start[nc - 1];
-        zr.a1 = P.top_colour_start[nc];
+  if (part != 2) {
+    for (int c = 0; c < nc; ++c) sweep(c, true);
+    if (m > 0) {
+      // the rows swept by the last launch have a zero residual
+      ZeroRows zr;
+      if (nc > 0) {
+        if (nc - 1 < nct) {
+          zr.a0 = P.top_colour_start[nc - 1];
+          zr.a1 = P.top_colour_start[nc];
+        }
+        if (nc - 1 < ncb) {
+          zr.b0 = P.bar_colour_start[nc - 1];
+          zr.b1 = P.bar_colour_start[nc];
+        }
       }
-      if (nc - 1 < ncb) {
-        zr.b0 = P.bar_colour_start[nc - 1];
-        zr.b1 = P.bar_colour_start[nc];
-      }
+      launch_spmv<T>(st, K, h->A, 1, 0, n, zz, rr, v.res, nullptr, done, h->order_all, zr, r2, m);
     }
-    launch_spmv<T>(st, K, h->A, 1, 0, n, zz, rr, v.res, nullptr, done, h->order_all, zr);
+  }
+  if (part == 1) return;
+  if (m > 0) {
     launch_csr_rect<T>(st, K, h->Et, false, v.res, h->S[0].g<T>(), done);
     vcycle<T>(st, K, h->S, 0, done);
     launch_rect<T>(st, K, h->E, true, h->S[0].x<T>(), zz, done);
@@ -543,10 +591,15 @@ void sor_cycle(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *
 // w = Z Vcyc_Abar(Z^T rr) on stream st (the additive smoother; rows of the top
 // block of w stay zero)
 template <class T>
-void additive_smoother(Handle *h, hipStream_t st, int K, const T *rr, const int *done) {
+void additive_smoother(Handle *h, hipStream_t st, int K, const T *rr, const int *done, bool reuse = false) {
   T *saved = h->Ab[0].g<T>();
   h->Ab[0].g<T>() = const_cast<T *>(rr);
-  vcycle<T>(st, K, h->Ab, 0, done);
+  Reuse R;
+  R.gs = h->reuse_gs;
+  R.gs_start = &h->reuse_gs_start;
+  R.res = h->reuse_res;
+  R.nres = h->n_reuse_res;
+  vcycle<T>(st, K, h->Ab, 0, done, reuse ? &R : nullptr);
   h->Ab[0].g<T>() = saved;
 }
 
@@ -557,23 +610,33 @@ bool has_branch(const Handle *h) {
   return h->opt.pc == VEMG_PC_VL_ADDITIVE || (h->opt.pc == VEMG_PC_VL_ADDITIVE_ONLY && h->P.n_top > 0);
 }
 
-// second branch, on stream st2
+// Whether the additive smoother takes the SOR cycle's forward sweep and
+// residual for a batch of K columns.  The smoother then starts only after
+// that part of the SOR cycle, which costs overlap; it pays when the sweeps
+// it saves are long (wide batches).
+constexpr int kShareMinBatch = 4;
+bool shares(const Handle *h, int K) { return h->reuse && K >= kShareMinBatch; }
+
+// second branch, on stream st2 (when shares(h, K) it follows the first part
+// of the SOR cycle, whose values it takes)
 template <class T>
 void precond_branch(Handle *h, hipStream_t st2, int K, const T *rr, const int *done) {
   if (h->opt.pc == VEMG_PC_VL_ADDITIVE) {
-    additive_smoother<T>(h, st2, K, rr, done);
+    additive_smoother<T>(h, st2, K, rr, done, shares(h, K));
   } else {
     launch_csr_rect<T>(st2, K, h->Et, false, rr, h->S[0].g<T>(), done);
     vcycle<T>(st2, K, h->S, 0, done);
   }
 }
 
-// first branch, on stream st
+// first branch, on stream st.  When shares(h, K) it comes in two parts around
+// the fork of the second branch: part 1 (the SOR cycle's forward sweep and
+// residual, shared with the second branch), then part 2.
 template <class T>
-void precond_main(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *done) {
+void precond_main(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *done, int part = 0) {
   if (h->opt.pc == VEMG_PC_VL_ADDITIVE)
-    sor_cycle<T>(h, st, K, rr, zz, done);
-  else
+    sor_cycle<T>(h, st, K, rr, zz, done, shares(h, K) ? part : 0, shares(h, K) && part == 1);
+  else if (part != 1)
     additive_smoother<T>(h, st, K, rr, done);
 }
 
@@ -598,11 +661,12 @@ void precond(Handle *h, int K, const T *rr, T *zz, double *part, int64_t *np, co
   int64_t n = P.n;
   Work<T> &v = work_of<T>(h);
   if (has_branch(h)) {
+    if (shares(h, K)) precond_main<T>(h, st, K, rr, zz, done, 1);
     HIPCHK(hipEventRecord(h->ev_fork, st));
     HIPCHK(hipStreamWaitEvent(h->work2, h->ev_fork, 0));
     precond_branch<T>(h, h->work2, K, rr, done);
     HIPCHK(hipEventRecord(h->ev_join, h->work2));
-    precond_main<T>(h, st, K, rr, zz, done);
+    precond_main<T>(h, st, K, rr, zz, done, shares(h, K) ? 2 : 0);
     HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
     *np = precond_join<T>(h, st, K, rr, zz, part, done);
     return;
@@ -645,6 +709,20 @@ void precond(Handle *h, int K, const T *rr, T *zz, double *part, int64_t *np, co
   }
 }
 
+// The additive smoother reads the top columns of its x and takes them as
+// zero, so the top block of v64.w and v32.w must be zero.  Vectors are laid
+// out [n][K]: a call with K columns writes the non-top rows at [n_top K,
+// n K), which a later call with more columns reads as part of its top block
+// [0, n_top K).  Every call with K columns calls this first.
+void batch_layout(Handle *h, int K) {
+  const int64_t m = h->P.n_top;
+  if (K > h->w_clean && m > 0) {
+    launch_fill<double>(h->work, h->v64.w, m * K, 0.0, nullptr);
+    launch_fill<float>(h->work, h->v32.w, m * K, 0.0f, nullptr);
+  }
+  h->w_clean = K;
+}
+
 // FP64 CG with the preconditioner applied in FP32 (columns scaled by scale_in)
 int64_t precond_mixed(Handle *h, int K, const double *rr, double *zz, const int *done) {
   hipStream_t st = h->work;
@@ -663,7 +741,7 @@ int64_t precond_mixed(Handle *h, int K, const double *rr, double *zz, const int 
 // Krylov update.  Eagerly they run back to back with an event fork and join;
 // as graphs each segment is captured on its own and launched on its stream,
 // so that the two branches overlap on the device.
-enum Segment { kSegPre = 0, kSegBranch = 1, kSegMain = 2, kSegPost = 3 };
+enum Segment { kSegPre = 0, kSegBranch = 1, kSegMain = 2, kSegPost = 3, kSegMainFront = 4 };
 
 // Reliable update of the mixed-precision solve (FP32 PCG on A d = b / ||b||):
 // the FP32 correction accumulated since the last update is scaled by ||b||,
@@ -706,12 +784,15 @@ void pcg_segment(Handle *h, int K, int kind, int seg) {
       else
         precond_branch<T>(h, h->work2, K, v.r, done);
       break;
-    case kSegMain:
+    case kSegMainFront:
+    case kSegMain: {
+      const int part = !shares(h, K) ? 0 : seg == kSegMainFront ? 1 : 2;
       if (mixed)
-        precond_main<float>(h, st, K, h->v32.tmp, h->v32.z, done);
+        precond_main<float>(h, st, K, h->v32.tmp, h->v32.z, done, part);
       else
-        precond_main<T>(h, st, K, v.r, v.z, done);
+        precond_main<T>(h, st, K, v.r, v.z, done, part);
       break;
+    }
     case kSegPost: {
       int64_t np;
       if constexpr (std::is_same<T, double>::value) {
@@ -741,6 +822,7 @@ void pcg_iteration(Handle *h, int K, int kind) {
   const int *done = &h->scal->all_done;
   if (has_branch(h)) {
     pcg_segment<T>(h, K, kind, kSegPre);
+    if (shares(h, K)) pcg_segment<T>(h, K, kind, kSegMainFront);
     HIPCHK(hipEventRecord(h->ev_fork, st));
     HIPCHK(hipStreamWaitEvent(h->work2, h->ev_fork, 0));
     pcg_segment<T>(h, K, kind, kSegBranch);
@@ -768,7 +850,7 @@ void pcg_iteration(Handle *h, int K, int kind) {
 
 void destroy_graphs(Handle *h) {
   for (auto &kv : h->graphs)
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 5; ++i) {
       if (kv.second.exec[i]) (void)hipGraphExecDestroy(kv.second.exec[i]);
       if (kv.second.graph[i]) (void)hipGraphDestroy(kv.second.graph[i]);
     }
@@ -793,8 +875,8 @@ const IterGraphs *iteration_graphs(Handle *h, int K, int kind) {
   if (!h->allow_capture) return nullptr;
   IterGraphs ig;
   if (has_branch(h)) {
-    ig.parts = 4;
-    for (int seg = 0; seg < 4; ++seg)
+    ig.parts = shares(h, K) ? 5 : 4;
+    for (int seg = 0; seg < ig.parts; ++seg)
       capture(seg == kSegBranch ? h->work2 : h->work, &ig.graph[seg], &ig.exec[seg],
               [&]() { pcg_segment<T>(h, K, kind, seg); });
   } else {
@@ -813,6 +895,7 @@ void run_iteration(Handle *h, int K, int kind) {
     HIPCHK(hipGraphLaunch(ig->exec[0], h->work));
   } else {
     HIPCHK(hipGraphLaunch(ig->exec[kSegPre], h->work));
+    if (ig->parts == 5) HIPCHK(hipGraphLaunch(ig->exec[kSegMainFront], h->work));
     HIPCHK(hipEventRecord(h->ev_fork, h->work));
     HIPCHK(hipStreamWaitEvent(h->work2, h->ev_fork, 0));
     HIPCHK(hipGraphLaunch(ig->exec[kSegBranch], h->work2));
@@ -878,6 +961,7 @@ void rhs_norms(Handle *h, int K, double *bb) {
 // PCG (FP64, or FP64 with FP32 preconditioner) with restarts from the true
 // residual; h->b holds K columns (storage order), result in v64.x.
 void solve_cg(Handle *h, int K, double rtol, int max_iter, ColResult *res) {
+  batch_layout(h, K);
   hipStream_t st = h->work;
   int64_t n = h->P.n;
   Work<double> &v = h->v64;
@@ -981,6 +1065,7 @@ Scal iterate_reliable(Handle *h, int K) {
 // and, if it is not met, restarted from it (at most max_restarts times, while
 // each restart at least halves it).  h->b holds K columns.
 void solve_ir(Handle *h, int K, double rtol, int max_iter, ColResult *res) {
+  batch_layout(h, K);
   hipStream_t st = h->work;
   int64_t n = h->P.n;
   Work<float> &v = h->v32;
@@ -1118,6 +1203,44 @@ void upload(Handle *h) {
   };
   h->order_all = slice_order(0, n);
   h->order_bar = slice_order(m, n);
+  // The SOR cycle and the additive smoother both start with a forward sweep
+  // from zero on the same right-hand side; the smoother holds the top rows at
+  // zero where the SOR cycle has swept them.  A non-top row of colour c gets
+  // the same value in both, bit for bit, unless one of its neighbours of an
+  // earlier colour is a top row or such a row itself ("dirty"); its residual
+  // is the same unless the row, or a neighbour, is dirty or a neighbour is a
+  // top row, or the two zero it differently (the smoother zeroes its last
+  // colour, the SOR cycle the rows of its last launch).
+  if (h->opt.pc == VEMG_PC_VL_ADDITIVE && m > 0) {
+    const Csr &O = P.Aoff;
+    const int ncb = (int)P.bar_colour_start.size() - 1, nct = (int)P.top_colour_start.size() - 1;
+    const bool same_last = std::max(nct, ncb) == ncb;
+    std::vector<uint8_t> dirty(n, 0);
+    std::vector<int32_t> rows, res;
+    h->reuse_gs_start.assign(1, 0);
+    for (int c = 0; c < ncb; ++c) {
+      for (int64_t i = P.bar_colour_start[c]; i < P.bar_colour_start[c + 1]; ++i) {
+        for (int64_t k = O.ptr[i]; k < O.ptr[i + 1]; ++k) {
+          const int64_t j = O.idx[k];
+          if (P.colour[j] < c && (j < m || dirty[j])) {
+            dirty[i] = 1;
+            break;
+          }
+        }
+        if (dirty[i]) rows.push_back((int32_t)i);
+      }
+      h->reuse_gs_start.push_back((int64_t)rows.size());
+    }
+    for (int64_t i = m; i < n; ++i) {
+      bool d = dirty[i] || (!same_last && ncb > 0 && P.colour[i] == ncb - 1);
+      for (int64_t k = O.ptr[i]; k < O.ptr[i + 1] && !d; ++k) d = O.idx[k] < m || dirty[O.idx[k]];
+      if (d) res.push_back((int32_t)i);
+    }
+    h->reuse_gs = h->ar.upload(rows, st);
+    h->reuse_res = h->ar.upload(res, st);
+    h->n_reuse_res = (int64_t)res.size();
+    h->reuse = true;
+  }
   int64_t npmax = (std::max(sell_blocks(0, n), vec_blocks(n)) + 8) * kMaxBatch;
   h->part_pq = h->ar.alloc<double>(npmax);
   h->part_rr = h->ar.alloc<double>(npmax);
@@ -1204,6 +1327,7 @@ int do_solve(Handle *h, int nrhs, const double *b_nat, double *x_nat, double rto
 
 template <class T>
 void apply_op(Handle *h, int op, const T *in, T *out) {
+  batch_layout(h, 1);
   hipStream_t st = h->work;
   const Problem &P = h->P;
   int64_t n = P.n, m = P.n_top;
@@ -1340,6 +1464,7 @@ int do_time(Handle *h, int op, int K, int reps, double *avg_ms, int *launches) {
   if (op == VEMG_OP_GS_COARSE && (h->Ab.size() < 2 || h->Ab[1].coarsest)) return VEMG_ERR_STATE;
   if ((op == VEMG_OP_ET || op == VEMG_OP_E) && (P.n_top == 0 || h->S.empty())) return VEMG_ERR_STATE;
   if (K != 1 && K != 2 && K != 4 && K != 8) return VEMG_ERR_INVALID_ARG;
+  batch_layout(h, K);
   int nc = std::max((int)P.top_colour_start.size() - 1, (int)P.bar_colour_start.size() - 1);
   if (op == VEMG_OP_GS_COARSE) {
     nc = (int)h->Ab[1].pc_start.size() - 1;
@@ -1654,6 +1779,7 @@ SlotStop lane_stop(const Lane &L) {
 // (re)start the slot columns in mask: join (x = 0, r = b) or restart (r = res)
 void lane_start(Lane &L, unsigned mask, bool restart) {
   Handle *h = L.h;
+  batch_layout(h, kMaxBatch);
   hipStream_t st = h->work;
   int64_t n = h->P.n, N = h->P.n_nodes;
   if (!restart)

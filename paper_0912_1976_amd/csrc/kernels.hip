@@ -230,6 +230,38 @@ __device__ __forceinline__ Row<T, C> fine_row(const Sell &A, int64_t s, int t, i
   return out;
 }
 
+// y_r = g_r - (A x)_r by lane q of row r's lanes; the rows of zr are written
+// as zero without reading their entries (their residual is zero in exact
+// arithmetic); with y2, a row r >= y2_from is also stored there.
+template <class T, int K>
+__device__ __forceinline__ void residual_row(const Sell &A, int64_t r, int q, const T *__restrict__ x,
+                                             const T *__restrict__ g, T *y, const ZeroRows &zr, T *y2,
+                                             int64_t y2_from) {
+  constexpr int LPR = row_lanes<T, K>(), C = K / LPR;
+  Row<T, C> out;
+  if ((r >= zr.a0 && r < zr.a1) || (r >= zr.b0 && r < zr.b1)) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) out.v[k] = T(0);
+  } else {
+    const Row<T, C> xr = ldp<T, K, C>(x, r, q);
+    out = fine_row<T, K, C, 1>(A, r >> 6, (int)(r & 63), q, r, x, xr, g);
+  }
+  stp<T, K, C>(y, r, q, out);
+  if (y2 && r >= y2_from) stp<T, K, C>(y2, r, q, out);
+}
+
+// The residual form on the listed rows rows[0 .. nr) only.
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void k_spmv_rows(Sell A, const int32_t *__restrict__ rows, int64_t nr,
+                                                     const T *__restrict__ x, const T *__restrict__ g,
+                                                     T *__restrict__ y, const int *__restrict__ done, ZeroRows zr) {
+  constexpr int LPR = row_lanes<T, K>();
+  if (done && *done) return;
+  const int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / LPR;
+  if (i >= nr) return;
+  residual_row<T, K>(A, rows[i], (int)(threadIdx.x % LPR), x, g, y, zr, (T *)nullptr, 0);
+}
+
 // Blocks of kBlock rows (four slices), row_lanes<T, K>() lanes per row.
 // order (may be null): the i-th slice of the range visited is s_first +
 // order[i], a permutation of the range's slices; the blocks of one XCD take a
@@ -238,7 +270,7 @@ template <class T, int K, int MODE, bool DOT>
 __global__ __launch_bounds__((kBlock * row_lanes<T, K>())) void k_spmv(
     Sell A, int64_t r0, int64_t r1, int64_t s_first, int64_t ns, int64_t nb, const int32_t *__restrict__ order,
     const T *__restrict__ x, const T *__restrict__ g, T *__restrict__ y, double *__restrict__ partial,
-    const int *__restrict__ done, ZeroRows zr) {
+    const int *__restrict__ done, ZeroRows zr, T *__restrict__ y2, int64_t y2_from) {
   constexpr int LPR = row_lanes<T, K>(), C = K / LPR;
   static_assert(!(MODE == 1 && DOT), "the residual form has no block reduction");
   if (done && *done) return;
@@ -252,12 +284,10 @@ __global__ __launch_bounds__((kBlock * row_lanes<T, K>())) void k_spmv(
 #pragma unroll
   for (int k = 0; k < C; ++k) prod[k] = 0.0;
   if (i < ns && r >= r0 && r < r1) {
-    if (MODE == 1 && ((r >= zr.a0 && r < zr.a1) || (r >= zr.b0 && r < zr.b1))) {
-      Row<T, C> zero;
-#pragma unroll
-      for (int k = 0; k < C; ++k) zero.v[k] = T(0);
-      stp<T, K, C>(y, r, q, zero);
-      return;  // MODE 1 has no block reduction, so the lane may leave
+    if constexpr (MODE == 1) {
+      // no block reduction in this form, so the lane may leave
+      residual_row<T, K>(A, r, q, x, g, y, zr, y2, y2_from);
+      return;
     }
     const Row<T, C> xr = ldp<T, K, C>(x, r, q);
     const Row<T, C> out = fine_row<T, K, C, MODE>(A, s, t, q, r, x, xr, g);
@@ -275,6 +305,8 @@ template <class T>
 struct GsDev {
   int64_t r0[2], r1[2], sf[2], nb[2];
   T *x;
+  T *x2;            // null, or a second output for the rows r >= x2_from
+  int64_t x2_from;
   int n;
   int64_t nbt;
 };
@@ -297,26 +329,14 @@ __device__ __forceinline__ Row<T, C> gs_apply(T d0, T d1, const Row<T, C> &xr, c
   return out;
 }
 
-// one slice per block (a colour holds few rows, so small blocks spread them
-// over every CU), row_lanes<T, K>() lanes per row; up to two row ranges (the
-// top and the non-top rows of one colour)
+// One Gauss-Seidel step of row r by lane q of its row_lanes<T, K>() lanes
+// (columns [q C, q C + C)); with x2, a row r >= x2_from is also stored there.
 template <class T, int K, bool ZS>
-__global__ __launch_bounds__((kWave * row_lanes<T, K>())) void k_gs(Sell A, GsDev<T> J, const T *__restrict__ g,
-                                                                   const int *__restrict__ done, ZeroStart z) {
+__device__ __forceinline__ void gs_row(const Sell &A, int64_t r, int q, const T *__restrict__ g, T *x, T *x2,
+                                       int64_t x2_from, const ZeroStart &z) {
   constexpr int LPR = row_lanes<T, K>(), C = K / LPR;
-  if (done && *done) return;
-  int64_t blk = xcd_block(blockIdx.x, J.nbt);
-  int j = 0;
-  while (j + 1 < J.n && blk >= J.nb[j]) {
-    blk -= J.nb[j];
-    ++j;
-  }
-  const int64_t r0 = J.r0[j], r1 = J.r1[j];
-  T *x = J.x;
-  const int t = threadIdx.x / LPR, q = threadIdx.x % LPR;
-  const int64_t s = J.sf[j] + blk;
-  const int64_t r = s * 64 + t;
-  if (r < r0 || r >= r1) return;
+  const int64_t s = r >> 6;
+  const int t = (int)(r & 63);
   Row<T, C> xr;
   if constexpr (ZS) {
 #pragma unroll
@@ -334,7 +354,44 @@ __global__ __launch_bounds__((kWave * row_lanes<T, K>())) void k_gs(Sell A, GsDe
   }
   T acc[C], off;
   sell_row<T, K, C, true, ZS>(A, s, t, q, x, xr, acc, off, z);
-  stp<T, K, C>(x, r, q, gs_apply<T, C>(d0, d1, xr, gr, acc, off));
+  const Row<T, C> out = gs_apply<T, C>(d0, d1, xr, gr, acc, off);
+  stp<T, K, C>(x, r, q, out);
+  if (x2 && r >= x2_from) stp<T, K, C>(x2, r, q, out);
+}
+
+// one slice per block (a colour holds few rows, so small blocks spread them
+// over every CU), row_lanes<T, K>() lanes per row; up to two row ranges (the
+// top and the non-top rows of one colour)
+template <class T, int K, bool ZS>
+__global__ __launch_bounds__((kWave * row_lanes<T, K>())) void k_gs(Sell A, GsDev<T> J, const T *__restrict__ g,
+                                                                   const int *__restrict__ done, ZeroStart z) {
+  constexpr int LPR = row_lanes<T, K>(), C = K / LPR;
+  if (done && *done) return;
+  int64_t blk = xcd_block(blockIdx.x, J.nbt);
+  int j = 0;
+  while (j + 1 < J.n && blk >= J.nb[j]) {
+    blk -= J.nb[j];
+    ++j;
+  }
+  const int64_t r0 = J.r0[j], r1 = J.r1[j];
+  const int t = threadIdx.x / LPR, q = threadIdx.x % LPR;
+  const int64_t s = J.sf[j] + blk;
+  const int64_t r = s * 64 + t;
+  if (r < r0 || r >= r1) return;
+  gs_row<T, K, ZS>(A, r, q, g, J.x, J.x2, J.x2_from, z);
+}
+
+// The listed rows rows[0 .. nr) (rows that share no entries), each by its
+// row_lanes<T, K>() lanes, with the arithmetic of k_gs.
+template <class T, int K, bool ZS>
+__global__ __launch_bounds__(kBlock) void k_gs_rows(Sell A, const int32_t *__restrict__ rows, int64_t nr,
+                                                   const T *__restrict__ g, T *x, const int *__restrict__ done,
+                                                   ZeroStart z) {
+  constexpr int LPR = row_lanes<T, K>();
+  if (done && *done) return;
+  const int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / LPR;
+  if (i >= nr) return;
+  gs_row<T, K, ZS>(A, rows[i], (int)(threadIdx.x % LPR), g, x, (T *)nullptr, 0, z);
 }
 
 template <class T, int K, bool ACC>
@@ -1237,7 +1294,7 @@ void launch_slot_copy(hipStream_t stm, unsigned mask, const double *z, double *p
 
 template <class T>
 void launch_spmv(hipStream_t stm, int K, const Sell &A, int mode, int64_t r0, int64_t r1, const T *x, const T *g,
-                 T *y, double *partial, const int *done, const int32_t *order, ZeroRows zr) {
+                 T *y, double *partial, const int *done, const int32_t *order, ZeroRows zr, T *y2, int64_t y2_from) {
   int64_t nb = sell_blocks(r0, r1);
   if (!nb) return;
   int64_t sf = r0 / kWave, ns = (r1 + kWave - 1) / kWave - sf;
@@ -1246,13 +1303,13 @@ void launch_spmv(hipStream_t stm, int K, const Sell &A, int mode, int64_t r0, in
     if (mode == 0) {
       if (partial)
         hipLaunchKernelGGL((k_spmv<T, KK, 0, true>), grid(nb), blk, 0, stm, A, r0, r1, sf, ns, nb, order, x, g, y,
-                           partial, done, zr);
+                           partial, done, zr, y2, y2_from);
       else
         hipLaunchKernelGGL((k_spmv<T, KK, 0, false>), grid(nb), blk, 0, stm, A, r0, r1, sf, ns, nb, order, x, g, y,
-                           partial, done, zr);
+                           partial, done, zr, y2, y2_from);
     } else {
       hipLaunchKernelGGL((k_spmv<T, KK, 1, false>), grid(nb), blk, 0, stm, A, r0, r1, sf, ns, nb, order, x, g, y,
-                         partial, done, zr);
+                         partial, done, zr, y2, y2_from);
     }
   })
 }
@@ -1262,10 +1319,35 @@ static inline int64_t slices(int64_t r0, int64_t r1) {
 }
 
 template <class T>
+void launch_spmv_rows(hipStream_t stm, int K, const Sell &A, const int32_t *rows, int64_t nr, const T *x, const T *g,
+                      T *y, const int *done, ZeroRows zr) {
+  if (nr <= 0) return;
+  VEMG_K_SWITCH(K, {
+    const int64_t nb = (nr * row_lanes<T, KK>() + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL((k_spmv_rows<T, KK>), grid(nb), dim3(kBlock), 0, stm, A, rows, nr, x, g, y, done, zr);
+  })
+}
+
+template <class T>
+void launch_gs_rows(hipStream_t stm, int K, const Sell &A, const int32_t *rows, int64_t nr, const T *g, T *x,
+                    const int *done, ZeroStart zs) {
+  if (nr <= 0) return;
+  VEMG_K_SWITCH(K, {
+    const int64_t nb = (nr * row_lanes<T, KK>() + kBlock - 1) / kBlock;
+    if (zs.on)
+      hipLaunchKernelGGL((k_gs_rows<T, KK, true>), grid(nb), dim3(kBlock), 0, stm, A, rows, nr, g, x, done, zs);
+    else
+      hipLaunchKernelGGL((k_gs_rows<T, KK, false>), grid(nb), dim3(kBlock), 0, stm, A, rows, nr, g, x, done, zs);
+  })
+}
+
+template <class T>
 void launch_gs(hipStream_t stm, int K, const Sell &A, int64_t a0, int64_t a1, int64_t b0, int64_t b1, const T *g,
-               T *x, const int *done, ZeroStart zs) {
+               T *x, const int *done, ZeroStart zs, T *x2, int64_t x2_from) {
   GsDev<T> J{};
   J.x = x;
+  J.x2 = x2;
+  J.x2_from = x2_from;
   const int64_t ra[2] = {a0, b0}, rb[2] = {a1, b1};
   for (int i = 0; i < 2; ++i) {
     const int64_t nb = slices(ra[i], rb[i]);
@@ -1467,9 +1549,13 @@ void launch_pcg_resume(hipStream_t stm, int, Scal *s, unsigned keep) {
 
 #define VEMG_INSTANTIATE(T)                                                                                          \
   template void launch_spmv<T>(hipStream_t, int, const Sell &, int, int64_t, int64_t, const T *, const T *, T *,      \
-                               double *, const int *, const int32_t *, ZeroRows);                                    \
+                               double *, const int *, const int32_t *, ZeroRows, T *, int64_t);                      \
+  template void launch_spmv_rows<T>(hipStream_t, int, const Sell &, const int32_t *, int64_t, const T *, const T *,   \
+                                    T *, const int *, ZeroRows);                                                     \
   template void launch_gs<T>(hipStream_t, int, const Sell &, int64_t, int64_t, int64_t, int64_t, const T *, T *,       \
-                             const int *, ZeroStart);                                                                \
+                             const int *, ZeroStart, T *, int64_t);                                                  \
+  template void launch_gs_rows<T>(hipStream_t, int, const Sell &, const int32_t *, int64_t, const T *, T *,           \
+                                  const int *, ZeroStart);                                                           \
   template void launch_rect<T>(hipStream_t, int, const Sell &, bool, const T *, T *, const int *);                    \
   template void launch_prolong_sum<T>(hipStream_t, int, const Sell &, int64_t, const T *, const T *, const T *, T *,   \
                                       double *, const int *);                                                        \

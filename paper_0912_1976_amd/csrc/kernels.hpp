@@ -94,9 +94,17 @@ struct ZeroRows {
 // (optional): the range's slices in visit order (offsets from slice r0 / 64),
 // so that the blocks of one XCD take one spatial region of every colour.  In
 // mode 1 the rows of zr get y = 0 without reading their entries.
+// Mode 1 only: with y2, the rows r >= y2_from are also stored to y2 (a copy
+// of the result for a second consumer).
 template <class T>
 void launch_spmv(hipStream_t st, int K, const Sell &A, int mode, int64_t r0, int64_t r1, const T *x, const T *g,
-                 T *y, double *partial, const int *done, const int32_t *order = nullptr, ZeroRows zr = ZeroRows());
+                 T *y, double *partial, const int *done, const int32_t *order = nullptr, ZeroRows zr = ZeroRows(),
+                 T *y2 = nullptr, int64_t y2_from = 0);
+// y = g - A x (mode 1 of launch_spmv, the same arithmetic row by row) on the
+// listed rows rows[0 .. nr) only, rows of zr written as zero.
+template <class T>
+void launch_spmv_rows(hipStream_t st, int K, const Sell &A, const int32_t *rows, int64_t nr, const T *x, const T *g,
+                      T *y, const int *done, ZeroRows zr);
 // One multicolour Gauss-Seidel step on the rows [a0,a1) and [b0,b1) (rows of
 // one colour): x_i += (g_i - (A x)_i) / a_ii.
 // Zero start (the first sweep from x = 0): of the top block (j < n_top) only
@@ -107,9 +115,15 @@ struct ZeroStart {
   bool on = false;
   int64_t n_top = 0, top_lim = 0, bar_lim = 0;
 };
+// With x2, the updated rows r >= x2_from are also stored to x2.
 template <class T>
 void launch_gs(hipStream_t st, int K, const Sell &A, int64_t a0, int64_t a1, int64_t b0, int64_t b1, const T *g,
-               T *x, const int *done, ZeroStart zs = ZeroStart());
+               T *x, const int *done, ZeroStart zs = ZeroStart(), T *x2 = nullptr, int64_t x2_from = 0);
+// The Gauss-Seidel step of launch_gs (the same arithmetic row by row) on the
+// listed rows rows[0 .. nr) only; the rows must share no entries.
+template <class T>
+void launch_gs_rows(hipStream_t st, int K, const Sell &A, const int32_t *rows, int64_t nr, const T *g, T *x,
+                    const int *done, ZeroStart zs);
 // y = E x (accumulate: y += E x) for a rectangular SELL matrix, rows [0, nrows).
 template <class T>
 void launch_rect(hipStream_t st, int K, const Sell &E, bool accumulate, const T *x, T *y, const int *done);

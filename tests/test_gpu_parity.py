@@ -271,6 +271,23 @@ def test_deterministic_and_batched_equals_single(nrhs, precision):
         assert torch.equal(xb[k], x1)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed_pc"])
+def test_batch_after_narrower_solves_equals_fresh_handle(precision):
+    # vectors are laid out [n][K], so a narrower solve leaves its non-top rows
+    # where a wider batch's top block lies; the additive smoother takes that
+    # block as zero, and a batch must not depend on what the handle solved
+    # before
+    m, s, o = _build(RAGGED, "N", precision=precision)
+    B = np.stack([s.rhs(fourier_field(m.xyz, RAGGED["H"], 300 + k)) for k in range(8)])
+    f = lib.Solver(m.xyz, m.tets, m.top, device=0, coarse_max=64, precision=precision)
+    xf, itf, _, _ = f.solve(B, rtol=1e-9)
+    for K in (1, 2, 4):
+        s.solve(B[:K] if K > 1 else B[0], rtol=1e-9)
+        xs, its, _, _ = s.solve(B, rtol=1e-9)
+        assert list(its) == list(itf) and torch.equal(xs, xf), K
+    f.close()
+
+
 def test_edge_cases():
     m, s, o = _build(RAGGED, "N", coarse_max=64)
     z = np.zeros(m.n)
