@@ -149,11 +149,19 @@ def vcycle_bytes(rows, off, pnnz, K, elt, val, fine_rows=None, fine_nnz=None):
     return total
 
 
+# The library's additive smoother takes the SOR cycle's fine forward sweep and
+# residual for batches of this many columns or more (the rows where the two
+# differ, a few per cent, are swept again; their bytes are not counted).
+SHARE_MIN_BATCH = 4
+
+
 def iteration_bytes(info, K=1, pc="vl_as", precision="fp64"):
     """Algorithmic bytes of one PCG iteration (preconditioner included) for a
     batch of K columns, from the built arrays' sizes.  Mixed precision: the
     preconditioner in FP32 (values and vectors), the Krylov part in FP64, plus
-    the demotion of r and promotion of z."""
+    the demotion of r and promotion of z.  With the shared forward sweep the
+    additive smoother's fine sweep and residual are replaced by the SOR
+    cycle's stores of x and r into the smoother's vectors."""
     n = info["n"]
     pe, pv = (4, 4) if precision != "fp64" else (8, 8)
     krylov = spmv_bytes(info, K) + 6 * n * 8 * K + 3 * n * 8 * K   # q = A p with p.q; x, r update; p = z + beta p
@@ -163,6 +171,10 @@ def iteration_bytes(info, K=1, pc="vl_as", precision="fp64"):
     nbar = info["n"] - info["n_top"]
     a_cycle = vcycle_bytes(info["abar_rows"], info["abar_nnz"], info["p_nnz_abar"], K, pe, pv,
                            fine_rows=nbar, fine_nnz=info["abar_nnz"][0])
+    if pc == "vl_as" and info["n_top"] and K >= SHARE_MIN_BATCH:
+        a_cycle -= (gs_sweep_bytes(None, K, pe, pv, rows=nbar, nnz=info["abar_nnz"][0])
+                    + spmv_bytes(None, K, pe, pv, residual=True, rows=nbar, nnz=info["abar_nnz"][0]))
+        a_cycle += 2 * nbar * pe * K
     join = 4 * n * pe * K + n * 8 * K  # z += w over the non-top rows with r.z; (mixed) r read for the dot
     mixed = (n * 8 * K + n * 4 * K) * 2 if precision != "fp64" else 0
     if pc == "vl_sor":
@@ -207,8 +219,11 @@ def kernel_rates(s, info, vemg, K=1, reps=20, precision="fp64"):
 #           A_bar level 1), plus the CG product
 #   vl_sor: the SOR cycle alone plus the CG product
 #   vl_add: the A_bar V-cycle plus the CG product
+# (vl_as with SHARE_MIN_BATCH columns or more: the A_bar V-cycle's forward
+# sweep and residual come from the SOR cycle, so 3 full sweeps and 2 SpMVs)
 PER_ITERATION = {"vl_as": (4, 3, 2), "vl_sor": (2, 2, 0), "vl_add": (2, 2, 2), "jacobi": (0, 1, 0),
                  "none": (0, 1, 0)}
+PER_ITERATION_SHARED = {"vl_as": (3, 2, 2)}
 KERNEL_NAMES = {
     "gs": "k_gs<double, {K}, false> (fine multicolour SOR, one colour per launch)",
     "spmv": "k_spmv<double, {K}, 0, true> (fine difference-form SpMV fused with p.q)",
@@ -222,7 +237,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 def dominant_kernel(rates, pc, K):
     """The hot kernel with the largest share of one iteration's time: its
     algorithmic bytes and average duration per launch (the roofline entry)."""
-    n_gs, n_spmv, n_cgs = PER_ITERATION[pc]
+    n_gs, n_spmv, n_cgs = (PER_ITERATION_SHARED[pc] if pc in PER_ITERATION_SHARED and K >= SHARE_MIN_BATCH
+                           else PER_ITERATION[pc])
     share = {"gs": n_gs * rates["fine_sweep"]["ms"], "spmv": n_spmv * rates["spmv"]["ms"],
              "cgs": n_cgs * rates.get("coarse_sweep", {"ms": 0.0})["ms"]}
     key = max(share, key=share.get)
