@@ -615,7 +615,9 @@ bool has_branch(const Handle *h) {
 // that part of the SOR cycle, which costs overlap; it pays when the sweeps
 // it saves are long (wide batches).
 constexpr int kShareMinBatch = 4;
-bool shares(const Handle *h, int K) { return h->reuse && K >= kShareMinBatch; }
+bool shares(const Handle *h, int K) {
+  return h->reuse && h->opt.pc == VEMG_PC_VL_ADDITIVE && K >= kShareMinBatch;
+}
 
 // second branch, on stream st2 (when shares(h, K) it follows the first part
 // of the SOR cycle, whose values it takes)
@@ -1211,7 +1213,7 @@ void upload(Handle *h) {
   // is the same unless the row, or a neighbour, is dirty or a neighbour is a
   // top row, or the two zero it differently (the smoother zeroes its last
   // colour, the SOR cycle the rows of its last launch).
-  if (h->opt.pc == VEMG_PC_VL_ADDITIVE && m > 0) {
+  if (m > 0) {  // for every preconditioner: a handle may be switched to VL + additive smoother
     const Csr &O = P.Aoff;
     const int ncb = (int)P.bar_colour_start.size() - 1, nct = (int)P.top_colour_start.size() - 1;
     const bool same_last = std::max(nct, ncb) == ncb;

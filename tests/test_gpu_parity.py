@@ -271,6 +271,21 @@ def test_deterministic_and_batched_equals_single(nrhs, precision):
         assert torch.equal(xb[k], x1)
 
 
+def test_switching_preconditioner_with_a_batch_equals_fresh_handles():
+    # batches of four or more columns let the additive smoother take the SOR
+    # cycle's forward sweep; a handle created for another preconditioner and
+    # switched reproduces fresh handles bit for bit
+    m, s, o = _build(RAGGED, "N", pc="vl_sor")
+    B = np.stack([s.rhs(fourier_field(m.xyz, RAGGED["H"], 400 + k)) for k in range(4)])
+    for pc in ("vl_as", "vl_add", "vl_sor", "vl_as"):
+        s.set_preconditioner(pc)
+        x1, it1, _, _ = s.solve(B, rtol=1e-9)
+        f = lib.Solver(m.xyz, m.tets, m.top, pc=pc, device=0, coarse_max=64)
+        x2, it2, _, _ = f.solve(B, rtol=1e-9)
+        assert list(it1) == list(it2) and torch.equal(x1, x2), pc
+        f.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed_pc"])
 def test_batch_after_narrower_solves_equals_fresh_handle(precision):
     # vectors are laid out [n][K], so a narrower solve leaves its non-top rows
