@@ -84,15 +84,20 @@ struct Arena {
 // (difference form: the deficit) else a_ii.  FP32 copy: a_ij / a_ii with
 // s32 = a_ii and dh32 = d / a_ii (square), or float(a_ij) (rectangular).
 Sell pack_sell(Arena &ar, hipStream_t st, const Csr &A, bool square, const std::vector<double> *d,
-               const std::vector<double> *diag, int64_t *stored = nullptr) {
-  int64_t n = A.nrows, ns = (n + kWave - 1) / kWave;
+               const std::vector<double> *diag, int64_t *stored = nullptr,
+               const std::vector<int32_t> *subset = nullptr) {
+  // subset: pack only these rows of A, row i of the result being A's row
+  // (*subset)[i] with its entries (columns unchanged) in the same order
+  int64_t n = subset ? (int64_t)subset->size() : A.nrows, ns = (n + kWave - 1) / kWave;
+  auto row_of = [&](int64_t i) -> int64_t { return subset ? (int64_t)(*subset)[i] : i; };
   std::vector<int64_t> sptr(ns + 1, 0);
   std::vector<int64_t> len(n);
-  for (int64_t r = 0; r < n; ++r) {
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t r = row_of(i);
     int64_t c = 0;
     for (int64_t k = A.ptr[r]; k < A.ptr[r + 1]; ++k)
       if (!(square && A.idx[k] == r)) ++c;
-    len[r] = c;
+    len[i] = c;
   }
   for (int64_t s = 0; s < ns; ++s) {
     int64_t L = 0;
@@ -103,30 +108,31 @@ Sell pack_sell(Arena &ar, hipStream_t st, const Csr &A, bool square, const std::
   std::vector<double> val(sptr[ns], 0.0);
   std::vector<float> val32(sptr[ns], 0.0f);
   std::vector<double> dv(square ? n : 0, 0.0), ad(square ? n : 0, 0.0);
-  for (int64_t r = 0; square && r < n; ++r) {
-    if (diag) ad[r] = (*diag)[r];
+  for (int64_t i = 0; square && i < n; ++i) {
+    const int64_t r = row_of(i);
+    if (diag) ad[i] = (*diag)[r];
     for (int64_t e = A.ptr[r]; e < A.ptr[r + 1]; ++e)
-      if (A.idx[e] == r) ad[r] = A.val[e];
-    dv[r] = d ? (*d)[r] : ad[r];
+      if (A.idx[e] == r) ad[i] = A.val[e];
+    dv[i] = d ? (*d)[r] : ad[i];
   }
   for (int64_t s = 0; s < ns; ++s) {
     int64_t L = (sptr[s + 1] - sptr[s]) / kWave;
     for (int t = 0; t < kWave; ++t) {
-      int64_t r = s * kWave + t;
+      const int64_t i = s * kWave + t, r = i < n ? row_of(i) : -1;
       int64_t k = 0;
-      if (r < n) {
+      if (i < n) {
         for (int64_t e = A.ptr[r]; e < A.ptr[r + 1]; ++e) {
           if (square && A.idx[e] == r) continue;
           int64_t pos = sptr[s] + k * kWave + t;
           col[pos] = A.idx[e];
           val[pos] = A.val[e];
-          val32[pos] = square ? (float)(A.val[e] / ad[r]) : (float)A.val[e];
+          val32[pos] = square ? (float)(A.val[e] / ad[i]) : (float)A.val[e];
           ++k;
         }
       }
       for (; k < L; ++k) {
         int64_t pos = sptr[s] + k * kWave + t;
-        col[pos] = (square && r < n) ? (int32_t)r : 0;
+        col[pos] = (square && i < n) ? (int32_t)r : 0;
         val[pos] = 0.0;
         val32[pos] = 0.0f;
       }
@@ -298,6 +304,10 @@ struct vemg_solver_s {
   // differ, per colour for the sweep (reuse_gs[reuse_gs_start[c] ..
   // reuse_gs_start[c+1]), and for the residual (reuse_res, n_reuse_res)
   bool reuse = false;
+  // the rows of reuse_gs of each colour, and those of reuse_res, packed as
+  // SELL matrices of their own (entries read coalesced)
+  std::vector<vemg::Sell> reuse_gs_sell;
+  vemg::Sell reuse_res_sell;
   // the top block of the additive smoother's x (rows [0, n_top) of v64.w and
   // v32.w) is zero in the layout of every batch width up to w_clean
   int w_clean = vemg::kMaxBatch;
@@ -449,8 +459,10 @@ void build_levels(Handle *h, std::vector<Level> &H, std::vector<DLevel> &D, int 
 struct Reuse {
   const int32_t *gs = nullptr;           // dirty rows, colour by colour
   const std::vector<int64_t> *gs_start = nullptr;
+  const std::vector<Sell> *gs_sell = nullptr;  // those rows of each colour, packed
   const int32_t *res = nullptr;          // rows whose residual is recomputed
   int64_t nres = 0;
+  const Sell *res_sell = nullptr;        // those rows, packed
 };
 
 template <class T>
@@ -506,9 +518,9 @@ void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *
       zs.top_lim = 0;
       zs.bar_lim = L.cstart[c];
       const int64_t a = (*reuse->gs_start)[c], b = (*reuse->gs_start)[c + 1];
-      launch_gs_rows<T>(st, K, L.As, reuse->gs + a, b - a, g, x, done, zs);
+      launch_gs_rows<T>(st, K, (*reuse->gs_sell)[c], reuse->gs + a, b - a, g, x, done, zs);
     }
-    launch_spmv_rows<T>(st, K, L.As, reuse->res, reuse->nres, x, g, r, done, zr);
+    launch_spmv_rows<T>(st, K, *reuse->res_sell, reuse->res, reuse->nres, x, g, r, done, zr);
   } else {
     for (int c = 0; c < nc; ++c) gs(c, true);
   }
@@ -597,8 +609,10 @@ void additive_smoother(Handle *h, hipStream_t st, int K, const T *rr, const int 
   Reuse R;
   R.gs = h->reuse_gs;
   R.gs_start = &h->reuse_gs_start;
+  R.gs_sell = &h->reuse_gs_sell;
   R.res = h->reuse_res;
   R.nres = h->n_reuse_res;
+  R.res_sell = &h->reuse_res_sell;
   vcycle<T>(st, K, h->Ab, 0, done, reuse ? &R : nullptr);
   h->Ab[0].g<T>() = saved;
 }
@@ -1220,7 +1234,9 @@ void upload(Handle *h) {
     std::vector<uint8_t> dirty(n, 0);
     std::vector<int32_t> rows, res;
     h->reuse_gs_start.assign(1, 0);
+    h->reuse_gs_sell.clear();
     for (int c = 0; c < ncb; ++c) {
+      std::vector<int32_t> rc;
       for (int64_t i = P.bar_colour_start[c]; i < P.bar_colour_start[c + 1]; ++i) {
         for (int64_t k = O.ptr[i]; k < O.ptr[i + 1]; ++k) {
           const int64_t j = O.idx[k];
@@ -1229,9 +1245,11 @@ void upload(Handle *h) {
             break;
           }
         }
-        if (dirty[i]) rows.push_back((int32_t)i);
+        if (dirty[i]) rc.push_back((int32_t)i);
       }
+      rows.insert(rows.end(), rc.begin(), rc.end());
       h->reuse_gs_start.push_back((int64_t)rows.size());
+      h->reuse_gs_sell.push_back(pack_sell(h->ar, st, P.Aoff, true, &P.d, &P.diag, nullptr, &rc));
     }
     for (int64_t i = m; i < n; ++i) {
       bool d = dirty[i] || (!same_last && ncb > 0 && P.colour[i] == ncb - 1);
@@ -1240,6 +1258,7 @@ void upload(Handle *h) {
     }
     h->reuse_gs = h->ar.upload(rows, st);
     h->reuse_res = h->ar.upload(res, st);
+    h->reuse_res_sell = pack_sell(h->ar, st, P.Aoff, true, &P.d, &P.diag, nullptr, &res);
     h->n_reuse_res = (int64_t)res.size();
     h->reuse = true;
   }

@@ -200,18 +200,20 @@ __device__ __forceinline__ void block_sum_rows(const double (&v)[K / LPR], doubl
 // ------------------------------------------------------------- fine matrix
 // (A x)_r in difference form (MODE 0), or g_r - (A x)_r (MODE 1), columns
 // [q C, q C + C); the row's own operands are loaded before its entries
+// (mi: the row's index in A, r: its index in the vectors; equal unless A
+// holds a subset of the rows)
 template <class T, int K, int C, int MODE>
-__device__ __forceinline__ Row<T, C> fine_row(const Sell &A, int64_t s, int t, int q, int64_t r,
+__device__ __forceinline__ Row<T, C> fine_row(const Sell &A, int64_t s, int t, int q, int64_t mi, int64_t r,
                                               const T *__restrict__ x, const Row<T, C> &xr,
                                               const T *__restrict__ g) {
   Row<T, C> gr;
   if (MODE == 1) gr = ldp<T, K, C>(g, r, q);
   T d0, d1 = T(0);
   if constexpr (std::is_same<T, double>::value) {
-    d0 = A.d64[r];
+    d0 = A.d64[mi];
   } else {
-    d0 = A.s32[r];
-    d1 = A.dh32[r];
+    d0 = A.s32[mi];
+    d1 = A.dh32[mi];
   }
   T acc[C], off;
   sell_row<T, K, C, true>(A, s, t, q, x, xr, acc, off);
@@ -234,7 +236,7 @@ __device__ __forceinline__ Row<T, C> fine_row(const Sell &A, int64_t s, int t, i
 // as zero without reading their entries (their residual is zero in exact
 // arithmetic); with y2, a row r >= y2_from is also stored there.
 template <class T, int K>
-__device__ __forceinline__ void residual_row(const Sell &A, int64_t r, int q, const T *__restrict__ x,
+__device__ __forceinline__ void residual_row(const Sell &A, int64_t mi, int64_t r, int q, const T *__restrict__ x,
                                              const T *__restrict__ g, T *y, const ZeroRows &zr, T *y2,
                                              int64_t y2_from) {
   constexpr int LPR = row_lanes<T, K>(), C = K / LPR;
@@ -244,22 +246,24 @@ __device__ __forceinline__ void residual_row(const Sell &A, int64_t r, int q, co
     for (int k = 0; k < C; ++k) out.v[k] = T(0);
   } else {
     const Row<T, C> xr = ldp<T, K, C>(x, r, q);
-    out = fine_row<T, K, C, 1>(A, r >> 6, (int)(r & 63), q, r, x, xr, g);
+    out = fine_row<T, K, C, 1>(A, mi >> 6, (int)(mi & 63), q, mi, r, x, xr, g);
   }
   stp<T, K, C>(y, r, q, out);
   if (y2 && r >= y2_from) stp<T, K, C>(y2, r, q, out);
 }
 
-// The residual form on the listed rows rows[0 .. nr) only.
+// The residual form on the listed rows rows[0 .. nr) only: As holds those
+// rows (row i of As is row rows[i] of the matrix, its entries in the same
+// order), so that its entries are read coalesced.
 template <class T, int K>
-__global__ __launch_bounds__(kBlock) void k_spmv_rows(Sell A, const int32_t *__restrict__ rows, int64_t nr,
+__global__ __launch_bounds__(kBlock) void k_spmv_rows(Sell As, const int32_t *__restrict__ rows, int64_t nr,
                                                      const T *__restrict__ x, const T *__restrict__ g,
                                                      T *__restrict__ y, const int *__restrict__ done, ZeroRows zr) {
   constexpr int LPR = row_lanes<T, K>();
   if (done && *done) return;
   const int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / LPR;
   if (i >= nr) return;
-  residual_row<T, K>(A, rows[i], (int)(threadIdx.x % LPR), x, g, y, zr, (T *)nullptr, 0);
+  residual_row<T, K>(As, i, rows[i], (int)(threadIdx.x % LPR), x, g, y, zr, (T *)nullptr, 0);
 }
 
 // Blocks of kBlock rows (four slices), row_lanes<T, K>() lanes per row.
@@ -286,11 +290,11 @@ __global__ __launch_bounds__((kBlock * row_lanes<T, K>())) void k_spmv(
   if (i < ns && r >= r0 && r < r1) {
     if constexpr (MODE == 1) {
       // no block reduction in this form, so the lane may leave
-      residual_row<T, K>(A, r, q, x, g, y, zr, y2, y2_from);
+      residual_row<T, K>(A, r, r, q, x, g, y, zr, y2, y2_from);
       return;
     }
     const Row<T, C> xr = ldp<T, K, C>(x, r, q);
-    const Row<T, C> out = fine_row<T, K, C, MODE>(A, s, t, q, r, x, xr, g);
+    const Row<T, C> out = fine_row<T, K, C, MODE>(A, s, t, q, r, r, x, xr, g);
     stp<T, K, C>(y, r, q, out);
     if (DOT) {
 #pragma unroll
@@ -331,12 +335,13 @@ __device__ __forceinline__ Row<T, C> gs_apply(T d0, T d1, const Row<T, C> &xr, c
 
 // One Gauss-Seidel step of row r by lane q of its row_lanes<T, K>() lanes
 // (columns [q C, q C + C)); with x2, a row r >= x2_from is also stored there.
+// (mi: the row's index in A, r: its index in the vectors)
 template <class T, int K, bool ZS>
-__device__ __forceinline__ void gs_row(const Sell &A, int64_t r, int q, const T *__restrict__ g, T *x, T *x2,
-                                       int64_t x2_from, const ZeroStart &z) {
+__device__ __forceinline__ void gs_row(const Sell &A, int64_t mi, int64_t r, int q, const T *__restrict__ g, T *x,
+                                       T *x2, int64_t x2_from, const ZeroStart &z) {
   constexpr int LPR = row_lanes<T, K>(), C = K / LPR;
-  const int64_t s = r >> 6;
-  const int t = (int)(r & 63);
+  const int64_t s = mi >> 6;
+  const int t = (int)(mi & 63);
   Row<T, C> xr;
   if constexpr (ZS) {
 #pragma unroll
@@ -347,10 +352,10 @@ __device__ __forceinline__ void gs_row(const Sell &A, int64_t r, int q, const T 
   const Row<T, C> gr = ldp<T, K, C>(g, r, q);
   T d0, d1 = T(0);
   if constexpr (std::is_same<T, double>::value) {
-    d0 = A.d64[r];
+    d0 = A.d64[mi];
   } else {
-    d0 = A.s32[r];
-    d1 = A.dh32[r];
+    d0 = A.s32[mi];
+    d1 = A.dh32[mi];
   }
   T acc[C], off;
   sell_row<T, K, C, true, ZS>(A, s, t, q, x, xr, acc, off, z);
@@ -378,20 +383,21 @@ __global__ __launch_bounds__((kWave * row_lanes<T, K>())) void k_gs(Sell A, GsDe
   const int64_t s = J.sf[j] + blk;
   const int64_t r = s * 64 + t;
   if (r < r0 || r >= r1) return;
-  gs_row<T, K, ZS>(A, r, q, g, J.x, J.x2, J.x2_from, z);
+  gs_row<T, K, ZS>(A, r, r, q, g, J.x, J.x2, J.x2_from, z);
 }
 
 // The listed rows rows[0 .. nr) (rows that share no entries), each by its
-// row_lanes<T, K>() lanes, with the arithmetic of k_gs.
+// row_lanes<T, K>() lanes, with the arithmetic of k_gs; As holds those rows
+// (row i of As is row rows[i] of the matrix, its entries in the same order).
 template <class T, int K, bool ZS>
-__global__ __launch_bounds__(kBlock) void k_gs_rows(Sell A, const int32_t *__restrict__ rows, int64_t nr,
+__global__ __launch_bounds__(kBlock) void k_gs_rows(Sell As, const int32_t *__restrict__ rows, int64_t nr,
                                                    const T *__restrict__ g, T *x, const int *__restrict__ done,
                                                    ZeroStart z) {
   constexpr int LPR = row_lanes<T, K>();
   if (done && *done) return;
   const int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / LPR;
   if (i >= nr) return;
-  gs_row<T, K, ZS>(A, rows[i], (int)(threadIdx.x % LPR), g, x, (T *)nullptr, 0, z);
+  gs_row<T, K, ZS>(As, i, rows[i], (int)(threadIdx.x % LPR), g, x, (T *)nullptr, 0, z);
 }
 
 template <class T, int K, bool ACC>

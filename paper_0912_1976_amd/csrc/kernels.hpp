@@ -101,7 +101,9 @@ void launch_spmv(hipStream_t st, int K, const Sell &A, int mode, int64_t r0, int
                  T *y, double *partial, const int *done, const int32_t *order = nullptr, ZeroRows zr = ZeroRows(),
                  T *y2 = nullptr, int64_t y2_from = 0);
 // y = g - A x (mode 1 of launch_spmv, the same arithmetic row by row) on the
-// listed rows rows[0 .. nr) only, rows of zr written as zero.
+// listed rows rows[0 .. nr) only, rows of zr written as zero.  A holds
+// exactly those rows: its row i is the matrix's row rows[i], with the same
+// entries in the same order.
 template <class T>
 void launch_spmv_rows(hipStream_t st, int K, const Sell &A, const int32_t *rows, int64_t nr, const T *x, const T *g,
                       T *y, const int *done, ZeroRows zr);
@@ -120,7 +122,8 @@ template <class T>
 void launch_gs(hipStream_t st, int K, const Sell &A, int64_t a0, int64_t a1, int64_t b0, int64_t b1, const T *g,
                T *x, const int *done, ZeroStart zs = ZeroStart(), T *x2 = nullptr, int64_t x2_from = 0);
 // The Gauss-Seidel step of launch_gs (the same arithmetic row by row) on the
-// listed rows rows[0 .. nr) only; the rows must share no entries.
+// listed rows rows[0 .. nr) only; the rows must share no entries.  A holds
+// exactly those rows, as for launch_spmv_rows.
 template <class T>
 void launch_gs_rows(hipStream_t st, int K, const Sell &A, const int32_t *rows, int64_t nr, const T *g, T *x,
                     const int *done, ZeroStart zs);
