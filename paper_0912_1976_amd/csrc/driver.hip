@@ -268,8 +268,8 @@ enum GraphKind { kGraphFP64 = 0, kGraphFP32 = 1, kGraphMixedPC = 2, kGraphFP32Re
 
 // the captured graphs of one PCG iteration: a single graph, or four segments
 struct IterGraphs {
-  hipGraph_t graph[5] = {};
-  hipGraphExec_t exec[5] = {};
+  hipGraph_t graph[7] = {};
+  hipGraphExec_t exec[7] = {};
   int parts = 0;
 };
 
@@ -282,7 +282,8 @@ struct vemg_solver_s {
   hipStream_t user = nullptr, work = nullptr, work2 = nullptr;  // work2: parallel preconditioner branch
   bool own_streams = true;  // false: work and work2 belong to a server's stream pool
   size_t footprint = 0;     // device bytes of the uploaded setup (counted before the upload)
-  hipEvent_t ev = nullptr, ev_fork = nullptr, ev_join = nullptr;
+  // ev_res: the SOR cycle's residual is done (the shared forward sweep)
+  hipEvent_t ev = nullptr, ev_fork = nullptr, ev_join = nullptr, ev_res = nullptr;
   std::string err;
   bool ready = false;
   vemg::Problem P;
@@ -463,6 +464,7 @@ struct Reuse {
   const int32_t *res = nullptr;          // rows whose residual is recomputed
   int64_t nres = 0;
   const Sell *res_sell = nullptr;        // those rows, packed
+  int phase = 0;  // 1: the dirty rows' sweep only; 2: the residual rows and the rest of the cycle
 };
 
 template <class T>
@@ -509,16 +511,20 @@ void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *
     zr.b1 = L.cstart[nc];
   }
   if (reuse && L.fine && L.cstart_top.empty()) {
-    // x and r hold the SOR cycle's values; sweep and recompute only the rows
-    // where the two differ, with the same arithmetic
-    for (int c = 0; c < nc; ++c) {
-      ZeroStart zs;
-      zs.on = true;
-      zs.n_top = L.n_top;
-      zs.top_lim = 0;
-      zs.bar_lim = L.cstart[c];
-      const int64_t a = (*reuse->gs_start)[c], b = (*reuse->gs_start)[c + 1];
-      launch_gs_rows<T>(st, K, (*reuse->gs_sell)[c], reuse->gs + a, b - a, g, x, done, zs);
+    // x and r hold the SOR cycle's values (x once its forward sweep is done,
+    // r once its residual is); sweep and recompute only the rows where the
+    // two differ, with the same arithmetic
+    if (reuse->phase == 1) {
+      for (int c = 0; c < nc; ++c) {
+        ZeroStart zs;
+        zs.on = true;
+        zs.n_top = L.n_top;
+        zs.top_lim = 0;
+        zs.bar_lim = L.cstart[c];
+        const int64_t a = (*reuse->gs_start)[c], b = (*reuse->gs_start)[c + 1];
+        launch_gs_rows<T>(st, K, (*reuse->gs_sell)[c], reuse->gs + a, b - a, g, x, done, zs);
+      }
+      return;
     }
     launch_spmv_rows<T>(st, K, *reuse->res_sell, reuse->res, reuse->nres, x, g, r, done, zr);
   } else {
@@ -542,9 +548,9 @@ void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *
 // One vertical-lumping multigrid cycle on stream st (Section 6, second
 // preconditioner): forward multicolour SOR on A from zero, E~ coarse
 // correction through one V-cycle on the surface operator, backward SOR.
-// part: 0 the whole cycle, 1 the forward sweep and the residual (with
-// share, their non-top rows are also stored to the additive smoother's fine
-// vectors), 2 the rest
+// part: 0 the whole cycle, 1 the forward sweep, 3 the residual, 2 the rest;
+// with share, the forward sweep's and the residual's non-top rows are also
+// stored to the additive smoother's fine vectors
 template <class T>
 void sor_cycle(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *done, int part = 0,
                bool share = false) {
@@ -573,8 +579,9 @@ void sor_cycle(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *
     zs.bar_lim = P.bar_colour_start[std::min(c, ncb)];
     launch_gs<T>(st, K, h->A, a0, a1, b0, b1, rr, zz, done, zs, first ? x2 : nullptr, m);
   };
-  if (part != 2) {
+  if (part == 0 || part == 1)
     for (int c = 0; c < nc; ++c) sweep(c, true);
+  if (part == 0 || part == 3) {
     if (m > 0) {
       // the rows swept by the last launch have a zero residual
       ZeroRows zr;
@@ -591,7 +598,7 @@ void sor_cycle(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *
       launch_spmv<T>(st, K, h->A, 1, 0, n, zz, rr, v.res, nullptr, done, h->order_all, zr, r2, m);
     }
   }
-  if (part == 1) return;
+  if (part == 1 || part == 3) return;
   if (m > 0) {
     launch_csr_rect<T>(st, K, h->Et, false, v.res, h->S[0].g<T>(), done);
     vcycle<T>(st, K, h->S, 0, done);
@@ -602,8 +609,10 @@ void sor_cycle(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *
 
 // w = Z Vcyc_Abar(Z^T rr) on stream st (the additive smoother; rows of the top
 // block of w stay zero)
+// phase 0: the whole V-cycle; 1 and 2: its two parts beside the SOR cycle's
+// shared forward sweep (see Reuse)
 template <class T>
-void additive_smoother(Handle *h, hipStream_t st, int K, const T *rr, const int *done, bool reuse = false) {
+void additive_smoother(Handle *h, hipStream_t st, int K, const T *rr, const int *done, int phase = 0) {
   T *saved = h->Ab[0].g<T>();
   h->Ab[0].g<T>() = const_cast<T *>(rr);
   Reuse R;
@@ -613,7 +622,8 @@ void additive_smoother(Handle *h, hipStream_t st, int K, const T *rr, const int 
   R.res = h->reuse_res;
   R.nres = h->n_reuse_res;
   R.res_sell = &h->reuse_res_sell;
-  vcycle<T>(st, K, h->Ab, 0, done, reuse ? &R : nullptr);
+  R.phase = phase;
+  vcycle<T>(st, K, h->Ab, 0, done, phase ? &R : nullptr);
   h->Ab[0].g<T>() = saved;
 }
 
@@ -633,26 +643,27 @@ bool shares(const Handle *h, int K) {
   return h->reuse && h->opt.pc == VEMG_PC_VL_ADDITIVE && K >= kShareMinBatch;
 }
 
-// second branch, on stream st2 (when shares(h, K) it follows the first part
-// of the SOR cycle, whose values it takes)
+// second branch, on stream st2.  When shares(h, K) it comes in two phases:
+// 1 after the SOR cycle's forward sweep, 2 after its residual.
 template <class T>
-void precond_branch(Handle *h, hipStream_t st2, int K, const T *rr, const int *done) {
+void precond_branch(Handle *h, hipStream_t st2, int K, const T *rr, const int *done, int phase = 0) {
   if (h->opt.pc == VEMG_PC_VL_ADDITIVE) {
-    additive_smoother<T>(h, st2, K, rr, done, shares(h, K));
+    additive_smoother<T>(h, st2, K, rr, done, shares(h, K) ? phase : 0);
   } else {
     launch_csr_rect<T>(st2, K, h->Et, false, rr, h->S[0].g<T>(), done);
     vcycle<T>(st2, K, h->S, 0, done);
   }
 }
 
-// first branch, on stream st.  When shares(h, K) it comes in two parts around
-// the fork of the second branch: part 1 (the SOR cycle's forward sweep and
-// residual, shared with the second branch), then part 2.
+// first branch, on stream st.  When shares(h, K) it comes in three parts:
+// 1 the SOR cycle's forward sweep and 3 its residual (both shared with the
+// second branch), then 2 the rest.
 template <class T>
 void precond_main(Handle *h, hipStream_t st, int K, const T *rr, T *zz, const int *done, int part = 0) {
   if (h->opt.pc == VEMG_PC_VL_ADDITIVE)
-    sor_cycle<T>(h, st, K, rr, zz, done, shares(h, K) ? part : 0, shares(h, K) && part == 1);
-  else if (part != 1)
+    sor_cycle<T>(h, st, K, rr, zz, done, shares(h, K) ? part : 0,
+                 shares(h, K) && (part == 1 || part == 3));
+  else if (part == 0 || part == 2)
     additive_smoother<T>(h, st, K, rr, done);
 }
 
@@ -677,12 +688,19 @@ void precond(Handle *h, int K, const T *rr, T *zz, double *part, int64_t *np, co
   int64_t n = P.n;
   Work<T> &v = work_of<T>(h);
   if (has_branch(h)) {
-    if (shares(h, K)) precond_main<T>(h, st, K, rr, zz, done, 1);
+    const bool sh = shares(h, K);
+    if (sh) precond_main<T>(h, st, K, rr, zz, done, 1);
     HIPCHK(hipEventRecord(h->ev_fork, st));
     HIPCHK(hipStreamWaitEvent(h->work2, h->ev_fork, 0));
-    precond_branch<T>(h, h->work2, K, rr, done);
+    precond_branch<T>(h, h->work2, K, rr, done, sh ? 1 : 0);
+    if (sh) {
+      precond_main<T>(h, st, K, rr, zz, done, 3);
+      HIPCHK(hipEventRecord(h->ev_res, st));
+      HIPCHK(hipStreamWaitEvent(h->work2, h->ev_res, 0));
+      precond_branch<T>(h, h->work2, K, rr, done, 2);
+    }
     HIPCHK(hipEventRecord(h->ev_join, h->work2));
-    precond_main<T>(h, st, K, rr, zz, done, shares(h, K) ? 2 : 0);
+    precond_main<T>(h, st, K, rr, zz, done, sh ? 2 : 0);
     HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
     *np = precond_join<T>(h, st, K, rr, zz, part, done);
     return;
@@ -757,7 +775,18 @@ int64_t precond_mixed(Handle *h, int K, const double *rr, double *zz, const int 
 // Krylov update.  Eagerly they run back to back with an event fork and join;
 // as graphs each segment is captured on its own and launched on its stream,
 // so that the two branches overlap on the device.
-enum Segment { kSegPre = 0, kSegBranch = 1, kSegMain = 2, kSegPost = 3, kSegMainFront = 4 };
+// (with the shared forward sweep also kSegMainFront, the SOR cycle's forward
+// sweep; kSegMainRes, its residual; kSegBranchRest, the second branch's part
+// after that residual)
+enum Segment {
+  kSegPre = 0,
+  kSegBranch = 1,
+  kSegMain = 2,
+  kSegPost = 3,
+  kSegMainFront = 4,
+  kSegMainRes = 5,
+  kSegBranchRest = 6
+};
 
 // Reliable update of the mixed-precision solve (FP32 PCG on A d = b / ||b||):
 // the FP32 correction accumulated since the last update is scaled by ||b||,
@@ -795,14 +824,18 @@ void pcg_segment(Handle *h, int K, int kind, int seg) {
         if (kind == kGraphFP32Reliable) reliable_update(h, K);
       break;
     case kSegBranch:
+    case kSegBranchRest: {
+      const int phase = !shares(h, K) ? 0 : seg == kSegBranch ? 1 : 2;
       if (mixed)
-        precond_branch<float>(h, h->work2, K, h->v32.tmp, done);
+        precond_branch<float>(h, h->work2, K, h->v32.tmp, done, phase);
       else
-        precond_branch<T>(h, h->work2, K, v.r, done);
+        precond_branch<T>(h, h->work2, K, v.r, done, phase);
       break;
+    }
     case kSegMainFront:
+    case kSegMainRes:
     case kSegMain: {
-      const int part = !shares(h, K) ? 0 : seg == kSegMainFront ? 1 : 2;
+      const int part = !shares(h, K) ? 0 : seg == kSegMainFront ? 1 : seg == kSegMainRes ? 3 : 2;
       if (mixed)
         precond_main<float>(h, st, K, h->v32.tmp, h->v32.z, done, part);
       else
@@ -837,11 +870,18 @@ void pcg_iteration(Handle *h, int K, int kind) {
   Work<T> &v = work_of<T>(h);
   const int *done = &h->scal->all_done;
   if (has_branch(h)) {
+    const bool sh = shares(h, K);
     pcg_segment<T>(h, K, kind, kSegPre);
-    if (shares(h, K)) pcg_segment<T>(h, K, kind, kSegMainFront);
+    if (sh) pcg_segment<T>(h, K, kind, kSegMainFront);
     HIPCHK(hipEventRecord(h->ev_fork, st));
     HIPCHK(hipStreamWaitEvent(h->work2, h->ev_fork, 0));
     pcg_segment<T>(h, K, kind, kSegBranch);
+    if (sh) {
+      pcg_segment<T>(h, K, kind, kSegMainRes);
+      HIPCHK(hipEventRecord(h->ev_res, st));
+      HIPCHK(hipStreamWaitEvent(h->work2, h->ev_res, 0));
+      pcg_segment<T>(h, K, kind, kSegBranchRest);
+    }
     HIPCHK(hipEventRecord(h->ev_join, h->work2));
     pcg_segment<T>(h, K, kind, kSegMain);
     HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
@@ -866,7 +906,7 @@ void pcg_iteration(Handle *h, int K, int kind) {
 
 void destroy_graphs(Handle *h) {
   for (auto &kv : h->graphs)
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; i < 7; ++i) {
       if (kv.second.exec[i]) (void)hipGraphExecDestroy(kv.second.exec[i]);
       if (kv.second.graph[i]) (void)hipGraphDestroy(kv.second.graph[i]);
     }
@@ -891,9 +931,9 @@ const IterGraphs *iteration_graphs(Handle *h, int K, int kind) {
   if (!h->allow_capture) return nullptr;
   IterGraphs ig;
   if (has_branch(h)) {
-    ig.parts = shares(h, K) ? 5 : 4;
+    ig.parts = shares(h, K) ? 7 : 4;
     for (int seg = 0; seg < ig.parts; ++seg)
-      capture(seg == kSegBranch ? h->work2 : h->work, &ig.graph[seg], &ig.exec[seg],
+      capture(seg == kSegBranch || seg == kSegBranchRest ? h->work2 : h->work, &ig.graph[seg], &ig.exec[seg],
               [&]() { pcg_segment<T>(h, K, kind, seg); });
   } else {
     ig.parts = 1;
@@ -910,11 +950,18 @@ void run_iteration(Handle *h, int K, int kind) {
   } else if (ig->parts == 1) {
     HIPCHK(hipGraphLaunch(ig->exec[0], h->work));
   } else {
+    const bool sh = ig->parts == 7;
     HIPCHK(hipGraphLaunch(ig->exec[kSegPre], h->work));
-    if (ig->parts == 5) HIPCHK(hipGraphLaunch(ig->exec[kSegMainFront], h->work));
+    if (sh) HIPCHK(hipGraphLaunch(ig->exec[kSegMainFront], h->work));
     HIPCHK(hipEventRecord(h->ev_fork, h->work));
     HIPCHK(hipStreamWaitEvent(h->work2, h->ev_fork, 0));
     HIPCHK(hipGraphLaunch(ig->exec[kSegBranch], h->work2));
+    if (sh) {
+      HIPCHK(hipGraphLaunch(ig->exec[kSegMainRes], h->work));
+      HIPCHK(hipEventRecord(h->ev_res, h->work));
+      HIPCHK(hipStreamWaitEvent(h->work2, h->ev_res, 0));
+      HIPCHK(hipGraphLaunch(ig->exec[kSegBranchRest], h->work2));
+    }
     HIPCHK(hipEventRecord(h->ev_join, h->work2));
     HIPCHK(hipGraphLaunch(ig->exec[kSegMain], h->work));
     HIPCHK(hipStreamWaitEvent(h->work, h->ev_join, 0));
@@ -2014,6 +2061,7 @@ vemg_status create_handle(const vemg_options *o, int device, hipStream_t user, c
       HIPCHK(hipEventCreateWithFlags(&h->ev, hipEventDisableTiming));
       HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
       HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&h->ev_res, hipEventDisableTiming));
     }
     return VEMG_OK;
   });
@@ -2231,6 +2279,7 @@ vemg_status vemg_destroy(vemg_solver s) {
     if (s->ev) (void)hipEventDestroy(s->ev);
     if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
     if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+    if (s->ev_res) (void)hipEventDestroy(s->ev_res);
     if (s->own_streams && s->work) (void)hipStreamDestroy(s->work);
     if (s->own_streams && s->work2) (void)hipStreamDestroy(s->work2);
   }
