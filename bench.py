@@ -152,7 +152,7 @@ def vcycle_bytes(rows, off, pnnz, K, elt, val, fine_rows=None, fine_nnz=None):
 # The library's additive smoother takes the SOR cycle's fine forward sweep and
 # residual for batches of this many columns or more (the rows where the two
 # differ, a few per cent, are swept again; their bytes are not counted).
-SHARE_MIN_BATCH = 4
+SHARE_MIN_BATCH = 1
 
 
 def iteration_bytes(info, K=1, pc="vl_as", precision="fp64"):
@@ -219,8 +219,9 @@ def kernel_rates(s, info, vemg, K=1, reps=20, precision="fp64"):
 #           A_bar level 1), plus the CG product
 #   vl_sor: the SOR cycle alone plus the CG product
 #   vl_add: the A_bar V-cycle plus the CG product
-# (vl_as with SHARE_MIN_BATCH columns or more: the A_bar V-cycle's forward
-# sweep and residual come from the SOR cycle, so 3 full sweeps and 2 SpMVs)
+# (vl_as with SHARE_MIN_BATCH columns or more, every batch: the A_bar
+# V-cycle's forward sweep and residual come from the SOR cycle, so 3 full
+# sweeps and 2 SpMVs)
 PER_ITERATION = {"vl_as": (4, 3, 2), "vl_sor": (2, 2, 0), "vl_add": (2, 2, 2), "jacobi": (0, 1, 0),
                  "none": (0, 1, 0)}
 PER_ITERATION_SHARED = {"vl_as": (3, 2, 2)}

@@ -636,9 +636,9 @@ bool has_branch(const Handle *h) {
 
 // Whether the additive smoother takes the SOR cycle's forward sweep and
 // residual for a batch of K columns.  The smoother then starts only after
-// that part of the SOR cycle, which costs overlap; it pays when the sweeps
-// it saves are long (wide batches).
-constexpr int kShareMinBatch = 4;
+// that sweep, which costs overlap; with the dirty rows packed and the second
+// fork after the SOR cycle's residual it pays from one column on.
+constexpr int kShareMinBatch = 1;
 bool shares(const Handle *h, int K) {
   return h->reuse && h->opt.pc == VEMG_PC_VL_ADDITIVE && K >= kShareMinBatch;
 }
