@@ -150,9 +150,9 @@ def vcycle_bytes(rows, off, pnnz, K, elt, val, fine_rows=None, fine_nnz=None):
 
 
 # The library's additive smoother takes the SOR cycle's fine forward sweep and
-# residual for batches of this many columns or more (the rows where the two
-# differ, a few per cent, are swept again; their bytes are not counted).
-SHARE_MIN_BATCH = 1
+# residual on meshes of this many fine unknowns or more (the rows where the
+# two differ, a few per cent, are swept again; their bytes are not counted).
+SHARE_MIN_ROWS = 1000000
 
 
 def iteration_bytes(info, K=1, pc="vl_as", precision="fp64"):
@@ -171,7 +171,7 @@ def iteration_bytes(info, K=1, pc="vl_as", precision="fp64"):
     nbar = info["n"] - info["n_top"]
     a_cycle = vcycle_bytes(info["abar_rows"], info["abar_nnz"], info["p_nnz_abar"], K, pe, pv,
                            fine_rows=nbar, fine_nnz=info["abar_nnz"][0])
-    if pc == "vl_as" and info["n_top"] and K >= SHARE_MIN_BATCH:
+    if pc == "vl_as" and info["n_top"] and n >= SHARE_MIN_ROWS:
         a_cycle -= (gs_sweep_bytes(None, K, pe, pv, rows=nbar, nnz=info["abar_nnz"][0])
                     + spmv_bytes(None, K, pe, pv, residual=True, rows=nbar, nnz=info["abar_nnz"][0]))
         a_cycle += 2 * nbar * pe * K
@@ -219,7 +219,7 @@ def kernel_rates(s, info, vemg, K=1, reps=20, precision="fp64"):
 #           A_bar level 1), plus the CG product
 #   vl_sor: the SOR cycle alone plus the CG product
 #   vl_add: the A_bar V-cycle plus the CG product
-# (vl_as with SHARE_MIN_BATCH columns or more, every batch: the A_bar
+# (vl_as on meshes of SHARE_MIN_ROWS fine unknowns or more: the A_bar
 # V-cycle's forward sweep and residual come from the SOR cycle, so 3 full
 # sweeps and 2 SpMVs)
 PER_ITERATION = {"vl_as": (4, 3, 2), "vl_sor": (2, 2, 0), "vl_add": (2, 2, 2), "jacobi": (0, 1, 0),
@@ -235,10 +235,11 @@ KERNEL_NAMES = {
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
 
-def dominant_kernel(rates, pc, K):
+def dominant_kernel(rates, pc, K, n):
     """The hot kernel with the largest share of one iteration's time: its
-    algorithmic bytes and average duration per launch (the roofline entry)."""
-    n_gs, n_spmv, n_cgs = (PER_ITERATION_SHARED[pc] if pc in PER_ITERATION_SHARED and K >= SHARE_MIN_BATCH
+    algorithmic bytes and average duration per launch (the roofline entry);
+    n: the fine unknowns (whether the forward sweep is shared)."""
+    n_gs, n_spmv, n_cgs = (PER_ITERATION_SHARED[pc] if pc in PER_ITERATION_SHARED and n >= SHARE_MIN_ROWS
                            else PER_ITERATION[pc])
     share = {"gs": n_gs * rates["fine_sweep"]["ms"], "spmv": n_spmv * rates["spmv"]["ms"],
              "cgs": n_cgs * rates.get("coarse_sweep", {"ms": 0.0})["ms"]}
@@ -874,7 +875,7 @@ def main():
 
     # live per-kernel timing (HIP events on the library's stream) and the roofline
     rates = kernel_rates(s, info, vemg, K, reps=20)
-    dom_key, dom = dominant_kernel(rates, args.pc, K)
+    dom_key, dom = dominant_kernel(rates, args.pc, K, info["n"])
     achieved = dom["bytes_per_launch"] / (dom["ms_per_launch"] * 1e-3) / 1e9
     traffic = measured_traffic(dom_key, args.workload, K)
     it_bytes = iteration_bytes(info, K, args.pc)

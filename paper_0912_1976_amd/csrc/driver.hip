@@ -15,6 +15,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -309,6 +310,7 @@ struct vemg_solver_s {
   // SELL matrices of their own (entries read coalesced)
   std::vector<vemg::Sell> reuse_gs_sell;
   vemg::Sell reuse_res_sell;
+  int64_t share_min_rows = 0;  // fine unknowns from which the forward sweep is shared
   // the top block of the additive smoother's x (rows [0, n_top) of v64.w and
   // v32.w) is zero in the layout of every batch width up to w_clean
   int w_clean = vemg::kMaxBatch;
@@ -635,12 +637,22 @@ bool has_branch(const Handle *h) {
 }
 
 // Whether the additive smoother takes the SOR cycle's forward sweep and
-// residual for a batch of K columns.  The smoother then starts only after
-// that sweep, which costs overlap; with the dirty rows packed and the second
-// fork after the SOR cycle's residual it pays from one column on.
-constexpr int kShareMinBatch = 1;
-bool shares(const Handle *h, int K) {
-  return h->reuse && h->opt.pc == VEMG_PC_VL_ADDITIVE && K >= kShareMinBatch;
+// residual.  The smoother then starts only after that sweep, which costs
+// overlap; the sweeps it saves outweigh that only when they are long: on
+// meshes of a million fine unknowns and more (any batch width), not below.
+// The environment's VEMG_SHARE_MIN_ROWS, when set, replaces that bound (0:
+// always), so that small meshes can exercise the shared form.
+constexpr int64_t kShareMinRows = 1000000;
+int64_t share_min_rows() {
+  if (const char *e = std::getenv("VEMG_SHARE_MIN_ROWS")) {
+    char *end = nullptr;
+    const long long v = std::strtoll(e, &end, 10);
+    if (end != e && *end == '\0' && v >= 0) return (int64_t)v;
+  }
+  return kShareMinRows;
+}
+bool shares(const Handle *h, int) {
+  return h->reuse && h->opt.pc == VEMG_PC_VL_ADDITIVE && h->P.n >= h->share_min_rows;
 }
 
 // second branch, on stream st2.  When shares(h, K) it comes in two phases:
@@ -1306,6 +1318,7 @@ void upload(Handle *h) {
     h->reuse_gs = h->ar.upload(rows, st);
     h->reuse_res = h->ar.upload(res, st);
     h->reuse_res_sell = pack_sell(h->ar, st, P.Aoff, true, &P.d, &P.diag, nullptr, &res);
+    h->share_min_rows = share_min_rows();
     h->n_reuse_res = (int64_t)res.size();
     h->reuse = true;
   }

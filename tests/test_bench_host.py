@@ -145,13 +145,20 @@ def test_iteration_bytes_add_up_the_preconditioner_branches():
     # the additive smoother's V-cycle on A_bar is the difference (plus the join)
     a_cycle = bench.vcycle_bytes(info["abar_rows"], info["abar_nnz"], info["p_nnz_abar"], 1, 8, 8,
                                  fine_rows=90, fine_nnz=1150)
-    # with the shared forward sweep its fine forward sweep and residual are
-    # the SOR cycle's, which stores x and r of the 90 non-top rows once more
+    join = 4 * 100 * 8 + 100 * 8
+    assert bench.SHARE_MIN_ROWS > 100
+    assert full - sor == a_cycle + join - 2 * 100 * 8
+    # on a mesh large enough to share the forward sweep, the smoother's fine
+    # forward sweep and residual are the SOR cycle's, which stores x and r of
+    # the 90 non-top rows once more
     shared = (bench.gs_sweep_bytes(None, 1, 8, 8, rows=90, nnz=1150)
               + bench.spmv_bytes(None, 1, 8, 8, residual=True, rows=90, nnz=1150))
-    assert bench.SHARE_MIN_BATCH == 1
-    join = 4 * 100 * 8 + 100 * 8
-    assert full - sor == a_cycle - shared + 2 * 90 * 8 + join - 2 * 100 * 8
+    saved = bench.SHARE_MIN_ROWS
+    try:
+        bench.SHARE_MIN_ROWS = 100
+        assert bench.iteration_bytes(info, 1, "vl_as") == full - shared + 2 * 90 * 8
+    finally:
+        bench.SHARE_MIN_ROWS = saved
     # batches and FP32 preconditioners scale the vector traffic, not the matrices
     assert bench.iteration_bytes(info, 8, "vl_as") > full
     assert bench.iteration_bytes(info, 1, "vl_as", "mixed_pc") < full + 4 * 100 * 12

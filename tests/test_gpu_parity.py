@@ -271,6 +271,26 @@ def test_deterministic_and_batched_equals_single(nrhs, precision):
         assert torch.equal(xb[k], x1)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed_pc", "mixed_ir"])
+def test_shared_forward_sweep_equals_the_plain_one(precision, monkeypatch):
+    # on meshes of a million fine unknowns the additive smoother takes the SOR
+    # cycle's forward sweep and residual for the rows they share, sweeping and
+    # recomputing only the rows where the two differ; forced on this small
+    # mesh, it reproduces the plain form's solutions bit for bit
+    m, plain, o = _build(RAGGED, "N", precision=precision)
+    monkeypatch.setenv("VEMG_SHARE_MIN_ROWS", "0")
+    shared = lib.Solver(m.xyz, m.tets, m.top, device=0, coarse_max=64, precision=precision)
+    monkeypatch.delenv("VEMG_SHARE_MIN_ROWS")
+    B = np.stack([plain.rhs(fourier_field(m.xyz, RAGGED["H"], 500 + k)) for k in range(8)])
+    for K in (1, 4, 8):
+        Bk = B[0] if K == 1 else B[:K]
+        x1, it1, _, _ = plain.solve(Bk, rtol=1e-9)
+        x2, it2, _, _ = shared.solve(Bk, rtol=1e-9)
+        assert list(np.atleast_1d(it1)) == list(np.atleast_1d(it2)), K
+        assert torch.equal(x1, x2), K
+    shared.close()
+
+
 def test_switching_preconditioner_with_a_batch_equals_fresh_handles():
     # batches of four or more columns let the additive smoother take the SOR
     # cycle's forward sweep; a handle created for another preconditioner and
