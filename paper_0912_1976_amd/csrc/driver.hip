@@ -311,6 +311,7 @@ struct vemg_solver_s {
   std::vector<vemg::Sell> reuse_gs_sell;
   vemg::Sell reuse_res_sell;
   int64_t share_min_rows = 0;  // fine unknowns from which the forward sweep is shared
+  bool reuse_full_res = false;  // no top surface: the smoother's residual is computed in full
   // the top block of the additive smoother's x (rows [0, n_top) of v64.w and
   // v32.w) is zero in the layout of every batch width up to w_clean
   int w_clean = vemg::kMaxBatch;
@@ -466,6 +467,7 @@ struct Reuse {
   const int32_t *res = nullptr;          // rows whose residual is recomputed
   int64_t nres = 0;
   const Sell *res_sell = nullptr;        // those rows, packed
+  bool full_res = false;                 // recompute every row's residual (no top surface)
   int phase = 0;  // 1: the dirty rows' sweep only; 2: the residual rows and the rest of the cycle
 };
 
@@ -528,7 +530,10 @@ void vcycle(hipStream_t st, int K, std::vector<DLevel> &H, size_t l, const int *
       }
       return;
     }
-    launch_spmv_rows<T>(st, K, *reuse->res_sell, reuse->res, reuse->nres, x, g, r, done, zr);
+    if (reuse->full_res)
+      launch_spmv<T>(st, K, L.As, 1, L.row0, L.row0 + L.n, x, g, r, nullptr, done, L.order, zr);
+    else
+      launch_spmv_rows<T>(st, K, *reuse->res_sell, reuse->res, reuse->nres, x, g, r, done, zr);
   } else {
     for (int c = 0; c < nc; ++c) gs(c, true);
   }
@@ -624,6 +629,7 @@ void additive_smoother(Handle *h, hipStream_t st, int K, const T *rr, const int 
   R.res = h->reuse_res;
   R.nres = h->n_reuse_res;
   R.res_sell = &h->reuse_res_sell;
+  R.full_res = h->reuse_full_res;
   R.phase = phase;
   vcycle<T>(st, K, h->Ab, 0, done, phase ? &R : nullptr);
   h->Ab[0].g<T>() = saved;
@@ -1286,7 +1292,7 @@ void upload(Handle *h) {
   // is the same unless the row, or a neighbour, is dirty or a neighbour is a
   // top row, or the two zero it differently (the smoother zeroes its last
   // colour, the SOR cycle the rows of its last launch).
-  if (m > 0) {  // for every preconditioner: a handle may be switched to VL + additive smoother
+  {  // for every preconditioner: a handle may be switched to VL + additive smoother
     const Csr &O = P.Aoff;
     const int ncb = (int)P.bar_colour_start.size() - 1, nct = (int)P.top_colour_start.size() - 1;
     const bool same_last = std::max(nct, ncb) == ncb;
@@ -1315,6 +1321,10 @@ void upload(Handle *h) {
       for (int64_t k = O.ptr[i]; k < O.ptr[i + 1] && !d; ++k) d = O.idx[k] < m || dirty[O.idx[k]];
       if (d) res.push_back((int32_t)i);
     }
+    // without a top surface no row is dirty, but the SOR cycle computes no
+    // residual: the smoother computes all of its own
+    h->reuse_full_res = m == 0;
+    if (h->reuse_full_res) res.clear();
     h->reuse_gs = h->ar.upload(rows, st);
     h->reuse_res = h->ar.upload(res, st);
     h->reuse_res_sell = pack_sell(h->ar, st, P.Aoff, true, &P.d, &P.diag, nullptr, &res);

@@ -271,15 +271,18 @@ def test_deterministic_and_batched_equals_single(nrhs, precision):
         assert torch.equal(xb[k], x1)
 
 
+@pytest.mark.parametrize("mode", ["N", "D"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed_pc", "mixed_ir"])
-def test_shared_forward_sweep_equals_the_plain_one(precision, monkeypatch):
+def test_shared_forward_sweep_equals_the_plain_one(precision, mode, monkeypatch):
     # on meshes of a million fine unknowns the additive smoother takes the SOR
     # cycle's forward sweep and residual for the rows they share, sweeping and
-    # recomputing only the rows where the two differ; forced on this small
-    # mesh, it reproduces the plain form's solutions bit for bit
-    m, plain, o = _build(RAGGED, "N", precision=precision)
+    # recomputing only the rows where the two differ (with the whole top
+    # fixed, every row is shared and the residual is computed in full);
+    # forced on this small mesh, it reproduces the plain form's solutions bit
+    # for bit
+    m, plain, o = _build(RAGGED, mode, precision=precision)
     monkeypatch.setenv("VEMG_SHARE_MIN_ROWS", "0")
-    shared = lib.Solver(m.xyz, m.tets, m.top, device=0, coarse_max=64, precision=precision)
+    shared = lib.Solver(m.xyz, m.tets, m.top, top_bc=mode, device=0, coarse_max=64, precision=precision)
     monkeypatch.delenv("VEMG_SHARE_MIN_ROWS")
     B = np.stack([plain.rhs(fourier_field(m.xyz, RAGGED["H"], 500 + k)) for k in range(8)])
     for K in (1, 4, 8):
